@@ -1,0 +1,143 @@
+/*
+ * hpmg.h — C ABI of libhpmg.so: matrix-free hp-multigrid for symmetric
+ * interior penalty DG (SIPG) discretisations of -div(kappa grad u) = f on
+ * the unit box with homogeneous Dirichlet conditions, on AMD MI355X (gfx950).
+ *
+ * Method: arXiv 2510.00998 ("Implementation techniques for multigrid
+ * solvers for high-order Discontinuous Galerkin methods").  The smoother is
+ * the single-touch block-Jacobi sweep with auxiliary facet (trace)
+ * variables and shift-and-fuse (Section 4.2, technique shift-and-fuse and
+ * Algorithm BlockJacobi with loop fusion); the multigrid cycle follows
+ * Section 5 (Algorithms CoarseGridCorrection and MGMult, hp-multigrid of
+ * Section 5.2) with a gradual p-coarsening to continuous Q1 and
+ * h-coarsening by two.
+ *
+ * Conventions (all entry points):
+ *  - Vectors are DEVICE pointers owned by the caller, cell-major: cell
+ *    c = cx + n*cy (+ n^2*cz), local node i = a + N*b (+ N^2*c), N = p+1,
+ *    x fastest, Gauss-Lobatto nodes.  `nrhs` right-hand sides are stacked
+ *    back to back ([rhs][dof]).
+ *  - All work is enqueued on `stream` (0 = the null stream).  Only
+ *    hpmg_solve synchronises the stream (it reads one 8-byte norm per
+ *    iteration back to the host).
+ *  - No function throws; each returns a status.  A message describing the
+ *    last failure of the calling thread is available from hpmg_last_error.
+ *  - Right-hand sides are load vectors b_i = int f phi_i, not samples of f.
+ */
+#ifndef HPMG_H
+#define HPMG_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hpmg_ctx* hpmg_handle; /* opaque, owned by the library */
+
+typedef enum {
+  HPMG_OK = 0,
+  HPMG_E_INVALID = 1,       /* bad argument (null pointer, size, unsupported range) */
+  HPMG_E_NOMEM = 2,         /* device or host allocation failed */
+  HPMG_E_DEVICE = 3,        /* a HIP call failed (no device, launch failure, ...) */
+  HPMG_E_NOT_CONVERGED = 4, /* hpmg_solve reached maxit before rtol */
+  HPMG_E_BREAKDOWN = 5,     /* non-finite value met in hpmg_solve (e.g. NaN in b) */
+  HPMG_E_UNSUPPORTED = 6    /* valid request this build does not implement */
+} hpmg_status;
+
+typedef enum { HPMG_F64 = 0, HPMG_F32 = 1 } hpmg_dtype;
+
+/* Precision of the multigrid cycle used inside hpmg_solve.  F64: everything
+ * in double.  F32: smoother, transfers and coarse levels in float inside the
+ * FP64 outer iteration (fine residual, update and coarsest solve in double). */
+typedef enum { HPMG_PREC_F64 = 0, HPMG_PREC_F32 = 1 } hpmg_precision;
+
+/* Unit box [0,1]^dim with n[0] cells per axis (n[1], n[2] must equal n[0]).
+ * dim in {2, 3}, n >= 2. */
+typedef struct { int dim; int n[3]; } hpmg_mesh;
+
+/* Diffusion coefficient, piecewise constant per cell.  per_cell = 0: the
+ * value kappa_const (> 0) everywhere.  per_cell = 1: kappa points to n^dim
+ * HOST doubles (> 0, finite), copied during setup. */
+typedef struct { int per_cell; double kappa_const; const double* kappa; } hpmg_coeff;
+
+typedef struct {
+  double sigma0;      /* penalty sigma = sigma0 (p+1)^2 / h on interior facets, 2 sigma on boundary facets (default 2) */
+  double omega_dg;    /* block-Jacobi relaxation on DG levels, 0 < omega <= 1 (default 0.7) */
+  double omega_cg;    /* point-Jacobi relaxation on Q1 levels (default 2/3) */
+  int nu_pre;         /* smoothing steps before the coarse correction (default 2) */
+  int nu_post;        /* smoothing steps after it (default 2) */
+  int coarsest_n;     /* stop h-coarsening once n <= coarsest_n (default 4) */
+  int precision;      /* hpmg_precision of the cycle inside hpmg_solve (default F32) */
+  int max_rhs;        /* largest nrhs any call will use (default 1) */
+} hpmg_options;
+
+/* Fill *opt with the defaults listed above. */
+void hpmg_default_options(hpmg_options* opt);
+
+/* Build the level hierarchy on the current HIP device: 1D reference data,
+ * fast-diagonalisation data of the cell blocks A_{K<-K} (per boundary class
+ * for constant kappa, per cell for variable kappa), Q1 coarse operators by
+ * Galerkin products, device buffers.  1 <= p <= 8.  The result is written to
+ * *out; release it with hpmg_destroy.  Paper: Section 4.1 (Schur complement
+ * block A_{K<-K}, technique precompute-block-inverse), Section 5.2. */
+hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff,
+                       const hpmg_options* opt, hipStream_t stream, hpmg_handle* out);
+
+/* Number of DG degrees of freedom n^dim (p+1)^dim of one right-hand side. */
+size_t hpmg_ndof(hpmg_handle h);
+
+/* Load vector b_i = int f phi_i ((p+3)-point Gauss per direction) for a
+ * built-in f: kind 0: f = params[0] (constant); kind 1: f = -Laplace of
+ * prod_i sin(params[0] pi x_i) (i.e. dim params[0]^2 pi^2 prod sin); b is a
+ * device FP64 vector of hpmg_ndof entries.  Paper: Section 2.3.1, b(v). */
+hpmg_status hpmg_load_vector(hpmg_handle h, int kind, const double* params, double* b,
+                             hipStream_t stream);
+
+/* y = A u for the SIPG operator A of eq. weak_form_IP (matrix-free:
+ * trace projection then one fused cell traversal).  dtype selects double or
+ * float vectors; u and y must not overlap. */
+hpmg_status hpmg_apply_A(hpmg_handle h, hpmg_dtype dtype, const void* u, void* y, int nrhs,
+                         hipStream_t stream);
+
+/* nsweeps block-Jacobi steps u <- u + omega A_{K<-K}^{-1} (b - A u) in
+ * place (Algorithm BlockJacobi with loop fusion: one projection traversal,
+ * then one fused traversal per step).  nsweeps >= 0. */
+hpmg_status hpmg_smooth(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nsweeps,
+                        int nrhs, hipStream_t stream);
+
+/* One V(nu_pre, nu_post) cycle of the hp-multigrid in place on u
+ * (Algorithm MGMult body with CoarseGridCorrection; gradual p-coarsening,
+ * Q1, h-coarsening, dense coarsest solve). */
+hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nrhs,
+                        hipStream_t stream);
+
+typedef struct {
+  int iterations;            /* outer iterations done */
+  double initial_residual;   /* ||b - A u0||_2 */
+  double final_residual;     /* ||b - A u||_2 (recurrence value, FP64) */
+  double residual_history[256]; /* relative residuals, entry k after iteration k */
+  double seconds;            /* wall time of the call */
+} hpmg_solve_info;
+
+/* Solve A u = b to ||b - A u||_2 <= rtol ||b - A u0||_2 with flexible CG
+ * preconditioned by one V-cycle (precision from the options) in FP64.  u
+ * holds the initial guess on entry.  info may be NULL (host pointer).
+ * Returns HPMG_E_NOT_CONVERGED after maxit iterations, HPMG_E_BREAKDOWN on a
+ * non-finite residual.  Paper: Section 5 (MGMult, exit criterion), with the
+ * unpreconditioned residual as exit test. */
+hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, double rtol,
+                       int maxit, hpmg_solve_info* info, hipStream_t stream);
+
+/* Release every resource of the handle (NULL is ignored). */
+void hpmg_destroy(hpmg_handle h);
+
+const char* hpmg_status_string(hpmg_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* hpmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPMG_H */

@@ -1,0 +1,200 @@
+"""Python binding of libhpmg.so (matrix-free SIPG-DG hp-multigrid on MI355X).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Vectors are torch tensors on the GPU (float64 or float32, contiguous,
+cell-major layout described in include/hpmg.h); work is enqueued on the
+current torch stream.  Importing this package fails loudly if the library
+has not been built (python -m paper_2510_00998_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhpmg.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "hpmg.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libhpmg.so not built at {LIB_PATH}; run `python -m paper_2510_00998_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+STATUS = {0: "HPMG_OK", 1: "HPMG_E_INVALID", 2: "HPMG_E_NOMEM", 3: "HPMG_E_DEVICE",
+          4: "HPMG_E_NOT_CONVERGED", 5: "HPMG_E_BREAKDOWN", 6: "HPMG_E_UNSUPPORTED"}
+F64, F32 = 0, 1
+PREC_F64, PREC_F32 = 0, 1
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3)]
+
+
+class Coeff(ctypes.Structure):
+    _fields_ = [("per_cell", ctypes.c_int), ("kappa_const", ctypes.c_double),
+                ("kappa", ctypes.POINTER(ctypes.c_double))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("sigma0", ctypes.c_double), ("omega_dg", ctypes.c_double), ("omega_cg", ctypes.c_double),
+                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("coarsest_n", ctypes.c_int),
+                ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("initial_residual", ctypes.c_double),
+                ("final_residual", ctypes.c_double), ("residual_history", ctypes.c_double * 256),
+                ("seconds", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_lib.hpmg_default_options.argtypes = [ctypes.POINTER(Options)]
+_lib.hpmg_default_options.restype = None
+_lib.hpmg_setup.argtypes = [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Coeff), ctypes.POINTER(Options),
+                            _vp, ctypes.POINTER(_vp)]
+_lib.hpmg_setup.restype = ctypes.c_int
+_lib.hpmg_ndof.argtypes = [_vp]
+_lib.hpmg_ndof.restype = ctypes.c_size_t
+_lib.hpmg_load_vector.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp]
+_lib.hpmg_load_vector.restype = ctypes.c_int
+_lib.hpmg_apply_A.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]
+_lib.hpmg_apply_A.restype = ctypes.c_int
+_lib.hpmg_smooth.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+_lib.hpmg_smooth.restype = ctypes.c_int
+_lib.hpmg_vcycle.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]
+_lib.hpmg_vcycle.restype = ctypes.c_int
+_lib.hpmg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                            ctypes.POINTER(SolveInfo), _vp]
+_lib.hpmg_solve.restype = ctypes.c_int
+_lib.hpmg_destroy.argtypes = [_vp]
+_lib.hpmg_destroy.restype = None
+_lib.hpmg_status_string.argtypes = [ctypes.c_int]
+_lib.hpmg_status_string.restype = ctypes.c_char_p
+_lib.hpmg_last_error.argtypes = []
+_lib.hpmg_last_error.restype = ctypes.c_char_p
+
+
+class HpmgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.hpmg_last_error().decode()
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise HpmgError(st, where)
+
+
+def library():
+    """The loaded ctypes library (for ABI tests)."""
+    return _lib
+
+
+def declared_symbols() -> list[str]:
+    """Names of the functions declared in include/hpmg.h."""
+    txt = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"\b(hpmg_[a-z_A]+)\s*\(", txt)))
+
+
+def default_options() -> Options:
+    o = Options()
+    _lib.hpmg_default_options(ctypes.byref(o))
+    return o
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype_code=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype_code is not None:
+        want = torch.float64 if dtype_code == F64 else torch.float32
+        if t.dtype != want:
+            raise TypeError(f"expected {want}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+class Solver:
+    """One SIPG problem -div(kappa grad u) = f on [0,1]^dim (hpmg_setup)."""
+
+    def __init__(self, dim: int, n: int, p: int, kappa=1.0, stream=None, **options):
+        opt = default_options()
+        for k, v in options.items():
+            if not hasattr(opt, k):
+                raise KeyError(f"unknown option {k}")
+            setattr(opt, k, v)
+        mesh = Mesh(dim, (ctypes.c_int * 3)(n, n, n))
+        self._kappa_buf = None
+        if np.isscalar(kappa):
+            coeff = Coeff(0, float(kappa), None)
+        else:
+            arr = np.ascontiguousarray(np.asarray(kappa, dtype=np.float64))
+            if arr.shape != (n ** dim,):
+                raise ValueError("kappa must hold one value per cell")
+            self._kappa_buf = arr
+            coeff = Coeff(1, 0.0, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = ctypes.c_void_p()
+        _check(_lib.hpmg_setup(ctypes.byref(mesh), p, ctypes.byref(coeff), ctypes.byref(opt), _stream(stream),
+                               ctypes.byref(h)), "hpmg_setup")
+        self._h = h
+        self.dim, self.n, self.p, self.options = dim, n, p, opt
+        self.ndof = int(_lib.hpmg_ndof(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hpmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_vector(self, kind: int, param: float, b, stream=None):
+        prm = (ctypes.c_double * 1)(param)
+        _check(_lib.hpmg_load_vector(self._h, kind, prm, _ptr(b, F64), _stream(stream)), "hpmg_load_vector")
+        return b
+
+    def apply_A(self, u, y, nrhs: int = 1, stream=None):
+        c = _code(u)
+        _check(_lib.hpmg_apply_A(self._h, c, _ptr(u, c), _ptr(y, c), nrhs, _stream(stream)), "hpmg_apply_A")
+        return y
+
+    def smooth(self, u, b, nsweeps: int, nrhs: int = 1, stream=None):
+        c = _code(u)
+        _check(_lib.hpmg_smooth(self._h, c, _ptr(u, c), _ptr(b, c), nsweeps, nrhs, _stream(stream)), "hpmg_smooth")
+        return u
+
+    def vcycle(self, u, b, nrhs: int = 1, stream=None):
+        c = _code(u)
+        _check(_lib.hpmg_vcycle(self._h, c, _ptr(u, c), _ptr(b, c), nrhs, _stream(stream)), "hpmg_vcycle")
+        return u
+
+    def solve(self, u, b, rtol: float = 1e-10, maxit: int = 200, nrhs: int = 1, stream=None, check=True):
+        info = SolveInfo()
+        st = _lib.hpmg_solve(self._h, _ptr(u, F64), _ptr(b, F64), nrhs, rtol, maxit, ctypes.byref(info),
+                             _stream(stream))
+        if check:
+            _check(st, "hpmg_solve")
+        return info, st

@@ -1,0 +1,362 @@
+// Kernels of the continuous Q1 levels (paper Section 2.4 point-Jacobi with
+// the accumulated diagonal; Section 5.2 h-multigrid), the DG -> Q1 gather of
+// restricted residuals, the dense coarsest solve, and the FP64 vector
+// operations of the outer Krylov iteration.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace hpmg {
+
+namespace {
+
+template <int D>
+__device__ __forceinline__ void vcoords(int v, int nv, int (&x)[3]) {
+  x[0] = v % nv;
+  x[1] = (v / nv) % nv;
+  x[2] = (D == 3) ? v / (nv * nv) : 0;
+}
+
+// out = u + omega Dinv (b - A u)   (mode 0; u = 0 if uzero)
+// out = b - A u                    (mode 1)
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict__ st, const T* __restrict__ dinv,
+                                                    const T* __restrict__ u, const T* __restrict__ b,
+                                                    T* __restrict__ out, T omega, int mode, int uzero) {
+  constexpr int NS = (D == 2) ? 9 : 27;
+  const int total = (D == 2) ? nv * nv : nv * nv * nv;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= total) return;
+  T au = 0;
+  if (!uzero) {
+    int x[3];
+    vcoords<D>(v, nv, x);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = (D == 3) ? s / 9 - 1 : 0;
+      const int X = x[0] + dx, Y = x[1] + dy, Z = x[2] + dz;
+      if (X < 0 || X >= nv || Y < 0 || Y >= nv || (D == 3 && (Z < 0 || Z >= nv))) continue;
+      const int w = X + nv * (Y + nv * Z);
+      au += st[(size_t)v * NS + s] * u[w];
+    }
+  }
+  if (mode == 0) {
+    const T u0 = uzero ? T(0) : u[v];
+    out[v] = u0 + omega * dinv[v] * (b[v] - au);
+  } else {
+    out[v] = b[v] - au;
+  }
+}
+
+// b_c = P^T r_f with the tensor-product 1D transfer: coarse interior index I
+// gathers up to three fine interior indices ridx[3I..3I+2] with weights rw.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, const int* __restrict__ ridx,
+                                                     const T* __restrict__ rw, const T* __restrict__ rf,
+                                                     T* __restrict__ bc) {
+  const int total = (D == 2) ? nvc * nvc : nvc * nvc * nvc;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= total) return;
+  int x[3];
+  vcoords<D>(v, nvc, x);
+  T s = 0;
+  for (int c = 0; c < (D == 3 ? 3 : 1); ++c) {
+    const int iz = (D == 3) ? ridx[3 * x[2] + c] : 0;
+    const T wz = (D == 3) ? rw[3 * x[2] + c] : T(1);
+    if (iz < 0) continue;
+    for (int b2 = 0; b2 < 3; ++b2) {
+      const int iy = ridx[3 * x[1] + b2];
+      if (iy < 0) continue;
+      const T wy = rw[3 * x[1] + b2];
+      for (int a2 = 0; a2 < 3; ++a2) {
+        const int ix = ridx[3 * x[0] + a2];
+        if (ix < 0) continue;
+        s += wz * wy * rw[3 * x[0] + a2] * rf[ix + nvf * (iy + nvf * iz)];
+      }
+    }
+  }
+  bc[v] = s;
+}
+
+// u_f += P e_c: fine interior index i interpolates from up to two coarse
+// interior indices pidx[2i..2i+1] with weights pw.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cg_prolong(int nvf, int nvc, const int* __restrict__ pidx,
+                                                    const T* __restrict__ pw, const T* __restrict__ ec,
+                                                    T* __restrict__ uf) {
+  const int total = (D == 2) ? nvf * nvf : nvf * nvf * nvf;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= total) return;
+  int x[3];
+  vcoords<D>(v, nvf, x);
+  T s = 0;
+  for (int c = 0; c < (D == 3 ? 2 : 1); ++c) {
+    const int iz = (D == 3) ? pidx[2 * x[2] + c] : 0;
+    const T wz = (D == 3) ? pw[2 * x[2] + c] : T(1);
+    if (iz < 0) continue;
+    for (int b2 = 0; b2 < 2; ++b2) {
+      const int iy = pidx[2 * x[1] + b2];
+      if (iy < 0) continue;
+      const T wy = pw[2 * x[1] + b2];
+      for (int a2 = 0; a2 < 2; ++a2) {
+        const int ix = pidx[2 * x[0] + a2];
+        if (ix < 0) continue;
+        s += wz * wy * pw[2 * x[0] + a2] * ec[ix + nvc * (iy + nvc * iz)];
+      }
+    }
+  }
+  uf[v] += s;
+}
+
+// Q1 right-hand side from the per-cell corner contributions of the
+// restricted DG residual: b_V = sum over the 2^d cells around V.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_gather_corners(int n, const T* __restrict__ contrib, T* __restrict__ bcg) {
+  const int nv = n - 1;
+  const int total = (D == 2) ? nv * nv : nv * nv * nv;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= total) return;
+  int x[3];
+  vcoords<D>(v, nv, x);
+  constexpr int NCOR = 1 << D;
+  T s = 0;
+#pragma unroll
+  for (int c = 0; c < NCOR; ++c) {
+    const int ix = c & 1, iy = (c >> 1) & 1, iz = (c >> 2) & 1;
+    const int cx = x[0] + ix, cy = x[1] + iy, cz = (D == 3) ? x[2] + iz : 0;  // vertex v+1 -> cell v+ix
+    const int cell = cx + n * (cy + n * cz);
+    const int corner = (1 - ix) + 2 * (1 - iy) + ((D == 3) ? 4 * (1 - iz) : 0);
+    s += contrib[(size_t)cell * NCOR + corner];
+  }
+  bcg[v] = s;
+}
+
+// x = Ainv b on the coarsest level (dense FP64 inverse from a Cholesky
+// factorisation done at setup).
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_solve(int m, const double* __restrict__ Ainv, const T* __restrict__ b,
+                                                     T* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double s = 0.0;
+  for (int j = 0; j < m; ++j) s += Ainv[(size_t)i * m + j] * (double)b[j];
+  x[i] = (T)s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ x, size_t n, T v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] = v;
+}
+
+// ------------------------------------------------------------- FP64 Krylov
+constexpr int RED_BLOCKS = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  return s;
+}
+
+// partial[k*RED_BLOCKS + blk] for up to two dot products
+__global__ __launch_bounds__(256) void k_dot2(size_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                              const double* __restrict__ z, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double s0 = 0.0, s1 = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double xi = x[i];
+    s0 += xi * y[i];
+    if (z) s1 += xi * z[i];
+  }
+  double t0 = block_sum(s0, sh);
+  __syncthreads();
+  double t1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = t0;
+    partial[RED_BLOCKS + blockIdx.x] = t1;
+  }
+}
+
+// Sum the partials into slots and apply the scalar step of the flexible CG:
+//  op 0: s[a0] = sum0
+//  op 1: beta: s[3] = first ? 0 : (sum0 - sum1)/s[2]; s[2] = sum0 (rho)
+//  op 2: alpha: s[5] = s[2] / sum0
+//  op 3: s[6] = sum0 (r.r), s[7] = 1/sqrt(sum0), s[8] = sqrt(sum0)
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int nblk, double* __restrict__ s,
+                                                  int op, int a0, int first) {
+  __shared__ double sh[4];
+  double v0 = 0.0, v1 = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    v0 += partial[i];
+    v1 += partial[RED_BLOCKS + i];
+  }
+  const double t0 = block_sum(v0, sh);
+  __syncthreads();
+  const double t1 = block_sum(v1, sh);
+  if (threadIdx.x == 0) {
+    if (op == 0) {
+      s[a0] = t0;
+    } else if (op == 1) {
+      s[3] = first ? 0.0 : (t0 - t1) / s[2];
+      s[2] = t0;
+    } else if (op == 2) {
+      s[5] = s[2] / t0;
+    } else {
+      s[6] = t0;
+      s[7] = t0 > 0.0 ? 1.0 / sqrt(t0) : 1.0;
+      s[8] = sqrt(t0);
+    }
+  }
+}
+
+// p = z + beta p (p = z when beta == 0: the first iteration never reads
+// the previous search direction)
+__global__ __launch_bounds__(256) void k_update_p(size_t n, const double* __restrict__ z, double* __restrict__ p,
+                                                  const double* __restrict__ s) {
+  const double beta = s[3];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
+}
+
+// u += alpha p; r_old = r; r -= alpha q; partial r.r
+__global__ __launch_bounds__(256) void k_update_ur(size_t n, double* __restrict__ u, double* __restrict__ r,
+                                                   double* __restrict__ rold, const double* __restrict__ p,
+                                                   const double* __restrict__ q, const double* __restrict__ s,
+                                                   double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const double alpha = s[5];
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    u[i] += alpha * p[i];
+    const double ri = r[i];
+    rold[i] = ri;
+    const double rn = ri - alpha * q[i];
+    r[i] = rn;
+    acc += rn * rn;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = t;
+    partial[RED_BLOCKS + blockIdx.x] = 0.0;
+  }
+}
+
+// y = (float)(x * s[7])  (scaled cast for the FP32 cycle)
+__global__ __launch_bounds__(256) void k_cast_down(size_t n, const double* __restrict__ x, float* __restrict__ y,
+                                                   const double* __restrict__ s) {
+  const double sc = s[7];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (float)(x[i] * sc);
+}
+
+// y = (double)x * s[8]
+__global__ __launch_bounds__(256) void k_cast_up(size_t n, const float* __restrict__ x, double* __restrict__ y,
+                                                 const double* __restrict__ s) {
+  const double sc = s[8];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i] * sc;
+}
+
+inline unsigned nblocks(size_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+inline unsigned gs_blocks(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (unsigned)(b < RED_BLOCKS ? (b ? b : 1) : RED_BLOCKS);
+}
+
+}  // namespace
+
+template <typename T>
+void cg_stencil(int D, int nv, const T* st, const T* dinv, const T* u, const T* b, T* out, T omega, int mode,
+                int uzero, hipStream_t s) {
+  const size_t total = (D == 2) ? (size_t)nv * nv : (size_t)nv * nv * nv;
+  if (D == 2)
+    hipLaunchKernelGGL((k_cg_stencil<T, 2>), dim3(nblocks(total)), dim3(256), 0, s, nv, st, dinv, u, b, out, omega, mode,
+                       uzero);
+  else
+    hipLaunchKernelGGL((k_cg_stencil<T, 3>), dim3(nblocks(total)), dim3(256), 0, s, nv, st, dinv, u, b, out, omega, mode,
+                       uzero);
+}
+
+template <typename T>
+void cg_restrict(int D, int nvf, int nvc, const int* ridx, const T* rw, const T* rf, T* bc, hipStream_t s) {
+  const size_t total = (D == 2) ? (size_t)nvc * nvc : (size_t)nvc * nvc * nvc;
+  if (D == 2)
+    hipLaunchKernelGGL((k_cg_restrict<T, 2>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
+  else
+    hipLaunchKernelGGL((k_cg_restrict<T, 3>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
+}
+
+template <typename T>
+void cg_prolong(int D, int nvf, int nvc, const int* pidx, const T* pw, const T* ec, T* uf, hipStream_t s) {
+  const size_t total = (D == 2) ? (size_t)nvf * nvf : (size_t)nvf * nvf * nvf;
+  if (D == 2)
+    hipLaunchKernelGGL((k_cg_prolong<T, 2>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, pidx, pw, ec, uf);
+  else
+    hipLaunchKernelGGL((k_cg_prolong<T, 3>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, pidx, pw, ec, uf);
+}
+
+template <typename T>
+void gather_corners(int D, int n, const T* contrib, T* bcg, hipStream_t s) {
+  const size_t nv = n - 1;
+  const size_t total = (D == 2) ? nv * nv : nv * nv * nv;
+  if (D == 2)
+    hipLaunchKernelGGL((k_gather_corners<T, 2>), dim3(nblocks(total)), dim3(256), 0, s, n, contrib, bcg);
+  else
+    hipLaunchKernelGGL((k_gather_corners<T, 3>), dim3(nblocks(total)), dim3(256), 0, s, n, contrib, bcg);
+}
+
+template <typename T>
+void dense_solve(int m, const double* Ainv, const T* b, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_dense_solve<T>), dim3(nblocks(m)), dim3(256), 0, s, m, Ainv, b, x);
+}
+
+template <typename T>
+void fill(T* x, size_t n, T v, hipStream_t s) {
+  unsigned g = nblocks(n);
+  if (g > 8192) g = 8192;
+  if (g == 0) g = 1;
+  hipLaunchKernelGGL((k_fill<T>), dim3(g), dim3(256), 0, s, x, n, v);
+}
+
+void krylov_dot(size_t n, const double* x, const double* y, const double* z, double* partial, double* scal, int op,
+                int a0, int first, hipStream_t s) {
+  const unsigned g = gs_blocks(n);
+  hipLaunchKernelGGL(k_dot2, dim3(g), dim3(256), 0, s, n, x, y, z, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, (int)g, scal, op, a0, first);
+}
+
+void krylov_update_p(size_t n, const double* z, double* p, const double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(gs_blocks(n)), dim3(256), 0, s, n, z, p, scal);
+}
+
+void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double* p, const double* q, double* partial,
+                      double* scal, hipStream_t s) {
+  const unsigned g = gs_blocks(n);
+  hipLaunchKernelGGL(k_update_ur, dim3(g), dim3(256), 0, s, n, u, r, rold, p, q, scal, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, (int)g, scal, 3, 0, 0);
+}
+
+void cast_down(size_t n, const double* x, float* y, const double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_down, dim3(gs_blocks(n)), dim3(256), 0, s, n, x, y, scal);
+}
+
+void cast_up(size_t n, const float* x, double* y, const double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_up, dim3(gs_blocks(n)), dim3(256), 0, s, n, x, y, scal);
+}
+
+#define HPMG_INST(T)                                                                                           \
+  template void cg_stencil<T>(int, int, const T*, const T*, const T*, const T*, T*, T, int, int, hipStream_t); \
+  template void cg_restrict<T>(int, int, int, const int*, const T*, const T*, T*, hipStream_t);                \
+  template void cg_prolong<T>(int, int, int, const int*, const T*, const T*, T*, hipStream_t);                 \
+  template void gather_corners<T>(int, int, const T*, T*, hipStream_t);                                        \
+  template void dense_solve<T>(int, const double*, const T*, T*, hipStream_t);                                 \
+  template void fill<T>(T*, size_t, T, hipStream_t);
+HPMG_INST(float)
+HPMG_INST(double)
+#undef HPMG_INST
+
+}  // namespace hpmg

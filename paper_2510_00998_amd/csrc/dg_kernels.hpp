@@ -1,0 +1,84 @@
+// Matrix-free SIPG kernels on DG levels (gfx950).
+//
+// One thread per 1D line of a cell ("pencil"): a cell of N^d nodes owns
+// N^(d-1) threads; a block holds CPB whole cells (about 256 threads).  The
+// block stages the cell data of its cells, which are consecutive in memory,
+// through LDS with coalesced loads, applies sum-factorised 1D contractions
+// along x, y, z with the line in registers, and writes back coalesced.
+//
+// Operator (paper Section 2.3.1 eq. weak_form_IP with theta = -1 and the
+// facet form eq. weak_form_IP_facet_spaces): in reference units the cell
+// block is the Kronecker sum A_{K<-K} = h^(d-2) sum_k M x .. x L_k x .. x M,
+// L_k = kappa_K Khat + facet terms of the two facets normal to axis k.  The
+// neighbour coupling enters only through the traces (value g and outward
+// normal derivative q = h du/dn) that each neighbour projected onto the
+// shared facet (technique projection-variables); the flux variables
+// w = kappa_F (q'/2 - sigma_hat g') and w' = kappa_F g'/2 (technique
+// numerical-flux-outcome) are formed in registers and lifted back with the
+// facet mass.  The block inverse uses the fast diagonalisation
+// A_{K<-K}^{-1} = h^(2-d) (S x S x S) diag(1/(lx+ly+lz)) (S x S x S)^T with
+// L_k S = M S diag(l), S^T M S = I.
+//
+// Sweep (technique shift-and-fuse, Algorithm BlockJacobi with loop fusion):
+// each cell reads its own u, b and the neighbours' old traces, computes
+//   u_new = (1-omega) u + omega A_{K<-K}^{-1} (b - A_{c<-f} w),
+// which equals u + omega A_{K<-K}^{-1}(b - A u) (block-Jacobi, eq.
+// block-Jacobi-IP) because A_{K<-K}^{-1} A_{K<-K} u = u, and writes u_new
+// and its traces into the other trace buffer (ping-pong, so every cell of a
+// sweep sees old traces: Jacobi semantics without a copy of u).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hpmg {
+
+template <int D, int N>
+struct DGShape {
+  static constexpr int L = (D == 2) ? N : N * N;  // lines per cell = nodes per facet
+  static constexpr int NV = L * N;                // nodes per cell
+  static constexpr int NF = 2 * D;                // facets per cell
+  static constexpr int CPB = (256 / L) > 0 ? (256 / L) : 1;
+  static constexpr int NT = CPB * L;
+  static constexpr int EGS = 2 * N * N + N;       // S, Si, lambda of one direction
+};
+
+// Per-level reference data (type T), in global memory:
+//   [0, N^2)            Mhat (1D mass on [0,1], symmetric)
+//   [N^2, N^2+N)        ep0: outward normal derivative functional at x=0
+//   [N^2+N, N^2+2N)     ep1: same at x=1
+//   [N^2+2N, ...)       E: interpolation to the fine nodes from the next
+//                       coarser nodes, E[a*NC + j] (only when NC > 0)
+template <int N>
+struct RefOff {
+  static constexpr int M = 0, EP0 = N * N, EP1 = N * N + N, E = N * N + 2 * N;
+};
+
+template <typename T>
+struct DGArgs {
+  int n, ncell;
+  int vark;            // 0: class tables (constant kappa), 1: per-cell eigendata + kappa
+  T kappa_const;
+  const T* ref;        // RefOff layout
+  const T* eig;        // vark=0: [4 classes][S N^2 | Si N^2 | lam N]; vark=1: [cell][D][S N^2 | lam N]
+  const T* kappa;      // vark=1: per cell
+  T h_fwd;             // h^(2-d): scales b in the sweep
+  T h_apply;           // h^(d-2): scales A u
+  T sigma_hat;         // sigma * h = sigma0 (p_penalty+1)^2
+  T omega;
+  const T* u_in;       // cell vector
+  T* u_out;            // cell vector (may alias u_in)
+  const T* b;          // cell vector
+  const T* tr_in;      // traces [2D][ncell][2][L]
+  T* tr_out;
+  T* out;              // apply: y; resid: r (NC=0) or coarse right-hand side
+  const T* coarse;     // prolong: coarse cell vector (DG) or Q1 interior vertex vector (CG)
+  int coarse_cg;       // prolong/restrict partner is Q1 (vertex gather) rather than DG
+  long long vstride;   // per right-hand side stride of cell vectors
+  long long tstride;   // per right-hand side stride of trace buffers
+  long long cstride;   // per right-hand side stride of coarse vectors
+};
+
+template <typename T, int D, int N> void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s);
+template <typename T, int D, int N, int NC> void launch_apply(const DGArgs<T>& a, int nrhs, bool resid, hipStream_t s);
+template <typename T, int D, int N, int NC> void launch_prolong(const DGArgs<T>& a, int nrhs, hipStream_t s);
+
+}  // namespace hpmg

@@ -1,0 +1,742 @@
+// Kernel bodies for dg_kernels.hpp (included by the per-instantiation .hip
+// files).  See dg_kernels.hpp for the mathematics.
+#pragma once
+#include "dg_kernels.hpp"
+
+namespace hpmg {
+namespace dgk {
+
+// Offset of the first node of the line of thread `ln` along axis k, and the
+// node stride along that axis (x fastest).  The facet node index of the line
+// on the facets normal to k is `ln` itself for every axis.
+template <int D, int N>
+__device__ __forceinline__ int line_base(int k, int ln) {
+  if constexpr (D == 2) {
+    return k == 0 ? N * ln : ln;
+  } else {
+    const int i0 = ln % N, i1 = ln / N;
+    if (k == 0) return N * i0 + N * N * i1;
+    if (k == 1) return i0 + N * N * i1;
+    return i0 + N * i1;
+  }
+}
+template <int N>
+__device__ __forceinline__ constexpr int line_stride(int k) {
+  return k == 0 ? 1 : (k == 1 ? N : N * N);
+}
+
+// out = G in, G row-major N x N (TR: G^T)
+template <int N, bool TR, typename T>
+__device__ __forceinline__ void mv(const T* __restrict__ G, const T (&in)[N], T (&out)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += (TR ? G[j * N + i] : G[i * N + j]) * in[j];
+    out[i] = s;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ int ipow(int n, int k) {
+  return k == 0 ? 1 : (k == 1 ? n : n * n);
+}
+
+// Stage the per-cell eigendata (S, Si = S^T M, lambda per axis) and facet
+// coefficients kappa_F (0 on boundary facets) of the block's cells.
+template <typename T, int D, int N>
+__device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int nc, T* sE, T* sKF) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  const int tid = threadIdx.x;
+  if (!a.vark) {
+    for (int i = tid; i < nc * D * Sh::EGS; i += Sh::NT) {
+      const int e = i % Sh::EGS;
+      const int ck = i / Sh::EGS;
+      const int k = ck % D, cl = ck / D;
+      const int c = c0 + cl;
+      const int x = (c / ipow<D>(a.n, k)) % a.n;
+      const int cls = (x == 0 ? 1 : 0) | (x == a.n - 1 ? 2 : 0);
+      sE[i] = a.eig[cls * Sh::EGS + e];
+    }
+  } else {
+    for (int i = tid; i < nc * D * (NN + N); i += Sh::NT) {
+      const int e = i % (NN + N);
+      const int ck = i / (NN + N);
+      const T v = a.eig[(size_t)(c0 + ck / D) * D * (NN + N) + (size_t)(ck % D) * (NN + N) + e];
+      sE[ck * Sh::EGS + (e < NN ? e : NN + e)] = v;  // lambda goes after the Si slot
+    }
+  }
+  for (int i = tid; i < nc * Sh::NF; i += Sh::NT) {
+    const int cl = i / Sh::NF, f = i % Sh::NF;
+    const int k = f >> 1, s = f & 1;
+    const int c = c0 + cl;
+    const int st = ipow<D>(a.n, k);
+    const int x = (c / st) % a.n;
+    const bool bdy = s ? (x == a.n - 1) : (x == 0);
+    T kf = 0;
+    if (!bdy) {
+      if (a.vark) {
+        const T k0 = a.kappa[c], k1 = a.kappa[s ? c + st : c - st];
+        kf = T(2) * k0 * k1 / (k0 + k1);
+      } else {
+        kf = a.kappa_const;
+      }
+    }
+    sKF[i] = kf;
+  }
+}
+
+// Si = S^T M for every staged (cell, axis) when the data came per cell.
+template <typename T, int D, int N>
+__device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  const T* Mh = a.ref + RefOff<N>::M;
+  for (int i = threadIdx.x; i < nc * D * NN; i += Sh::NT) {
+    const int e = i % NN, ck = i / NN;
+    const int r = e / N, col = e % N;
+    const T* S = sE + ck * Sh::EGS;
+    T s = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) s += S[m * N + r] * Mh[m * N + col];
+    sE[ck * Sh::EGS + NN + e] = s;
+  }
+}
+
+// Neighbour traces of the block's cells: sNB[cl][f][field][L] = traces the
+// neighbour across facet f wrote on its facet f^1 (zeros on the boundary).
+template <typename T, int D, int N>
+__device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc, T* sNB) {
+  using Sh = DGShape<D, N>;
+  constexpr int TL = 2 * Sh::L;
+  const int tid = threadIdx.x;
+  for (int f = 0; f < Sh::NF; ++f) {
+    const int k = f >> 1, s = f & 1;
+    const int st = ipow<D>(a.n, k);
+    const int off = s ? st : -st;
+    const T* src = tr + (size_t)(f ^ 1) * a.ncell * TL;
+    for (int i = tid; i < nc * TL; i += Sh::NT) {
+      const int cl = i / TL, e = i % TL;
+      const int c = c0 + cl;
+      const int x = (c / st) % a.n;
+      const bool bdy = s ? (x == a.n - 1) : (x == 0);
+      sNB[(cl * Sh::NF + f) * TL + e] = bdy ? T(0) : src[(size_t)(c + off) * TL + e];
+    }
+  }
+}
+
+// Facet pre-pass: turn (g', q') into the lifted flux fields
+//   F1 = T_f (kappa_F (q'/2 - sigma_hat g')),  F2 = T_f (kappa_F g'/2),
+// T_f = G_t1 x G_t2 over the tangential axes with G_t = Si_t for t < k
+// (axes already transformed when facet k is processed) and Mhat otherwise.
+template <typename T, int D, int N>
+__device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int nc, T* sNB, const T* sE, const T* sKF) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  constexpr int L = Sh::L;
+  const T* Mh = a.ref + RefOff<N>::M;
+  const int tid = threadIdx.x;
+  if constexpr (D == 2) {
+    for (int i = tid; i < nc * Sh::NF; i += Sh::NT) {
+      const int cl = i / Sh::NF, f = i % Sh::NF;
+      const int k = f >> 1;
+      const int t1 = 1 - k;
+      const T* G = (t1 < k) ? (sE + (cl * D + t1) * Sh::EGS + NN) : Mh;
+      T* g = sNB + (cl * Sh::NF + f) * 2 * L;
+      const T kf = sKF[i];
+      T al[N], be[N], o1[N], o2[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        al[j] = kf * (T(0.5) * g[L + j] - a.sigma_hat * g[j]);
+        be[j] = T(0.5) * kf * g[j];
+      }
+      mv<N, false>(G, al, o1);
+      mv<N, false>(G, be, o2);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        g[j] = o1[j];
+        g[L + j] = o2[j];
+      }
+    }
+    __syncthreads();
+  } else {
+    // pass A: along the first tangential axis (stride 1 in the facet index)
+    for (int i = tid; i < nc * Sh::NF * N; i += Sh::NT) {
+      const int i2 = i % N, cf = i / N;
+      const int cl = cf / Sh::NF, f = cf % Sh::NF;
+      const int k = f >> 1;
+      const int t1 = (k == 0) ? 1 : 0;
+      const T* G = (t1 < k) ? (sE + (cl * D + t1) * Sh::EGS + NN) : Mh;
+      T* g = sNB + cf * 2 * L + N * i2;
+      const T kf = sKF[cf];
+      T al[N], be[N], o1[N], o2[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        al[j] = kf * (T(0.5) * g[L + j] - a.sigma_hat * g[j]);
+        be[j] = T(0.5) * kf * g[j];
+      }
+      mv<N, false>(G, al, o1);
+      mv<N, false>(G, be, o2);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        g[j] = o1[j];
+        g[L + j] = o2[j];
+      }
+    }
+    __syncthreads();
+    // pass B: along the second tangential axis (stride N)
+    for (int i = tid; i < nc * Sh::NF * N; i += Sh::NT) {
+      const int i1 = i % N, cf = i / N;
+      const int cl = cf / Sh::NF, f = cf % Sh::NF;
+      const int k = f >> 1;
+      const int t2 = (k == 2) ? 1 : 2;
+      const T* G = (t2 < k) ? (sE + (cl * D + t2) * Sh::EGS + NN) : Mh;
+      T* g = sNB + cf * 2 * L + i1;
+      T x1[N], x2[N], o1[N], o2[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        x1[j] = g[N * j];
+        x2[j] = g[L + N * j];
+      }
+      mv<N, false>(G, x1, o1);
+      mv<N, false>(G, x2, o2);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        g[N * j] = o1[j];
+        g[L + N * j] = o2[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// r -= lift of facets (k,0) and (k,1): value part at the facet node, normal
+// derivative part along the line (sweep, SIGN = -1) or r += (apply, +1).
+template <typename T, int D, int N, int SIGN>
+__device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int ln, const T* sNB, T (&r)[N]) {
+  using Sh = DGShape<D, N>;
+  constexpr int L = Sh::L;
+  const T* ep0 = a.ref + RefOff<N>::EP0;
+  const T* ep1 = a.ref + RefOff<N>::EP1;
+  const T* f0 = sNB + (cl * Sh::NF + 2 * k) * 2 * L;
+  const T* f1 = f0 + 2 * L;
+  const T v0 = f0[ln], d0 = f0[L + ln], v1 = f1[ln], d1 = f1[L + ln];
+  if constexpr (SIGN < 0) {
+    r[0] -= v0;
+    r[N - 1] -= v1;
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] -= ep0[j] * d0 + ep1[j] * d1;
+  } else {
+    r[0] += v0;
+    r[N - 1] += v1;
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] += ep0[j] * d0 + ep1[j] * d1;
+  }
+}
+
+// Traces of a line along axis k into the staging array sTR[cl][f][field][L].
+template <typename T, int D, int N>
+__device__ __forceinline__ void line_traces(const DGArgs<T>& a, int cl, int k, int ln, const T (&u)[N], T* sTR) {
+  using Sh = DGShape<D, N>;
+  constexpr int L = Sh::L;
+  const T* ep0 = a.ref + RefOff<N>::EP0;
+  const T* ep1 = a.ref + RefOff<N>::EP1;
+  T d0 = 0, d1 = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    d0 += ep0[j] * u[j];
+    d1 += ep1[j] * u[j];
+  }
+  T* t0 = sTR + (cl * Sh::NF + 2 * k) * 2 * L;
+  T* t1 = t0 + 2 * L;
+  t0[ln] = u[0];
+  t0[L + ln] = d0;
+  t1[ln] = u[N - 1];
+  t1[L + ln] = d1;
+}
+
+// Traces of all axes but x from the staged cell vector, then coalesced
+// stores of the cell vector and of the traces of interior facets.
+template <typename T, int D, int N>
+__device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int c0, int nc, const T* sU, T* sTR,
+                                                        T* uout, T* trout) {
+  using Sh = DGShape<D, N>;
+  constexpr int L = Sh::L;
+  constexpr int TL = 2 * L;
+  const int tid = threadIdx.x;
+  const int cl = tid / L, ln = tid % L;
+  if (tid < Sh::NT && cl < nc) {
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      const int base = cl * Sh::NV + line_base<D, N>(k, ln);
+      T u[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) u[j] = sU[base + j * line_stride<N>(k)];
+      line_traces<T, D, N>(a, cl, k, ln, u, sTR);
+    }
+  }
+  __syncthreads();
+  if (uout) {
+    T* dst = uout + (size_t)c0 * Sh::NV;
+    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) dst[i] = sU[i];
+  }
+  for (int f = 0; f < Sh::NF; ++f) {
+    const int k = f >> 1, s = f & 1;
+    const int st = ipow<D>(a.n, k);
+    T* dst = trout + ((size_t)f * a.ncell + c0) * TL;
+    for (int i = tid; i < nc * TL; i += Sh::NT) {
+      const int cl2 = i / TL, e = i % TL;
+      const int x = ((c0 + cl2) / st) % a.n;
+      const bool bdy = s ? (x == a.n - 1) : (x == 0);
+      if (!bdy) dst[i] = sTR[(cl2 * Sh::NF + f) * TL + e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused block-Jacobi sweep.  UZERO: u is identically zero on entry (first
+// sweep of a coarse-level smoothing with zero initial guess): u and the
+// neighbour traces are not read.
+template <typename T, int D, int N, bool UZERO>
+__global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  constexpr int L = Sh::L;
+  __shared__ T sU[Sh::CPB * Sh::NV];
+  __shared__ T sW[Sh::CPB * Sh::NV];
+  __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
+  __shared__ T sE[Sh::CPB * D * Sh::EGS];
+  __shared__ T sKF[Sh::CPB * Sh::NF];
+
+  const int c0 = blockIdx.x * Sh::CPB;
+  const int nc = min(Sh::CPB, a.ncell - c0);
+  const size_t rv = (size_t)blockIdx.y * a.vstride, rt = (size_t)blockIdx.y * a.tstride;
+  const int tid = threadIdx.x;
+  const int cl = tid / L, ln = tid % L;
+  const bool act = tid < Sh::NT && cl < nc;
+
+  {
+    const T* bs = a.b + rv + (size_t)c0 * Sh::NV;
+    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sW[i] = bs[i];
+    if (!UZERO) {
+      const T* us = a.u_in + rv + (size_t)c0 * Sh::NV;
+      for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = us[i];
+      load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
+    }
+    load_cell_data<T, D, N>(a, c0, nc, sE, sKF);
+  }
+  __syncthreads();
+  if (a.vark) {
+    make_si<T, D, N>(a, nc, sE);
+    __syncthreads();
+  }
+  if (!UZERO) facet_prepass<T, D, N>(a, nc, sNB, sE, sKF);
+
+  // forward transforms S^T along x, y(, z) with the facet lifts subtracted
+  // just before each axis is transformed
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (act) {
+      const int base = cl * Sh::NV + line_base<D, N>(k, ln);
+      constexpr int dummy = 0;
+      (void)dummy;
+      T r[N], t[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
+      if (k == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[j] *= a.h_fwd;
+      }
+      if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
+      const T* Ek = sE + (cl * D + k) * Sh::EGS;
+      mv<N, true>(Ek, r, t);  // S^T
+      if (k == D - 1) {
+        // diagonal scaling and the first inverse transform along the last axis
+        const T* l0 = sE + (cl * D + 0) * Sh::EGS + 2 * NN;
+        const T* l1 = sE + (cl * D + 1) * Sh::EGS + 2 * NN;
+        T lsum;
+        if constexpr (D == 2) {
+          lsum = l0[ln];
+#pragma unroll
+          for (int j = 0; j < N; ++j) t[j] /= (lsum + l1[j]);
+        } else {
+          const T* l2 = sE + (cl * D + 2) * Sh::EGS + 2 * NN;
+          lsum = l0[ln % N] + l1[ln / N];
+#pragma unroll
+          for (int j = 0; j < N; ++j) t[j] /= (lsum + l2[j]);
+        }
+        mv<N, false>(Ek, t, r);  // S
+#pragma unroll
+        for (int j = 0; j < N; ++j) t[j] = r[j];
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
+    }
+    __syncthreads();
+  }
+  // inverse transforms S along the remaining axes, last one fused with the
+  // update and the x-facet traces
+  T* sTR = sNB;  // the flux fields are consumed; reuse as trace staging
+#pragma unroll
+  for (int k = D - 2; k >= 0; --k) {
+    if (act) {
+      const int base = cl * Sh::NV + line_base<D, N>(k, ln);
+      T r[N], t[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
+      mv<N, false>(sE + (cl * D + k) * Sh::EGS, r, t);
+      if (k == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const T uo = UZERO ? T(0) : sU[base + j];
+          t[j] = (T(1) - a.omega) * uo + a.omega * t[j];
+          sU[base + j] = t[j];
+        }
+        line_traces<T, D, N>(a, cl, 0, ln, t, sTR);
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
+      }
+    }
+    __syncthreads();
+  }
+  finish_traces_and_store<T, D, N>(a, c0, nc, sU, sTR, a.u_out + rv, a.tr_out + rt);
+}
+
+// ---------------------------------------------------------------------------
+// y = A u (RESID: r = b - A u), optionally restricted to the next coarser
+// level: NC > 0 gives per cell (E^T x E^T x E^T) r with E the interpolation
+// from the coarse nodes (DG_q: a coarse cell vector; Q1: the 2^d corner
+// contributions of each cell, summed over cells by the gather kernel).
+// Needs the traces of u in tr_in.
+template <typename T, int D, int N, int NC, bool RESID>
+__global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  constexpr int L = Sh::L;
+  __shared__ T sU[Sh::CPB * Sh::NV];
+  __shared__ T sW[Sh::CPB * Sh::NV];
+  __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
+  __shared__ T sE[Sh::CPB * D * Sh::EGS];
+  __shared__ T sKF[Sh::CPB * Sh::NF];
+
+  const int c0 = blockIdx.x * Sh::CPB;
+  const int nc = min(Sh::CPB, a.ncell - c0);
+  const size_t rv = (size_t)blockIdx.y * a.vstride, rt = (size_t)blockIdx.y * a.tstride;
+  const int tid = threadIdx.x;
+  const int cl = tid / L, ln = tid % L;
+  const bool act = tid < Sh::NT && cl < nc;
+
+  {
+    const T* us = a.u_in + rv + (size_t)c0 * Sh::NV;
+    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = us[i];
+    load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
+    load_cell_data<T, D, N>(a, c0, nc, sE, sKF);
+  }
+  __syncthreads();
+  if (a.vark) {
+    make_si<T, D, N>(a, nc, sE);
+    __syncthreads();
+  }
+  facet_prepass<T, D, N>(a, nc, sNB, sE, sKF);
+
+  // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
+  // lifts added right after each axis is transformed back.
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (act) {
+      const int base = cl * Sh::NV + line_base<D, N>(k, ln);
+      T r[N], t[N];
+      const T* src = (k == 0) ? sU : sW;
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] = src[base + j * line_stride<N>(k)];
+      const T* Ek = sE + (cl * D + k) * Sh::EGS;
+      mv<N, false>(Ek + NN, r, t);  // Si
+      if (k == D - 1) {
+        const T* l0 = sE + (cl * D + 0) * Sh::EGS + 2 * NN;
+        const T* l1 = sE + (cl * D + 1) * Sh::EGS + 2 * NN;
+        if constexpr (D == 2) {
+          const T ls = l0[ln];
+#pragma unroll
+          for (int j = 0; j < N; ++j) t[j] *= (ls + l1[j]);
+        } else {
+          const T* l2 = sE + (cl * D + 2) * Sh::EGS + 2 * NN;
+          const T ls = l0[ln % N] + l1[ln / N];
+#pragma unroll
+          for (int j = 0; j < N; ++j) t[j] *= (ls + l2[j]);
+        }
+        mv<N, true>(Ek + NN, t, r);  // Si^T
+        add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, r);
+#pragma unroll
+        for (int j = 0; j < N; ++j) t[j] = r[j];
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
+    }
+    __syncthreads();
+  }
+  if (RESID) {  // sU is free now: stage b for the final axis
+    const T* bs = a.b + rv + (size_t)c0 * Sh::NV;
+    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = bs[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = D - 2; k >= 0; --k) {
+    if (act) {
+      const int base = cl * Sh::NV + line_base<D, N>(k, ln);
+      T r[N], t[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
+      mv<N, true>(sE + (cl * D + k) * Sh::EGS + NN, r, t);
+      add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, t);
+      if (k == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          t[j] *= a.h_apply;
+          if (RESID) t[j] = sU[base + j] - t[j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
+    }
+    __syncthreads();
+  }
+  if constexpr (NC == 0) {
+    T* dst = a.out + rv + (size_t)c0 * Sh::NV;
+    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) dst[i] = sW[i];
+  } else {
+    // restriction (E^T)^(x d) of the cell residual, one axis per pass
+    const T* E = a.ref + RefOff<N>::E;
+    constexpr int NCD = (D == 2) ? NC * NC : NC * NC * NC;
+    T* dst = a.out + (size_t)blockIdx.y * a.cstride + (size_t)c0 * NCD;
+    // x: sW[cl][..][a] -> sU[cl][..][a'] (a' + NC*ln)
+    for (int i = tid; i < nc * L; i += Sh::NT) {
+      const int c2 = i / L, l2 = i % L;
+      T x[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + j + N * l2];
+#pragma unroll
+      for (int jc = 0; jc < NC; ++jc) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += E[j * NC + jc] * x[j];
+        sU[c2 * Sh::NV + jc + NC * l2] = s;
+      }
+    }
+    __syncthreads();
+    if constexpr (D == 2) {
+      // y: sU[cl][b][a'] -> dst[a' + NC b']
+      for (int i = tid; i < nc * NC; i += Sh::NT) {
+        const int c2 = i / NC, ac = i % NC;
+        T x[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) x[j] = sU[c2 * Sh::NV + ac + NC * j];
+#pragma unroll
+        for (int bc = 0; bc < NC; ++bc) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) s += E[j * NC + bc] * x[j];
+          dst[(size_t)c2 * NCD + ac + NC * bc] = s;
+        }
+      }
+    } else {
+      // y: sU[cl][c][b][a'] (a' + NC(b + N c)) -> sW[cl][c][b'][a'] (a' + NC(b' + NC c))
+      for (int i = tid; i < nc * NC * N; i += Sh::NT) {
+        const int c2 = i / (NC * N), rem = i % (NC * N);
+        const int ac = rem % NC, cz = rem / NC;
+        T x[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) x[j] = sU[c2 * Sh::NV + ac + NC * (j + N * cz)];
+#pragma unroll
+        for (int bc = 0; bc < NC; ++bc) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) s += E[j * NC + bc] * x[j];
+          sW[c2 * Sh::NV + ac + NC * (bc + NC * cz)] = s;
+        }
+      }
+      __syncthreads();
+      // z: sW[cl][c][b'][a'] -> dst[a' + NC b' + NC^2 c']
+      for (int i = tid; i < nc * NC * NC; i += Sh::NT) {
+        const int c2 = i / (NC * NC), rem = i % (NC * NC);
+        T x[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + rem + NC * NC * j];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) s += E[j * NC + cc] * x[j];
+          dst[(size_t)c2 * NCD + rem + NC * NC * cc] = s;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// u += P e (NC > 0; DG_q cell vector or Q1 vertex vector) and projection of
+// u onto the facet traces (NC = 0: projection only, Algorithm BlockJacobi
+// warm-up; NC > 0: fused prolongation + projection, Section 5.1.1).
+template <typename T, int D, int N, int NC>
+__global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
+  using Sh = DGShape<D, N>;
+  constexpr int L = Sh::L;
+  __shared__ T sU[Sh::CPB * Sh::NV];
+  __shared__ T sW[Sh::CPB * Sh::NV];
+  __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
+
+  const int c0 = blockIdx.x * Sh::CPB;
+  const int nc = min(Sh::CPB, a.ncell - c0);
+  const size_t rv = (size_t)blockIdx.y * a.vstride, rt = (size_t)blockIdx.y * a.tstride;
+  const int tid = threadIdx.x;
+  const int cl = tid / L, ln = tid % L;
+  const bool act = tid < Sh::NT && cl < nc;
+  constexpr int NCD = (NC == 0) ? 0 : ((D == 2) ? NC * NC : NC * NC * NC);
+
+  {
+    const T* us = a.u_in + rv + (size_t)c0 * Sh::NV;
+    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = us[i];
+    if constexpr (NC > 0) {
+      const T* cs = a.coarse + (size_t)blockIdx.y * a.cstride;
+      if (!a.coarse_cg) {
+        for (int i = tid; i < nc * NCD; i += Sh::NT) sW[(i / NCD) * Sh::NV + i % NCD] = cs[(size_t)c0 * NCD + i];
+      } else {
+        // Q1 corner values of each cell from the interior-vertex vector
+        const int nv = a.n - 1;
+        for (int i = tid; i < nc * NCD; i += Sh::NT) {
+          const int c2 = i / NCD, corner = i % NCD;
+          const int c = c0 + c2;
+          int vid = 0, mul = 1;
+          bool inside = true;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const int v = (c / ipow<D>(a.n, k)) % a.n + ((corner >> k) & 1);
+            inside = inside && v > 0 && v < a.n;
+            vid += (v - 1) * mul;
+            mul *= nv;
+          }
+          sW[c2 * Sh::NV + corner] = inside ? cs[vid] : T(0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (NC > 0) {
+    const T* E = a.ref + RefOff<N>::E;
+    if constexpr (D == 3) {
+      // z: [c'][b'][a'] -> sNB[cl][c][b'][a'] (a' + NC b' + NC^2 c)
+      for (int i = tid; i < nc * NC * NC; i += Sh::NT) {
+        const int c2 = i / (NC * NC), rem = i % (NC * NC);
+        T x[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) x[j] = sW[c2 * Sh::NV + rem + NC * NC * j];
+#pragma unroll
+        for (int cz = 0; cz < N; ++cz) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) s += E[cz * NC + j] * x[j];
+          sNB[c2 * Sh::NF * 2 * L + rem + NC * NC * cz] = s;
+        }
+      }
+      __syncthreads();
+      // y: sNB[c][b'][a'] -> sW[cl][c][b][a'] (a' + NC b + NC N c)
+      for (int i = tid; i < nc * NC * N; i += Sh::NT) {
+        const int c2 = i / (NC * N), rem = i % (NC * N);
+        const int ac = rem % NC, cz = rem / NC;
+        T x[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) x[j] = sNB[c2 * Sh::NF * 2 * L + ac + NC * j + NC * NC * cz];
+#pragma unroll
+        for (int by = 0; by < N; ++by) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) s += E[by * NC + j] * x[j];
+          sW[c2 * Sh::NV + ac + NC * (by + N * cz)] = s;
+        }
+      }
+      __syncthreads();
+    } else {
+      // y: [b'][a'] -> sNB[cl][b][a'] -> copy back into sW layout (a' + NC b)
+      for (int i = tid; i < nc * NC; i += Sh::NT) {
+        const int c2 = i / NC, ac = i % NC;
+        T x[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) x[j] = sW[c2 * Sh::NV + ac + NC * j];
+#pragma unroll
+        for (int by = 0; by < N; ++by) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) s += E[by * NC + j] * x[j];
+          sNB[c2 * Sh::NF * 2 * L + ac + NC * by] = s;
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < nc * NC * N; i += Sh::NT) {
+        const int c2 = i / (NC * N), rem = i % (NC * N);
+        sW[c2 * Sh::NV + rem] = sNB[c2 * Sh::NF * 2 * L + rem];
+      }
+      __syncthreads();
+    }
+  }
+  // x: line of thread ln (facet index = (b[,c])), add the prolongated
+  // correction, then the x-facet traces.  sTR aliases sNB, whose last
+  // readers finished before the preceding barrier.
+  T* sTR = sNB;
+  if (act) {
+    const int base = cl * Sh::NV + line_base<D, N>(0, ln);
+    T u[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) u[j] = sU[base + j];
+    if constexpr (NC > 0) {
+      const T* E = a.ref + RefOff<N>::E;
+      T x[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) x[j] = sW[cl * Sh::NV + j + NC * ln];
+#pragma unroll
+      for (int ax = 0; ax < N; ++ax) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) s += E[ax * NC + j] * x[j];
+        u[ax] += s;
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) sU[base + j] = u[j];
+    }
+    line_traces<T, D, N>(a, cl, 0, ln, u, sTR);
+  }
+  __syncthreads();
+  finish_traces_and_store<T, D, N>(a, c0, nc, sU, sTR, NC > 0 ? a.u_out + rv : nullptr, a.tr_out + rt);
+}
+
+}  // namespace dgk
+
+template <typename T, int D, int N>
+void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s) {
+  using Sh = DGShape<D, N>;
+  dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
+  if (uzero)
+    hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true>), grid, dim3(Sh::NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false>), grid, dim3(Sh::NT), 0, s, a);
+}
+
+template <typename T, int D, int N, int NC>
+void launch_apply(const DGArgs<T>& a, int nrhs, bool resid, hipStream_t s) {
+  using Sh = DGShape<D, N>;
+  dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
+  if (resid)
+    hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true>), grid, dim3(Sh::NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false>), grid, dim3(Sh::NT), 0, s, a);
+}
+
+template <typename T, int D, int N, int NC>
+void launch_prolong(const DGArgs<T>& a, int nrhs, hipStream_t s) {
+  using Sh = DGShape<D, N>;
+  dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
+  hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC>), grid, dim3(Sh::NT), 0, s, a);
+}
+
+}  // namespace hpmg

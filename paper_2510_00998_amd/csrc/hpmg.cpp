@@ -1,0 +1,1001 @@
+// libhpmg: level hierarchy, multigrid cycle, outer solver and the C ABI
+// declared in include/hpmg.h.
+#include "hpmg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "basis.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct HpmgError : std::runtime_error {
+  hpmg_status st;
+  HpmgError(hpmg_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHK(expr)                                                                                       \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess)                                                                                  \
+      throw HpmgError(e_ == hipErrorOutOfMemory ? HPMG_E_NOMEM : HPMG_E_DEVICE,                           \
+                      std::string(#expr) + ": " + hipGetErrorString(e_));                                  \
+  } while (0)
+
+void require(bool c, const std::string& msg) {
+  if (!c) throw HpmgError(HPMG_E_INVALID, msg);
+}
+
+// Device allocation owned by the handle.
+struct DevMem {
+  std::vector<void*> ptrs;
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    HIPCHK(hipMalloc(&p, bytes));
+    ptrs.push_back(p);
+    return p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = (T*)alloc(v.size() * sizeof(T));
+    HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  ~DevMem() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// Per-precision device data of one DG level.
+template <typename T>
+struct DGData {
+  T* ref = nullptr;
+  T* eig = nullptr;
+  T* kappa = nullptr;
+  T* u = nullptr;        // coarse levels only
+  T* b = nullptr;        // coarse levels only
+  T* tr[2] = {nullptr, nullptr};
+  T* contrib = nullptr;  // corner contributions (last DG level, restriction to Q1)
+};
+
+struct DGLevel {
+  int p = 0, N = 0, NC = 0;  // NC: nodes per direction of the next coarser level (2: Q1)
+  bool next_cg = false;
+  double sigma_hat = 0.0;
+  size_t ndof = 0, trsize = 0;  // per right-hand side
+  DGData<double> d;
+  DGData<float> f;
+};
+
+template <typename T>
+struct CGData {
+  T* st = nullptr;
+  T* dinv = nullptr;
+  T* u[2] = {nullptr, nullptr};
+  T* b = nullptr;
+  T* r = nullptr;
+  T* rw = nullptr;  // restriction weights to the next coarser level
+  T* pw = nullptr;  // prolongation weights from it
+};
+
+struct CGLevel {
+  int n = 0, nv = 0;
+  size_t size = 0;
+  int cur = 0;                // which of u[0], u[1] holds the iterate
+  int* ridx = nullptr;        // [nvc][3]
+  int* pidx = nullptr;        // [nv][2]
+  CGData<double> d;
+  CGData<float> f;
+};
+
+}  // namespace
+
+struct hpmg_ctx {
+  int dim = 0, n = 0, p = 0, ncell = 0;
+  bool vark = false;
+  double kappa_const = 1.0;
+  std::vector<double> kappa;
+  hpmg_options opt{};
+  size_t ndof = 0;
+  std::vector<DGLevel> dg;
+  std::vector<CGLevel> cg;
+  double* coarse_inv = nullptr;  // dense inverse of the coarsest Q1 operator
+  int coarse_m = 0;
+  // outer solver workspace (FP64) and the FP32 cycle vectors
+  double *r = nullptr, *rold = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
+  float *r32 = nullptr, *z32 = nullptr;
+  double *partial = nullptr, *scal = nullptr;
+  double* host_scal = nullptr;  // pinned
+  DevMem mem;
+  ~hpmg_ctx() {
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+namespace {
+
+template <typename T>
+DGData<T>& data(DGLevel& l);
+template <>
+DGData<double>& data<double>(DGLevel& l) { return l.d; }
+template <>
+DGData<float>& data<float>(DGLevel& l) { return l.f; }
+template <typename T>
+CGData<T>& data(CGLevel& l);
+template <>
+CGData<double>& data<double>(CGLevel& l) { return l.d; }
+template <>
+CGData<float>& data<float>(CGLevel& l) { return l.f; }
+
+// ------------------------------------------------------------------ setup
+// 1D operator of one axis of the cell block in reference units (Kronecker
+// factor L_k of A_{K<-K}): kappa_K Khat plus, for each of the two facets,
+// c1 (e ep^T + ep e^T) + c2 e e^T with (c1, c2) = (-kF/2, sigma_hat kF) on
+// interior facets and (-kappa_K, 2 sigma_hat kappa_K) on boundary facets.
+void axis_operator(const hpmg::Basis1D& B, double kK, double kF0, bool bdy0, double kF1, bool bdy1,
+                   double sigma_hat, std::vector<double>& L) {
+  const int N = B.N;
+  L.assign((size_t)N * N, 0.0);
+  for (int i = 0; i < N * N; ++i) L[i] = kK * B.K[i];
+  for (int s = 0; s < 2; ++s) {
+    const bool bdy = s ? bdy1 : bdy0;
+    const double kF = s ? kF1 : kF0;
+    const double c1 = bdy ? -kK : -0.5 * kF;
+    const double c2 = bdy ? 2.0 * sigma_hat * kK : sigma_hat * kF;
+    const int ie = s ? N - 1 : 0;
+    const std::vector<double>& ep = s ? B.ep1 : B.ep0;
+    for (int j = 0; j < N; ++j) {
+      L[(size_t)ie * N + j] += c1 * ep[j];
+      L[(size_t)j * N + ie] += c1 * ep[j];
+    }
+    L[(size_t)ie * N + ie] += c2;
+  }
+}
+
+void eig_of(const hpmg::Basis1D& B, const std::vector<double>& L, double* S, double* lam) {
+  if (!hpmg::gen_sym_eig(L.data(), B.M.data(), B.N, S, lam))
+    throw HpmgError(HPMG_E_DEVICE, "mass matrix not positive definite");
+  for (int i = 0; i < B.N; ++i)
+    if (!(lam[i] > 0.0) || !std::isfinite(lam[i]))
+      throw HpmgError(HPMG_E_INVALID, "cell block is not positive definite (penalty too small?)");
+}
+
+void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg::Basis1D* Bnext,
+                    hipStream_t s) {
+  const int N = B.N, NN = N * N, D = h->dim;
+  L.ndof = (size_t)h->ncell * ipow(N, D);
+  L.trsize = (size_t)2 * D * h->ncell * 2 * ipow(N, D - 1);
+  // reference data
+  std::vector<double> ref;
+  ref.insert(ref.end(), B.M.begin(), B.M.end());
+  ref.insert(ref.end(), B.ep0.begin(), B.ep0.end());
+  ref.insert(ref.end(), B.ep1.begin(), B.ep1.end());
+  if (Bnext) {
+    std::vector<double> E = hpmg::interp_matrix(B.xi, Bnext->xi);
+    ref.insert(ref.end(), E.begin(), E.end());
+  } else {
+    for (int a = 0; a < N; ++a) {
+      ref.push_back(1.0 - B.xi[a]);
+      ref.push_back(B.xi[a]);
+    }
+  }
+  L.d.ref = h->mem.upload(ref, s);
+  L.f.ref = h->mem.upload(cast_vec<float>(ref), s);
+  // eigendata of the cell blocks
+  const int EGS = 2 * NN + N;
+  std::vector<double> Lm;
+  if (!h->vark) {
+    std::vector<double> tab((size_t)4 * EGS, 0.0);
+    const double k = h->kappa_const;
+    for (int cls = 0; cls < 4; ++cls) {
+      if (cls == 3 && h->n > 1) {  // both facets on the boundary only when n == 1
+        std::copy(tab.begin(), tab.begin() + EGS, tab.begin() + 3 * EGS);
+        continue;
+      }
+      axis_operator(B, k, k, cls & 1, k, (cls >> 1) & 1, L.sigma_hat, Lm);
+      double* S = &tab[(size_t)cls * EGS];
+      double* Si = S + NN;
+      double* lam = S + 2 * NN;
+      eig_of(B, Lm, S, lam);
+      for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) {
+          double acc = 0.0;
+          for (int m = 0; m < N; ++m) acc += S[m * N + r] * B.M[m * N + c];
+          Si[r * N + c] = acc;
+        }
+    }
+    L.d.eig = h->mem.upload(tab, s);
+    L.f.eig = h->mem.upload(cast_vec<float>(tab), s);
+  } else {
+    const int W = NN + N;
+    std::vector<double> tab((size_t)h->ncell * D * W);
+    const int n = h->n;
+    const double* kap = h->kappa.data();
+    const double sh = L.sigma_hat;
+    const unsigned nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    std::vector<std::string> err(nth);
+    for (unsigned t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        try {
+          std::vector<double> Lloc;
+          for (int c = (int)t; c < h->ncell; c += (int)nth) {
+            for (int k = 0; k < D; ++k) {
+              const int st = ipow(n, k);
+              const int x = (c / st) % n;
+              const bool b0 = x == 0, b1 = x == n - 1;
+              const double kK = kap[c];
+              const double k0 = b0 ? 0.0 : 2.0 * kK * kap[c - st] / (kK + kap[c - st]);
+              const double k1 = b1 ? 0.0 : 2.0 * kK * kap[c + st] / (kK + kap[c + st]);
+              axis_operator(B, kK, k0, b0, k1, b1, sh, Lloc);
+              double* S = &tab[((size_t)c * D + k) * W];
+              eig_of(B, Lloc, S, S + NN);
+            }
+          }
+        } catch (const std::exception& e) {
+          err[t] = e.what();
+        }
+      });
+    for (auto& x : th) x.join();
+    for (auto& e : err)
+      if (!e.empty()) throw HpmgError(HPMG_E_INVALID, e);
+    L.d.eig = h->mem.upload(tab, s);
+    L.f.eig = h->mem.upload(cast_vec<float>(tab), s);
+    L.d.kappa = h->mem.upload(h->kappa, s);
+    L.f.kappa = h->mem.upload(cast_vec<float>(h->kappa), s);
+  }
+  const size_t R = (size_t)h->opt.max_rhs;
+  for (int b = 0; b < 2; ++b) {
+    L.d.tr[b] = (double*)h->mem.alloc(L.trsize * R * sizeof(double));
+    L.f.tr[b] = (float*)h->mem.alloc(L.trsize * R * sizeof(float));
+  }
+}
+
+// Q1 element stiffness on a cell of width h: h^(d-2) sum_k K1 (x) M1 ...
+void q1_element(int D, double h, std::vector<double>& Ke) {
+  const double M1[2][2] = {{1.0 / 3, 1.0 / 6}, {1.0 / 6, 1.0 / 3}};
+  const double K1[2][2] = {{1.0, -1.0}, {-1.0, 1.0}};
+  const int nc = 1 << D;
+  Ke.assign((size_t)nc * nc, 0.0);
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < D; ++k) {
+        double t = 1.0;
+        for (int m = 0; m < D; ++m) {
+          const int a = (i >> m) & 1, b = (j >> m) & 1;
+          t *= (m == k) ? K1[a][b] : M1[a][b];
+        }
+        s += t;
+      }
+      Ke[(size_t)i * nc + j] = s * std::pow(h, D - 2);
+    }
+}
+
+int nstencil(int D) { return D == 2 ? 9 : 27; }
+
+// Finest Q1 operator: Galerkin product of the DG operator with the Q1
+// interpolation, i.e. sum_K kappa_K (grad phi_i, grad phi_j)_K on interior
+// vertices, as a 3^d-point stencil per vertex.
+std::vector<double> q1_stencil(int D, int n, const std::vector<double>& kap) {
+  const int nv = n - 1, NS = nstencil(D), ncor = 1 << D;
+  const size_t nvt = (size_t)ipow(nv, D);
+  std::vector<double> st(nvt * NS, 0.0), Ke;
+  q1_element(D, 1.0 / n, Ke);
+  const int ncell = ipow(n, D);
+  for (int c = 0; c < ncell; ++c) {
+    int cc[3] = {c % n, (c / n) % n, D == 3 ? c / (n * n) : 0};
+    for (int i = 0; i < ncor; ++i) {
+      int vi[3] = {0, 0, 0};
+      bool in = true;
+      for (int k = 0; k < D; ++k) {
+        vi[k] = cc[k] + ((i >> k) & 1);
+        in = in && vi[k] > 0 && vi[k] < n;
+      }
+      if (!in) continue;
+      const size_t row = (vi[0] - 1) + (size_t)nv * ((vi[1] - 1) + (size_t)nv * (D == 3 ? vi[2] - 1 : 0));
+      for (int j = 0; j < ncor; ++j) {
+        int off = 0, mul = 1;
+        bool jin = true;
+        for (int k = 0; k < D; ++k) {
+          const int vj = cc[k] + ((j >> k) & 1);
+          jin = jin && vj > 0 && vj < n;
+          off += (vj - vi[k] + 1) * mul;
+          mul *= 3;
+        }
+        if (!jin) continue;
+        st[row * NS + off] += kap[c] * Ke[(size_t)i * ncor + j];
+      }
+    }
+  }
+  return st;
+}
+
+// 1D interpolation from the coarse vertex grid (every other fine vertex, the
+// last fine vertex always kept) to the fine vertices 0..n.
+std::vector<int> coarse_positions(int n) {
+  std::vector<int> pos;
+  for (int i = 0; i <= n; i += 2) pos.push_back(i);
+  if (pos.back() != n) pos.push_back(n);
+  return pos;
+}
+
+struct Transfer1D {
+  std::vector<std::vector<std::pair<int, double>>> parents;  // fine vertex -> (coarse vertex, weight)
+};
+
+Transfer1D transfer_1d(int n) {
+  std::vector<int> pos = coarse_positions(n);
+  Transfer1D T;
+  T.parents.resize(n + 1);
+  for (int i = 0; i <= n; ++i) {
+    auto it = std::lower_bound(pos.begin(), pos.end(), i);
+    const int J = (int)(it - pos.begin());
+    if (pos[J] == i) {
+      T.parents[i].push_back({J, 1.0});
+    } else {
+      const double t = double(i - pos[J - 1]) / double(pos[J] - pos[J - 1]);
+      T.parents[i].push_back({J - 1, 1.0 - t});
+      T.parents[i].push_back({J, t});
+    }
+  }
+  return T;
+}
+
+// Galerkin coarse stencil P^T A P with the tensor-product 1D transfer.
+std::vector<double> rap(int D, int n, const std::vector<double>& st, int nc) {
+  const int nv = n - 1, nvc = nc - 1, NS = nstencil(D);
+  Transfer1D T1 = transfer_1d(n);
+  std::vector<double> out((size_t)ipow(nvc, D) * NS, 0.0);
+  const size_t nvt = (size_t)ipow(nv, D);
+  for (size_t v = 0; v < nvt; ++v) {
+    int x[3] = {(int)(v % nv), (int)((v / nv) % nv), D == 3 ? (int)(v / ((size_t)nv * nv)) : 0};
+    for (int s = 0; s < NS; ++s) {
+      const double a = st[v * NS + s];
+      if (a == 0.0) continue;
+      int y[3] = {x[0] + s % 3 - 1, x[1] + (s / 3) % 3 - 1, D == 3 ? x[2] + s / 9 - 1 : 0};
+      // parents of fine interior vertex x+1 and y+1 (1-based vertex ids)
+      auto& px = T1.parents[x[0] + 1];
+      auto& py = T1.parents[x[1] + 1];
+      auto& qx = T1.parents[y[0] + 1];
+      auto& qy = T1.parents[y[1] + 1];
+      static const std::vector<std::pair<int, double>> one = {{1, 1.0}};
+      auto& pz = D == 3 ? T1.parents[x[2] + 1] : one;
+      auto& qz = D == 3 ? T1.parents[y[2] + 1] : one;
+      for (auto& Iz : pz)
+        for (auto& Iy : py)
+          for (auto& Ix : px) {
+            if (Ix.first < 1 || Ix.first > nvc || Iy.first < 1 || Iy.first > nvc) continue;
+            if (D == 3 && (Iz.first < 1 || Iz.first > nvc)) continue;
+            const double wI = Ix.second * Iy.second * Iz.second;
+            const size_t row = (Ix.first - 1) + (size_t)nvc * ((Iy.first - 1) + (size_t)nvc * (D == 3 ? Iz.first - 1 : 0));
+            for (auto& Jz : qz)
+              for (auto& Jy : qy)
+                for (auto& Jx : qx) {
+                  if (Jx.first < 1 || Jx.first > nvc || Jy.first < 1 || Jy.first > nvc) continue;
+                  if (D == 3 && (Jz.first < 1 || Jz.first > nvc)) continue;
+                  const int off = (Jx.first - Ix.first + 1) + 3 * (Jy.first - Iy.first + 1) +
+                                  (D == 3 ? 9 * (Jz.first - Iz.first + 1) : 0);
+                  out[row * NS + off] += wI * Jx.second * Jy.second * Jz.second * a;
+                }
+          }
+    }
+  }
+  return out;
+}
+
+void build_cg_levels(hpmg_ctx* h, hipStream_t s) {
+  const int D = h->dim;
+  std::vector<double> kap = h->vark ? h->kappa : std::vector<double>(h->ncell, h->kappa_const);
+  std::vector<double> st = q1_stencil(D, h->n, kap);
+  int m = h->n;
+  while (true) {
+    CGLevel L;
+    L.n = m;
+    L.nv = m - 1;
+    L.size = (size_t)ipow(L.nv, D);
+    const int NS = nstencil(D);
+    std::vector<double> dinv(L.size);
+    for (size_t v = 0; v < L.size; ++v) dinv[v] = 1.0 / st[v * NS + NS / 2];
+    L.d.st = h->mem.upload(st, s);
+    L.f.st = h->mem.upload(cast_vec<float>(st), s);
+    L.d.dinv = h->mem.upload(dinv, s);
+    L.f.dinv = h->mem.upload(cast_vec<float>(dinv), s);
+    const size_t R = h->opt.max_rhs;
+    for (int b = 0; b < 2; ++b) {
+      L.d.u[b] = (double*)h->mem.alloc(L.size * R * sizeof(double));
+      L.f.u[b] = (float*)h->mem.alloc(L.size * R * sizeof(float));
+    }
+    L.d.b = (double*)h->mem.alloc(L.size * R * sizeof(double));
+    L.f.b = (float*)h->mem.alloc(L.size * R * sizeof(float));
+    L.d.r = (double*)h->mem.alloc(L.size * R * sizeof(double));
+    L.f.r = (float*)h->mem.alloc(L.size * R * sizeof(float));
+    const bool last = m <= h->opt.coarsest_n;
+    if (last) {
+      // dense inverse of the coarsest operator by Cholesky (FP64)
+      const int M = (int)L.size;
+      std::vector<double> A((size_t)M * M, 0.0);
+      for (int v = 0; v < M; ++v) {
+        int x[3] = {v % L.nv, (v / L.nv) % L.nv, D == 3 ? v / (L.nv * L.nv) : 0};
+        for (int k = 0; k < NS; ++k) {
+          int y[3] = {x[0] + k % 3 - 1, x[1] + (k / 3) % 3 - 1, D == 3 ? x[2] + k / 9 - 1 : 0};
+          if (y[0] < 0 || y[0] >= L.nv || y[1] < 0 || y[1] >= L.nv || y[2] < 0 || y[2] >= (D == 3 ? L.nv : 1)) continue;
+          const int w = y[0] + L.nv * (y[1] + L.nv * y[2]);
+          A[(size_t)v * M + w] = st[(size_t)v * NS + k];
+        }
+      }
+      std::vector<double> C((size_t)M * M, 0.0);
+      for (int j = 0; j < M; ++j) {
+        double d = A[(size_t)j * M + j];
+        for (int k = 0; k < j; ++k) d -= C[(size_t)j * M + k] * C[(size_t)j * M + k];
+        require(d > 0.0, "coarsest operator not positive definite");
+        C[(size_t)j * M + j] = std::sqrt(d);
+        for (int i = j + 1; i < M; ++i) {
+          double t = A[(size_t)i * M + j];
+          for (int k = 0; k < j; ++k) t -= C[(size_t)i * M + k] * C[(size_t)j * M + k];
+          C[(size_t)i * M + j] = t / C[(size_t)j * M + j];
+        }
+      }
+      std::vector<double> inv((size_t)M * M, 0.0), e(M), y(M);
+      for (int col = 0; col < M; ++col) {
+        std::fill(e.begin(), e.end(), 0.0);
+        e[col] = 1.0;
+        for (int i = 0; i < M; ++i) {
+          double t = e[i];
+          for (int k = 0; k < i; ++k) t -= C[(size_t)i * M + k] * y[k];
+          y[i] = t / C[(size_t)i * M + i];
+        }
+        for (int i = M - 1; i >= 0; --i) {
+          double t = y[i];
+          for (int k = i + 1; k < M; ++k) t -= C[(size_t)k * M + i] * e[k];
+          e[i] = t / C[(size_t)i * M + i];
+        }
+        for (int i = 0; i < M; ++i) inv[(size_t)i * M + col] = e[i];
+      }
+      h->coarse_inv = h->mem.upload(inv, s);
+      h->coarse_m = M;
+      h->cg.push_back(L);
+      break;
+    }
+    // transfer to the next coarser grid
+    std::vector<int> pos = coarse_positions(m);
+    const int mc = (int)pos.size() - 1;
+    const int nvc = mc - 1;
+    Transfer1D T1 = transfer_1d(m);
+    std::vector<int> ridx((size_t)nvc * 3, -1), pidx((size_t)L.nv * 2, -1);
+    std::vector<double> rw((size_t)nvc * 3, 0.0), pw((size_t)L.nv * 2, 0.0);
+    std::vector<int> cnt(nvc, 0);
+    for (int i = 1; i < m; ++i) {  // fine interior vertex i
+      int k = 0;
+      for (auto& pr : T1.parents[i]) {
+        if (pr.first >= 1 && pr.first <= nvc) {
+          pidx[(size_t)(i - 1) * 2 + k] = pr.first - 1;
+          pw[(size_t)(i - 1) * 2 + k] = pr.second;
+          const int I = pr.first - 1;
+          ridx[(size_t)I * 3 + cnt[I]] = i - 1;
+          rw[(size_t)I * 3 + cnt[I]] = pr.second;
+          ++cnt[I];
+        }
+        ++k;
+      }
+    }
+    L.ridx = h->mem.upload(ridx, s);
+    L.pidx = h->mem.upload(pidx, s);
+    L.d.rw = h->mem.upload(rw, s);
+    L.f.rw = h->mem.upload(cast_vec<float>(rw), s);
+    L.d.pw = h->mem.upload(pw, s);
+    L.f.pw = h->mem.upload(cast_vec<float>(pw), s);
+    st = rap(D, m, st, mc);
+    h->cg.push_back(L);
+    m = mc;
+  }
+}
+
+// --------------------------------------------------------------- execution
+template <typename T>
+hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
+  hpmg::DGArgs<T> a{};
+  DGData<T>& d = data<T>(L);
+  a.n = h->n;
+  a.ncell = h->ncell;
+  a.vark = h->vark ? 1 : 0;
+  a.kappa_const = (T)h->kappa_const;
+  a.ref = d.ref;
+  a.eig = d.eig;
+  a.kappa = d.kappa;
+  const double hh = 1.0 / h->n;
+  a.h_fwd = (T)std::pow(hh, 2 - h->dim);
+  a.h_apply = (T)std::pow(hh, h->dim - 2);
+  a.sigma_hat = (T)L.sigma_hat;
+  a.omega = (T)h->opt.omega_dg;
+  a.vstride = (long long)L.ndof;
+  a.tstride = (long long)L.trsize;
+  return a;
+}
+
+template <typename T>
+void dg_run(hpmg_ctx* h, int op, const hpmg::DGArgs<T>& a, int N, int nrhs, int flag, hipStream_t s) {
+  if (!hpmg::dg_dispatch(h->dim, N, op, a, nrhs, flag, s))
+    throw HpmgError(HPMG_E_UNSUPPORTED, "no kernel for this degree");
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+void project(hpmg_ctx* h, int l, const T* u, T* tr, int nrhs, hipStream_t s) {
+  DGLevel& L = h->dg[l];
+  hpmg::DGArgs<T> a = dg_args<T>(h, L);
+  a.u_in = u;
+  a.tr_out = tr;
+  dg_run(h, hpmg::OP_PROJECT, a, L.N, nrhs, 0, s);
+}
+
+template <typename T>
+void sweep(hpmg_ctx* h, int l, T* u, const T* b, const T* trin, T* trout, bool uzero, int nrhs, hipStream_t s) {
+  DGLevel& L = h->dg[l];
+  hpmg::DGArgs<T> a = dg_args<T>(h, L);
+  a.u_in = u;
+  a.u_out = u;
+  a.b = b;
+  a.tr_in = trin;
+  a.tr_out = trout;
+  dg_run(h, hpmg::OP_SWEEP, a, L.N, nrhs, uzero ? 1 : 0, s);
+}
+
+template <typename T>
+void apply(hpmg_ctx* h, int l, const T* u, const T* tr, const T* b, T* out, int nrhs, hipStream_t s) {
+  DGLevel& L = h->dg[l];
+  hpmg::DGArgs<T> a = dg_args<T>(h, L);
+  a.u_in = u;
+  a.tr_in = tr;
+  a.b = b;
+  a.out = out;
+  dg_run(h, hpmg::OP_APPLY, a, L.N, nrhs, b ? 1 : 0, s);
+}
+
+template <typename T>
+void vcycle_cg(hpmg_ctx* h, int m, bool uzero, hipStream_t s) {
+  CGLevel& L = h->cg[m];
+  CGData<T>& d = data<T>(L);
+  const int D = h->dim;
+  if (m + 1 == (int)h->cg.size()) {
+    hpmg::dense_solve<T>(h->coarse_m, h->coarse_inv, d.b, d.u[0], s);
+    L.cur = 0;
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  const T w = (T)h->opt.omega_cg;
+  int cur = 0;
+  bool zero = uzero;
+  for (int i = 0; i < h->opt.nu_pre; ++i) {
+    hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, d.u[cur], d.b, d.u[cur ^ 1], w, 0, zero ? 1 : 0, s);
+    cur ^= 1;
+    zero = false;
+  }
+  if (zero) {
+    hpmg::fill<T>(d.u[cur], L.size, T(0), s);
+    zero = false;
+  }
+  hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, d.u[cur], d.b, d.r, w, 1, 0, s);
+  CGLevel& C = h->cg[m + 1];
+  CGData<T>& dc = data<T>(C);
+  hpmg::cg_restrict<T>(D, L.nv, C.nv, L.ridx, d.rw, d.r, dc.b, s);
+  vcycle_cg<T>(h, m + 1, true, s);
+  hpmg::cg_prolong<T>(D, L.nv, C.nv, L.pidx, d.pw, dc.u[C.cur], d.u[cur], s);
+  for (int i = 0; i < h->opt.nu_post; ++i) {
+    hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, d.u[cur], d.b, d.u[cur ^ 1], w, 0, 0, s);
+    cur ^= 1;
+  }
+  L.cur = cur;
+  HIPCHK(hipGetLastError());
+}
+
+// One V-cycle on DG level l; u, b are the level's vectors (for l = 0 the
+// caller's).  Traversals on the level: [projection], nu_pre sweeps,
+// residual + restriction, prolongation + projection, nu_post sweeps.
+template <typename T>
+void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) {
+  DGLevel& L = h->dg[l];
+  DGData<T>& d = data<T>(L);
+  int cur = 0;
+  bool zero = uzero;
+  if (zero && h->opt.nu_pre == 0) {
+    hpmg::fill<T>(u, L.ndof, T(0), s);
+    zero = false;
+  }
+  if (!zero) project<T>(h, l, u, d.tr[0], 1, s);
+  for (int i = 0; i < h->opt.nu_pre; ++i) {
+    sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], zero, 1, s);
+    cur ^= 1;
+    zero = false;
+  }
+  // residual and restriction
+  hpmg::DGArgs<T> a = dg_args<T>(h, L);
+  a.u_in = u;
+  a.tr_in = d.tr[cur];
+  a.b = b;
+  if (!L.next_cg) {
+    DGLevel& C = h->dg[l + 1];
+    DGData<T>& dc = data<T>(C);
+    a.out = dc.b;
+    a.cstride = (long long)C.ndof;
+    dg_run(h, hpmg::OP_RESTRICT, a, L.N, 1, 1, s);
+    vcycle_dg<T>(h, l + 1, dc.u, dc.b, true, s);
+    hpmg::DGArgs<T> pa = dg_args<T>(h, L);
+    pa.u_in = u;
+    pa.u_out = u;
+    pa.tr_out = d.tr[cur];
+    pa.coarse = dc.u;
+    pa.coarse_cg = 0;
+    pa.cstride = (long long)C.ndof;
+    dg_run(h, hpmg::OP_PROLONG, pa, L.N, 1, 0, s);
+  } else {
+    CGLevel& C = h->cg[0];
+    CGData<T>& dc = data<T>(C);
+    a.out = d.contrib;
+    a.cstride = (long long)h->ncell << h->dim;
+    dg_run(h, hpmg::OP_RESTRICT, a, L.N, 1, 1, s);
+    hpmg::gather_corners<T>(h->dim, h->n, d.contrib, dc.b, s);
+    vcycle_cg<T>(h, 0, true, s);
+    hpmg::DGArgs<T> pa = dg_args<T>(h, L);
+    pa.u_in = u;
+    pa.u_out = u;
+    pa.tr_out = d.tr[cur];
+    pa.coarse = dc.u[C.cur];
+    pa.coarse_cg = 1;
+    pa.cstride = (long long)C.size;
+    dg_run(h, hpmg::OP_PROLONG, pa, L.N, 1, 0, s);
+  }
+  for (int i = 0; i < h->opt.nu_post; ++i) {
+    sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], false, 1, s);
+    cur ^= 1;
+  }
+}
+
+hpmg_status fail(const HpmgError& e) {
+  g_last_error = e.what();
+  return e.st;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+void hpmg_default_options(hpmg_options* o) {
+  if (!o) return;
+  o->sigma0 = 2.0;
+  o->omega_dg = 0.7;
+  o->omega_cg = 2.0 / 3.0;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->coarsest_n = 4;
+  o->precision = HPMG_PREC_F32;
+  o->max_rhs = 1;
+}
+
+const char* hpmg_status_string(hpmg_status s) {
+  switch (s) {
+    case HPMG_OK: return "ok";
+    case HPMG_E_INVALID: return "invalid argument";
+    case HPMG_E_NOMEM: return "out of memory";
+    case HPMG_E_DEVICE: return "device error";
+    case HPMG_E_NOT_CONVERGED: return "not converged";
+    case HPMG_E_BREAKDOWN: return "breakdown";
+    case HPMG_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* hpmg_last_error(void) { return g_last_error.c_str(); }
+
+hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, const hpmg_options* opt,
+                       hipStream_t stream, hpmg_handle* out) {
+  try {
+    require(out != nullptr, "out is NULL");
+    *out = nullptr;
+    require(mesh != nullptr && coeff != nullptr, "mesh/coeff is NULL");
+    require(mesh->dim == 2 || mesh->dim == 3, "dim must be 2 or 3");
+    require(mesh->n[0] >= 2, "n must be >= 2");
+    require(mesh->n[1] == mesh->n[0] && (mesh->dim == 2 || mesh->n[2] == mesh->n[0]),
+            "only n x n (x n) meshes are supported");
+    require(p >= 1 && p <= 8, "p must be in [1, 8]");
+    const long long ncell_ll = mesh->dim == 2 ? (long long)mesh->n[0] * mesh->n[0]
+                                              : (long long)mesh->n[0] * mesh->n[0] * mesh->n[0];
+    require(ncell_ll < (1LL << 31) / 2, "mesh too large");
+    std::unique_ptr<hpmg_ctx> h(new hpmg_ctx());
+    if (opt) {
+      h->opt = *opt;
+    } else {
+      hpmg_default_options(&h->opt);
+    }
+    require(h->opt.sigma0 > 0.0 && std::isfinite(h->opt.sigma0), "sigma0 must be positive");
+    require(h->opt.omega_dg > 0.0 && h->opt.omega_dg <= 1.0, "omega_dg must be in (0, 1]");
+    require(h->opt.omega_cg > 0.0 && h->opt.omega_cg <= 1.0, "omega_cg must be in (0, 1]");
+    require(h->opt.nu_pre >= 0 && h->opt.nu_post >= 0 && h->opt.nu_pre + h->opt.nu_post > 0, "bad nu");
+    require(h->opt.coarsest_n >= 2, "coarsest_n must be >= 2");
+    require(h->opt.max_rhs >= 1, "max_rhs must be >= 1");
+    require(h->opt.precision == HPMG_PREC_F64 || h->opt.precision == HPMG_PREC_F32, "bad precision");
+    h->dim = mesh->dim;
+    h->n = mesh->n[0];
+    h->p = p;
+    h->ncell = (int)ncell_ll;
+    if (coeff->per_cell) {
+      require(coeff->kappa != nullptr, "kappa is NULL");
+      h->vark = true;
+      h->kappa.assign(coeff->kappa, coeff->kappa + h->ncell);
+      for (double k : h->kappa) require(k > 0.0 && std::isfinite(k), "kappa must be positive and finite");
+    } else {
+      require(coeff->kappa_const > 0.0 && std::isfinite(coeff->kappa_const), "kappa_const must be positive");
+      h->kappa_const = coeff->kappa_const;
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    // DG levels: p, floor(p/2), ... while >= 2, then Q1
+    std::vector<int> degs = {p};
+    for (int q = p / 2; q >= 2; q /= 2) degs.push_back(q);
+    const double sigma_hat = h->opt.sigma0 * (p + 1.0) * (p + 1.0);
+    std::vector<hpmg::Basis1D> bases;
+    for (int q : degs) bases.push_back(hpmg::make_basis(q));
+    h->dg.resize(degs.size());
+    for (size_t l = 0; l < degs.size(); ++l) {
+      DGLevel& L = h->dg[l];
+      L.p = degs[l];
+      L.N = degs[l] + 1;
+      L.next_cg = (l + 1 == degs.size());
+      L.NC = L.next_cg ? 2 : degs[l + 1] + 1;
+      require(L.NC == hpmg::nc_next(L.N), "internal: p schedule mismatch");
+      L.sigma_hat = sigma_hat;
+      build_dg_level(h.get(), L, bases[l], L.next_cg ? nullptr : &bases[l + 1], stream);
+      const size_t R = h->opt.max_rhs;
+      if (l > 0) {
+        L.d.u = (double*)h->mem.alloc(L.ndof * R * sizeof(double));
+        L.d.b = (double*)h->mem.alloc(L.ndof * R * sizeof(double));
+        L.f.u = (float*)h->mem.alloc(L.ndof * R * sizeof(float));
+        L.f.b = (float*)h->mem.alloc(L.ndof * R * sizeof(float));
+      }
+      if (L.next_cg) {
+        const size_t nct = (size_t)h->ncell << h->dim;
+        L.d.contrib = (double*)h->mem.alloc(nct * R * sizeof(double));
+        L.f.contrib = (float*)h->mem.alloc(nct * R * sizeof(float));
+      }
+    }
+    h->ndof = h->dg[0].ndof;
+    build_cg_levels(h.get(), stream);
+    // outer solver workspace
+    const size_t nd = h->ndof;
+    h->r = (double*)h->mem.alloc(nd * sizeof(double));
+    h->rold = (double*)h->mem.alloc(nd * sizeof(double));
+    h->z = (double*)h->mem.alloc(nd * sizeof(double));
+    h->pv = (double*)h->mem.alloc(nd * sizeof(double));
+    h->q = (double*)h->mem.alloc(nd * sizeof(double));
+    h->r32 = (float*)h->mem.alloc(nd * sizeof(float));
+    h->z32 = (float*)h->mem.alloc(nd * sizeof(float));
+    h->partial = (double*)h->mem.alloc(2 * hpmg::KRYLOV_RED_BLOCKS * sizeof(double));
+    h->scal = (double*)h->mem.alloc(16 * sizeof(double));
+    HIPCHK(hipHostMalloc((void**)&h->host_scal, 16 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipStreamSynchronize(stream));
+    *out = h.release();
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HPMG_E_NOMEM;
+  }
+}
+
+size_t hpmg_ndof(hpmg_handle h) { return h ? h->ndof : 0; }
+
+void hpmg_destroy(hpmg_handle h) { delete h; }
+
+hpmg_status hpmg_load_vector(hpmg_handle h, int kind, const double* params, double* b, hipStream_t stream) {
+  try {
+    require(h && b, "NULL argument");
+    require(kind == 0 || kind == 1, "kind must be 0 or 1");
+    require(params != nullptr, "params is NULL");
+    const int D = h->dim, n = h->n, N = h->p + 1;
+    const double hh = 1.0 / n;
+    hpmg::Basis1D B = hpmg::make_basis(h->p);
+    std::vector<double> xq, wq;
+    hpmg::gauss_legendre(h->p + 3, xq, wq);
+    std::vector<double> V = hpmg::interp_matrix(xq, B.xi);
+    const int nq = (int)xq.size();
+    // separable f: f = coef * prod_k g(x_k); per axis and cell coordinate,
+    // G[x][a] = h int g l_a over the cell
+    double coef;
+    std::vector<double> G((size_t)n * N, 0.0);
+    const double kf = kind == 1 ? params[0] : 0.0;
+    coef = kind == 0 ? params[0] : D * kf * kf * M_PI * M_PI;
+    for (int x = 0; x < n; ++x)
+      for (int a = 0; a < N; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) {
+          const double g = kind == 0 ? 1.0 : std::sin(kf * M_PI * (x + xq[q]) * hh);
+          s += wq[q] * g * V[(size_t)q * N + a];
+        }
+        G[(size_t)x * N + a] = s * hh;
+      }
+    std::vector<double> out(h->ndof);
+    const int nd = ipow(N, D);
+    for (int c = 0; c < h->ncell; ++c) {
+      const int cx = c % n, cy = (c / n) % n, cz = D == 3 ? c / (n * n) : 0;
+      for (int i = 0; i < nd; ++i) {
+        const int a = i % N, bb = (i / N) % N, cc = i / (N * N);
+        double v = coef * G[(size_t)cx * N + a] * G[(size_t)cy * N + bb];
+        if (D == 3) v *= G[(size_t)cz * N + cc];
+        out[(size_t)c * nd + i] = v;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(b, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+hpmg_status hpmg_apply_A(hpmg_handle h, hpmg_dtype dtype, const void* u, void* y, int nrhs, hipStream_t stream) {
+  try {
+    require(h && u && y, "NULL argument");
+    require(nrhs >= 1 && nrhs <= h->opt.max_rhs, "nrhs out of range");
+    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    require(u != y, "u and y must not overlap");
+    if (dtype == HPMG_F64) {
+      project<double>(h, 0, (const double*)u, h->dg[0].d.tr[0], nrhs, stream);
+      apply<double>(h, 0, (const double*)u, h->dg[0].d.tr[0], nullptr, (double*)y, nrhs, stream);
+    } else {
+      project<float>(h, 0, (const float*)u, h->dg[0].f.tr[0], nrhs, stream);
+      apply<float>(h, 0, (const float*)u, h->dg[0].f.tr[0], nullptr, (float*)y, nrhs, stream);
+    }
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+hpmg_status hpmg_smooth(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nsweeps, int nrhs,
+                        hipStream_t stream) {
+  try {
+    require(h && u && b, "NULL argument");
+    require(nrhs >= 1 && nrhs <= h->opt.max_rhs, "nrhs out of range");
+    require(nsweeps >= 0, "nsweeps must be >= 0");
+    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    if (nsweeps == 0) return HPMG_OK;
+    if (dtype == HPMG_F64) {
+      DGData<double>& d = h->dg[0].d;
+      project<double>(h, 0, (const double*)u, d.tr[0], nrhs, stream);
+      for (int k = 0; k < nsweeps; ++k)
+        sweep<double>(h, 0, (double*)u, (const double*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
+    } else {
+      DGData<float>& d = h->dg[0].f;
+      project<float>(h, 0, (const float*)u, d.tr[0], nrhs, stream);
+      for (int k = 0; k < nsweeps; ++k)
+        sweep<float>(h, 0, (float*)u, (const float*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
+    }
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nrhs, hipStream_t stream) {
+  try {
+    require(h && u && b, "NULL argument");
+    require(nrhs == 1, "vcycle supports nrhs == 1");
+    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    if (dtype == HPMG_F64)
+      vcycle_dg<double>(h, 0, (double*)u, (const double*)b, false, stream);
+    else
+      vcycle_dg<float>(h, 0, (float*)u, (const float*)b, false, stream);
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, double rtol, int maxit,
+                       hpmg_solve_info* info, hipStream_t stream) {
+  try {
+    require(h && u && b, "NULL argument");
+    require(nrhs >= 1, "nrhs must be >= 1");
+    require(rtol > 0.0 && maxit >= 1, "bad rtol/maxit");
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t nd = h->ndof;
+    DGData<double>& d = h->dg[0].d;
+    hpmg_status result = HPMG_OK;
+    int its_total = 0;
+    double r0_first = 0.0, rfin = 0.0;
+    std::vector<double> hist;
+    for (int rhs = 0; rhs < nrhs; ++rhs) {
+      double* ur = u + (size_t)rhs * nd;
+      const double* br = b + (size_t)rhs * nd;
+      // r = b - A u
+      project<double>(h, 0, ur, d.tr[0], 1, stream);
+      apply<double>(h, 0, ur, d.tr[0], br, h->r, 1, stream);
+      hpmg::krylov_dot(nd, h->r, h->r, nullptr, h->partial, h->scal, 3, 0, 0, stream);
+      HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      const double r0 = std::sqrt(h->host_scal[6]);
+      if (!std::isfinite(r0)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite initial residual");
+      if (rhs == 0) r0_first = r0;
+      double rn = r0;
+      int it = 0;
+      bool conv = r0 == 0.0;
+      while (!conv && it < maxit) {
+        // z = M r (one V-cycle, zero initial guess)
+        if (h->opt.precision == HPMG_PREC_F32) {
+          hpmg::cast_down(nd, h->r, h->r32, h->scal, stream);
+          vcycle_dg<float>(h, 0, h->z32, h->r32, true, stream);
+          hpmg::cast_up(nd, h->z32, h->z, h->scal, stream);
+        } else {
+          vcycle_dg<double>(h, 0, h->z, h->r, true, stream);
+        }
+        // beta, rho = z.r ; p = z + beta p
+        hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, it == 0 ? 1 : 0, stream);
+        hpmg::krylov_update_p(nd, h->z, h->pv, h->scal, stream);
+        // q = A p ; alpha = rho / p.q
+        project<double>(h, 0, h->pv, d.tr[0], 1, stream);
+        apply<double>(h, 0, h->pv, d.tr[0], nullptr, h->q, 1, stream);
+        hpmg::krylov_dot(nd, h->pv, h->q, nullptr, h->partial, h->scal, 2, 0, 0, stream);
+        hpmg::krylov_update_ur(nd, ur, h->r, h->rold, h->pv, h->q, h->partial, h->scal, stream);
+        HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        ++it;
+        rn = std::sqrt(h->host_scal[6]);
+        if (!std::isfinite(rn)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite residual");
+        if (rhs == 0) hist.push_back(rn / r0);
+        conv = rn <= rtol * r0;
+      }
+      its_total = std::max(its_total, it);
+      rfin = std::max(rfin, rn);
+      if (!conv) result = HPMG_E_NOT_CONVERGED;
+    }
+    if (info) {
+      info->iterations = its_total;
+      info->initial_residual = r0_first;
+      info->final_residual = rfin;
+      for (int i = 0; i < 256; ++i) info->residual_history[i] = i < (int)hist.size() ? hist[i] : 0.0;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (result != HPMG_OK) g_last_error = "maximum number of iterations reached";
+    return result;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+}  // extern "C"
+
+namespace hpmg {
+bool dg_dispatch(int dim, int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s) {
+  return dim == 2 ? dg_dispatch2(N, op, a, nrhs, flag, s) : dg_dispatch3(N, op, a, nrhs, flag, s);
+}
+bool dg_dispatch(int dim, int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s) {
+  return dim == 2 ? dg_dispatch2(N, op, a, nrhs, flag, s) : dg_dispatch3(N, op, a, nrhs, flag, s);
+}
+}  // namespace hpmg

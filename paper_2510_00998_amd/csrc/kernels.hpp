@@ -1,0 +1,56 @@
+// Host-callable launchers of every device kernel of libhpmg.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "dg_kernels.hpp"
+
+namespace hpmg {
+
+// Operations of the DG cell kernels (template dispatch by dimension, nodes
+// per direction N = p+1 and the coarse partner's N).
+enum DGOp {
+  OP_SWEEP = 0,       // fused block-Jacobi sweep (flag: u == 0 on entry)
+  OP_APPLY = 1,       // y = A u (flag: 1 -> r = b - A u)
+  OP_RESTRICT = 2,    // r = b - A u restricted to the next coarser level
+  OP_PROJECT = 3,     // traces of u
+  OP_PROLONG = 4      // u += P e, then traces of u
+};
+
+// Next coarser level of a DG level with N nodes per direction: DG with
+// NC = floor(p/2)+1 nodes while floor(p/2) >= 2, else Q1 (NC = 2).
+constexpr int nc_next(int N) { return ((N - 1) / 2 >= 2) ? (N - 1) / 2 + 1 : 2; }
+
+// Returns false if (dim, N) has no compiled kernel.
+bool dg_dispatch(int dim, int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch(int dim, int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch2(int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch2(int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch3(int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch3(int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s);
+
+template <typename T>
+void cg_stencil(int D, int nv, const T* st, const T* dinv, const T* u, const T* b, T* out, T omega, int mode,
+                int uzero, hipStream_t s);
+template <typename T>
+void cg_restrict(int D, int nvf, int nvc, const int* ridx, const T* rw, const T* rf, T* bc, hipStream_t s);
+template <typename T>
+void cg_prolong(int D, int nvf, int nvc, const int* pidx, const T* pw, const T* ec, T* uf, hipStream_t s);
+template <typename T>
+void gather_corners(int D, int n, const T* contrib, T* bcg, hipStream_t s);
+template <typename T>
+void dense_solve(int m, const double* Ainv, const T* b, T* x, hipStream_t s);
+template <typename T>
+void fill(T* x, size_t n, T v, hipStream_t s);
+
+constexpr int KRYLOV_RED_BLOCKS = 1024;
+void krylov_dot(size_t n, const double* x, const double* y, const double* z, double* partial, double* scal, int op,
+                int a0, int first, hipStream_t s);
+void krylov_update_p(size_t n, const double* z, double* p, const double* scal, hipStream_t s);
+void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double* p, const double* q, double* partial,
+                      double* scal, hipStream_t s);
+void cast_down(size_t n, const double* x, float* y, const double* scal, hipStream_t s);
+void cast_up(size_t n, const float* x, double* y, const double* scal, hipStream_t s);
+
+}  // namespace hpmg
