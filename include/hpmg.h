@@ -107,6 +107,21 @@ hpmg_status hpmg_apply_A(hpmg_handle h, hpmg_dtype dtype, const void* u, void* y
 hpmg_status hpmg_smooth(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nsweeps,
                         int nrhs, hipStream_t stream);
 
+/* Warm-up projection of Algorithm BlockJacobi (loop-fused form): writes
+ * the facet traces of u (value and outward normal derivative on every
+ * facet, technique projection-variables) into the handle's trace buffer for
+ * dtype.  Enables hpmg_sweep on the same u. */
+hpmg_status hpmg_project(hpmg_handle h, hpmg_dtype dtype, const void* u, int nrhs, hipStream_t stream);
+
+/* nsweeps fused single-touch block-Jacobi sweeps (one traversal each,
+ * technique shift-and-fuse) on u in place, reading the traces held by the
+ * handle and replacing them with those of the updated u.  Requires that the
+ * previous call on this handle and dtype was hpmg_project, hpmg_smooth or
+ * hpmg_sweep on the same u with the same nrhs and that u was not modified in
+ * between (HPMG_E_INVALID if no such state exists). */
+hpmg_status hpmg_sweep(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nsweeps, int nrhs,
+                       hipStream_t stream);
+
 /* One V(nu_pre, nu_post) cycle of the hp-multigrid in place on u
  * (Algorithm MGMult body with CoarseGridCorrection; gradual p-coarsening,
  * Q1, h-coarsening, dense coarsest solve). */

@@ -4,7 +4,7 @@ Argument marshalling only: every step of the solver runs in the HIP library.
 Vectors are torch tensors on the GPU (float64 or float32, contiguous,
 cell-major layout described in include/hpmg.h); work is enqueued on the
 current torch stream.  Importing this package fails loudly if the library
-has not been built (python -m paper_2510_00998_amd.build).
+has not been built (python paper_2510_00998_amd/csrc/build.py).
 """
 from __future__ import annotations
 
@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libhpmg.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "hpmg.h")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libhpmg.so not built at {LIB_PATH}; run `python -m paper_2510_00998_amd.build`")
+    raise ImportError(f"libhpmg.so not built at {LIB_PATH}; run `python paper_2510_00998_amd/csrc/build.py`")
 _lib = ctypes.CDLL(LIB_PATH)
 
 STATUS = {0: "HPMG_OK", 1: "HPMG_E_INVALID", 2: "HPMG_E_NOMEM", 3: "HPMG_E_DEVICE",
@@ -63,6 +63,10 @@ _lib.hpmg_apply_A.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]
 _lib.hpmg_apply_A.restype = ctypes.c_int
 _lib.hpmg_smooth.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
 _lib.hpmg_smooth.restype = ctypes.c_int
+_lib.hpmg_project.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp]
+_lib.hpmg_project.restype = ctypes.c_int
+_lib.hpmg_sweep.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+_lib.hpmg_sweep.restype = ctypes.c_int
 _lib.hpmg_vcycle.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]
 _lib.hpmg_vcycle.restype = ctypes.c_int
 _lib.hpmg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -184,6 +188,16 @@ class Solver:
     def smooth(self, u, b, nsweeps: int, nrhs: int = 1, stream=None):
         c = _code(u)
         _check(_lib.hpmg_smooth(self._h, c, _ptr(u, c), _ptr(b, c), nsweeps, nrhs, _stream(stream)), "hpmg_smooth")
+        return u
+
+    def project(self, u, nrhs: int = 1, stream=None):
+        c = _code(u)
+        _check(_lib.hpmg_project(self._h, c, _ptr(u, c), nrhs, _stream(stream)), "hpmg_project")
+        return u
+
+    def sweep(self, u, b, nsweeps: int = 1, nrhs: int = 1, stream=None):
+        c = _code(u)
+        _check(_lib.hpmg_sweep(self._h, c, _ptr(u, c), _ptr(b, c), nsweeps, nrhs, _stream(stream)), "hpmg_sweep")
         return u
 
     def vcycle(self, u, b, nrhs: int = 1, stream=None):

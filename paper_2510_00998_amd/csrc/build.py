@@ -1,6 +1,7 @@
 """Build libhpmg.so for gfx950 in-tree (hipcc, parallel object compilation).
 
-Usage: python -m paper_2510_00998_amd.build   (or call build_library()).
+Usage: python paper_2510_00998_amd/csrc/build.py
+Run as a script (it must not import the package, which loads the library).
 """
 from __future__ import annotations
 
@@ -9,9 +10,9 @@ import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
 
-PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.dirname(CSRC)
 ROOT = os.path.dirname(PKG)
-CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhpmg.so")

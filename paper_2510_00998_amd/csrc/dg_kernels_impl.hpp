@@ -42,28 +42,45 @@ __device__ __forceinline__ int ipow(int n, int k) {
   return k == 0 ? 1 : (k == 1 ? n : n * n);
 }
 
-// Stage the per-cell eigendata (S, Si = S^T M, lambda per axis) and facet
-// coefficients kappa_F (0 on boundary facets) of the block's cells.
-template <typename T, int D, int N>
+// Class of a cell along axis k for constant kappa: bit 0 = facet at the low
+// end is on the boundary, bit 1 = facet at the high end is.
+template <int D>
+__device__ __forceinline__ int axis_class(int c, int n, int k) {
+  const int x = (c / ipow<D>(n, k)) % n;
+  return (x == 0 ? 1 : 0) | (x == n - 1 ? 2 : 0);
+}
+
+// LDS size of the staged eigendata: constant kappa shares the 4 class
+// tables, variable kappa stages one set per cell and axis.
+template <int D, int N, bool VARK>
+struct EigLDS {
+  static constexpr int SIZE = VARK ? DGShape<D, N>::CPB * D * DGShape<D, N>::EGS : 4 * DGShape<D, N>::EGS;
+};
+
+// S | Si = S^T M | lambda of the cell (block slot cl, global index c) along k.
+template <typename T, int D, int N, bool VARK>
+__device__ __forceinline__ const T* eig_of(const T* sE, int cl, int c, int n, int k) {
+  using Sh = DGShape<D, N>;
+  if constexpr (VARK)
+    return sE + (cl * D + k) * Sh::EGS;
+  else
+    return sE + axis_class<D>(c, n, k) * Sh::EGS;
+}
+
+// Stage the eigendata and the facet coefficients kappa_F (0 on boundary
+// facets) of the block's cells.
+template <typename T, int D, int N, bool VARK>
 __device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int nc, T* sE, T* sKF) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   const int tid = threadIdx.x;
-  if (!a.vark) {
-    for (int i = tid; i < nc * D * Sh::EGS; i += Sh::NT) {
-      const int e = i % Sh::EGS;
-      const int ck = i / Sh::EGS;
-      const int k = ck % D, cl = ck / D;
-      const int c = c0 + cl;
-      const int x = (c / ipow<D>(a.n, k)) % a.n;
-      const int cls = (x == 0 ? 1 : 0) | (x == a.n - 1 ? 2 : 0);
-      sE[i] = a.eig[cls * Sh::EGS + e];
-    }
+  if constexpr (!VARK) {
+    for (int i = tid; i < 4 * Sh::EGS; i += Sh::NT) sE[i] = a.eig[i];
   } else {
     for (int i = tid; i < nc * D * (NN + N); i += Sh::NT) {
       const int e = i % (NN + N);
       const int ck = i / (NN + N);
-      const T v = a.eig[(size_t)(c0 + ck / D) * D * (NN + N) + (size_t)(ck % D) * (NN + N) + e];
+      const T v = a.eig[(size_t)c0 * D * (NN + N) + i];
       sE[ck * Sh::EGS + (e < NN ? e : NN + e)] = v;  // lambda goes after the Si slot
     }
   }
@@ -76,7 +93,7 @@ __device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int n
     const bool bdy = s ? (x == a.n - 1) : (x == 0);
     T kf = 0;
     if (!bdy) {
-      if (a.vark) {
+      if constexpr (VARK) {
         const T k0 = a.kappa[c], k1 = a.kappa[s ? c + st : c - st];
         kf = T(2) * k0 * k1 / (k0 + k1);
       } else {
@@ -130,8 +147,9 @@ __device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const 
 //   F1 = T_f (kappa_F (q'/2 - sigma_hat g')),  F2 = T_f (kappa_F g'/2),
 // T_f = G_t1 x G_t2 over the tangential axes with G_t = Si_t for t < k
 // (axes already transformed when facet k is processed) and Mhat otherwise.
-template <typename T, int D, int N>
-__device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int nc, T* sNB, const T* sE, const T* sKF) {
+template <typename T, int D, int N, bool VARK>
+__device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int c0, int nc, T* sNB, const T* sE,
+                                              const T* sKF) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
@@ -142,7 +160,7 @@ __device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int nc, T* sNB
       const int cl = i / Sh::NF, f = i % Sh::NF;
       const int k = f >> 1;
       const int t1 = 1 - k;
-      const T* G = (t1 < k) ? (sE + (cl * D + t1) * Sh::EGS + NN) : Mh;
+      const T* G = (t1 < k) ? (eig_of<T, D, N, VARK>(sE, cl, c0 + cl, a.n, t1) + NN) : Mh;
       T* g = sNB + (cl * Sh::NF + f) * 2 * L;
       const T kf = sKF[i];
       T al[N], be[N], o1[N], o2[N];
@@ -167,7 +185,7 @@ __device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int nc, T* sNB
       const int cl = cf / Sh::NF, f = cf % Sh::NF;
       const int k = f >> 1;
       const int t1 = (k == 0) ? 1 : 0;
-      const T* G = (t1 < k) ? (sE + (cl * D + t1) * Sh::EGS + NN) : Mh;
+      const T* G = (t1 < k) ? (eig_of<T, D, N, VARK>(sE, cl, c0 + cl, a.n, t1) + NN) : Mh;
       T* g = sNB + cf * 2 * L + N * i2;
       const T kf = sKF[cf];
       T al[N], be[N], o1[N], o2[N];
@@ -191,7 +209,7 @@ __device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int nc, T* sNB
       const int cl = cf / Sh::NF, f = cf % Sh::NF;
       const int k = f >> 1;
       const int t2 = (k == 2) ? 1 : 2;
-      const T* G = (t2 < k) ? (sE + (cl * D + t2) * Sh::EGS + NN) : Mh;
+      const T* G = (t2 < k) ? (eig_of<T, D, N, VARK>(sE, cl, c0 + cl, a.n, t2) + NN) : Mh;
       T* g = sNB + cf * 2 * L + i1;
       T x1[N], x2[N], o1[N], o2[N];
 #pragma unroll
@@ -256,8 +274,8 @@ __device__ __forceinline__ void line_traces(const DGArgs<T>& a, int cl, int k, i
   t1[L + ln] = d1;
 }
 
-// Traces of all axes but x from the staged cell vector, then coalesced
-// stores of the cell vector and of the traces of interior facets.
+// Traces of all axes but x from the staged cell vector sU, then coalesced
+// stores of the cell vector (if uout) and of the traces of interior facets.
 template <typename T, int D, int N>
 __device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int c0, int nc, const T* sU, T* sTR,
                                                         T* uout, T* trout) {
@@ -297,16 +315,16 @@ __device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int 
 // ---------------------------------------------------------------------------
 // Fused block-Jacobi sweep.  UZERO: u is identically zero on entry (first
 // sweep of a coarse-level smoothing with zero initial guess): u and the
-// neighbour traces are not read.
-template <typename T, int D, int N, bool UZERO>
+// neighbour traces are not read.  The x-line of u and b of each thread
+// stay in registers from the load to the update.
+template <typename T, int D, int N, bool UZERO, bool VARK>
 __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
-  __shared__ T sU[Sh::CPB * Sh::NV];
   __shared__ T sW[Sh::CPB * Sh::NV];
   __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
-  __shared__ T sE[Sh::CPB * D * Sh::EGS];
+  __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
   __shared__ T sKF[Sh::CPB * Sh::NF];
 
   const int c0 = blockIdx.x * Sh::CPB;
@@ -315,56 +333,59 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
   const int tid = threadIdx.x;
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
+  const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
 
-  {
-    const T* bs = a.b + rv + (size_t)c0 * Sh::NV;
-    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sW[i] = bs[i];
+  T ul[N], bl[N];
+  if (act) {
+    const T* bs = a.b + rv + (size_t)c0 * Sh::NV + base0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) bl[j] = bs[j];
     if (!UZERO) {
-      const T* us = a.u_in + rv + (size_t)c0 * Sh::NV;
-      for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = us[i];
-      load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
+      const T* us = a.u_in + rv + (size_t)c0 * Sh::NV + base0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) ul[j] = us[j];
     }
-    load_cell_data<T, D, N>(a, c0, nc, sE, sKF);
   }
+  if (!UZERO) load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
+  load_cell_data<T, D, N, VARK>(a, c0, nc, sE, sKF);
   __syncthreads();
-  if (a.vark) {
+  if constexpr (VARK) {
     make_si<T, D, N>(a, nc, sE);
     __syncthreads();
   }
-  if (!UZERO) facet_prepass<T, D, N>(a, nc, sNB, sE, sKF);
+  if (!UZERO) facet_prepass<T, D, N, VARK>(a, c0, nc, sNB, sE, sKF);
 
+  const int cc = c0 + (cl < nc ? cl : 0);
   // forward transforms S^T along x, y(, z) with the facet lifts subtracted
   // just before each axis is transformed
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     if (act) {
       const int base = cl * Sh::NV + line_base<D, N>(k, ln);
-      constexpr int dummy = 0;
-      (void)dummy;
       T r[N], t[N];
-#pragma unroll
-      for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       if (k == 0) {
 #pragma unroll
-        for (int j = 0; j < N; ++j) r[j] *= a.h_fwd;
+        for (int j = 0; j < N; ++j) r[j] = a.h_fwd * bl[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
       if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
-      const T* Ek = sE + (cl * D + k) * Sh::EGS;
+      const T* Ek = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k);
       mv<N, true>(Ek, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
-        const T* l0 = sE + (cl * D + 0) * Sh::EGS + 2 * NN;
-        const T* l1 = sE + (cl * D + 1) * Sh::EGS + 2 * NN;
-        T lsum;
+        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 0) + 2 * NN;
+        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 1) + 2 * NN;
         if constexpr (D == 2) {
-          lsum = l0[ln];
+          const T ls = l0[ln];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] /= (lsum + l1[j]);
+          for (int j = 0; j < N; ++j) t[j] /= (ls + l1[j]);
         } else {
-          const T* l2 = sE + (cl * D + 2) * Sh::EGS + 2 * NN;
-          lsum = l0[ln % N] + l1[ln / N];
+          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 2) + 2 * NN;
+          const T ls = l0[ln % N] + l1[ln / N];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] /= (lsum + l2[j]);
+          for (int j = 0; j < N; ++j) t[j] /= (ls + l2[j]);
         }
         mv<N, false>(Ek, t, r);  // S
 #pragma unroll
@@ -375,8 +396,8 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
     }
     __syncthreads();
   }
-  // inverse transforms S along the remaining axes, last one fused with the
-  // update and the x-facet traces
+  // inverse transforms S along the remaining axes; the last one is fused
+  // with the update, the store of u and the x-facet traces
   T* sTR = sNB;  // the flux fields are consumed; reuse as trace staging
 #pragma unroll
   for (int k = D - 2; k >= 0; --k) {
@@ -385,13 +406,15 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
       T r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      mv<N, false>(sE + (cl * D + k) * Sh::EGS, r, t);
+      mv<N, false>(eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k), r, t);
       if (k == 0) {
+        T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          const T uo = UZERO ? T(0) : sU[base + j];
-          t[j] = (T(1) - a.omega) * uo + a.omega * t[j];
-          sU[base + j] = t[j];
+          const T uo0 = UZERO ? T(0) : ul[j];
+          t[j] = (T(1) - a.omega) * uo0 + a.omega * t[j];
+          sW[base + j] = t[j];
+          uo[j] = t[j];
         }
         line_traces<T, D, N>(a, cl, 0, ln, t, sTR);
       } else {
@@ -401,7 +424,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
     }
     __syncthreads();
   }
-  finish_traces_and_store<T, D, N>(a, c0, nc, sU, sTR, a.u_out + rv, a.tr_out + rt);
+  finish_traces_and_store<T, D, N>(a, c0, nc, sW, sTR, nullptr, a.tr_out + rt);
 }
 
 // ---------------------------------------------------------------------------
@@ -410,15 +433,14 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
 // from the coarse nodes (DG_q: a coarse cell vector; Q1: the 2^d corner
 // contributions of each cell, summed over cells by the gather kernel).
 // Needs the traces of u in tr_in.
-template <typename T, int D, int N, int NC, bool RESID>
+template <typename T, int D, int N, int NC, bool RESID, bool VARK>
 __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
-  __shared__ T sU[Sh::CPB * Sh::NV];
   __shared__ T sW[Sh::CPB * Sh::NV];
   __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
-  __shared__ T sE[Sh::CPB * D * Sh::EGS];
+  __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
   __shared__ T sKF[Sh::CPB * Sh::NF];
 
   const int c0 = blockIdx.x * Sh::CPB;
@@ -427,20 +449,29 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
   const int tid = threadIdx.x;
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
+  const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
 
-  {
-    const T* us = a.u_in + rv + (size_t)c0 * Sh::NV;
-    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = us[i];
-    load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
-    load_cell_data<T, D, N>(a, c0, nc, sE, sKF);
+  T ul[N], bl[N];
+  if (act) {
+    const T* us = a.u_in + rv + (size_t)c0 * Sh::NV + base0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) ul[j] = us[j];
+    if (RESID) {
+      const T* bs = a.b + rv + (size_t)c0 * Sh::NV + base0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) bl[j] = bs[j];
+    }
   }
+  load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
+  load_cell_data<T, D, N, VARK>(a, c0, nc, sE, sKF);
   __syncthreads();
-  if (a.vark) {
+  if constexpr (VARK) {
     make_si<T, D, N>(a, nc, sE);
     __syncthreads();
   }
-  facet_prepass<T, D, N>(a, nc, sNB, sE, sKF);
+  facet_prepass<T, D, N, VARK>(a, c0, nc, sNB, sE, sKF);
 
+  const int cc = c0 + (cl < nc ? cl : 0);
   // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
   // lifts added right after each axis is transformed back.
 #pragma unroll
@@ -448,20 +479,24 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
     if (act) {
       const int base = cl * Sh::NV + line_base<D, N>(k, ln);
       T r[N], t[N];
-      const T* src = (k == 0) ? sU : sW;
+      if (k == 0) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) r[j] = src[base + j * line_stride<N>(k)];
-      const T* Ek = sE + (cl * D + k) * Sh::EGS;
+        for (int j = 0; j < N; ++j) r[j] = ul[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
+      }
+      const T* Ek = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k);
       mv<N, false>(Ek + NN, r, t);  // Si
       if (k == D - 1) {
-        const T* l0 = sE + (cl * D + 0) * Sh::EGS + 2 * NN;
-        const T* l1 = sE + (cl * D + 1) * Sh::EGS + 2 * NN;
+        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 0) + 2 * NN;
+        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 1) + 2 * NN;
         if constexpr (D == 2) {
           const T ls = l0[ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + l1[j]);
         } else {
-          const T* l2 = sE + (cl * D + 2) * Sh::EGS + 2 * NN;
+          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 2) + 2 * NN;
           const T ls = l0[ln % N] + l1[ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + l2[j]);
@@ -476,11 +511,6 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
     }
     __syncthreads();
   }
-  if (RESID) {  // sU is free now: stage b for the final axis
-    const T* bs = a.b + rv + (size_t)c0 * Sh::NV;
-    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = bs[i];
-  }
-  __syncthreads();
 #pragma unroll
   for (int k = D - 2; k >= 0; --k) {
     if (act) {
@@ -488,29 +518,37 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
       T r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      mv<N, true>(sE + (cl * D + k) * Sh::EGS + NN, r, t);
+      mv<N, true>(eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k) + NN, r, t);
       add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, t);
       if (k == 0) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           t[j] *= a.h_apply;
-          if (RESID) t[j] = sU[base + j] - t[j];
+          if (RESID) t[j] = bl[j] - t[j];
         }
-      }
+        if constexpr (NC == 0) {
+          T* dst = a.out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
-      for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
+          for (int j = 0; j < N; ++j) dst[j] = t[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < N; ++j) sW[base + j] = t[j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
+      }
     }
     __syncthreads();
   }
-  if constexpr (NC == 0) {
-    T* dst = a.out + rv + (size_t)c0 * Sh::NV;
-    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) dst[i] = sW[i];
-  } else {
-    // restriction (E^T)^(x d) of the cell residual, one axis per pass
+  if constexpr (NC > 0) {
+    // restriction (E^T)^(x d) of the cell residual, one axis per pass; sNB
+    // is free once every lift has been read (barrier above)
     const T* E = a.ref + RefOff<N>::E;
     constexpr int NCD = (D == 2) ? NC * NC : NC * NC * NC;
+    constexpr int NBS = Sh::NF * 2 * L;  // per-cell stride of sNB
     T* dst = a.out + (size_t)blockIdx.y * a.cstride + (size_t)c0 * NCD;
-    // x: sW[cl][..][a] -> sU[cl][..][a'] (a' + NC*ln)
+    // x: sW[cl][..][a] -> sNB[cl][ln][a'] (a' + NC*ln)
     for (int i = tid; i < nc * L; i += Sh::NT) {
       const int c2 = i / L, l2 = i % L;
       T x[N];
@@ -521,17 +559,17 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
         T s = 0;
 #pragma unroll
         for (int j = 0; j < N; ++j) s += E[j * NC + jc] * x[j];
-        sU[c2 * Sh::NV + jc + NC * l2] = s;
+        sNB[c2 * NBS + jc + NC * l2] = s;
       }
     }
     __syncthreads();
     if constexpr (D == 2) {
-      // y: sU[cl][b][a'] -> dst[a' + NC b']
+      // y: sNB[cl][b][a'] -> dst[a' + NC b']
       for (int i = tid; i < nc * NC; i += Sh::NT) {
         const int c2 = i / NC, ac = i % NC;
         T x[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = sU[c2 * Sh::NV + ac + NC * j];
+        for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + NC * j];
 #pragma unroll
         for (int bc = 0; bc < NC; ++bc) {
           T s = 0;
@@ -541,13 +579,13 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
         }
       }
     } else {
-      // y: sU[cl][c][b][a'] (a' + NC(b + N c)) -> sW[cl][c][b'][a'] (a' + NC(b' + NC c))
+      // y: sNB[cl][c][b][a'] (a' + NC(b + N c)) -> sW[cl][c][b'][a'] (a' + NC(b' + NC c))
       for (int i = tid; i < nc * NC * N; i += Sh::NT) {
         const int c2 = i / (NC * N), rem = i % (NC * N);
         const int ac = rem % NC, cz = rem / NC;
         T x[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = sU[c2 * Sh::NV + ac + NC * (j + N * cz)];
+        for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + NC * (j + N * cz)];
 #pragma unroll
         for (int bc = 0; bc < NC; ++bc) {
           T s = 0;
@@ -564,11 +602,11 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
 #pragma unroll
         for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + rem + NC * NC * j];
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
+        for (int ccz = 0; ccz < NC; ++ccz) {
           T s = 0;
 #pragma unroll
-          for (int j = 0; j < N; ++j) s += E[j * NC + cc] * x[j];
-          dst[(size_t)c2 * NCD + rem + NC * NC * cc] = s;
+          for (int j = 0; j < N; ++j) s += E[j * NC + ccz] * x[j];
+          dst[(size_t)c2 * NCD + rem + NC * NC * ccz] = s;
         }
       }
     }
@@ -716,20 +754,34 @@ template <typename T, int D, int N>
 void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s) {
   using Sh = DGShape<D, N>;
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
-  if (uzero)
-    hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true>), grid, dim3(Sh::NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false>), grid, dim3(Sh::NT), 0, s, a);
+  if (a.vark) {
+    if (uzero)
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, true>), grid, dim3(Sh::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, true>), grid, dim3(Sh::NT), 0, s, a);
+  } else {
+    if (uzero)
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, false>), grid, dim3(Sh::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, false>), grid, dim3(Sh::NT), 0, s, a);
+  }
 }
 
 template <typename T, int D, int N, int NC>
 void launch_apply(const DGArgs<T>& a, int nrhs, bool resid, hipStream_t s) {
   using Sh = DGShape<D, N>;
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
-  if (resid)
-    hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true>), grid, dim3(Sh::NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false>), grid, dim3(Sh::NT), 0, s, a);
+  if (a.vark) {
+    if (resid)
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, true>), grid, dim3(Sh::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, true>), grid, dim3(Sh::NT), 0, s, a);
+  } else {
+    if (resid)
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, false>), grid, dim3(Sh::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, false>), grid, dim3(Sh::NT), 0, s, a);
+  }
 }
 
 template <typename T, int D, int N, int NC>

@@ -131,6 +131,10 @@ struct hpmg_ctx {
   float *r32 = nullptr, *z32 = nullptr;
   double *partial = nullptr, *scal = nullptr;
   double* host_scal = nullptr;  // pinned
+  // which level-0 trace buffer holds the traces of the caller's u after
+  // hpmg_project / hpmg_smooth / hpmg_sweep (-1: none), per dtype
+  int trace_state[2] = {-1, -1};
+  int trace_rhs[2] = {0, 0};
   DevMem mem;
   ~hpmg_ctx() {
     if (host_scal) (void)hipHostFree(host_scal);
@@ -865,6 +869,7 @@ hpmg_status hpmg_apply_A(hpmg_handle h, hpmg_dtype dtype, const void* u, void* y
     require(nrhs >= 1 && nrhs <= h->opt.max_rhs, "nrhs out of range");
     require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
     require(u != y, "u and y must not overlap");
+    h->trace_state[dtype] = -1;
     if (dtype == HPMG_F64) {
       project<double>(h, 0, (const double*)u, h->dg[0].d.tr[0], nrhs, stream);
       apply<double>(h, 0, (const double*)u, h->dg[0].d.tr[0], nullptr, (double*)y, nrhs, stream);
@@ -886,6 +891,7 @@ hpmg_status hpmg_smooth(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
     require(nsweeps >= 0, "nsweeps must be >= 0");
     require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
     if (nsweeps == 0) return HPMG_OK;
+    h->trace_state[dtype] = -1;
     if (dtype == HPMG_F64) {
       DGData<double>& d = h->dg[0].d;
       project<double>(h, 0, (const double*)u, d.tr[0], nrhs, stream);
@@ -897,6 +903,52 @@ hpmg_status hpmg_smooth(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
       for (int k = 0; k < nsweeps; ++k)
         sweep<float>(h, 0, (float*)u, (const float*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
     }
+    h->trace_state[dtype] = nsweeps & 1;
+    h->trace_rhs[dtype] = nrhs;
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+hpmg_status hpmg_project(hpmg_handle h, hpmg_dtype dtype, const void* u, int nrhs, hipStream_t stream) {
+  try {
+    require(h && u, "NULL argument");
+    require(nrhs >= 1 && nrhs <= h->opt.max_rhs, "nrhs out of range");
+    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    h->trace_state[dtype] = -1;
+    if (dtype == HPMG_F64)
+      project<double>(h, 0, (const double*)u, h->dg[0].d.tr[0], nrhs, stream);
+    else
+      project<float>(h, 0, (const float*)u, h->dg[0].f.tr[0], nrhs, stream);
+    h->trace_state[dtype] = 0;
+    h->trace_rhs[dtype] = nrhs;
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+hpmg_status hpmg_sweep(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nsweeps, int nrhs,
+                       hipStream_t stream) {
+  try {
+    require(h && u && b, "NULL argument");
+    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    require(nsweeps >= 0, "nsweeps must be >= 0");
+    require(h->trace_state[dtype] >= 0, "no current traces: call hpmg_project first");
+    require(nrhs == h->trace_rhs[dtype], "nrhs differs from the call that produced the traces");
+    int cur = h->trace_state[dtype];
+    for (int k = 0; k < nsweeps; ++k) {
+      if (dtype == HPMG_F64) {
+        DGData<double>& d = h->dg[0].d;
+        sweep<double>(h, 0, (double*)u, (const double*)b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, stream);
+      } else {
+        DGData<float>& d = h->dg[0].f;
+        sweep<float>(h, 0, (float*)u, (const float*)b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, stream);
+      }
+      cur ^= 1;
+    }
+    h->trace_state[dtype] = cur;
     return HPMG_OK;
   } catch (const HpmgError& e) {
     return fail(e);
@@ -908,6 +960,7 @@ hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
     require(h && u && b, "NULL argument");
     require(nrhs == 1, "vcycle supports nrhs == 1");
     require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    h->trace_state[dtype] = -1;
     if (dtype == HPMG_F64)
       vcycle_dg<double>(h, 0, (double*)u, (const double*)b, false, stream);
     else
@@ -925,6 +978,7 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
     require(nrhs >= 1, "nrhs must be >= 1");
     require(rtol > 0.0 && maxit >= 1, "bad rtol/maxit");
     const auto t0 = std::chrono::steady_clock::now();
+    h->trace_state[0] = h->trace_state[1] = -1;
     const size_t nd = h->ndof;
     DGData<double>& d = h->dg[0].d;
     hpmg_status result = HPMG_OK;
