@@ -25,9 +25,18 @@ __device__ __forceinline__ constexpr int line_stride(int k) {
   return k == 0 ? 1 : (k == 1 ? N : N * N);
 }
 
+// Read-only data addressed uniformly across a wave: the constant address
+// space lets the compiler fetch it with scalar loads into SGPRs.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
 // out = G in, G row-major N x N (TR: G^T)
-template <int N, bool TR, typename T>
-__device__ __forceinline__ void mv(const T* __restrict__ G, const T (&in)[N], T (&out)[N]) {
+template <int N, bool TR, typename T, typename P>
+__device__ __forceinline__ void mv(P G, const T (&in)[N], T (&out)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T s = 0;
@@ -121,6 +130,31 @@ __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
   }
 }
 
+// Matrix of (cell, axis k) at offset `off` within its S | Si | lambda record,
+// applied to a line (TR: transposed).  Constant kappa: when every active
+// lane of the wave needs the same boundary class the record is read from
+// the global class table with scalar loads, else from the LDS copy.
+template <typename T, int D, int N, bool VARK, bool TR>
+__device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const T* sE, int cl, int c, int k, int off,
+                                         const T (&in)[N], T (&out)[N]) {
+  using Sh = DGShape<D, N>;
+  // matrices that fit in about 72 SGPRs take the scalar path
+  constexpr bool SCALAR_OK = N * N * (int)sizeof(T) / 4 <= 72;
+  if constexpr (VARK || !SCALAR_OK) {
+    if constexpr (VARK)
+      mv<N, TR>(sE + (cl * D + k) * Sh::EGS + off, in, out);
+    else
+      mv<N, TR>(sE + axis_class<D>(c, a.n, k) * Sh::EGS + off, in, out);
+  } else {
+    const int cls = axis_class<D>(c, a.n, k);
+    const int c0 = __builtin_amdgcn_readfirstlane(cls);
+    if (__all(cls == c0))
+      mv<N, TR>(as_const(a.eig) + c0 * Sh::EGS + off, in, out);
+    else
+      mv<N, TR>(sE + cls * Sh::EGS + off, in, out);
+  }
+}
+
 // Neighbour traces of the block's cells: sNB[cl][f][field][L] = traces the
 // neighbour across facet f wrote on its facet f^1 (zeros on the boundary).
 template <typename T, int D, int N>
@@ -147,82 +181,58 @@ __device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const 
 //   F1 = T_f (kappa_F (q'/2 - sigma_hat g')),  F2 = T_f (kappa_F g'/2),
 // T_f = G_t1 x G_t2 over the tangential axes with G_t = Si_t for t < k
 // (axes already transformed when facet k is processed) and Mhat otherwise.
+// Work items are ordered (facet, cell, line) so that a wave mostly sees one
+// facet direction and one matrix.
 template <typename T, int D, int N, bool VARK>
 __device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int c0, int nc, T* sNB, const T* sE,
                                               const T* sKF) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
-  const T* Mh = a.ref + RefOff<N>::M;
+  const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
   const int tid = threadIdx.x;
-  if constexpr (D == 2) {
-    for (int i = tid; i < nc * Sh::NF; i += Sh::NT) {
-      const int cl = i / Sh::NF, f = i % Sh::NF;
+  constexpr int LINES = (D == 2) ? 1 : N;  // lines per facet and pass
+  for (int pass = 0; pass < (D == 2 ? 1 : 2); ++pass) {
+    for (int i = tid; i < nc * Sh::NF * LINES; i += Sh::NT) {
+      const int f = i / (nc * LINES), rem = i % (nc * LINES);
+      const int cl = rem / LINES, li = rem % LINES;
       const int k = f >> 1;
-      const int t1 = 1 - k;
-      const T* G = (t1 < k) ? (eig_of<T, D, N, VARK>(sE, cl, c0 + cl, a.n, t1) + NN) : Mh;
-      T* g = sNB + (cl * Sh::NF + f) * 2 * L;
-      const T kf = sKF[i];
-      T al[N], be[N], o1[N], o2[N];
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        al[j] = kf * (T(0.5) * g[L + j] - a.sigma_hat * g[j]);
-        be[j] = T(0.5) * kf * g[j];
-      }
-      mv<N, false>(G, al, o1);
-      mv<N, false>(G, be, o2);
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        g[j] = o1[j];
-        g[L + j] = o2[j];
-      }
-    }
-    __syncthreads();
-  } else {
-    // pass A: along the first tangential axis (stride 1 in the facet index)
-    for (int i = tid; i < nc * Sh::NF * N; i += Sh::NT) {
-      const int i2 = i % N, cf = i / N;
-      const int cl = cf / Sh::NF, f = cf % Sh::NF;
-      const int k = f >> 1;
-      const int t1 = (k == 0) ? 1 : 0;
-      const T* G = (t1 < k) ? (eig_of<T, D, N, VARK>(sE, cl, c0 + cl, a.n, t1) + NN) : Mh;
-      T* g = sNB + cf * 2 * L + N * i2;
-      const T kf = sKF[cf];
-      T al[N], be[N], o1[N], o2[N];
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        al[j] = kf * (T(0.5) * g[L + j] - a.sigma_hat * g[j]);
-        be[j] = T(0.5) * kf * g[j];
-      }
-      mv<N, false>(G, al, o1);
-      mv<N, false>(G, be, o2);
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        g[j] = o1[j];
-        g[L + j] = o2[j];
-      }
-    }
-    __syncthreads();
-    // pass B: along the second tangential axis (stride N)
-    for (int i = tid; i < nc * Sh::NF * N; i += Sh::NT) {
-      const int i1 = i % N, cf = i / N;
-      const int cl = cf / Sh::NF, f = cf % Sh::NF;
-      const int k = f >> 1;
-      const int t2 = (k == 2) ? 1 : 2;
-      const T* G = (t2 < k) ? (eig_of<T, D, N, VARK>(sE, cl, c0 + cl, a.n, t2) + NN) : Mh;
-      T* g = sNB + cf * 2 * L + i1;
+      int t;
+      if constexpr (D == 2)
+        t = 1 - k;
+      else
+        t = pass == 0 ? ((k == 0) ? 1 : 0) : ((k == 2) ? 1 : 2);
+      // pass 0 runs along the first tangential axis (stride 1), pass 1 along
+      // the second (stride N)
+      const int st = pass == 0 ? 1 : N;
+      T* g = sNB + (cl * Sh::NF + f) * 2 * L + (pass == 0 ? N * li : li);
       T x1[N], x2[N], o1[N], o2[N];
+      if (pass == 0) {
+        const T kf = sKF[cl * Sh::NF + f];
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        x1[j] = g[N * j];
-        x2[j] = g[L + N * j];
+        for (int j = 0; j < N; ++j) {
+          const T gv = g[j], qv = g[L + j];
+          x1[j] = kf * (T(0.5) * qv - a.sigma_hat * gv);
+          x2[j] = T(0.5) * kf * gv;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          x1[j] = g[st * j];
+          x2[j] = g[L + st * j];
+        }
       }
-      mv<N, false>(G, x1, o1);
-      mv<N, false>(G, x2, o2);
+      if (t < k) {
+        stage_mv<T, D, N, VARK, false>(a, sE, cl, c0 + cl, t, NN, x1, o1);
+        stage_mv<T, D, N, VARK, false>(a, sE, cl, c0 + cl, t, NN, x2, o2);
+      } else {
+        mv<N, false>(Mh, x1, o1);
+        mv<N, false>(Mh, x2, o2);
+      }
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        g[N * j] = o1[j];
-        g[L + N * j] = o2[j];
+        g[st * j] = o1[j];
+        g[L + st * j] = o2[j];
       }
     }
     __syncthreads();
@@ -235,8 +245,8 @@ template <typename T, int D, int N, int SIGN>
 __device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int ln, const T* sNB, T (&r)[N]) {
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
-  const T* ep0 = a.ref + RefOff<N>::EP0;
-  const T* ep1 = a.ref + RefOff<N>::EP1;
+  const cptr<T> ep0 = as_const(a.ref) + RefOff<N>::EP0;
+  const cptr<T> ep1 = as_const(a.ref) + RefOff<N>::EP1;
   const T* f0 = sNB + (cl * Sh::NF + 2 * k) * 2 * L;
   const T* f1 = f0 + 2 * L;
   const T v0 = f0[ln], d0 = f0[L + ln], v1 = f1[ln], d1 = f1[L + ln];
@@ -258,8 +268,8 @@ template <typename T, int D, int N>
 __device__ __forceinline__ void line_traces(const DGArgs<T>& a, int cl, int k, int ln, const T (&u)[N], T* sTR) {
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
-  const T* ep0 = a.ref + RefOff<N>::EP0;
-  const T* ep1 = a.ref + RefOff<N>::EP1;
+  const cptr<T> ep0 = as_const(a.ref) + RefOff<N>::EP0;
+  const cptr<T> ep1 = as_const(a.ref) + RefOff<N>::EP1;
   T d0 = 0, d1 = 0;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -371,8 +381,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
       if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
-      const T* Ek = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k);
-      mv<N, true>(Ek, r, t);  // S^T
+      stage_mv<T, D, N, VARK, true>(a, sE, cl, cc, k, 0, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
         const T* l0 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 0) + 2 * NN;
@@ -387,7 +396,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] /= (ls + l2[j]);
         }
-        mv<N, false>(Ek, t, r);  // S
+        stage_mv<T, D, N, VARK, false>(a, sE, cl, cc, k, 0, t, r);  // S
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
       }
@@ -406,7 +415,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
       T r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      mv<N, false>(eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k), r, t);
+      stage_mv<T, D, N, VARK, false>(a, sE, cl, cc, k, 0, r, t);
       if (k == 0) {
         T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
@@ -486,8 +495,7 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
-      const T* Ek = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k);
-      mv<N, false>(Ek + NN, r, t);  // Si
+      stage_mv<T, D, N, VARK, false>(a, sE, cl, cc, k, NN, r, t);  // Si
       if (k == D - 1) {
         const T* l0 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 0) + 2 * NN;
         const T* l1 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 1) + 2 * NN;
@@ -501,7 +509,7 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + l2[j]);
         }
-        mv<N, true>(Ek + NN, t, r);  // Si^T
+        stage_mv<T, D, N, VARK, true>(a, sE, cl, cc, k, NN, t, r);  // Si^T
         add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, r);
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
@@ -518,7 +526,7 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
       T r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      mv<N, true>(eig_of<T, D, N, VARK>(sE, cl, cc, a.n, k) + NN, r, t);
+      stage_mv<T, D, N, VARK, true>(a, sE, cl, cc, k, NN, r, t);
       add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, t);
       if (k == 0) {
 #pragma unroll
@@ -544,7 +552,7 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
   if constexpr (NC > 0) {
     // restriction (E^T)^(x d) of the cell residual, one axis per pass; sNB
     // is free once every lift has been read (barrier above)
-    const T* E = a.ref + RefOff<N>::E;
+    const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
     constexpr int NCD = (D == 2) ? NC * NC : NC * NC * NC;
     constexpr int NBS = Sh::NF * 2 * L;  // per-cell stride of sNB
     T* dst = a.out + (size_t)blockIdx.y * a.cstride + (size_t)c0 * NCD;
@@ -662,7 +670,7 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
   }
   __syncthreads();
   if constexpr (NC > 0) {
-    const T* E = a.ref + RefOff<N>::E;
+    const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
     if constexpr (D == 3) {
       // z: [c'][b'][a'] -> sNB[cl][c][b'][a'] (a' + NC b' + NC^2 c)
       for (int i = tid; i < nc * NC * NC; i += Sh::NT) {
@@ -728,7 +736,7 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
 #pragma unroll
     for (int j = 0; j < N; ++j) u[j] = sU[base + j];
     if constexpr (NC > 0) {
-      const T* E = a.ref + RefOff<N>::E;
+      const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
       T x[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) x[j] = sW[cl * Sh::NV + j + NC * ln];
