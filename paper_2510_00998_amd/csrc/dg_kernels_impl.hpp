@@ -51,13 +51,47 @@ __device__ __forceinline__ int ipow(int n, int k) {
   return k == 0 ? 1 : (k == 1 ? n : n * n);
 }
 
+// Per-cell info staged in LDS once per block: [0] boundary mask (bit f set:
+// facet f = 2k + side lies on the domain boundary), [1..3] cell coordinates.
+// Everything else derives the boundary status from it, so the kernels divide
+// by the runtime mesh size only here.
+constexpr int INFO = 4;
+template <int D, int N>
+__device__ __forceinline__ void fill_cell_info(int n, int c0, int nc, int* sInfo) {
+  const int t = threadIdx.x;
+  if (t < nc) {
+    const int c = c0 + t;
+    int x[3];
+    x[0] = c % n;
+    const int r = c / n;
+    x[1] = (D == 2) ? r : r % n;
+    x[2] = (D == 2) ? 0 : r / n;
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) m |= (x[k] == 0 ? 1 : 0) << (2 * k) | (x[k] == n - 1 ? 2 : 0) << (2 * k);
+    sInfo[INFO * t + 0] = m;
+    sInfo[INFO * t + 1] = x[0];
+    sInfo[INFO * t + 2] = x[1];
+    sInfo[INFO * t + 3] = x[2];
+  }
+}
+
+// 1/d: hardware reciprocal refined by Newton steps (two for double, one for
+// float) to full precision.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  return r;
+}
+__device__ __forceinline__ float recip(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  return __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
+}
+
 // Class of a cell along axis k for constant kappa: bit 0 = facet at the low
 // end is on the boundary, bit 1 = facet at the high end is.
-template <int D>
-__device__ __forceinline__ int axis_class(int c, int n, int k) {
-  const int x = (c / ipow<D>(n, k)) % n;
-  return (x == 0 ? 1 : 0) | (x == n - 1 ? 2 : 0);
-}
+__device__ __forceinline__ int axis_class(int mask, int k) { return (mask >> (2 * k)) & 3; }
 
 // LDS size of the staged eigendata: constant kappa shares the 4 class
 // tables, variable kappa stages one set per cell and axis.
@@ -68,18 +102,19 @@ struct EigLDS {
 
 // S | Si = S^T M | lambda of the cell (block slot cl, global index c) along k.
 template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ const T* eig_of(const T* sE, int cl, int c, int n, int k) {
+__device__ __forceinline__ const T* eig_of(const T* sE, int cl, int mask, int k) {
   using Sh = DGShape<D, N>;
   if constexpr (VARK)
     return sE + (cl * D + k) * Sh::EGS;
   else
-    return sE + axis_class<D>(c, n, k) * Sh::EGS;
+    return sE + axis_class(mask, k) * Sh::EGS;
 }
 
 // Stage the eigendata and the facet coefficients kappa_F (0 on boundary
 // facets) of the block's cells.
 template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int nc, T* sE, T* sKF) {
+__device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int nc, const int* sInfo, T* sE,
+                                               T* sKF) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   const int tid = threadIdx.x;
@@ -98,8 +133,7 @@ __device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int n
     const int k = f >> 1, s = f & 1;
     const int c = c0 + cl;
     const int st = ipow<D>(a.n, k);
-    const int x = (c / st) % a.n;
-    const bool bdy = s ? (x == a.n - 1) : (x == 0);
+    const bool bdy = (sInfo[INFO * cl] >> f) & 1;
     T kf = 0;
     if (!bdy) {
       if constexpr (VARK) {
@@ -135,7 +169,7 @@ __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
 // lane of the wave needs the same boundary class the record is read from
 // the global class table with scalar loads, else from the LDS copy.
 template <typename T, int D, int N, bool VARK, bool TR>
-__device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const T* sE, int cl, int c, int k, int off,
+__device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const T* sE, int cl, int mask, int k, int off,
                                          const T (&in)[N], T (&out)[N]) {
   using Sh = DGShape<D, N>;
   // matrices that fit in about 72 SGPRs take the scalar path
@@ -144,9 +178,9 @@ __device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const T* sE, int cl
     if constexpr (VARK)
       mv<N, TR>(sE + (cl * D + k) * Sh::EGS + off, in, out);
     else
-      mv<N, TR>(sE + axis_class<D>(c, a.n, k) * Sh::EGS + off, in, out);
+      mv<N, TR>(sE + axis_class(mask, k) * Sh::EGS + off, in, out);
   } else {
-    const int cls = axis_class<D>(c, a.n, k);
+    const int cls = axis_class(mask, k);
     const int c0 = __builtin_amdgcn_readfirstlane(cls);
     if (__all(cls == c0))
       mv<N, TR>(as_const(a.eig) + c0 * Sh::EGS + off, in, out);
@@ -158,7 +192,8 @@ __device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const T* sE, int cl
 // Neighbour traces of the block's cells: sNB[cl][f][field][L] = traces the
 // neighbour across facet f wrote on its facet f^1 (zeros on the boundary).
 template <typename T, int D, int N>
-__device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc, T* sNB) {
+__device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc,
+                                                      const int* sInfo, T* sNB) {
   using Sh = DGShape<D, N>;
   constexpr int TL = 2 * Sh::L;
   const int tid = threadIdx.x;
@@ -167,11 +202,11 @@ __device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const 
     const int st = ipow<D>(a.n, k);
     const int off = s ? st : -st;
     const T* src = tr + (size_t)(f ^ 1) * a.ncell * TL;
+    (void)k;
     for (int i = tid; i < nc * TL; i += Sh::NT) {
       const int cl = i / TL, e = i % TL;
       const int c = c0 + cl;
-      const int x = (c / st) % a.n;
-      const bool bdy = s ? (x == a.n - 1) : (x == 0);
+      const bool bdy = (sInfo[INFO * cl] >> f) & 1;
       sNB[(cl * Sh::NF + f) * TL + e] = bdy ? T(0) : src[(size_t)(c + off) * TL + e];
     }
   }
@@ -184,7 +219,7 @@ __device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const 
 // Work items are ordered (facet, cell, line) so that a wave mostly sees one
 // facet direction and one matrix.
 template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int c0, int nc, T* sNB, const T* sE,
+__device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int nc, const int* sInfo, T* sNB, const T* sE,
                                               const T* sKF) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
@@ -223,8 +258,9 @@ __device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int c0, int nc
         }
       }
       if (t < k) {
-        stage_mv<T, D, N, VARK, false>(a, sE, cl, c0 + cl, t, NN, x1, o1);
-        stage_mv<T, D, N, VARK, false>(a, sE, cl, c0 + cl, t, NN, x2, o2);
+        const int mk = sInfo[INFO * cl];
+        stage_mv<T, D, N, VARK, false>(a, sE, cl, mk, t, NN, x1, o1);
+        stage_mv<T, D, N, VARK, false>(a, sE, cl, mk, t, NN, x2, o2);
       } else {
         mv<N, false>(Mh, x1, o1);
         mv<N, false>(Mh, x2, o2);
@@ -287,8 +323,8 @@ __device__ __forceinline__ void line_traces(const DGArgs<T>& a, int cl, int k, i
 // Traces of all axes but x from the staged cell vector sU, then coalesced
 // stores of the cell vector (if uout) and of the traces of interior facets.
 template <typename T, int D, int N>
-__device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int c0, int nc, const T* sU, T* sTR,
-                                                        T* uout, T* trout) {
+__device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int c0, int nc, const int* sInfo,
+                                                        const T* sU, T* sTR, T* uout, T* trout) {
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
   constexpr int TL = 2 * L;
@@ -310,13 +346,10 @@ __device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int 
     for (int i = tid; i < nc * Sh::NV; i += Sh::NT) dst[i] = sU[i];
   }
   for (int f = 0; f < Sh::NF; ++f) {
-    const int k = f >> 1, s = f & 1;
-    const int st = ipow<D>(a.n, k);
     T* dst = trout + ((size_t)f * a.ncell + c0) * TL;
     for (int i = tid; i < nc * TL; i += Sh::NT) {
       const int cl2 = i / TL, e = i % TL;
-      const int x = ((c0 + cl2) / st) % a.n;
-      const bool bdy = s ? (x == a.n - 1) : (x == 0);
+      const bool bdy = (sInfo[INFO * cl2] >> f) & 1;
       if (!bdy) dst[i] = sTR[(cl2 * Sh::NF + f) * TL + e];
     }
   }
@@ -336,6 +369,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
   __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
   __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
   __shared__ T sKF[Sh::CPB * Sh::NF];
+  __shared__ int sInfo[Sh::CPB * INFO];
 
   const int c0 = blockIdx.x * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -356,16 +390,18 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
       for (int j = 0; j < N; ++j) ul[j] = us[j];
     }
   }
-  if (!UZERO) load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
-  load_cell_data<T, D, N, VARK>(a, c0, nc, sE, sKF);
+  fill_cell_info<D, N>(a.n, c0, nc, sInfo);
+  __syncthreads();
+  if (!UZERO) load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sInfo, sNB);
+  load_cell_data<T, D, N, VARK>(a, c0, nc, sInfo, sE, sKF);
   __syncthreads();
   if constexpr (VARK) {
     make_si<T, D, N>(a, nc, sE);
     __syncthreads();
   }
-  if (!UZERO) facet_prepass<T, D, N, VARK>(a, c0, nc, sNB, sE, sKF);
+  if (!UZERO) facet_prepass<T, D, N, VARK>(a, nc, sInfo, sNB, sE, sKF);
 
-  const int cc = c0 + (cl < nc ? cl : 0);
+  const int mask = sInfo[INFO * (cl < nc ? cl : 0)];
   // forward transforms S^T along x, y(, z) with the facet lifts subtracted
   // just before each axis is transformed
 #pragma unroll
@@ -381,22 +417,22 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
       if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
-      stage_mv<T, D, N, VARK, true>(a, sE, cl, cc, k, 0, r, t);  // S^T
+      stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, 0, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
-        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 0) + 2 * NN;
-        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 1) + 2 * NN;
+        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, mask, 0) + 2 * NN;
+        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, mask, 1) + 2 * NN;
         if constexpr (D == 2) {
           const T ls = l0[ln];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] /= (ls + l1[j]);
+          for (int j = 0; j < N; ++j) t[j] *= recip(ls + l1[j]);
         } else {
-          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 2) + 2 * NN;
+          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, mask, 2) + 2 * NN;
           const T ls = l0[ln % N] + l1[ln / N];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] /= (ls + l2[j]);
+          for (int j = 0; j < N; ++j) t[j] *= recip(ls + l2[j]);
         }
-        stage_mv<T, D, N, VARK, false>(a, sE, cl, cc, k, 0, t, r);  // S
+        stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, 0, t, r);  // S
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
       }
@@ -415,7 +451,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
       T r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, false>(a, sE, cl, cc, k, 0, r, t);
+      stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, 0, r, t);
       if (k == 0) {
         T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
@@ -433,7 +469,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
     }
     __syncthreads();
   }
-  finish_traces_and_store<T, D, N>(a, c0, nc, sW, sTR, nullptr, a.tr_out + rt);
+  finish_traces_and_store<T, D, N>(a, c0, nc, sInfo, sW, sTR, nullptr, a.tr_out + rt);
 }
 
 // ---------------------------------------------------------------------------
@@ -451,6 +487,7 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
   __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
   __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
   __shared__ T sKF[Sh::CPB * Sh::NF];
+  __shared__ int sInfo[Sh::CPB * INFO];
 
   const int c0 = blockIdx.x * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -471,16 +508,18 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
       for (int j = 0; j < N; ++j) bl[j] = bs[j];
     }
   }
-  load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sNB);
-  load_cell_data<T, D, N, VARK>(a, c0, nc, sE, sKF);
+  fill_cell_info<D, N>(a.n, c0, nc, sInfo);
+  __syncthreads();
+  load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sInfo, sNB);
+  load_cell_data<T, D, N, VARK>(a, c0, nc, sInfo, sE, sKF);
   __syncthreads();
   if constexpr (VARK) {
     make_si<T, D, N>(a, nc, sE);
     __syncthreads();
   }
-  facet_prepass<T, D, N, VARK>(a, c0, nc, sNB, sE, sKF);
+  facet_prepass<T, D, N, VARK>(a, nc, sInfo, sNB, sE, sKF);
 
-  const int cc = c0 + (cl < nc ? cl : 0);
+  const int mask = sInfo[INFO * (cl < nc ? cl : 0)];
   // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
   // lifts added right after each axis is transformed back.
 #pragma unroll
@@ -495,21 +534,21 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
-      stage_mv<T, D, N, VARK, false>(a, sE, cl, cc, k, NN, r, t);  // Si
+      stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, NN, r, t);  // Si
       if (k == D - 1) {
-        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 0) + 2 * NN;
-        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 1) + 2 * NN;
+        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, mask, 0) + 2 * NN;
+        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, mask, 1) + 2 * NN;
         if constexpr (D == 2) {
           const T ls = l0[ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + l1[j]);
         } else {
-          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, cc, a.n, 2) + 2 * NN;
+          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, mask, 2) + 2 * NN;
           const T ls = l0[ln % N] + l1[ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + l2[j]);
         }
-        stage_mv<T, D, N, VARK, true>(a, sE, cl, cc, k, NN, t, r);  // Si^T
+        stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, NN, t, r);  // Si^T
         add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, r);
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
@@ -526,7 +565,7 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
       T r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, true>(a, sE, cl, cc, k, NN, r, t);
+      stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, NN, r, t);
       add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, t);
       if (k == 0) {
 #pragma unroll
@@ -632,6 +671,7 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
   __shared__ T sU[Sh::CPB * Sh::NV];
   __shared__ T sW[Sh::CPB * Sh::NV];
   __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
+  __shared__ int sInfo[Sh::CPB * INFO];
 
   const int c0 = blockIdx.x * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -639,6 +679,8 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
   const int tid = threadIdx.x;
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
+  fill_cell_info<D, N>(a.n, c0, nc, sInfo);
+  __syncthreads();
   constexpr int NCD = (NC == 0) ? 0 : ((D == 2) ? NC * NC : NC * NC * NC);
 
   {
@@ -653,12 +695,11 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
         const int nv = a.n - 1;
         for (int i = tid; i < nc * NCD; i += Sh::NT) {
           const int c2 = i / NCD, corner = i % NCD;
-          const int c = c0 + c2;
           int vid = 0, mul = 1;
           bool inside = true;
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            const int v = (c / ipow<D>(a.n, k)) % a.n + ((corner >> k) & 1);
+            const int v = sInfo[INFO * c2 + 1 + k] + ((corner >> k) & 1);
             inside = inside && v > 0 && v < a.n;
             vid += (v - 1) * mul;
             mul *= nv;
@@ -753,7 +794,7 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
     line_traces<T, D, N>(a, cl, 0, ln, u, sTR);
   }
   __syncthreads();
-  finish_traces_and_store<T, D, N>(a, c0, nc, sU, sTR, NC > 0 ? a.u_out + rv : nullptr, a.tr_out + rt);
+  finish_traces_and_store<T, D, N>(a, c0, nc, sInfo, sU, sTR, NC > 0 ? a.u_out + rv : nullptr, a.tr_out + rt);
 }
 
 }  // namespace dgk
