@@ -30,6 +30,31 @@ METRIC = "smoother DoFs/s & time-to-1e-10 residual, mixed vs FP64 on 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_q4_32cube_hbm_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2510_00998_amd", "csrc", "dg_kernels_impl.hpp")
+
+
+def counter_traffic(key):
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None if the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        line = line.strip()
+        if ":" in line and (line.startswith("source_sha256") or line.startswith("traffic_bytes")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != sha or key not in vals:
+        return None
+    return float(vals[key])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,12 +204,13 @@ def main():
                                "FCG to 1e-10",
                    "dim": dim, "n": n, "p": p, "ndof": nd, "sweeps_per_step": S},
         "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach64 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach64 / HBM_PEAK_GBS, "traffic": counter_traffic("traffic_bytes_per_launch_f64"),
                      "kernel": "k_sweep<double,3,5> (fused sweep, FP64)",
                      "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64},
         "sweep_dofs_per_s": {"f64": nd / t64, "f32": nd / t32},
         "sweep_roofline_f32": {"achieved": by32 / t32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by32 / t32 / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by32,
+                               "traffic": counter_traffic("traffic_bytes_per_launch_f32"),
                                "mean_launch_s": t32},
         "time_to_1e-10_s": tt,
         "solver_iterations": its,
