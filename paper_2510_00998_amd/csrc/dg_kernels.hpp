@@ -31,12 +31,21 @@
 
 namespace hpmg {
 
+// Cells per block: about 256 threads, unless a build overrides the 3D cell
+// count per block for one degree (HPMG_CPB3D_N / HPMG_CPB3D, tile tuning).
+#ifndef HPMG_CPB3D_N
+#define HPMG_CPB3D_N 0
+#define HPMG_CPB3D 0
+#endif
+#ifndef HPMG_MAX_THREADS
+#define HPMG_MAX_THREADS 256
+#endif
 template <int D, int N>
 struct DGShape {
   static constexpr int L = (D == 2) ? N : N * N;  // lines per cell = nodes per facet
   static constexpr int NV = L * N;                // nodes per cell
   static constexpr int NF = 2 * D;                // facets per cell
-  static constexpr int CPB = (256 / L) > 0 ? (256 / L) : 1;
+  static constexpr int CPB = (D == 3 && N == HPMG_CPB3D_N) ? HPMG_CPB3D : ((256 / L) > 0 ? (256 / L) : 1);
   static constexpr int NT = CPB * L;
   static constexpr int EGS = 2 * N * N + N;       // S, Si, lambda of one direction
 };
@@ -60,6 +69,7 @@ struct DGArgs {
   const T* ref;        // RefOff layout
   const T* eig;        // vark=0: [4 classes][S N^2 | Si N^2 | lam N]; vark=1: [cell][D][S N^2 | lam N]
   const T* kappa;      // vark=1: per cell
+  const unsigned char* bmask;  // per cell: bit 2k+side set if that facet is on the boundary
   T h_fwd;             // h^(2-d): scales b in the sweep
   T h_apply;           // h^(d-2): scales A u
   T sigma_hat;         // sigma * h = sigma0 (p_penalty+1)^2

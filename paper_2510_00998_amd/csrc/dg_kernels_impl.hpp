@@ -1,5 +1,17 @@
 // Kernel bodies for dg_kernels.hpp (included by the per-instantiation .hip
 // files).  See dg_kernels.hpp for the mathematics.
+//
+// Block structure of the fused sweep (3D, constant kappa):
+//   P1  u, b lines -> registers; neighbour traces -> flux fields, first
+//       tangential transform fused into the load -> LDS
+//   P2  second tangential transform of the flux fields
+//   P3..P5 forward transforms along x, y, z (lifts subtracted per axis),
+//       diagonal scaling, first inverse transform
+//   P6, P7 inverse transforms along y, x; update, store of u and of the
+//       x-facet traces straight from registers
+//   P8  y- and z-facet traces from the updated cell in LDS
+// Seven barriers; the facet traces are written by each cell for its own
+// interior facets and read once by the neighbour in the next sweep.
 #pragma once
 #include "dg_kernels.hpp"
 
@@ -51,31 +63,6 @@ __device__ __forceinline__ int ipow(int n, int k) {
   return k == 0 ? 1 : (k == 1 ? n : n * n);
 }
 
-// Per-cell info staged in LDS once per block: [0] boundary mask (bit f set:
-// facet f = 2k + side lies on the domain boundary), [1..3] cell coordinates.
-// Everything else derives the boundary status from it, so the kernels divide
-// by the runtime mesh size only here.
-constexpr int INFO = 4;
-template <int D, int N>
-__device__ __forceinline__ void fill_cell_info(int n, int c0, int nc, int* sInfo) {
-  const int t = threadIdx.x;
-  if (t < nc) {
-    const int c = c0 + t;
-    int x[3];
-    x[0] = c % n;
-    const int r = c / n;
-    x[1] = (D == 2) ? r : r % n;
-    x[2] = (D == 2) ? 0 : r / n;
-    int m = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) m |= (x[k] == 0 ? 1 : 0) << (2 * k) | (x[k] == n - 1 ? 2 : 0) << (2 * k);
-    sInfo[INFO * t + 0] = m;
-    sInfo[INFO * t + 1] = x[0];
-    sInfo[INFO * t + 2] = x[1];
-    sInfo[INFO * t + 3] = x[2];
-  }
-}
-
 // 1/d: hardware reciprocal refined by Newton steps (two for double, one for
 // float) to full precision.
 __device__ __forceinline__ double recip(double d) {
@@ -89,8 +76,8 @@ __device__ __forceinline__ float recip(float d) {
   return __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
 }
 
-// Class of a cell along axis k for constant kappa: bit 0 = facet at the low
-// end is on the boundary, bit 1 = facet at the high end is.
+// Boundary mask of a cell (bit f = 2k + side set: facet f on the domain
+// boundary); the class of the cell along axis k is (mask >> 2k) & 3.
 __device__ __forceinline__ int axis_class(int mask, int k) { return (mask >> (2 * k)) & 3; }
 
 // LDS size of the staged eigendata: constant kappa shares the 4 class
@@ -100,21 +87,10 @@ struct EigLDS {
   static constexpr int SIZE = VARK ? DGShape<D, N>::CPB * D * DGShape<D, N>::EGS : 4 * DGShape<D, N>::EGS;
 };
 
-// S | Si = S^T M | lambda of the cell (block slot cl, global index c) along k.
+// Stage the eigendata (and, per cell, kappa_F of every facet; 0 on the
+// boundary) of the block's cells.
 template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ const T* eig_of(const T* sE, int cl, int mask, int k) {
-  using Sh = DGShape<D, N>;
-  if constexpr (VARK)
-    return sE + (cl * D + k) * Sh::EGS;
-  else
-    return sE + axis_class(mask, k) * Sh::EGS;
-}
-
-// Stage the eigendata and the facet coefficients kappa_F (0 on boundary
-// facets) of the block's cells.
-template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int nc, const int* sInfo, T* sE,
-                                               T* sKF) {
+__device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, T* sE, T* sKF) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   const int tid = threadIdx.x;
@@ -124,26 +100,20 @@ __device__ __forceinline__ void load_cell_data(const DGArgs<T>& a, int c0, int n
     for (int i = tid; i < nc * D * (NN + N); i += Sh::NT) {
       const int e = i % (NN + N);
       const int ck = i / (NN + N);
-      const T v = a.eig[(size_t)c0 * D * (NN + N) + i];
-      sE[ck * Sh::EGS + (e < NN ? e : NN + e)] = v;  // lambda goes after the Si slot
+      sE[ck * Sh::EGS + (e < NN ? e : NN + e)] = a.eig[(size_t)c0 * D * (NN + N) + i];
     }
-  }
-  for (int i = tid; i < nc * Sh::NF; i += Sh::NT) {
-    const int cl = i / Sh::NF, f = i % Sh::NF;
-    const int k = f >> 1, s = f & 1;
-    const int c = c0 + cl;
-    const int st = ipow<D>(a.n, k);
-    const bool bdy = (sInfo[INFO * cl] >> f) & 1;
-    T kf = 0;
-    if (!bdy) {
-      if constexpr (VARK) {
+    for (int i = tid; i < nc * Sh::NF; i += Sh::NT) {
+      const int cl = i / Sh::NF, f = i % Sh::NF;
+      const int k = f >> 1, s = f & 1;
+      const int c = c0 + cl;
+      T kf = 0;
+      if (!((a.bmask[c] >> f) & 1)) {
+        const int st = ipow<D>(a.n, k);
         const T k0 = a.kappa[c], k1 = a.kappa[s ? c + st : c - st];
         kf = T(2) * k0 * k1 / (k0 + k1);
-      } else {
-        kf = a.kappa_const;
       }
+      sKF[i] = kf;
     }
-    sKF[i] = kf;
   }
 }
 
@@ -152,7 +122,7 @@ template <typename T, int D, int N>
 __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
-  const T* Mh = a.ref + RefOff<N>::M;
+  const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
   for (int i = threadIdx.x; i < nc * D * NN; i += Sh::NT) {
     const int e = i % NN, ck = i / NN;
     const int r = e / N, col = e % N;
@@ -167,110 +137,169 @@ __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
 // Matrix of (cell, axis k) at offset `off` within its S | Si | lambda record,
 // applied to a line (TR: transposed).  Constant kappa: when every active
 // lane of the wave needs the same boundary class the record is read from
-// the global class table with scalar loads, else from the LDS copy.
-template <typename T, int D, int N, bool VARK, bool TR>
+// the global class table with scalar loads; otherwise from the LDS copy
+// (LDS = true, after the block staged it) or per lane from global memory.
+template <typename T, int D, int N, bool VARK, bool TR, bool LDS = true>
 __device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const T* sE, int cl, int mask, int k, int off,
                                          const T (&in)[N], T (&out)[N]) {
   using Sh = DGShape<D, N>;
   // matrices that fit in about 72 SGPRs take the scalar path
   constexpr bool SCALAR_OK = N * N * (int)sizeof(T) / 4 <= 72;
-  if constexpr (VARK || !SCALAR_OK) {
-    if constexpr (VARK)
-      mv<N, TR>(sE + (cl * D + k) * Sh::EGS + off, in, out);
-    else
-      mv<N, TR>(sE + axis_class(mask, k) * Sh::EGS + off, in, out);
+  if constexpr (VARK) {
+    mv<N, TR>(sE + (cl * D + k) * Sh::EGS + off, in, out);
   } else {
     const int cls = axis_class(mask, k);
-    const int c0 = __builtin_amdgcn_readfirstlane(cls);
-    if (__all(cls == c0))
+    bool uni = false;
+    int c0 = cls;
+    if constexpr (SCALAR_OK) {
+      c0 = __builtin_amdgcn_readfirstlane(cls);
+      uni = __all(cls == c0);
+    }
+    if (uni)
       mv<N, TR>(as_const(a.eig) + c0 * Sh::EGS + off, in, out);
-    else
+    else if constexpr (LDS)
       mv<N, TR>(sE + cls * Sh::EGS + off, in, out);
+    else
+      mv<N, TR>(a.eig + cls * Sh::EGS + off, in, out);
   }
 }
 
-// Neighbour traces of the block's cells: sNB[cl][f][field][L] = traces the
-// neighbour across facet f wrote on its facet f^1 (zeros on the boundary).
+// Tangential axis of pass `pass` of the facet transform of facets normal to k.
+template <int D>
+__device__ __forceinline__ int tangential(int k, int pass) {
+  if constexpr (D == 2)
+    return 1 - k;
+  else
+    return pass == 0 ? ((k == 0) ? 1 : 0) : ((k == 2) ? 1 : 2);
+}
+
+// Facet flux fields.  From the neighbour's traces (g', q') across facet f
+//   F1 = T_f (kappa_F (q'/2 - sigma_hat g')),  F2 = T_f (kappa_F g'/2),
+// T_f = G_t1 x G_t2 over the tangential axes with G_t = Si_t for t < k
+// (axes already transformed when facet k is processed) and Mhat otherwise.
+// sNB[cl][f][F1|F2][L].  Pass 0 reads the neighbour traces (FROM_GLOBAL:
+// straight from the trace buffer, else from the plain LDS copy) and
+// transforms along t1; pass 1 transforms along t2 (3D).  Work items are
+// ordered (facet, cell, line) so that a wave mostly sees one facet
+// direction and therefore one matrix.
+template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL>
+__device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int c0, int nc, int pass, T* sNB,
+                                           const T* sE, const T* sKF) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  constexpr int L = Sh::L;
+  constexpr int TL = 2 * L;
+  constexpr int LINES = (D == 2) ? 1 : N;
+  const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
+  for (int i = threadIdx.x; i < Sh::CPB * Sh::NF * LINES; i += Sh::NT) {
+    const int f = i / (Sh::CPB * LINES), rem = i % (Sh::CPB * LINES);
+    const int cl = rem / LINES, li = rem % LINES;
+    if (cl >= nc) continue;
+    const int c = c0 + cl;
+    const int k = f >> 1;
+    const int t = tangential<D>(k, pass);
+    const int st = pass == 0 ? 1 : N;  // node stride along t within the facet
+    const int lo = pass == 0 ? N * li : li;
+    T* g = sNB + (cl * Sh::NF + f) * TL + lo;
+    const int mask = a.bmask[c];
+    T x1[N], x2[N], o1[N], o2[N];
+    if (pass == 0) {
+      if ((mask >> f) & 1) {  // boundary facet: no neighbour, zero flux fields
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          g[j] = T(0);
+          g[L + j] = T(0);
+        }
+        continue;
+      }
+      T gv[N], qv[N];
+      if constexpr (FROM_GLOBAL) {
+        const int s = f & 1;
+        const int stc = ipow<D>(a.n, k);
+        const T* src = tr + ((size_t)(f ^ 1) * a.ncell + (s ? c + stc : c - stc)) * TL + lo;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          gv[j] = src[j];
+          qv[j] = src[L + j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          gv[j] = g[j];
+          qv[j] = g[L + j];
+        }
+      }
+      T kf;
+      if constexpr (VARK)
+        kf = sKF[cl * Sh::NF + f];
+      else
+        kf = a.kappa_const;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        x1[j] = kf * (T(0.5) * qv[j] - a.sigma_hat * gv[j]);
+        x2[j] = T(0.5) * kf * gv[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        x1[j] = g[st * j];
+        x2[j] = g[L + st * j];
+      }
+    }
+    if (t < k) {
+      stage_mv<T, D, N, VARK, false, !FROM_GLOBAL>(a, sE, cl, mask, t, NN, x1, o1);
+      stage_mv<T, D, N, VARK, false, !FROM_GLOBAL>(a, sE, cl, mask, t, NN, x2, o2);
+    } else {
+      mv<N, false>(Mh, x1, o1);
+      mv<N, false>(Mh, x2, o2);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      g[st * j] = o1[j];
+      g[L + st * j] = o2[j];
+    }
+  }
+}
+
+// Plain copy of the neighbour traces into sNB (variable kappa path, whose
+// facet transform needs the staged per-cell eigendata).
 template <typename T, int D, int N>
-__device__ __forceinline__ void load_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc,
-                                                      const int* sInfo, T* sNB) {
+__device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc, T* sNB) {
   using Sh = DGShape<D, N>;
   constexpr int TL = 2 * Sh::L;
-  const int tid = threadIdx.x;
   for (int f = 0; f < Sh::NF; ++f) {
     const int k = f >> 1, s = f & 1;
     const int st = ipow<D>(a.n, k);
     const int off = s ? st : -st;
     const T* src = tr + (size_t)(f ^ 1) * a.ncell * TL;
-    (void)k;
-    for (int i = tid; i < nc * TL; i += Sh::NT) {
+    for (int i = threadIdx.x; i < nc * TL; i += Sh::NT) {
       const int cl = i / TL, e = i % TL;
       const int c = c0 + cl;
-      const bool bdy = (sInfo[INFO * cl] >> f) & 1;
+      const bool bdy = (a.bmask[c] >> f) & 1;
       sNB[(cl * Sh::NF + f) * TL + e] = bdy ? T(0) : src[(size_t)(c + off) * TL + e];
     }
   }
 }
 
-// Facet pre-pass: turn (g', q') into the lifted flux fields
-//   F1 = T_f (kappa_F (q'/2 - sigma_hat g')),  F2 = T_f (kappa_F g'/2),
-// T_f = G_t1 x G_t2 over the tangential axes with G_t = Si_t for t < k
-// (axes already transformed when facet k is processed) and Mhat otherwise.
-// Work items are ordered (facet, cell, line) so that a wave mostly sees one
-// facet direction and one matrix.
+// All facet flux fields of the block in sNB, and the eigendata in sE; ends
+// with a barrier.
 template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ void facet_prepass(const DGArgs<T>& a, int nc, const int* sInfo, T* sNB, const T* sE,
-                                              const T* sKF) {
-  using Sh = DGShape<D, N>;
-  constexpr int NN = N * N;
-  constexpr int L = Sh::L;
-  const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
-  const int tid = threadIdx.x;
-  constexpr int LINES = (D == 2) ? 1 : N;  // lines per facet and pass
-  for (int pass = 0; pass < (D == 2 ? 1 : 2); ++pass) {
-    for (int i = tid; i < nc * Sh::NF * LINES; i += Sh::NT) {
-      const int f = i / (nc * LINES), rem = i % (nc * LINES);
-      const int cl = rem / LINES, li = rem % LINES;
-      const int k = f >> 1;
-      int t;
-      if constexpr (D == 2)
-        t = 1 - k;
-      else
-        t = pass == 0 ? ((k == 0) ? 1 : 0) : ((k == 2) ? 1 : 2);
-      // pass 0 runs along the first tangential axis (stride 1), pass 1 along
-      // the second (stride N)
-      const int st = pass == 0 ? 1 : N;
-      T* g = sNB + (cl * Sh::NF + f) * 2 * L + (pass == 0 ? N * li : li);
-      T x1[N], x2[N], o1[N], o2[N];
-      if (pass == 0) {
-        const T kf = sKF[cl * Sh::NF + f];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          const T gv = g[j], qv = g[L + j];
-          x1[j] = kf * (T(0.5) * qv - a.sigma_hat * gv);
-          x2[j] = T(0.5) * kf * gv;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          x1[j] = g[st * j];
-          x2[j] = g[L + st * j];
-        }
-      }
-      if (t < k) {
-        const int mk = sInfo[INFO * cl];
-        stage_mv<T, D, N, VARK, false>(a, sE, cl, mk, t, NN, x1, o1);
-        stage_mv<T, D, N, VARK, false>(a, sE, cl, mk, t, NN, x2, o2);
-      } else {
-        mv<N, false>(Mh, x1, o1);
-        mv<N, false>(Mh, x2, o2);
-      }
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        g[st * j] = o1[j];
-        g[L + st * j] = o2[j];
-      }
-    }
+__device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int c0, int nc, T* sNB, T* sE, T* sKF) {
+  if constexpr (!VARK) {
+    facet_pass<T, D, N, false, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
+    load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
+    __syncthreads();
+  } else {
+    copy_neighbour_traces<T, D, N>(a, tr, c0, nc, sNB);
+    load_eig<T, D, N, true>(a, c0, nc, sE, sKF);
+    __syncthreads();
+    make_si<T, D, N>(a, nc, sE);
+    __syncthreads();
+    facet_pass<T, D, N, true, false>(a, tr, c0, nc, 0, sNB, sE, sKF);
+    __syncthreads();
+  }
+  if constexpr (D == 3) {
+    facet_pass<T, D, N, VARK, false>(a, tr, c0, nc, 1, sNB, sE, sKF);
     __syncthreads();
   }
 }
@@ -299,11 +328,14 @@ __device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int
   }
 }
 
-// Traces of a line along axis k into the staging array sTR[cl][f][field][L].
+// Traces (value, outward normal derivative) of a line along axis k, stored
+// straight to the trace buffer for the facets that are not on the boundary.
 template <typename T, int D, int N>
-__device__ __forceinline__ void line_traces(const DGArgs<T>& a, int cl, int k, int ln, const T (&u)[N], T* sTR) {
+__device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, int c, int mask, int k, int ln,
+                                                  const T (&u)[N]) {
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
+  constexpr int TL = 2 * L;
   const cptr<T> ep0 = as_const(a.ref) + RefOff<N>::EP0;
   const cptr<T> ep1 = as_const(a.ref) + RefOff<N>::EP1;
   T d0 = 0, d1 = 0;
@@ -312,46 +344,30 @@ __device__ __forceinline__ void line_traces(const DGArgs<T>& a, int cl, int k, i
     d0 += ep0[j] * u[j];
     d1 += ep1[j] * u[j];
   }
-  T* t0 = sTR + (cl * Sh::NF + 2 * k) * 2 * L;
-  T* t1 = t0 + 2 * L;
-  t0[ln] = u[0];
-  t0[L + ln] = d0;
-  t1[ln] = u[N - 1];
-  t1[L + ln] = d1;
+  if (!((mask >> (2 * k)) & 1)) {
+    T* t0 = trout + ((size_t)(2 * k) * a.ncell + c) * TL;
+    t0[ln] = u[0];
+    t0[L + ln] = d0;
+  }
+  if (!((mask >> (2 * k + 1)) & 1)) {
+    T* t1 = trout + ((size_t)(2 * k + 1) * a.ncell + c) * TL;
+    t1[ln] = u[N - 1];
+    t1[L + ln] = d1;
+  }
 }
 
-// Traces of all axes but x from the staged cell vector sU, then coalesced
-// stores of the cell vector (if uout) and of the traces of interior facets.
+// Traces of the y (and z) lines of the cell vector staged in sU.
 template <typename T, int D, int N>
-__device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int c0, int nc, const int* sInfo,
-                                                        const T* sU, T* sTR, T* uout, T* trout) {
+__device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, const T* sU, int cl, int c, int mask,
+                                                int ln) {
   using Sh = DGShape<D, N>;
-  constexpr int L = Sh::L;
-  constexpr int TL = 2 * L;
-  const int tid = threadIdx.x;
-  const int cl = tid / L, ln = tid % L;
-  if (tid < Sh::NT && cl < nc) {
 #pragma unroll
-    for (int k = 1; k < D; ++k) {
-      const int base = cl * Sh::NV + line_base<D, N>(k, ln);
-      T u[N];
+  for (int k = 1; k < D; ++k) {
+    const int base = cl * Sh::NV + line_base<D, N>(k, ln);
+    T u[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j) u[j] = sU[base + j * line_stride<N>(k)];
-      line_traces<T, D, N>(a, cl, k, ln, u, sTR);
-    }
-  }
-  __syncthreads();
-  if (uout) {
-    T* dst = uout + (size_t)c0 * Sh::NV;
-    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) dst[i] = sU[i];
-  }
-  for (int f = 0; f < Sh::NF; ++f) {
-    T* dst = trout + ((size_t)f * a.ncell + c0) * TL;
-    for (int i = tid; i < nc * TL; i += Sh::NT) {
-      const int cl2 = i / TL, e = i % TL;
-      const bool bdy = (sInfo[INFO * cl2] >> f) & 1;
-      if (!bdy) dst[i] = sTR[(cl2 * Sh::NF + f) * TL + e];
-    }
+    for (int j = 0; j < N; ++j) u[j] = sU[base + j * line_stride<N>(k)];
+    store_line_traces<T, D, N>(a, trout, c, mask, k, ln, u);
   }
 }
 
@@ -361,15 +377,14 @@ __device__ __forceinline__ void finish_traces_and_store(const DGArgs<T>& a, int 
 // neighbour traces are not read.  The x-line of u and b of each thread
 // stay in registers from the load to the update.
 template <typename T, int D, int N, bool UZERO, bool VARK>
-__global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
+__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_sweep(DGArgs<T> a) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
   __shared__ T sW[Sh::CPB * Sh::NV];
   __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
   __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
-  __shared__ T sKF[Sh::CPB * Sh::NF];
-  __shared__ int sInfo[Sh::CPB * INFO];
+  __shared__ T sKF[VARK ? Sh::CPB * Sh::NF : 1];
 
   const int c0 = blockIdx.x * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -377,7 +392,9 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
   const int tid = threadIdx.x;
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
+  const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
+  const int mask = a.bmask[c];
 
   T ul[N], bl[N];
   if (act) {
@@ -390,18 +407,17 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
       for (int j = 0; j < N; ++j) ul[j] = us[j];
     }
   }
-  fill_cell_info<D, N>(a.n, c0, nc, sInfo);
-  __syncthreads();
-  if (!UZERO) load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sInfo, sNB);
-  load_cell_data<T, D, N, VARK>(a, c0, nc, sInfo, sE, sKF);
-  __syncthreads();
-  if constexpr (VARK) {
-    make_si<T, D, N>(a, nc, sE);
+  if (!UZERO) {
+    flux_fields<T, D, N, VARK>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+  } else {
+    load_eig<T, D, N, VARK>(a, c0, nc, sE, sKF);
     __syncthreads();
+    if constexpr (VARK) {
+      make_si<T, D, N>(a, nc, sE);
+      __syncthreads();
+    }
   }
-  if (!UZERO) facet_prepass<T, D, N, VARK>(a, nc, sInfo, sNB, sE, sKF);
 
-  const int mask = sInfo[INFO * (cl < nc ? cl : 0)];
   // forward transforms S^T along x, y(, z) with the facet lifts subtracted
   // just before each axis is transformed
 #pragma unroll
@@ -420,17 +436,17 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
       stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, 0, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
-        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, mask, 0) + 2 * NN;
-        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, mask, 1) + 2 * NN;
+        const T* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
+        const T* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
         if constexpr (D == 2) {
-          const T ls = l0[ln];
+          const T ls = E0[2 * NN + ln];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] *= recip(ls + l1[j]);
+          for (int j = 0; j < N; ++j) t[j] *= recip(ls + E1[2 * NN + j]);
         } else {
-          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, mask, 2) + 2 * NN;
-          const T ls = l0[ln % N] + l1[ln / N];
+          const T* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
+          const T ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] *= recip(ls + l2[j]);
+          for (int j = 0; j < N; ++j) t[j] *= recip(ls + E2[2 * NN + j]);
         }
         stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, 0, t, r);  // S
 #pragma unroll
@@ -442,8 +458,8 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
     __syncthreads();
   }
   // inverse transforms S along the remaining axes; the last one is fused
-  // with the update, the store of u and the x-facet traces
-  T* sTR = sNB;  // the flux fields are consumed; reuse as trace staging
+  // with the update, the store of u and of the x-facet traces
+  T* trout = a.tr_out + rt;
 #pragma unroll
   for (int k = D - 2; k >= 0; --k) {
     if (act) {
@@ -461,7 +477,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
           sW[base + j] = t[j];
           uo[j] = t[j];
         }
-        line_traces<T, D, N>(a, cl, 0, ln, t, sTR);
+        store_line_traces<T, D, N>(a, trout, c, mask, 0, ln, t);
       } else {
 #pragma unroll
         for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
@@ -469,7 +485,7 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
     }
     __syncthreads();
   }
-  finish_traces_and_store<T, D, N>(a, c0, nc, sInfo, sW, sTR, nullptr, a.tr_out + rt);
+  if (act) store_yz_traces<T, D, N>(a, trout, sW, cl, c, mask, ln);
 }
 
 // ---------------------------------------------------------------------------
@@ -479,15 +495,14 @@ __global__ __launch_bounds__(256) void k_sweep(DGArgs<T> a) {
 // contributions of each cell, summed over cells by the gather kernel).
 // Needs the traces of u in tr_in.
 template <typename T, int D, int N, int NC, bool RESID, bool VARK>
-__global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
+__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_apply(DGArgs<T> a) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
   __shared__ T sW[Sh::CPB * Sh::NV];
   __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
   __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
-  __shared__ T sKF[Sh::CPB * Sh::NF];
-  __shared__ int sInfo[Sh::CPB * INFO];
+  __shared__ T sKF[VARK ? Sh::CPB * Sh::NF : 1];
 
   const int c0 = blockIdx.x * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -495,7 +510,9 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
   const int tid = threadIdx.x;
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
+  const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
+  const int mask = a.bmask[c];
 
   T ul[N], bl[N];
   if (act) {
@@ -508,18 +525,8 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
       for (int j = 0; j < N; ++j) bl[j] = bs[j];
     }
   }
-  fill_cell_info<D, N>(a.n, c0, nc, sInfo);
-  __syncthreads();
-  load_neighbour_traces<T, D, N>(a, a.tr_in + rt, c0, nc, sInfo, sNB);
-  load_cell_data<T, D, N, VARK>(a, c0, nc, sInfo, sE, sKF);
-  __syncthreads();
-  if constexpr (VARK) {
-    make_si<T, D, N>(a, nc, sE);
-    __syncthreads();
-  }
-  facet_prepass<T, D, N, VARK>(a, nc, sInfo, sNB, sE, sKF);
+  flux_fields<T, D, N, VARK>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
 
-  const int mask = sInfo[INFO * (cl < nc ? cl : 0)];
   // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
   // lifts added right after each axis is transformed back.
 #pragma unroll
@@ -536,17 +543,17 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
       }
       stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, NN, r, t);  // Si
       if (k == D - 1) {
-        const T* l0 = eig_of<T, D, N, VARK>(sE, cl, mask, 0) + 2 * NN;
-        const T* l1 = eig_of<T, D, N, VARK>(sE, cl, mask, 1) + 2 * NN;
+        const T* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
+        const T* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
         if constexpr (D == 2) {
-          const T ls = l0[ln];
+          const T ls = E0[2 * NN + ln];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] *= (ls + l1[j]);
+          for (int j = 0; j < N; ++j) t[j] *= (ls + E1[2 * NN + j]);
         } else {
-          const T* l2 = eig_of<T, D, N, VARK>(sE, cl, mask, 2) + 2 * NN;
-          const T ls = l0[ln % N] + l1[ln / N];
+          const T* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
+          const T ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
-          for (int j = 0; j < N; ++j) t[j] *= (ls + l2[j]);
+          for (int j = 0; j < N; ++j) t[j] *= (ls + E2[2 * NN + j]);
         }
         stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, NN, t, r);  // Si^T
         add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, r);
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
         for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
       }
     }
-    __syncthreads();
+    if (k > 0 || NC > 0) __syncthreads();
   }
   if constexpr (NC > 0) {
     // restriction (E^T)^(x d) of the cell residual, one axis per pass; sNB
@@ -662,16 +669,16 @@ __global__ __launch_bounds__(256) void k_apply(DGArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // u += P e (NC > 0; DG_q cell vector or Q1 vertex vector) and projection of
-// u onto the facet traces (NC = 0: projection only, Algorithm BlockJacobi
-// warm-up; NC > 0: fused prolongation + projection, Section 5.1.1).
+// u onto the facet traces (NC = 0: projection only, the warm-up traversal of
+// Algorithm BlockJacobi; NC > 0: fused prolongation + projection,
+// Section 5.1.1).
 template <typename T, int D, int N, int NC>
-__global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
+__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_prolong(DGArgs<T> a) {
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
   __shared__ T sU[Sh::CPB * Sh::NV];
-  __shared__ T sW[Sh::CPB * Sh::NV];
-  __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
-  __shared__ int sInfo[Sh::CPB * INFO];
+  __shared__ T sW[NC > 0 ? Sh::CPB * Sh::NV : 1];
+  __shared__ T sNB[NC > 0 ? Sh::CPB * Sh::NF * 2 * L : 1];
 
   const int c0 = blockIdx.x * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -679,38 +686,44 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
   const int tid = threadIdx.x;
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
-  fill_cell_info<D, N>(a.n, c0, nc, sInfo);
-  __syncthreads();
+  const int c = c0 + (act ? cl : 0);
+  const int mask = a.bmask[c];
   constexpr int NCD = (NC == 0) ? 0 : ((D == 2) ? NC * NC : NC * NC * NC);
 
-  {
-    const T* us = a.u_in + rv + (size_t)c0 * Sh::NV;
-    for (int i = tid; i < nc * Sh::NV; i += Sh::NT) sU[i] = us[i];
-    if constexpr (NC > 0) {
-      const T* cs = a.coarse + (size_t)blockIdx.y * a.cstride;
-      if (!a.coarse_cg) {
-        for (int i = tid; i < nc * NCD; i += Sh::NT) sW[(i / NCD) * Sh::NV + i % NCD] = cs[(size_t)c0 * NCD + i];
-      } else {
-        // Q1 corner values of each cell from the interior-vertex vector
-        const int nv = a.n - 1;
-        for (int i = tid; i < nc * NCD; i += Sh::NT) {
-          const int c2 = i / NCD, corner = i % NCD;
-          int vid = 0, mul = 1;
-          bool inside = true;
+  T u[N];
+  if (act) {
+    const T* us = a.u_in + rv + (size_t)c0 * Sh::NV + cl * Sh::NV + line_base<D, N>(0, ln);
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const int v = sInfo[INFO * c2 + 1 + k] + ((corner >> k) & 1);
-            inside = inside && v > 0 && v < a.n;
-            vid += (v - 1) * mul;
-            mul *= nv;
-          }
-          sW[c2 * Sh::NV + corner] = inside ? cs[vid] : T(0);
+    for (int j = 0; j < N; ++j) u[j] = us[j];
+  }
+  if constexpr (NC > 0) {
+    const T* cs = a.coarse + (size_t)blockIdx.y * a.cstride;
+    if (!a.coarse_cg) {
+      for (int i = tid; i < nc * NCD; i += Sh::NT) sW[(i / NCD) * Sh::NV + i % NCD] = cs[(size_t)c0 * NCD + i];
+    } else {
+      // Q1 corner values of each cell from the interior-vertex vector
+      const int nv = a.n - 1;
+      for (int i = tid; i < nc * NCD; i += Sh::NT) {
+        const int c2 = i / NCD, corner = i % NCD;
+        const int cc = c0 + c2;
+        int x[3];
+        x[0] = cc % a.n;
+        const int rr = cc / a.n;
+        x[1] = (D == 2) ? rr : rr % a.n;
+        x[2] = (D == 2) ? 0 : rr / a.n;
+        int vid = 0, mul = 1;
+        bool inside = true;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const int v = x[k] + ((corner >> k) & 1);
+          inside = inside && v > 0 && v < a.n;
+          vid += (v - 1) * mul;
+          mul *= nv;
         }
+        sW[c2 * Sh::NV + corner] = inside ? cs[vid] : T(0);
       }
     }
-  }
-  __syncthreads();
-  if constexpr (NC > 0) {
+    __syncthreads();
     const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
     if constexpr (D == 3) {
       // z: [c'][b'][a'] -> sNB[cl][c][b'][a'] (a' + NC b' + NC^2 c)
@@ -767,15 +780,11 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
       __syncthreads();
     }
   }
-  // x: line of thread ln (facet index = (b[,c])), add the prolongated
-  // correction, then the x-facet traces.  sTR aliases sNB, whose last
-  // readers finished before the preceding barrier.
-  T* sTR = sNB;
+  // x: line of thread ln (facet index = (b[,c])): add the prolongated
+  // correction, store u and the x-facet traces, stage u for the y/z traces
+  T* trout = a.tr_out + rt;
   if (act) {
     const int base = cl * Sh::NV + line_base<D, N>(0, ln);
-    T u[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) u[j] = sU[base + j];
     if constexpr (NC > 0) {
       const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
       T x[NC];
@@ -788,13 +797,16 @@ __global__ __launch_bounds__(256) void k_prolong(DGArgs<T> a) {
         for (int j = 0; j < NC; ++j) s += E[ax * NC + j] * x[j];
         u[ax] += s;
       }
+      T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base;
 #pragma unroll
-      for (int j = 0; j < N; ++j) sU[base + j] = u[j];
+      for (int j = 0; j < N; ++j) uo[j] = u[j];
     }
-    line_traces<T, D, N>(a, cl, 0, ln, u, sTR);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sU[base + j] = u[j];
+    store_line_traces<T, D, N>(a, trout, c, mask, 0, ln, u);
   }
   __syncthreads();
-  finish_traces_and_store<T, D, N>(a, c0, nc, sInfo, sU, sTR, NC > 0 ? a.u_out + rv : nullptr, a.tr_out + rt);
+  if (act) store_yz_traces<T, D, N>(a, trout, sU, cl, c, mask, ln);
 }
 
 }  // namespace dgk

@@ -125,6 +125,7 @@ struct hpmg_ctx {
   std::vector<DGLevel> dg;
   std::vector<CGLevel> cg;
   double* coarse_inv = nullptr;  // dense inverse of the coarsest Q1 operator
+  unsigned char* bmask = nullptr;  // per cell boundary-facet mask (all DG levels)
   int coarse_m = 0;
   // outer solver workspace (FP64) and the FP32 cycle vectors
   double *r = nullptr, *rold = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
@@ -532,6 +533,7 @@ hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
   a.ref = d.ref;
   a.eig = d.eig;
   a.kappa = d.kappa;
+  a.bmask = h->bmask;
   const double hh = 1.0 / h->n;
   a.h_fwd = (T)std::pow(hh, 2 - h->dim);
   a.h_apply = (T)std::pow(hh, h->dim - 2);
@@ -759,6 +761,21 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     }
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
+    {
+      std::vector<unsigned char> m(h->ncell);
+      const int n = h->n;
+      for (int c = 0; c < h->ncell; ++c) {
+        int v = 0, r = c;
+        for (int k = 0; k < h->dim; ++k) {
+          const int x = r % n;
+          r /= n;
+          v |= (x == 0 ? 1 : 0) << (2 * k);
+          v |= (x == n - 1 ? 1 : 0) << (2 * k + 1);
+        }
+        m[c] = (unsigned char)v;
+      }
+      h->bmask = h->mem.upload(m, stream);
+    }
     // DG levels: p, floor(p/2), ... while >= 2, then Q1
     std::vector<int> degs = {p};
     for (int q = p / 2; q >= 2; q /= 2) degs.push_back(q);
