@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=20, help="fused sweeps per precision per step")
-    ap.add_argument("--n", type=int, default=32)
-    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5],
+                    help="2: Q4 32^3 kappa=1 (headline); 3: Q3 64^3 log-uniform kappa; 5: Q5 96^3 log-normal kappa")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=6, help="mesh of the oracle's timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -114,17 +114,29 @@ def main():
     import paper_2510_00998_amd as hp
     from paper_2510_00998_amd import traffic
 
-    dim, n, p = 3, args.n, args.p
+    import synth
+    dim = 3
+    if args.config == 2:
+        n, p, kappa, fkind, wl = 32, 4, 1.0, 1, "u=prod sin(pi x_i)"
+    elif args.config == 3:
+        n, p, fkind = 64, 3, 0
+        kappa = synth.kappa_log_uniform(3, n, seed=1003)
+        wl = "kappa log-uniform in [1e-2,1e2] per cell (seed 1003), f=1"
+    else:
+        n, p, fkind = 96, 5, 0
+        kappa = synth.kappa_log_normal(3, n, seed=1005)
+        wl = "kappa log-normal (sigma_log 2, correlation length 0.1, seed 1005), f=1"
+    vark = not isinstance(kappa, float)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     t_setup = time.perf_counter()
-    g64 = hp.Solver(dim, n, p, 1.0, precision=hp.PREC_F64)
-    gmx = hp.Solver(dim, n, p, 1.0, precision=hp.PREC_F32)
+    g64 = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F64)
+    gmx = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F32)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     nd = g64.ndof
     b64 = torch.empty(nd, dtype=torch.float64, device=dev)
-    g64.load_vector(1, 1.0, b64)
+    g64.load_vector(fkind, 1.0, b64)
     b32 = b64.float()
     us64 = torch.zeros(nd, dtype=torch.float64, device=dev)
     us32 = torch.zeros(nd, dtype=torch.float32, device=dev)
@@ -167,8 +179,8 @@ def main():
     sw32 = [x for r in res for x in r["sw32"]]
     t64 = sum(sw64) / len(sw64)
     t32 = sum(sw32) / len(sw32)
-    by64 = traffic.sweep_bytes(dim, n, p, 8)
-    by32 = traffic.sweep_bytes(dim, n, p, 4)
+    by64 = traffic.sweep_bytes(dim, n, p, 8, per_cell_kappa=vark)
+    by32 = traffic.sweep_bytes(dim, n, p, 4, per_cell_kappa=vark)
     tt = {k: min(r[k][0] for r in res) for k in ("fp64", "mixed_f32")}
     its = {k: res[-1][k][1] for k in ("fp64", "mixed_f32")}
     ok = all(r[k][2] == 0 for r in res for k in ("fp64", "mixed_f32"))
@@ -186,6 +198,9 @@ def main():
         torch.cuda.synchronize()
 
     ach64 = by64 / t64 / 1e9
+    headline = args.config == 2
+    tkey64 = "traffic_bytes_per_launch_f64" if headline else "none"
+    tkey32 = "traffic_bytes_per_launch_f32" if headline else "none"
     line = {
         "metric": METRIC,
         "value": nd / t64,
@@ -199,18 +214,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3D Poisson SIPG Q{p} on {n}^3 hexes ({nd} DoFs), u=prod sin(pi x_i), "
-                               "fused single-touch block-Jacobi sweep + hp V(2,2) (Q4->Q2->Q1, h to 4^3), "
+        "config": {"workload": f"3D SIPG Q{p} on {n}^3 hexes ({nd} DoFs), {wl}, "
+                               "fused single-touch block-Jacobi sweep + hp V(2,2) (p halved to Q1, h to <=4^3), "
                                "FCG to 1e-10",
                    "dim": dim, "n": n, "p": p, "ndof": nd, "sweeps_per_step": S},
         "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach64 / HBM_PEAK_GBS, "traffic": counter_traffic("traffic_bytes_per_launch_f64"),
-                     "kernel": "k_sweep<double,3,5> (fused sweep, FP64)",
+                     "frac": ach64 / HBM_PEAK_GBS, "traffic": counter_traffic(tkey64),
+                     "kernel": f"k_sweep<double,3,{p + 1}> (fused sweep, FP64)",
                      "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64},
         "sweep_dofs_per_s": {"f64": nd / t64, "f32": nd / t32},
         "sweep_roofline_f32": {"achieved": by32 / t32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by32 / t32 / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by32,
-                               "traffic": counter_traffic("traffic_bytes_per_launch_f32"),
+                               "traffic": counter_traffic(tkey32),
                                "mean_launch_s": t32},
         "time_to_1e-10_s": tt,
         "solver_iterations": its,
@@ -218,7 +233,7 @@ def main():
         "mixed_solution_true_rel_residual": true_rel,
         "setup_s": t_setup,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and headline:
         line["cpu_baseline"] = cpu_baseline(dim, p, args.cpu_n)
     print(json.dumps(line), flush=True)
 

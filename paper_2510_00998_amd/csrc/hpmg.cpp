@@ -1017,6 +1017,7 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
       double rn = r0;
       int it = 0;
       bool conv = r0 == 0.0;
+      bool restart = true;
       while (!conv && it < maxit) {
         // z = M r (one V-cycle, zero initial guess)
         if (h->opt.precision == HPMG_PREC_F32) {
@@ -1027,7 +1028,8 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
           vcycle_dg<double>(h, 0, h->z, h->r, true, stream);
         }
         // beta, rho = z.r ; p = z + beta p
-        hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, it == 0 ? 1 : 0, stream);
+        hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart ? 1 : 0, stream);
+        restart = false;
         hpmg::krylov_update_p(nd, h->z, h->pv, h->scal, stream);
         // q = A p ; alpha = rho / p.q
         project<double>(h, 0, h->pv, d.tr[0], 1, stream);
@@ -1041,6 +1043,20 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
         if (!std::isfinite(rn)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite residual");
         if (rhs == 0) hist.push_back(rn / r0);
         conv = rn <= rtol * r0;
+        if (conv) {
+          // the recurrence residual drifts from b - A u in finite precision:
+          // accept only if the true residual meets the tolerance, else
+          // restart the iteration from it
+          project<double>(h, 0, ur, d.tr[0], 1, stream);
+          apply<double>(h, 0, ur, d.tr[0], br, h->r, 1, stream);
+          hpmg::krylov_dot(nd, h->r, h->r, nullptr, h->partial, h->scal, 3, 0, 0, stream);
+          HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
+          HIPCHK(hipStreamSynchronize(stream));
+          rn = std::sqrt(h->host_scal[6]);
+          if (!std::isfinite(rn)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite residual");
+          conv = rn <= rtol * r0;
+          restart = !conv;
+        }
       }
       its_total = std::max(its_total, it);
       rfin = std::max(rfin, rn);
