@@ -131,12 +131,14 @@ hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
 typedef struct {
   int iterations;            /* outer iterations done */
   double initial_residual;   /* ||b - A u0||_2 */
-  double final_residual;     /* ||b - A u||_2 (recurrence value, FP64) */
+  double final_residual;     /* true ||b - A u||_2 of the returned u (FP64) */
   double residual_history[256]; /* relative residuals, entry k after iteration k */
   double seconds;            /* wall time of the call */
 } hpmg_solve_info;
 
-/* Solve A u = b to ||b - A u||_2 <= rtol ||b - A u0||_2 with flexible CG
+/* Solve A u = b to ||b - A u||_2 <= rtol ||b - A u0||_2 (the true residual,
+ * recomputed whenever the recurrence converges; the iteration restarts from
+ * it if it misses rtol) with flexible CG
  * preconditioned by one V-cycle (precision from the options) in FP64.  u
  * holds the initial guess on entry.  info may be NULL (host pointer).
  * Returns HPMG_E_NOT_CONVERGED after maxit iterations, HPMG_E_BREAKDOWN on a
