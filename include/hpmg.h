@@ -150,6 +150,56 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
 /* Release every resource of the handle (NULL is ignored). */
 void hpmg_destroy(hpmg_handle h);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent problems (each set up by hpmg_setup, with its own mesh
+ * size and degree) solved together.  Every phase of the V-cycle (sweeps,
+ * residual + restriction, prolongation, Q1 levels, coarsest solve) runs as
+ * one persistent launch over a work list of (problem, cell block,
+ * right-hand side) items covering every problem at that level, so small
+ * and large problems share the chip instead of running one after another;
+ * one outer iteration of all problems is captured once as a HIP graph and
+ * replayed.  This is the GPU counterpart of the task-based execution that
+ * the paper uses to absorb uneven subdomain sizes (Section 6, subsections
+ * on task-based realisation and on imbalanced domain decomposition): here
+ * the uneven units are whole problems, merged into shared launches.
+ */
+typedef struct hpmg_batch_ctx* hpmg_batch; /* opaque, owned by the library */
+
+/* Group `count` handles into a batch (*out; release with
+ * hpmg_batch_destroy).  The handles must stay alive while the batch is
+ * used, must be distinct, and must all be 3D with constant kappa,
+ * 1 <= p <= 5, nu_pre >= 1 and equal nu_pre, nu_post (HPMG_E_INVALID
+ * otherwise).  The batch uses the handles' level data and workspaces:
+ * calls on a handle must not overlap a batch solve that contains it, and a
+ * batch solve invalidates the handle's trace state (as hpmg_solve does). */
+hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out);
+
+/* Solve every problem of the batch like hpmg_solve with the F32 cycle:
+ * flexible CG in FP64 preconditioned by one FP32 V-cycle, until the true
+ * residual satisfies ||b_j - A_j u_j||_2 <= rtol ||b_j - A_j u_j0||_2 for
+ * every problem j and right-hand side.  u[j], b[j] (host array of count
+ * DEVICE pointers each) hold nrhs stacked vectors of problem j
+ * (nrhs <= its max_rhs); u[j] is the initial guess on entry.  Converged
+ * segments stop changing while the others iterate.  infos (host, count
+ * entries, may be NULL) receives per problem the largest iteration count,
+ * initial and final true residual over its right-hand sides
+ * (residual_history is left zero).  The first call for a given nrhs builds
+ * the work lists, picks the persistent grid size by timing the V-cycle of
+ * the batch, and captures the iteration graph; later calls with the same
+ * nrhs reuse them.  Work runs on an internal stream of the batch after the
+ * caller's `stream` is synchronised; the call returns when done.
+ * HPMG_E_NOT_CONVERGED after maxit iterations, HPMG_E_BREAKDOWN if a
+ * segment met a non-finite value. */
+hpmg_status hpmg_batch_solve(hpmg_batch b, double* const* u, const double* const* rhs, int nrhs, double rtol,
+                             int maxit, hpmg_solve_info* infos, hipStream_t stream);
+
+/* Persistent grid size (blocks) chosen for the batch's launches by the
+ * last hpmg_batch_solve (0 before the first). */
+int hpmg_batch_grid(hpmg_batch b);
+
+/* Release the batch (not its handles; NULL is ignored). */
+void hpmg_batch_destroy(hpmg_batch b);
+
 const char* hpmg_status_string(hpmg_status s);
 /* Message of the last failure on the calling thread ("" if none). */
 const char* hpmg_last_error(void);

@@ -74,6 +74,15 @@ _lib.hpmg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes
 _lib.hpmg_solve.restype = ctypes.c_int
 _lib.hpmg_destroy.argtypes = [_vp]
 _lib.hpmg_destroy.restype = None
+_lib.hpmg_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]
+_lib.hpmg_batch_create.restype = ctypes.c_int
+_lib.hpmg_batch_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int, ctypes.POINTER(SolveInfo), _vp]
+_lib.hpmg_batch_solve.restype = ctypes.c_int
+_lib.hpmg_batch_grid.argtypes = [_vp]
+_lib.hpmg_batch_grid.restype = ctypes.c_int
+_lib.hpmg_batch_destroy.argtypes = [_vp]
+_lib.hpmg_batch_destroy.restype = None
 _lib.hpmg_status_string.argtypes = [ctypes.c_int]
 _lib.hpmg_status_string.restype = ctypes.c_char_p
 _lib.hpmg_last_error.argtypes = []
@@ -212,3 +221,47 @@ class Solver:
         if check:
             _check(st, "hpmg_solve")
         return info, st
+
+
+class Batch:
+    """Independent problems solved together (hpmg_batch_create / hpmg_batch_solve).
+
+    The solvers must stay alive while the batch is used; keep references."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (_vp * len(self.solvers))(*[s._h for s in self.solvers])
+        b = _vp()
+        _check(_lib.hpmg_batch_create(arr, len(self.solvers), ctypes.byref(b)), "hpmg_batch_create")
+        self._b = b
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib.hpmg_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def grid(self) -> int:
+        return int(_lib.hpmg_batch_grid(self._b))
+
+    def solve(self, us, bs, rtol: float = 1e-10, maxit: int = 200, nrhs: int = 1, stream=None, check=True):
+        """us[j], bs[j]: FP64 device tensors of nrhs * ndof_j values. Returns (infos, status)."""
+        m = len(self.solvers)
+        if len(us) != m or len(bs) != m:
+            raise ValueError("one u and one b per problem")
+        for s, u, b in zip(self.solvers, us, bs):
+            if u.numel() != nrhs * s.ndof or b.numel() != nrhs * s.ndof:
+                raise ValueError("vector size must be nrhs * ndof")
+        up = (_vp * m)(*[_ptr(u, F64) for u in us])
+        bp = (_vp * m)(*[_ptr(b, F64) for b in bs])
+        infos = (SolveInfo * m)()
+        st = _lib.hpmg_batch_solve(self._b, up, bp, nrhs, rtol, maxit, infos, _stream(stream))
+        if check:
+            _check(st, "hpmg_batch_solve")
+        return list(infos), st

@@ -1,0 +1,695 @@
+// Batched solver: many independent problems (each built by hpmg_setup with
+// its own mesh, degree and max_rhs) solved together.  Every phase of the hp
+// V-cycle runs as one persistent launch over a work list that covers every
+// problem and right-hand side at that level; one iteration of the FP64
+// flexible CG (FP32 V-cycle inside) is captured once as a HIP graph and
+// replayed.  The persistent grid size is chosen by timing the V-cycle
+// (autotuning) at the first solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <memory>
+#include <vector>
+
+#include "batch.hpp"
+#include "internal.hpp"
+
+using namespace hpmg::detail;
+
+namespace {
+
+struct Launch {
+  int kind = 0;  // 0: DG float, 1: DG double, 2: Q1 float
+  int op = 0;
+  const void* args = nullptr;
+  const hpmg::WorkItem* items = nullptr;
+  int nitems = 0;
+};
+
+}  // namespace
+
+// Everything that depends on the number of right-hand sides: workspace,
+// segment tables, launch lists and the captured iteration.
+struct BatchPlan {
+  int nrhs = 0;
+  int grid = 0;  // persistent grid (blocks) of the batched launches, 0: not tuned
+  DevMem mem;
+  double *r = nullptr, *rold = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  float *r32 = nullptr, *z32 = nullptr;
+  double *partial = nullptr, *scal = nullptr;
+  int* count = nullptr;
+  hpmg::SegTable seg{};
+  double** seg_u = nullptr;  // device tables of the caller's vectors, set per call
+  const double** seg_b = nullptr;
+  std::vector<Launch> vcycle, applyp;
+  Launch proj_u, resid_r, resid_q;  // projection of u; b - A u into r or into q
+  hpmg::DGArgs<double>* resid_args = nullptr;
+  std::vector<hpmg::DGArgs<double>> resid_args_h;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~BatchPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+struct hpmg_batch_ctx {
+  std::vector<hpmg_handle> hs;
+  hipStream_t st = nullptr;
+  int* host_count = nullptr;  // pinned
+  std::unique_ptr<BatchPlan> plan;
+  ~hpmg_batch_ctx() {
+    plan.reset();
+    if (host_count) (void)hipHostFree(host_count);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+template <typename T>
+struct Table {
+  std::vector<T> args;
+  std::vector<hpmg::WorkItem> items;
+};
+
+int cpb_of(int N) {
+  switch (N) {
+    case 2: return hpmg::DGShape<3, 2>::CPB;
+    case 3: return hpmg::DGShape<3, 3>::CPB;
+    case 4: return hpmg::DGShape<3, 4>::CPB;
+    case 5: return hpmg::DGShape<3, 5>::CPB;
+    default: return hpmg::DGShape<3, 6>::CPB;
+  }
+}
+
+// Launch builder: collects per-problem arguments and work items, uploads.
+struct Builder {
+  BatchPlan* b;
+  hipStream_t s;
+  template <typename T>
+  Launch dg(int op, Table<hpmg::DGArgs<T>>& t) {
+    Launch L;
+    L.kind = sizeof(T) == 4 ? 0 : 1;
+    L.op = op;
+    if (t.items.empty()) return L;
+    L.args = b->mem.upload(t.args, s);
+    L.items = b->mem.upload(t.items, s);
+    L.nitems = (int)t.items.size();
+    return L;
+  }
+  Launch cg(Table<hpmg::CGArgs<float>>& t) {
+    Launch L;
+    L.kind = 2;
+    if (t.items.empty()) return L;
+    L.args = b->mem.upload(t.args, s);
+    L.items = b->mem.upload(t.items, s);
+    L.nitems = (int)t.items.size();
+    return L;
+  }
+};
+
+template <typename T>
+void add_dg_items(Table<hpmg::DGArgs<T>>& t, const hpmg::DGArgs<T>& a, int N, int nrhs) {
+  const int idx = (int)t.args.size();
+  t.args.push_back(a);
+  const int nb = (a.ncell + cpb_of(N) - 1) / cpb_of(N);
+  for (int r = 0; r < nrhs; ++r)
+    for (int blk = 0; blk < nb; ++blk) t.items.push_back(hpmg::WorkItem{idx, blk, r, N});
+}
+
+void add_cg_items(Table<hpmg::CGArgs<float>>& t, const hpmg::CGArgs<float>& a, int count, int nrhs) {
+  const int idx = (int)t.args.size();
+  t.args.push_back(a);
+  const int nb = (count + 255) / 256;
+  for (int r = 0; r < nrhs; ++r)
+    for (int blk = 0; blk < nb; ++blk) t.items.push_back(hpmg::WorkItem{idx, blk, r, 0});
+}
+
+// Per-problem cursor through the V-cycle schedule.
+struct PState {
+  int ndg = 0, ncg = 0;
+  std::vector<int> dgcur, cgcur;  // current trace buffer / current Q1 iterate
+};
+
+// FP32 V-cycle of every problem with a zero initial guess on level 0
+// (u = z32 segment, b = r32 segment), as a list of batched launches.
+void build_vcycle(BatchPlan* B, const std::vector<hpmg_handle>& hs, const std::vector<size_t>& off0, hipStream_t s) {
+  Builder bld{B, s};
+  const int R = B->nrhs;
+  const int np = (int)hs.size();
+  std::vector<PState> ps(np);
+  int lmax = 0;
+  for (int j = 0; j < np; ++j) {
+    ps[j].ndg = (int)hs[j]->dg.size();
+    ps[j].ncg = (int)hs[j]->cg.size();
+    ps[j].dgcur.assign(ps[j].ndg, 0);
+    ps[j].cgcur.assign(ps[j].ncg, 0);
+    lmax = std::max(lmax, ps[j].ndg + ps[j].ncg);
+  }
+  const hpmg_options& O = hs[0]->opt;
+  // level-l vectors of problem j
+  auto dg_u = [&](int j, int l) -> float* { return l == 0 ? B->z32 + off0[j] : hs[j]->dg[l].f.u; };
+  auto dg_b = [&](int j, int l) -> float* { return l == 0 ? B->r32 + off0[j] : hs[j]->dg[l].f.b; };
+
+  std::vector<Launch>& out = B->vcycle;
+  // recursive descent over the level index
+  std::function<void(int)> rec = [&](int l) {
+    std::vector<int> P;
+    for (int j = 0; j < np; ++j)
+      if (l < ps[j].ndg + ps[j].ncg) P.push_back(j);
+    if (P.empty()) return;
+    auto is_dg = [&](int j) { return l < ps[j].ndg; };
+    auto cgl = [&](int j) { return l - ps[j].ndg; };
+    auto coarsest = [&](int j) { return !is_dg(j) && cgl(j) == ps[j].ncg - 1; };
+    // coarsest levels: dense solve
+    {
+      Table<hpmg::CGArgs<float>> t;
+      for (int j : P)
+        if (coarsest(j)) {
+          hpmg_ctx* h = hs[j];
+          CGLevel& C = h->cg[cgl(j)];
+          hpmg::CGArgs<float> a{};
+          a.op = hpmg::CGOP_DENSE;
+          a.m = h->coarse_m;
+          a.Ainv = h->coarse_inv;
+          a.in = C.f.b;
+          a.out = C.f.u[0];
+          a.sin = a.sout = (long long)C.size;
+          ps[j].cgcur[cgl(j)] = 0;
+          add_cg_items(t, a, a.m, R);
+        }
+      Launch L = bld.cg(t);
+      if (L.nitems) out.push_back(L);
+    }
+    // pre-smoothing
+    for (int i = 0; i < O.nu_pre; ++i) {
+      Table<hpmg::DGArgs<float>> td;
+      Table<hpmg::CGArgs<float>> tc;
+      for (int j : P) {
+        hpmg_ctx* h = hs[j];
+        if (is_dg(j)) {
+          DGLevel& L = h->dg[l];
+          int& cur = ps[j].dgcur[l];
+          hpmg::DGArgs<float> a = dg_args<float>(h, L);
+          a.u_in = a.u_out = dg_u(j, l);
+          a.b = dg_b(j, l);
+          a.tr_in = L.f.tr[cur];
+          a.tr_out = L.f.tr[cur ^ 1];
+          cur ^= 1;
+          add_dg_items(td, a, L.N, R);
+        } else if (!coarsest(j)) {
+          CGLevel& C = h->cg[cgl(j)];
+          int& cur = ps[j].cgcur[cgl(j)];
+          hpmg::CGArgs<float> a{};
+          a.op = hpmg::CGOP_JACOBI;
+          a.nv = C.nv;
+          a.uzero = i == 0;
+          a.omega = (float)O.omega_cg;
+          a.st = C.f.st;
+          a.dinv = C.f.dinv;
+          a.u = C.f.u[cur];
+          a.b = C.f.b;
+          a.out = C.f.u[cur ^ 1];
+          a.su = a.sb = a.sout = (long long)C.size;
+          cur ^= 1;
+          add_cg_items(tc, a, (int)C.size, R);
+        }
+      }
+      Launch L1 = bld.dg<float>(i == 0 ? hpmg::BOP_SWEEP0 : hpmg::BOP_SWEEP, td);
+      if (L1.nitems) out.push_back(L1);
+      Launch L2 = bld.cg(tc);
+      if (L2.nitems) out.push_back(L2);
+    }
+    // residual and restriction
+    {
+      Table<hpmg::DGArgs<float>> td;
+      Table<hpmg::CGArgs<float>> tg, tr, tre;
+      for (int j : P) {
+        hpmg_ctx* h = hs[j];
+        if (is_dg(j)) {
+          DGLevel& L = h->dg[l];
+          hpmg::DGArgs<float> a = dg_args<float>(h, L);
+          a.u_in = dg_u(j, l);
+          a.b = dg_b(j, l);
+          a.tr_in = L.f.tr[ps[j].dgcur[l]];
+          if (!L.next_cg) {
+            a.out = h->dg[l + 1].f.b;
+            a.cstride = (long long)h->dg[l + 1].ndof;
+          } else {
+            a.out = L.f.contrib;
+            a.cstride = (long long)h->ncell << 3;
+            CGLevel& C = h->cg[0];
+            hpmg::CGArgs<float> g{};
+            g.op = hpmg::CGOP_GATHER;
+            g.n = h->n;
+            g.in = L.f.contrib;
+            g.out = C.f.b;
+            g.sin = (long long)h->ncell << 3;
+            g.sout = (long long)C.size;
+            add_cg_items(tg, g, (int)C.size, R);
+          }
+          add_dg_items(td, a, L.N, R);
+        } else if (!coarsest(j)) {
+          CGLevel& C = h->cg[cgl(j)];
+          CGLevel& Cc = h->cg[cgl(j) + 1];
+          hpmg::CGArgs<float> a{};
+          a.op = hpmg::CGOP_RESID;
+          a.nv = C.nv;
+          a.st = C.f.st;
+          a.u = C.f.u[ps[j].cgcur[cgl(j)]];
+          a.b = C.f.b;
+          a.out = C.f.r;
+          a.su = a.sb = a.sout = (long long)C.size;
+          add_cg_items(tr, a, (int)C.size, R);
+          hpmg::CGArgs<float> rr{};
+          rr.op = hpmg::CGOP_RESTRICT;
+          rr.nv = C.nv;
+          rr.nvc = Cc.nv;
+          rr.idx = C.ridx;
+          rr.w = C.f.rw;
+          rr.in = C.f.r;
+          rr.out = Cc.f.b;
+          rr.sin = (long long)C.size;
+          rr.sout = (long long)Cc.size;
+          add_cg_items(tre, rr, (int)Cc.size, R);
+        }
+      }
+      Launch L1 = bld.dg<float>(hpmg::BOP_RESTRICT, td);
+      if (L1.nitems) out.push_back(L1);
+      Launch L2 = bld.cg(tg);
+      if (L2.nitems) out.push_back(L2);
+      Launch L3 = bld.cg(tr);
+      if (L3.nitems) out.push_back(L3);
+      Launch L4 = bld.cg(tre);
+      if (L4.nitems) out.push_back(L4);
+    }
+    rec(l + 1);
+    // prolongation
+    {
+      Table<hpmg::DGArgs<float>> td;
+      Table<hpmg::CGArgs<float>> tc;
+      for (int j : P) {
+        if (coarsest(j)) continue;
+        hpmg_ctx* h = hs[j];
+        if (is_dg(j)) {
+          DGLevel& L = h->dg[l];
+          hpmg::DGArgs<float> a = dg_args<float>(h, L);
+          a.u_in = a.u_out = dg_u(j, l);
+          a.tr_out = L.f.tr[ps[j].dgcur[l]];
+          if (!L.next_cg) {
+            a.coarse = h->dg[l + 1].f.u;
+            a.coarse_cg = 0;
+            a.cstride = (long long)h->dg[l + 1].ndof;
+          } else {
+            a.coarse = h->cg[0].f.u[ps[j].cgcur[0]];
+            a.coarse_cg = 1;
+            a.cstride = (long long)h->cg[0].size;
+          }
+          add_dg_items(td, a, L.N, R);
+        } else {
+          CGLevel& C = h->cg[cgl(j)];
+          CGLevel& Cc = h->cg[cgl(j) + 1];
+          hpmg::CGArgs<float> a{};
+          a.op = hpmg::CGOP_PROLONG;
+          a.nv = C.nv;
+          a.nvc = Cc.nv;
+          a.idx = C.pidx;
+          a.w = C.f.pw;
+          a.in = Cc.f.u[ps[j].cgcur[cgl(j) + 1]];
+          a.out = C.f.u[ps[j].cgcur[cgl(j)]];
+          a.sin = (long long)Cc.size;
+          a.sout = (long long)C.size;
+          add_cg_items(tc, a, (int)C.size, R);
+        }
+      }
+      Launch L1 = bld.dg<float>(hpmg::BOP_PROLONG, td);
+      if (L1.nitems) out.push_back(L1);
+      Launch L2 = bld.cg(tc);
+      if (L2.nitems) out.push_back(L2);
+    }
+    // post-smoothing
+    for (int i = 0; i < O.nu_post; ++i) {
+      Table<hpmg::DGArgs<float>> td;
+      Table<hpmg::CGArgs<float>> tc;
+      for (int j : P) {
+        if (coarsest(j)) continue;
+        hpmg_ctx* h = hs[j];
+        if (is_dg(j)) {
+          DGLevel& L = h->dg[l];
+          int& cur = ps[j].dgcur[l];
+          hpmg::DGArgs<float> a = dg_args<float>(h, L);
+          a.u_in = a.u_out = dg_u(j, l);
+          a.b = dg_b(j, l);
+          a.tr_in = L.f.tr[cur];
+          a.tr_out = L.f.tr[cur ^ 1];
+          cur ^= 1;
+          add_dg_items(td, a, L.N, R);
+        } else {
+          CGLevel& C = h->cg[cgl(j)];
+          int& cur = ps[j].cgcur[cgl(j)];
+          hpmg::CGArgs<float> a{};
+          a.op = hpmg::CGOP_JACOBI;
+          a.nv = C.nv;
+          a.uzero = 0;
+          a.omega = (float)O.omega_cg;
+          a.st = C.f.st;
+          a.dinv = C.f.dinv;
+          a.u = C.f.u[cur];
+          a.b = C.f.b;
+          a.out = C.f.u[cur ^ 1];
+          a.su = a.sb = a.sout = (long long)C.size;
+          cur ^= 1;
+          add_cg_items(tc, a, (int)C.size, R);
+        }
+      }
+      Launch L1 = bld.dg<float>(hpmg::BOP_SWEEP, td);
+      if (L1.nitems) out.push_back(L1);
+      Launch L2 = bld.cg(tc);
+      if (L2.nitems) out.push_back(L2);
+    }
+  };
+  rec(0);
+}
+
+void run(BatchPlan* B, const std::vector<Launch>& v, hipStream_t s) {
+  const int grid = B->grid > 0 ? B->grid : 1024;  // before tuning: a default
+  for (const Launch& L : v) {
+    if (L.kind == 0)
+      hpmg::batch_dg<float>(L.op, (const hpmg::DGArgs<float>*)L.args, L.items, L.nitems, grid, s);
+    else if (L.kind == 1)
+      hpmg::batch_dg<double>(L.op, (const hpmg::DGArgs<double>*)L.args, L.items, L.nitems, grid, s);
+    else
+      hpmg::batch_cg<float>((const hpmg::CGArgs<float>*)L.args, L.items, L.nitems, grid, s);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+// One iteration of the flexible CG for every segment.
+void iteration(BatchPlan* B, double rtol2, hipStream_t s) {
+  const hpmg::SegTable& t = B->seg;
+  hpmg::bk_cast_down(t, B->r, B->r32, B->scal, s);
+  run(B, B->vcycle, s);
+  hpmg::bk_cast_up(t, B->z32, B->z, B->scal, s);
+  hpmg::bk_dot(t, B->z, B->r, B->rold, B->partial, s);
+  hpmg::bk_finalize(t, 1, B->partial, B->scal, rtol2, s);
+  hpmg::bk_update_p(t, B->z, B->p, B->scal, s);
+  run(B, B->applyp, s);
+  hpmg::bk_dot(t, B->p, B->q, nullptr, B->partial, s);
+  hpmg::bk_finalize(t, 2, B->partial, B->scal, rtol2, s);
+  hpmg::bk_update_ur(t, B->r, B->rold, B->p, B->q, B->scal, B->partial, s);
+  hpmg::bk_finalize(t, 3, B->partial, B->scal, rtol2, s);
+  hpmg::bk_count(t, B->scal, B->count, s);
+  HIPCHK(hipGetLastError());
+}
+
+// b - A u of the caller's vectors (FP64) into r (into_q = false) or q
+void residual(BatchPlan* B, bool into_q, hipStream_t s) {
+  run(B, {B->proj_u, into_q ? B->resid_q : B->resid_r}, s);
+}
+
+// Workspace, segment tables and launch lists for nrhs right-hand sides.
+std::unique_ptr<BatchPlan> make_plan(const std::vector<hpmg_handle>& hs, int nrhs, hipStream_t s) {
+  std::unique_ptr<BatchPlan> B(new BatchPlan());
+  B->nrhs = nrhs;
+  const int np = (int)hs.size(), R = nrhs;
+  // segments: one per (problem, right-hand side), [problem][rhs][dof] in
+  // the workspace vectors
+  std::vector<size_t> off0(np);
+  std::vector<long long> seg_off;
+  std::vector<int> seg_len, cstart, ccount;
+  std::vector<int2> chunks;
+  size_t tot = 0;
+  for (int j = 0; j < np; ++j) {
+    off0[j] = tot;
+    const size_t nd = hs[j]->ndof;
+    for (int r = 0; r < R; ++r) {
+      seg_off.push_back((long long)(tot + r * nd));
+      seg_len.push_back((int)nd);
+      cstart.push_back((int)chunks.size());
+      int cnt = 0;
+      for (size_t e = 0; e < nd; e += hpmg::BATCH_CHUNK, ++cnt)
+        chunks.push_back(int2{(int)seg_off.size() - 1, (int)e});
+      ccount.push_back(cnt);
+    }
+    tot += nd * R;
+  }
+  DevMem& M = B->mem;
+  B->r = (double*)M.alloc(tot * sizeof(double));
+  B->rold = (double*)M.alloc(tot * sizeof(double));
+  B->z = (double*)M.alloc(tot * sizeof(double));
+  B->p = (double*)M.alloc(tot * sizeof(double));
+  B->q = (double*)M.alloc(tot * sizeof(double));
+  B->r32 = (float*)M.alloc(tot * sizeof(float));
+  B->z32 = (float*)M.alloc(tot * sizeof(float));
+  const int nseg = (int)seg_off.size();
+  B->partial = (double*)M.alloc(2 * chunks.size() * sizeof(double));
+  B->scal = (double*)M.alloc((size_t)nseg * hpmg::BATCH_SCAL * sizeof(double));
+  B->count = (int*)M.alloc(4 * sizeof(int));
+  B->seg.off = M.upload(seg_off, s);
+  B->seg.len = M.upload(seg_len, s);
+  B->seg.chunks = M.upload(chunks, s);
+  B->seg.cstart = M.upload(cstart, s);
+  B->seg.ccount = M.upload(ccount, s);
+  B->seg.nseg = nseg;
+  B->seg.nchunks = (int)chunks.size();
+  B->seg_u = (double**)M.alloc(nseg * sizeof(double*));
+  B->seg_b = (const double**)M.alloc(nseg * sizeof(double*));
+  B->seg.u = B->seg_u;
+  B->seg.b = B->seg_b;
+  // FP32 V-cycle of every problem
+  build_vcycle(B.get(), hs, off0, s);
+  // FP64 q = A p (projection, then apply) and b - A u of the caller's vectors
+  Builder bld{B.get(), s};
+  Table<hpmg::DGArgs<double>> tp, ta, tpu, tr;
+  for (int j = 0; j < np; ++j) {
+    hpmg_ctx* h = hs[j];
+    DGLevel& L = h->dg[0];
+    hpmg::DGArgs<double> a = dg_args<double>(h, L);
+    a.u_in = B->p + off0[j];
+    a.tr_out = L.d.tr[0];
+    add_dg_items(tp, a, L.N, R);
+    hpmg::DGArgs<double> c = dg_args<double>(h, L);
+    c.u_in = B->p + off0[j];
+    c.tr_in = L.d.tr[0];
+    c.out = B->q + off0[j];
+    add_dg_items(ta, c, L.N, R);
+    hpmg::DGArgs<double> pu = dg_args<double>(h, L);
+    pu.tr_out = L.d.tr[0];
+    add_dg_items(tpu, pu, L.N, R);
+    hpmg::DGArgs<double> rr = dg_args<double>(h, L);
+    rr.tr_in = L.d.tr[0];
+    add_dg_items(tr, rr, L.N, R);
+  }
+  B->applyp.push_back(bld.dg<double>(hpmg::BOP_PROJECT, tp));
+  B->applyp.push_back(bld.dg<double>(hpmg::BOP_APPLY, ta));
+  // the residual launches share one argument table whose u, b are the
+  // caller's, set per call: [0, np) projection of u, [np, 2np) b - A u
+  // into r, [2np, 3np) the same into q
+  std::vector<hpmg::DGArgs<double>> all = tpu.args;
+  for (int k = 1; k <= 2; ++k)
+    for (int j = 0; j < np; ++j) {
+      all.push_back(tr.args[j]);
+      all.back().out = (k == 1 ? B->r : B->q) + off0[j];
+    }
+  B->resid_args = (hpmg::DGArgs<double>*)M.alloc(all.size() * sizeof(hpmg::DGArgs<double>));
+  B->resid_args_h = all;
+  auto shifted = [&](int by) {
+    std::vector<hpmg::WorkItem> v = tr.items;
+    for (auto& w : v) w.x += by;
+    return M.upload(v, s);
+  };
+  const int nt = (int)tr.items.size();
+  B->proj_u = Launch{1, hpmg::BOP_PROJECT, B->resid_args, M.upload(tpu.items, s), (int)tpu.items.size()};
+  B->resid_r = Launch{1, hpmg::BOP_RESID, B->resid_args, shifted(np), nt};
+  B->resid_q = Launch{1, hpmg::BOP_RESID, B->resid_args, shifted(2 * np), nt};
+  HIPCHK(hipStreamSynchronize(s));
+  return B;
+}
+
+// Persistent grid size: the fastest of a few candidates on the V-cycle of
+// the batch (run on the current r32).
+int autotune_grid(BatchPlan* B, hipStream_t s) {
+  int best = 1024;
+  double tbest = 1e30;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int g : {256, 512, 1024, 2048, 4096}) {
+    B->grid = g;
+    run(B, B->vcycle, s);  // warm-up
+    HIPCHK(hipEventRecord(e0, s));
+    run(B, B->vcycle, s);
+    run(B, B->vcycle, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < tbest) {
+      tbest = ms;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out) {
+  try {
+    require(out != nullptr, "out is NULL");
+    *out = nullptr;
+    require(hs != nullptr && count >= 1, "need at least one handle");
+    std::unique_ptr<hpmg_batch_ctx> B(new hpmg_batch_ctx());
+    for (int j = 0; j < count; ++j) {
+      hpmg_ctx* h = hs[j];
+      require(h != nullptr, "NULL handle in batch");
+      for (int k = 0; k < j; ++k) require(hs[k] != h, "a handle appears twice in the batch");
+      require(h->dim == 3, "batched solver supports dim = 3");
+      require(!h->vark, "batched solver supports constant kappa");
+      require(h->p + 1 >= hpmg::BATCH_NMIN && h->p + 1 <= hpmg::BATCH_NMAX, "batched solver supports 1 <= p <= 5");
+      require(h->opt.nu_pre >= 1, "batched solver needs nu_pre >= 1");
+      require(h->opt.nu_pre == hs[0]->opt.nu_pre && h->opt.nu_post == hs[0]->opt.nu_post,
+              "all problems of a batch need the same nu_pre, nu_post");
+      B->hs.push_back(h);
+    }
+    HIPCHK(hipStreamCreateWithFlags(&B->st, hipStreamNonBlocking));
+    HIPCHK(hipHostMalloc((void**)&B->host_count, 4 * sizeof(int), hipHostMallocDefault));
+    *out = B.release();
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    set_last_error(e.what());
+    return e.st;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return HPMG_E_NOMEM;
+  }
+}
+
+void hpmg_batch_destroy(hpmg_batch b) { delete b; }
+
+int hpmg_batch_grid(hpmg_batch b) { return b && b->plan ? b->plan->grid : 0; }
+
+hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* const* b, int nrhs, double rtol,
+                             int maxit, hpmg_solve_info* infos, hipStream_t stream) {
+  try {
+    require(bt && u && b, "NULL argument");
+    require(nrhs >= 1, "nrhs must be >= 1");
+    require(rtol > 0.0 && maxit >= 1, "bad rtol/maxit");
+    const auto t0 = std::chrono::steady_clock::now();
+    const std::vector<hpmg_handle>& hs = bt->hs;
+    const int np = (int)hs.size(), R = nrhs;
+    for (int j = 0; j < np; ++j) {
+      require(u[j] && b[j], "NULL vector in batch");
+      require(hs[j]->opt.max_rhs >= nrhs, "nrhs exceeds a handle's max_rhs");
+      hs[j]->trace_state[0] = hs[j]->trace_state[1] = -1;
+    }
+    hipStream_t s = bt->st;
+    // work queued on the caller's stream (e.g. writes of u, b) completes first
+    HIPCHK(hipStreamSynchronize(stream));
+    if (!bt->plan || bt->plan->nrhs != nrhs) {
+      bt->plan.reset();
+      bt->plan = make_plan(hs, nrhs, s);
+    }
+    BatchPlan* B = bt->plan.get();
+    std::vector<double*> su;
+    std::vector<const double*> sb;
+    for (int j = 0; j < np; ++j) {
+      const size_t nd = hs[j]->ndof;
+      for (int r = 0; r < R; ++r) {
+        su.push_back(u[j] + r * nd);
+        sb.push_back(b[j] + r * nd);
+      }
+      for (int k = 0; k < 3; ++k) {
+        B->resid_args_h[k * np + j].u_in = u[j];
+        B->resid_args_h[k * np + j].b = b[j];
+      }
+    }
+    HIPCHK(hipMemcpyAsync(B->seg_u, su.data(), su.size() * sizeof(double*), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B->seg_b, sb.data(), sb.size() * sizeof(double*), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(B->resid_args, B->resid_args_h.data(),
+                          B->resid_args_h.size() * sizeof(hpmg::DGArgs<double>), hipMemcpyHostToDevice, s));
+    const double rtol2 = rtol * rtol;
+    int* hc = bt->host_count;
+    auto sync_count = [&]() {
+      HIPCHK(hipMemcpyAsync(hc, B->count, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    };
+    // initial residual
+    residual(B, false, s);
+    hpmg::bk_dot(B->seg, B->r, B->r, nullptr, B->partial, s);
+    hpmg::bk_finalize(B->seg, 4, B->partial, B->scal, rtol2, s);
+    hpmg::bk_count(B->seg, B->scal, B->count, s);
+    if (B->grid == 0) {
+      hpmg::bk_cast_down(B->seg, B->r, B->r32, B->scal, s);
+      B->grid = autotune_grid(B, s);
+    }
+    // one flexible-CG iteration of every segment, captured once and replayed
+    if (!B->exec) {
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      iteration(B, rtol2, s);
+      HIPCHK(hipStreamEndCapture(s, &B->graph));
+      HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    }
+    sync_count();
+    int it = 0;
+    while (hc[0] > 0 && it < maxit) {
+      HIPCHK(hipGraphLaunch(B->exec, s));
+      ++it;
+      sync_count();
+      if (hc[1] > 0) {
+        // true residual of the segments whose recurrence converged; those
+        // that miss the tolerance restart from it
+        residual(B, true, s);
+        hpmg::bk_dot(B->seg, B->q, B->q, nullptr, B->partial, s);
+        hpmg::bk_finalize(B->seg, 5, B->partial, B->scal, rtol2, s);
+        hpmg::bk_select(B->seg, B->q, B->r, B->scal, s);
+        hpmg::bk_count(B->seg, B->scal, B->count, s);
+        sync_count();
+      }
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (infos) {
+      std::vector<double> sc((size_t)B->seg.nseg * hpmg::BATCH_SCAL);
+      HIPCHK(hipMemcpy(sc.data(), B->scal, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int j = 0; j < np; ++j) {
+        hpmg_solve_info& I = infos[j];
+        I.iterations = 0;
+        I.initial_residual = 0.0;
+        I.final_residual = 0.0;
+        for (int r = 0; r < R; ++r) {
+          const double* q = &sc[(size_t)(j * R + r) * hpmg::BATCH_SCAL];
+          I.iterations = std::max(I.iterations, (int)q[13]);
+          I.initial_residual = std::max(I.initial_residual, std::sqrt(q[9]));
+          I.final_residual = std::max(I.final_residual, std::sqrt(q[12]));
+        }
+        for (int k = 0; k < 256; ++k) I.residual_history[k] = 0.0;
+        I.seconds = secs;
+      }
+    }
+    if (hc[2] > 0) {
+      set_last_error("breakdown (non-finite value or zero curvature) in a batched solve");
+      return HPMG_E_BREAKDOWN;
+    }
+    if (hc[0] > 0) {
+      set_last_error("maximum number of iterations reached");
+      return HPMG_E_NOT_CONVERGED;
+    }
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    set_last_error(e.what());
+    return e.st;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return HPMG_E_NOMEM;
+  }
+}
+
+}  // extern "C"

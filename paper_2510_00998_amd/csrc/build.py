@@ -25,6 +25,8 @@ SOURCES = [
     "dg_inst_2d_float.hip",
     "dg_inst_2d_double.hip",
     "dg_inst_3d_float.hip",
+    "batch_kernels.hip",
+    "batch.cpp",
     "dg_inst_3d_double.hip",
 ]
 

@@ -76,6 +76,14 @@ __device__ __forceinline__ float recip(float d) {
   return __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
 }
 
+// Thread index within the block's NT working threads; threads beyond NT
+// (a batched launch uses one block size for every degree) get an index past
+// every work range, so they only take part in the barriers.
+template <int D, int N>
+__device__ __forceinline__ int work_tid() {
+  return threadIdx.x < DGShape<D, N>::NT ? (int)threadIdx.x : (1 << 28);
+}
+
 // Boundary mask of a cell (bit f = 2k + side set: facet f on the domain
 // boundary); the class of the cell along axis k is (mask >> 2k) & 3.
 __device__ __forceinline__ int axis_class(int mask, int k) { return (mask >> (2 * k)) & 3; }
@@ -93,7 +101,7 @@ template <typename T, int D, int N, bool VARK>
 __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, T* sE, T* sKF) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
-  const int tid = threadIdx.x;
+  const int tid = work_tid<D, N>();
   if constexpr (!VARK) {
     for (int i = tid; i < 4 * Sh::EGS; i += Sh::NT) sE[i] = a.eig[i];
   } else {
@@ -123,7 +131,7 @@ __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
-  for (int i = threadIdx.x; i < nc * D * NN; i += Sh::NT) {
+  for (int i = work_tid<D, N>(); i < nc * D * NN; i += Sh::NT) {
     const int e = i % NN, ck = i / NN;
     const int r = e / N, col = e % N;
     const T* S = sE + ck * Sh::EGS;
@@ -191,7 +199,7 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
   constexpr int TL = 2 * L;
   constexpr int LINES = (D == 2) ? 1 : N;
   const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
-  for (int i = threadIdx.x; i < Sh::CPB * Sh::NF * LINES; i += Sh::NT) {
+  for (int i = work_tid<D, N>(); i < Sh::CPB * Sh::NF * LINES; i += Sh::NT) {
     const int f = i / (Sh::CPB * LINES), rem = i % (Sh::CPB * LINES);
     const int cl = rem / LINES, li = rem % LINES;
     if (cl >= nc) continue;
@@ -272,7 +280,7 @@ __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const 
     const int st = ipow<D>(a.n, k);
     const int off = s ? st : -st;
     const T* src = tr + (size_t)(f ^ 1) * a.ncell * TL;
-    for (int i = threadIdx.x; i < nc * TL; i += Sh::NT) {
+    for (int i = work_tid<D, N>(); i < nc * TL; i += Sh::NT) {
       const int cl = i / TL, e = i % TL;
       const int c = c0 + cl;
       const bool bdy = (a.bmask[c] >> f) & 1;
@@ -376,20 +384,28 @@ __device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, co
 // sweep of a coarse-level smoothing with zero initial guess): u and the
 // neighbour traces are not read.  The x-line of u and b of each thread
 // stay in registers from the load to the update.
+// LDS bytes of the sweep / apply bodies.
+template <typename T, int D, int N, bool VARK>
+constexpr int cell_lds_bytes() {
+  using Sh = DGShape<D, N>;
+  return (int)sizeof(T) *
+         (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK>::SIZE + (VARK ? Sh::CPB * Sh::NF : 1));
+}
+
 template <typename T, int D, int N, bool UZERO, bool VARK>
-__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_sweep(DGArgs<T> a) {
+__device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
-  __shared__ T sW[Sh::CPB * Sh::NV];
-  __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
-  __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
-  __shared__ T sKF[VARK ? Sh::CPB * Sh::NF : 1];
+  T* sW = (T*)lds;
+  T* sNB = sW + Sh::CPB * Sh::NV;
+  T* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
+  T* sKF = sE + EigLDS<D, N, VARK>::SIZE;
 
-  const int c0 = blockIdx.x * Sh::CPB;
+  const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
-  const size_t rv = (size_t)blockIdx.y * a.vstride, rt = (size_t)blockIdx.y * a.tstride;
-  const int tid = threadIdx.x;
+  const size_t rv = (size_t)by * a.vstride, rt = (size_t)by * a.tstride;
+  const int tid = work_tid<D, N>();
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
   const int c = c0 + (act ? cl : 0);
@@ -488,6 +504,12 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_sweep(DGArgs<T> a) {
   if (act) store_yz_traces<T, D, N>(a, trout, sW, cl, c, mask, ln);
 }
 
+template <typename T, int D, int N, bool UZERO, bool VARK>
+__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_sweep(DGArgs<T> a) {
+  __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
+  sweep_body<T, D, N, UZERO, VARK>(a, blockIdx.x, blockIdx.y, lds);
+}
+
 // ---------------------------------------------------------------------------
 // y = A u (RESID: r = b - A u), optionally restricted to the next coarser
 // level: NC > 0 gives per cell (E^T x E^T x E^T) r with E the interpolation
@@ -495,19 +517,19 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_sweep(DGArgs<T> a) {
 // contributions of each cell, summed over cells by the gather kernel).
 // Needs the traces of u in tr_in.
 template <typename T, int D, int N, int NC, bool RESID, bool VARK>
-__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_apply(DGArgs<T> a) {
+__device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
-  __shared__ T sW[Sh::CPB * Sh::NV];
-  __shared__ T sNB[Sh::CPB * Sh::NF * 2 * L];
-  __shared__ T sE[EigLDS<D, N, VARK>::SIZE];
-  __shared__ T sKF[VARK ? Sh::CPB * Sh::NF : 1];
+  T* sW = (T*)lds;
+  T* sNB = sW + Sh::CPB * Sh::NV;
+  T* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
+  T* sKF = sE + EigLDS<D, N, VARK>::SIZE;
 
-  const int c0 = blockIdx.x * Sh::CPB;
+  const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
-  const size_t rv = (size_t)blockIdx.y * a.vstride, rt = (size_t)blockIdx.y * a.tstride;
-  const int tid = threadIdx.x;
+  const size_t rv = (size_t)by * a.vstride, rt = (size_t)by * a.tstride;
+  const int tid = work_tid<D, N>();
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
   const int c = c0 + (act ? cl : 0);
@@ -601,7 +623,7 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_apply(DGArgs<T> a) {
     const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
     constexpr int NCD = (D == 2) ? NC * NC : NC * NC * NC;
     constexpr int NBS = Sh::NF * 2 * L;  // per-cell stride of sNB
-    T* dst = a.out + (size_t)blockIdx.y * a.cstride + (size_t)c0 * NCD;
+    T* dst = a.out + (size_t)by * a.cstride + (size_t)c0 * NCD;
     // x: sW[cl][..][a] -> sNB[cl][ln][a'] (a' + NC*ln)
     for (int i = tid; i < nc * L; i += Sh::NT) {
       const int c2 = i / L, l2 = i % L;
@@ -667,23 +689,35 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_apply(DGArgs<T> a) {
   }
 }
 
+template <typename T, int D, int N, int NC, bool RESID, bool VARK>
+__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_apply(DGArgs<T> a) {
+  __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
+  apply_body<T, D, N, NC, RESID, VARK>(a, blockIdx.x, blockIdx.y, lds);
+}
+
 // ---------------------------------------------------------------------------
 // u += P e (NC > 0; DG_q cell vector or Q1 vertex vector) and projection of
 // u onto the facet traces (NC = 0: projection only, the warm-up traversal of
 // Algorithm BlockJacobi; NC > 0: fused prolongation + projection,
 // Section 5.1.1).
 template <typename T, int D, int N, int NC>
-__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_prolong(DGArgs<T> a) {
+constexpr int prolong_lds_bytes() {
+  using Sh = DGShape<D, N>;
+  return (int)sizeof(T) * (Sh::CPB * Sh::NV + (NC > 0 ? Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L : 0));
+}
+
+template <typename T, int D, int N, int NC>
+__device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
-  __shared__ T sU[Sh::CPB * Sh::NV];
-  __shared__ T sW[NC > 0 ? Sh::CPB * Sh::NV : 1];
-  __shared__ T sNB[NC > 0 ? Sh::CPB * Sh::NF * 2 * L : 1];
+  T* sU = (T*)lds;
+  T* sW = sU + Sh::CPB * Sh::NV;
+  T* sNB = sW + Sh::CPB * Sh::NV;
 
-  const int c0 = blockIdx.x * Sh::CPB;
+  const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
-  const size_t rv = (size_t)blockIdx.y * a.vstride, rt = (size_t)blockIdx.y * a.tstride;
-  const int tid = threadIdx.x;
+  const size_t rv = (size_t)by * a.vstride, rt = (size_t)by * a.tstride;
+  const int tid = work_tid<D, N>();
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
   const int c = c0 + (act ? cl : 0);
@@ -697,7 +731,7 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_prolong(DGArgs<T> a) {
     for (int j = 0; j < N; ++j) u[j] = us[j];
   }
   if constexpr (NC > 0) {
-    const T* cs = a.coarse + (size_t)blockIdx.y * a.cstride;
+    const T* cs = a.coarse + (size_t)by * a.cstride;
     if (!a.coarse_cg) {
       for (int i = tid; i < nc * NCD; i += Sh::NT) sW[(i / NCD) * Sh::NV + i % NCD] = cs[(size_t)c0 * NCD + i];
     } else {
@@ -807,6 +841,12 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_prolong(DGArgs<T> a) {
   }
   __syncthreads();
   if (act) store_yz_traces<T, D, N>(a, trout, sU, cl, c, mask, ln);
+}
+
+template <typename T, int D, int N, int NC>
+__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_prolong(DGArgs<T> a) {
+  __shared__ __attribute__((aligned(16))) char lds[prolong_lds_bytes<T, D, N, NC>()];
+  prolong_body<T, D, N, NC>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 }  // namespace dgk

@@ -1,0 +1,188 @@
+// Internal state of a libhpmg handle, shared by the single-problem and the
+// batched drivers (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "hpmg.h"
+#include "kernels.hpp"
+
+namespace hpmg {
+namespace detail {
+
+void set_last_error(const std::string& m);
+
+
+
+struct HpmgError : std::runtime_error {
+  hpmg_status st;
+  HpmgError(hpmg_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHK(expr)                                                                                       \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess)                                                                                  \
+      throw HpmgError(e_ == hipErrorOutOfMemory ? HPMG_E_NOMEM : HPMG_E_DEVICE,                           \
+                      std::string(#expr) + ": " + hipGetErrorString(e_));                                  \
+  } while (0)
+
+inline void require(bool c, const std::string& msg) {
+  if (!c) throw HpmgError(HPMG_E_INVALID, msg);
+}
+
+// Device allocation owned by the handle.
+struct DevMem {
+  std::vector<void*> ptrs;
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    HIPCHK(hipMalloc(&p, bytes));
+    ptrs.push_back(p);
+    return p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = (T*)alloc(v.size() * sizeof(T));
+    HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  ~DevMem() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+inline int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// Per-precision device data of one DG level.
+template <typename T>
+struct DGData {
+  T* ref = nullptr;
+  T* eig = nullptr;
+  T* kappa = nullptr;
+  T* u = nullptr;        // coarse levels only
+  T* b = nullptr;        // coarse levels only
+  T* tr[2] = {nullptr, nullptr};
+  T* contrib = nullptr;  // corner contributions (last DG level, restriction to Q1)
+};
+
+struct DGLevel {
+  int p = 0, N = 0, NC = 0;  // NC: nodes per direction of the next coarser level (2: Q1)
+  bool next_cg = false;
+  double sigma_hat = 0.0;
+  size_t ndof = 0, trsize = 0;  // per right-hand side
+  DGData<double> d;
+  DGData<float> f;
+};
+
+template <typename T>
+struct CGData {
+  T* st = nullptr;
+  T* dinv = nullptr;
+  T* u[2] = {nullptr, nullptr};
+  T* b = nullptr;
+  T* r = nullptr;
+  T* rw = nullptr;  // restriction weights to the next coarser level
+  T* pw = nullptr;  // prolongation weights from it
+};
+
+struct CGLevel {
+  int n = 0, nv = 0;
+  size_t size = 0;
+  int cur = 0;                // which of u[0], u[1] holds the iterate
+  int* ridx = nullptr;        // [nvc][3]
+  int* pidx = nullptr;        // [nv][2]
+  CGData<double> d;
+  CGData<float> f;
+};
+
+}  // namespace detail
+}  // namespace hpmg
+
+struct hpmg_ctx {
+  int dim = 0, n = 0, p = 0, ncell = 0;
+  bool vark = false;
+  double kappa_const = 1.0;
+  std::vector<double> kappa;
+  hpmg_options opt{};
+  size_t ndof = 0;
+  std::vector<hpmg::detail::DGLevel> dg;
+  std::vector<hpmg::detail::CGLevel> cg;
+  double* coarse_inv = nullptr;  // dense inverse of the coarsest Q1 operator
+  unsigned char* bmask = nullptr;  // per cell boundary-facet mask (all DG levels)
+  int coarse_m = 0;
+  // outer solver workspace (FP64) and the FP32 cycle vectors
+  double *r = nullptr, *rold = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
+  float *r32 = nullptr, *z32 = nullptr;
+  double *partial = nullptr, *scal = nullptr;
+  double* host_scal = nullptr;  // pinned
+  // which level-0 trace buffer holds the traces of the caller's u after
+  // hpmg_project / hpmg_smooth / hpmg_sweep (-1: none), per dtype
+  int trace_state[2] = {-1, -1};
+  int trace_rhs[2] = {0, 0};
+  hpmg::detail::DevMem mem;
+  ~hpmg_ctx() {
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+namespace hpmg {
+namespace detail {
+
+template <typename T>
+DGData<T>& data(DGLevel& l);
+template <>
+inline DGData<double>& data<double>(DGLevel& l) { return l.d; }
+template <>
+inline DGData<float>& data<float>(DGLevel& l) { return l.f; }
+template <typename T>
+CGData<T>& data(CGLevel& l);
+template <>
+inline CGData<double>& data<double>(CGLevel& l) { return l.d; }
+template <>
+inline CGData<float>& data<float>(CGLevel& l) { return l.f; }
+
+template <typename T>
+inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
+  hpmg::DGArgs<T> a{};
+  DGData<T>& d = data<T>(L);
+  a.n = h->n;
+  a.ncell = h->ncell;
+  a.vark = h->vark ? 1 : 0;
+  a.kappa_const = (T)h->kappa_const;
+  a.ref = d.ref;
+  a.eig = d.eig;
+  a.kappa = d.kappa;
+  a.bmask = h->bmask;
+  const double hh = 1.0 / h->n;
+  a.h_fwd = (T)std::pow(hh, 2 - h->dim);
+  a.h_apply = (T)std::pow(hh, h->dim - 2);
+  a.sigma_hat = (T)L.sigma_hat;
+  a.omega = (T)h->opt.omega_dg;
+  a.vstride = (long long)L.ndof;
+  a.tstride = (long long)L.trsize;
+  return a;
+}
+
+template <typename T>
+inline void dg_run(hpmg_ctx* h, int op, const hpmg::DGArgs<T>& a, int N, int nrhs, int flag, hipStream_t s) {
+  if (!hpmg::dg_dispatch(h->dim, N, op, a, nrhs, flag, s))
+    throw HpmgError(HPMG_E_UNSUPPORTED, "no kernel for this degree");
+  HIPCHK(hipGetLastError());
+}
+
+
+}  // namespace detail
+}  // namespace hpmg

@@ -72,3 +72,17 @@ def test_default_options():
     o = hp.default_options()
     assert o.sigma0 == 2.0 and o.nu_pre == 2 and o.nu_post == 2
     assert abs(o.omega_dg - 0.7) < 1e-15 and abs(o.omega_cg - 2 / 3) < 1e-15
+
+
+def test_batch_null_arguments_rejected():
+    lib = hp.library()
+    out = ctypes.c_void_p()
+    assert lib.hpmg_batch_create(None, 1, ctypes.byref(out)) == 1
+    assert not out.value
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.hpmg_batch_create(arr, 0, ctypes.byref(out)) == 1
+    assert lib.hpmg_batch_create(arr, 1, ctypes.byref(out)) == 1  # NULL handle
+    assert lib.hpmg_batch_create(arr, 1, None) == 1
+    assert lib.hpmg_batch_solve(None, None, None, 1, 1e-10, 10, None, None) == 1
+    assert lib.hpmg_batch_grid(None) == 0
+    lib.hpmg_batch_destroy(None)

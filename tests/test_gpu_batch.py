@@ -1,0 +1,157 @@
+"""Batched solves (hpmg_batch_create / hpmg_batch_solve) of problems with
+different mesh sizes and degrees in shared persistent launches, through the
+C ABI, against the CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import SIPG, Hierarchy
+from tests.gpu_common import log, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (n, p): every degree the batched kernels take, odd and even n, a mesh
+# with a single interior Q1 vertex, a problem with two DG levels
+PROBLEMS = [(4, 1), (5, 2), (3, 3), (6, 4), (3, 5), (7, 2), (2, 1)]
+KAPPA = 1.7
+SEED = 4242
+
+
+def _rhs(j, nd, nrhs, base=SEED):
+    return np.concatenate([synth.random_rhs(nd, seed=synth.batched_rhs_seed(base, j, r)) for r in range(nrhs)])
+
+
+def _batch(problems, max_rhs=2):
+    import paper_2510_00998_amd as hp
+    solvers = [hp.Solver(3, n, p, KAPPA, max_rhs=max_rhs) for n, p in problems]
+    return solvers, hp.Batch(solvers)
+
+
+def test_one_iteration_matches_oracle():
+    """maxit = 1 from u0 = 0: u1 = alpha z, z = V-cycle(r0), alpha = z.r0 / z.A z.
+    Checks every phase of the batched FP32 V-cycle element by element."""
+    nrhs = 2
+    solvers, batch = _batch(PROBLEMS)
+    us, bs, refs = [], [], []
+    for j, ((n, p), s) in enumerate(zip(PROBLEMS, solvers)):
+        b = _rhs(j, s.ndof, nrhs)
+        H = Hierarchy(3, n, p, KAPPA)
+        A = H.levels[0].A
+        ref = []
+        for r in range(nrhs):
+            br = b[r * s.ndof:(r + 1) * s.ndof]
+            z = H.precondition(br)
+            ref.append((z @ br) / (z @ (A @ z)) * z)
+        refs.append(np.concatenate(ref))
+        us.append(torch.zeros(nrhs * s.ndof, dtype=torch.float64, device="cuda"))
+        bs.append(to_dev(b, torch.float64))
+    log(f"batch one iteration: {PROBLEMS} nrhs={nrhs}")
+    infos, st = batch.solve(us, bs, rtol=1e-10, maxit=1, nrhs=nrhs, check=False)
+    import paper_2510_00998_amd as hp
+    log(f"  status {st}: {hp.library().hpmg_last_error().decode()}")
+    assert st == 4  # not converged after one iteration
+    for j, (n, p) in enumerate(PROBLEMS):
+        nd = solvers[j].ndof
+        got = to_host(us[j])
+        for r in range(nrhs):
+            err = rel_err(got[r * nd:(r + 1) * nd], refs[j][r * nd:(r + 1) * nd])
+            log(f"  n={n} p={p} rhs={r}: rel err {err:.3e}")
+            assert err <= 1e-3
+        assert infos[j].iterations == 1
+    assert batch.grid in (256, 512, 1024, 2048, 4096)
+
+
+def test_batch_solve_reaches_tolerance_and_matches_single():
+    nrhs = 2
+    solvers, batch = _batch(PROBLEMS)
+    us, bs, bh = [], [], []
+    for j, s in enumerate(solvers):
+        b = _rhs(j, s.ndof, nrhs, base=SEED + 1)
+        bh.append(b)
+        us.append(torch.zeros(nrhs * s.ndof, dtype=torch.float64, device="cuda"))
+        bs.append(to_dev(b, torch.float64))
+    log(f"batch solve: {PROBLEMS} nrhs={nrhs}")
+    infos, st = batch.solve(us, bs, rtol=1e-10, maxit=200, nrhs=nrhs)
+    assert st == 0
+    for j, ((n, p), s) in enumerate(zip(PROBLEMS, solvers)):
+        A = SIPG(3, n, p, KAPPA).A
+        nd = s.ndof
+        u = to_host(us[j])
+        worst = 0.0
+        for r in range(nrhs):
+            br = bh[j][r * nd:(r + 1) * nd]
+            worst = max(worst, np.linalg.norm(br - A @ u[r * nd:(r + 1) * nd]) / np.linalg.norm(br))
+        # the single-problem solver with the same cycle on the same vectors
+        uj = torch.zeros(nrhs * nd, dtype=torch.float64, device="cuda")
+        info1, st1 = s.solve(uj, bs[j], rtol=1e-10, maxit=200, nrhs=nrhs)
+        log(f"  n={n} p={p}: its batch {infos[j].iterations} single {info1.iterations} "
+            f"oracle residual {worst:.3e} final {infos[j].final_residual:.3e}")
+        assert st1 == 0
+        assert worst <= 2e-10
+        assert infos[j].final_residual <= 1e-10 * infos[j].initial_residual * (1 + 1e-6)
+        assert abs(infos[j].iterations - info1.iterations) <= 2
+        assert rel_err(u, to_host(uj)) <= 1e-8
+
+
+def test_batch_reuse_nonzero_guess_and_nrhs_change():
+    solvers, batch = _batch(PROBLEMS)
+    for call, (nrhs, base) in enumerate([(2, SEED + 2), (2, SEED + 3), (1, SEED + 4)]):
+        us, bs, bh, u0h = [], [], [], []
+        for j, s in enumerate(solvers):
+            b = _rhs(j, s.ndof, nrhs, base=base)
+            u0 = synth.random_vector(nrhs * s.ndof, seed=base * 100 + j)
+            bh.append(b)
+            u0h.append(u0)
+            us.append(to_dev(u0, torch.float64))
+            bs.append(to_dev(b, torch.float64))
+        log(f"batch call {call}: nrhs={nrhs}")
+        infos, st = batch.solve(us, bs, rtol=1e-10, maxit=200, nrhs=nrhs)
+        assert st == 0
+        for j, ((n, p), s) in enumerate(zip(PROBLEMS, solvers)):
+            A = SIPG(3, n, p, KAPPA).A
+            nd = s.ndof
+            u = to_host(us[j])
+            for r in range(nrhs):
+                sl = slice(r * nd, (r + 1) * nd)
+                r0 = np.linalg.norm(bh[j][sl] - A @ u0h[j][sl])
+                rr = np.linalg.norm(bh[j][sl] - A @ u[sl]) / r0
+                assert rr <= 2e-10, (call, n, p, r, rr)
+
+
+def test_batch_zero_rhs_problem_stays_zero():
+    problems = [(4, 2), (3, 4), (5, 1)]
+    solvers, batch = _batch(problems, max_rhs=1)
+    us, bs = [], []
+    for j, s in enumerate(solvers):
+        b = np.zeros(s.ndof) if j == 1 else _rhs(j, s.ndof, 1)
+        us.append(torch.zeros(s.ndof, dtype=torch.float64, device="cuda"))
+        bs.append(to_dev(b, torch.float64))
+    infos, st = batch.solve(us, bs, rtol=1e-10, maxit=200, nrhs=1)
+    assert st == 0
+    assert infos[1].iterations == 0 and infos[1].initial_residual == 0.0
+    assert np.all(to_host(us[1]) == 0.0)
+    for j in (0, 2):
+        n, p = problems[j]
+        A = SIPG(3, n, p, KAPPA).A
+        b = to_host(bs[j])
+        assert np.linalg.norm(b - A @ to_host(us[j])) <= 2e-10 * np.linalg.norm(b)
+
+
+def test_batch_rejects_unsupported_handles():
+    import paper_2510_00998_amd as hp
+    s2 = hp.Solver(2, 4, 2, 1.0)
+    with pytest.raises(hp.HpmgError):
+        hp.Batch([s2])
+    s6 = hp.Solver(3, 3, 6, 1.0)
+    with pytest.raises(hp.HpmgError):
+        hp.Batch([s6])
+    sv = hp.Solver(3, 3, 2, synth.kappa_log_uniform(3, 3, seed=5))
+    with pytest.raises(hp.HpmgError):
+        hp.Batch([sv])
+    s = hp.Solver(3, 3, 2, 1.0, max_rhs=1)
+    b = hp.Batch([s])
+    u = torch.zeros(2 * s.ndof, dtype=torch.float64, device="cuda")
+    with pytest.raises(hp.HpmgError):
+        b.solve([u], [u.clone()], nrhs=2)
