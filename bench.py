@@ -55,14 +55,19 @@ def counter_traffic(key):
     return float(vals[key])
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=20, help="fused sweeps per precision per step")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5],
-                    help="2: Q4 32^3 kappa=1 (headline); 3: Q3 64^3 log-uniform kappa; 5: Q5 96^3 log-normal kappa")
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5],
+                    help="2: Q4 32^3 kappa=1 (headline); 3: Q3 64^3 log-uniform kappa; "
+                         "4: 64 problems x 4 RHS batched; 5: Q5 96^3 log-normal kappa")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=6, help="mesh of the oracle's timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -103,12 +108,171 @@ def cpu_baseline(dim, p, n_sample):
     }
 
 
+def run_batched(args):
+    """64 independent 3D Poisson problems (n uniform in 8..48, p uniform in
+    1..5, seed 1004), 4 right-hand sides N(0,1) per DoF each, solved together
+    by the batched solver.  One step = batched FP64 and FP32 smoothing of all
+    problems (S sweeps each) + one batched mixed-precision solve to 1e-10.
+    Afterwards, once: the same problems solved one after another by the
+    single-problem solver with the FP32 cycle and with the FP64 cycle."""
+    import torch
+
+    import paper_2510_00998_amd as hp
+    import synth
+    from paper_2510_00998_amd import traffic
+
+    probs = synth.batched_problem_list()
+    R = 4
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    t_setup = time.perf_counter()
+    solvers = [hp.Solver(3, n, p, 1.0, max_rhs=R, precision=hp.PREC_F32) for n, p in probs]
+    batch = hp.Batch(solvers)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    _progress(f"set up {len(solvers)} problems in {t_setup:.1f} s")
+    ndofs = [s.ndof for s in solvers]
+    total = R * sum(ndofs)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1004)
+    bs = [torch.randn(R * nd, dtype=torch.float64, device=dev, generator=gen) for nd in ndofs]
+    us = [torch.zeros_like(b) for b in bs]
+    bs32 = [b.float() for b in bs]
+    us32 = [torch.zeros_like(b) for b in bs32]
+    S = args.sweeps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+
+    def step(record):
+        out = {}
+        for k, (uu, bb) in enumerate(((us, bs), (us32, bs32))):
+            e = evs[3 * k:3 * k + 3]
+            e[0].record(stream)
+            batch.smooth(uu, bb, 0, nrhs=R)
+            e[1].record(stream)
+            batch.smooth(uu, bb, S, nrhs=R)
+            e[2].record(stream)
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, st = batch.solve(us, bs, rtol=1e-10, maxit=200, nrhs=R)
+        out["solve"] = (time.perf_counter() - t0, max(i.iterations for i in infos), st)
+        if record:
+            for k, name in ((0, "f64"), (1, "f32")):
+                e = evs[3 * k:3 * k + 3]
+                tp = e[0].elapsed_time(e[1]) * 1e-3
+                ts = e[1].elapsed_time(e[2]) * 1e-3
+                out[name] = (ts - tp) / S
+        return out
+
+    for i in range(args.warmup):
+        step(False)
+        _progress(f"warm-up step {i} done")
+    torch.cuda.synchronize()
+    T0 = time.perf_counter()
+    res = []
+    for i in range(args.steps):
+        res.append(step(True))
+        _progress(f"step {i}: batched solve {res[-1]['solve'][0]:.3f} s, {res[-1]['solve'][1]} its")
+    torch.cuda.synchronize()
+    T = time.perf_counter() - T0
+    t64 = sum(r["f64"] for r in res) / len(res)
+    t32 = sum(r["f32"] for r in res) / len(res)
+    t_batch = min(r["solve"][0] for r in res)
+    its_batch = res[-1]["solve"][1]
+    ok = all(r["solve"][2] == 0 for r in res)
+
+    # worst true relative residual of the batched solutions (FP64 apply)
+    worst = 0.0
+    for s, u, b in zip(solvers, us, bs):
+        y = torch.empty_like(u)
+        s.apply_A(u, y, nrhs=R)
+        for r in range(R):
+            sl = slice(r * s.ndof, (r + 1) * s.ndof)
+            worst = max(worst, float(torch.linalg.vector_norm(b[sl] - y[sl]) / torch.linalg.vector_norm(b[sl])))
+
+    # the same problems one after another: single-problem solver, FP32 cycle
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_seq_mx = 0
+    for s, u, b in zip(solvers, us, bs):
+        u.zero_()
+        info, st = s.solve(u, b, rtol=1e-10, maxit=200, nrhs=R)
+        its_seq_mx = max(its_seq_mx, info.iterations)
+        ok = ok and st == 0
+    torch.cuda.synchronize()
+    t_seq_mx = time.perf_counter() - t0
+    _progress(f"sequential mixed solves {t_seq_mx:.3f} s")
+    grid = batch.grid
+    by64 = R * sum(traffic.sweep_bytes(3, n, p, 8) for n, p in probs)
+    by32 = R * sum(traffic.sweep_bytes(3, n, p, 4) for n, p in probs)
+    del us32, bs32, batch
+    del solvers
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    # FP64 cycle, one problem after another (set up one at a time)
+    t_seq_64 = 0.0
+    its_seq_64 = 0
+    for (n, p), u, b in zip(probs, us, bs):
+        s = hp.Solver(3, n, p, 1.0, max_rhs=R, precision=hp.PREC_F64)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info, st = s.solve(u, b, rtol=1e-10, maxit=200, nrhs=R)
+        torch.cuda.synchronize()
+        t_seq_64 += time.perf_counter() - t0
+        its_seq_64 = max(its_seq_64, info.iterations)
+        ok = ok and st == 0
+        s.close()
+    _progress(f"sequential FP64 solves {t_seq_64:.3f} s")
+
+    ach = by64 / t64 / 1e9
+    line = {
+        "metric": METRIC,
+        "value": total / t64,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "64 independent 3D Poisson SIPG problems, n uniform in 8..48, p uniform in 1..5 "
+                               "(seed 1004), 4 RHS N(0,1) per DoF each, batched: one launch per phase over all "
+                               "problems, captured FCG iteration, FP32 V(2,2) inside FP64 FCG to 1e-10",
+                   "problems": len(probs), "rhs": R, "total_dofs": total, "sweeps_per_step": S},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_dg_batch<double,BOP_SWEEP> (batched fused sweep of all problems, FP64)",
+                     "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64},
+        "sweep_dofs_per_s": {"f64": total / t64, "f32": total / t32},
+        "sweep_roofline_f32": {"achieved": by32 / t32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": by32 / t32 / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by32,
+                               "mean_launch_s": t32},
+        "time_to_1e-10_s": {"batched_mixed": t_batch, "sequential_mixed": t_seq_mx, "sequential_fp64": t_seq_64},
+        "solver_iterations": {"batched_mixed": its_batch, "sequential_mixed": its_seq_mx,
+                              "sequential_fp64": its_seq_64},
+        "solves_converged": ok,
+        "batched_worst_true_rel_residual": worst,
+        "persistent_grid": grid,
+        "setup_s": t_setup,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "requested_gpus": args.gpus}))
         sys.exit(2)
+    if args.config == 4:
+        run_batched(args)
+        return
     import torch
 
     import paper_2510_00998_amd as hp

@@ -193,6 +193,18 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
 hpmg_status hpmg_batch_solve(hpmg_batch b, double* const* u, const double* const* rhs, int nrhs, double rtol,
                              int maxit, hpmg_solve_info* infos, hipStream_t stream);
 
+/* Block-Jacobi smoothing of every problem of the batch on its finest level,
+ * like hpmg_smooth: projection of the traces of u, then nsweeps fused
+ * sweeps (Section 4.2, Algorithm BlockJacobi with loop fusion), each one
+ * launch over all problems and right-hand sides.  u[j], b[j]: host array
+ * of count DEVICE pointers to nrhs stacked vectors of problem j in dtype
+ * (u updated in place).  Enqueued on `stream`; successive calls on one
+ * batch must use one stream (they share an argument table).  The first
+ * call for a dtype and nrhs tunes the persistent grid on internal vectors.
+ * Invalidates the handles' trace state. */
+hpmg_status hpmg_batch_smooth(hpmg_batch b, hpmg_dtype dtype, void* const* u, const void* const* rhs,
+                              int nsweeps, int nrhs, hipStream_t stream);
+
 /* Persistent grid size (blocks) chosen for the batch's launches by the
  * last hpmg_batch_solve (0 before the first). */
 int hpmg_batch_grid(hpmg_batch b);

@@ -79,6 +79,9 @@ _lib.hpmg_batch_create.restype = ctypes.c_int
 _lib.hpmg_batch_solve.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, ctypes.POINTER(SolveInfo), _vp]
 _lib.hpmg_batch_solve.restype = ctypes.c_int
+_lib.hpmg_batch_smooth.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
+                                   ctypes.c_int, _vp]
+_lib.hpmg_batch_smooth.restype = ctypes.c_int
 _lib.hpmg_batch_grid.argtypes = [_vp]
 _lib.hpmg_batch_grid.restype = ctypes.c_int
 _lib.hpmg_batch_destroy.argtypes = [_vp]
@@ -249,6 +252,19 @@ class Batch:
     @property
     def grid(self) -> int:
         return int(_lib.hpmg_batch_grid(self._b))
+
+    def smooth(self, us, bs, nsweeps: int, nrhs: int = 1, stream=None):
+        """Projection plus nsweeps fused sweeps of every problem (FP64 or FP32 tensors)."""
+        m = len(self.solvers)
+        if len(us) != m or len(bs) != m:
+            raise ValueError("one u and one b per problem")
+        c = _code(us[0])
+        for s, u, b in zip(self.solvers, us, bs):
+            if u.numel() != nrhs * s.ndof or b.numel() != nrhs * s.ndof:
+                raise ValueError("vector size must be nrhs * ndof")
+        up = (_vp * m)(*[_ptr(u, c) for u in us])
+        bp = (_vp * m)(*[_ptr(b, c) for b in bs])
+        _check(_lib.hpmg_batch_smooth(self._b, c, up, bp, nsweeps, nrhs, _stream(stream)), "hpmg_batch_smooth")
 
     def solve(self, us, bs, rtol: float = 1e-10, maxit: int = 200, nrhs: int = 1, stream=None, check=True):
         """us[j], bs[j]: FP64 device tensors of nrhs * ndof_j values. Returns (infos, status)."""

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <memory>
 #include <vector>
@@ -35,6 +36,8 @@ struct Launch {
 // segment tables, launch lists and the captured iteration.
 struct BatchPlan {
   int nrhs = 0;
+  std::vector<size_t> off0;  // offset of each problem in the workspace vectors
+  size_t total = 0;          // their length
   int grid = 0;  // persistent grid (blocks) of the batched launches, 0: not tuned
   DevMem mem;
   double *r = nullptr, *rold = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
@@ -50,9 +53,24 @@ struct BatchPlan {
   std::vector<hpmg::DGArgs<double>> resid_args_h;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // level-0 smoothing of the caller's vectors (hpmg_batch_smooth), per
+  // dtype: argument table [projection | even sweep | odd sweep] x problems
+  // whose u, b are set per call through a pinned staging copy
+  struct Smooth {
+    void* args = nullptr;
+    void* host = nullptr;
+    size_t bytes = 0;
+    Launch proj, even, odd;
+    int grid = 0;
+    hipEvent_t copied = nullptr;  // the last staging copy has completed
+  } sm[2];
   ~BatchPlan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (auto& S : sm) {
+      if (S.copied) (void)hipEventDestroy(S.copied);
+      if (S.host) (void)hipHostFree(S.host);
+    }
   }
 };
 
@@ -375,8 +393,7 @@ void build_vcycle(BatchPlan* B, const std::vector<hpmg_handle>& hs, const std::v
   rec(0);
 }
 
-void run(BatchPlan* B, const std::vector<Launch>& v, hipStream_t s) {
-  const int grid = B->grid > 0 ? B->grid : 1024;  // before tuning: a default
+void run_grid(const std::vector<Launch>& v, int grid, hipStream_t s) {
   for (const Launch& L : v) {
     if (L.kind == 0)
       hpmg::batch_dg<float>(L.op, (const hpmg::DGArgs<float>*)L.args, L.items, L.nitems, grid, s);
@@ -386,6 +403,10 @@ void run(BatchPlan* B, const std::vector<Launch>& v, hipStream_t s) {
       hpmg::batch_cg<float>((const hpmg::CGArgs<float>*)L.args, L.items, L.nitems, grid, s);
   }
   HIPCHK(hipGetLastError());
+}
+
+void run(BatchPlan* B, const std::vector<Launch>& v, hipStream_t s) {
+  run_grid(v, B->grid > 0 ? B->grid : 1024, s);  // before tuning: a default
 }
 
 // One iteration of the flexible CG for every segment.
@@ -437,6 +458,8 @@ std::unique_ptr<BatchPlan> make_plan(const std::vector<hpmg_handle>& hs, int nrh
     }
     tot += nd * R;
   }
+  B->off0 = off0;
+  B->total = tot;
   DevMem& M = B->mem;
   B->r = (double*)M.alloc(tot * sizeof(double));
   B->rold = (double*)M.alloc(tot * sizeof(double));
@@ -538,6 +561,112 @@ int autotune_grid(BatchPlan* B, hipStream_t s) {
   return best;
 }
 
+template <typename T>
+T* ws_u(BatchPlan* B);
+template <>
+double* ws_u<double>(BatchPlan* B) { return B->z; }
+template <>
+float* ws_u<float>(BatchPlan* B) { return B->z32; }
+template <typename T>
+T* ws_b(BatchPlan* B);
+template <>
+double* ws_b<double>(BatchPlan* B) { return B->r; }
+template <>
+float* ws_b<float>(BatchPlan* B) { return B->r32; }
+
+// Point the staged smoothing table at u, b and copy it to the device on s.
+template <typename T>
+void stage_smooth(BatchPlan* B, BatchPlan::Smooth& S, int np, T* const* u, const T* const* b, hipStream_t s) {
+  HIPCHK(hipEventSynchronize(S.copied));  // the previous copy has left the staging buffer
+  hpmg::DGArgs<T>* a = (hpmg::DGArgs<T>*)S.host;
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < np; ++j) {
+      a[k * np + j].u_in = u[j];
+      a[k * np + j].u_out = u[j];
+      a[k * np + j].b = b[j];
+    }
+  HIPCHK(hipMemcpyAsync(S.args, S.host, S.bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(S.copied, s));
+}
+
+template <typename T>
+void smooth_launches(BatchPlan::Smooth& S, int nsweeps, int grid, hipStream_t s) {
+  std::vector<Launch> v = {S.proj};
+  for (int i = 0; i < nsweeps; ++i) v.push_back((i & 1) ? S.odd : S.even);
+  run_grid(v, grid, s);
+}
+
+// Tables of hpmg_batch_smooth for dtype T; the persistent grid is tuned on
+// the workspace vectors (zeroed), never on the caller's.
+template <typename T>
+void prepare_smooth(BatchPlan* B, const std::vector<hpmg_handle>& hs, hipStream_t s) {
+  BatchPlan::Smooth& S = B->sm[sizeof(T) == 8 ? 1 : 0];
+  if (S.args) return;
+  const int np = (int)hs.size(), R = B->nrhs;
+  Table<hpmg::DGArgs<T>> t;
+  std::vector<hpmg::DGArgs<T>> all(3 * np);
+  for (int j = 0; j < np; ++j) {
+    hpmg_ctx* h = hs[j];
+    DGLevel& L = h->dg[0];
+    DGData<T>& d = data<T>(L);
+    hpmg::DGArgs<T> a = dg_args<T>(h, L);
+    add_dg_items(t, a, L.N, R);
+    all[j] = a;
+    all[j].tr_out = d.tr[0];
+    all[np + j] = a;
+    all[np + j].tr_in = d.tr[0];
+    all[np + j].tr_out = d.tr[1];
+    all[2 * np + j] = a;
+    all[2 * np + j].tr_in = d.tr[1];
+    all[2 * np + j].tr_out = d.tr[0];
+  }
+  S.bytes = all.size() * sizeof(hpmg::DGArgs<T>);
+  S.args = B->mem.alloc(S.bytes);
+  HIPCHK(hipHostMalloc(&S.host, S.bytes, hipHostMallocDefault));
+  std::memcpy(S.host, all.data(), S.bytes);
+  HIPCHK(hipEventCreateWithFlags(&S.copied, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(S.copied, s));
+  auto shifted = [&](int by) {
+    std::vector<hpmg::WorkItem> v = t.items;
+    for (auto& w : v) w.x += by;
+    return B->mem.upload(v, s);
+  };
+  const int ni = (int)t.items.size();
+  const int kind = sizeof(T) == 8 ? 1 : 0;
+  S.proj = Launch{kind, hpmg::BOP_PROJECT, S.args, shifted(0), ni};
+  S.even = Launch{kind, hpmg::BOP_SWEEP, S.args, shifted(np), ni};
+  S.odd = Launch{kind, hpmg::BOP_SWEEP, S.args, shifted(2 * np), ni};
+  // grid: persistent candidates and one block per item
+  std::vector<T*> su(np);
+  std::vector<const T*> sb(np);
+  for (int j = 0; j < np; ++j) {
+    su[j] = ws_u<T>(B) + B->off0[j];
+    sb[j] = ws_b<T>(B) + B->off0[j];
+  }
+  hpmg::fill<T>(ws_u<T>(B), B->total, T(0), s);
+  hpmg::fill<T>(ws_b<T>(B), B->total, T(0), s);
+  stage_smooth<T>(B, S, np, su.data(), sb.data(), s);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double tbest = 1e30;
+  for (int g : {1024, 2048, 4096, 8192, ni}) {
+    smooth_launches<T>(S, 1, g, s);  // warm-up
+    HIPCHK(hipEventRecord(e0, s));
+    smooth_launches<T>(S, 4, g, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < tbest) {
+      tbest = ms;
+      S.grid = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 }  // namespace
 
 extern "C" {
@@ -576,6 +705,46 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
 void hpmg_batch_destroy(hpmg_batch b) { delete b; }
 
 int hpmg_batch_grid(hpmg_batch b) { return b && b->plan ? b->plan->grid : 0; }
+
+hpmg_status hpmg_batch_smooth(hpmg_batch bt, hpmg_dtype dtype, void* const* u, const void* const* b, int nsweeps,
+                              int nrhs, hipStream_t stream) {
+  try {
+    require(bt && u && b, "NULL argument");
+    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    require(nsweeps >= 0, "nsweeps must be >= 0");
+    require(nrhs >= 1, "nrhs must be >= 1");
+    const std::vector<hpmg_handle>& hs = bt->hs;
+    const int np = (int)hs.size();
+    for (int j = 0; j < np; ++j) {
+      require(u[j] && b[j], "NULL vector in batch");
+      require(hs[j]->opt.max_rhs >= nrhs, "nrhs exceeds a handle's max_rhs");
+      hs[j]->trace_state[0] = hs[j]->trace_state[1] = -1;
+    }
+    if (!bt->plan || bt->plan->nrhs != nrhs) {
+      bt->plan.reset();
+      bt->plan = make_plan(hs, nrhs, bt->st);
+    }
+    BatchPlan* B = bt->plan.get();
+    if (dtype == HPMG_F64) {
+      prepare_smooth<double>(B, hs, stream);
+      BatchPlan::Smooth& S = B->sm[1];
+      stage_smooth<double>(B, S, np, (double* const*)u, (const double* const*)b, stream);
+      smooth_launches<double>(S, nsweeps, S.grid, stream);
+    } else {
+      prepare_smooth<float>(B, hs, stream);
+      BatchPlan::Smooth& S = B->sm[0];
+      stage_smooth<float>(B, S, np, (float* const*)u, (const float* const*)b, stream);
+      smooth_launches<float>(S, nsweeps, S.grid, stream);
+    }
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    set_last_error(e.what());
+    return e.st;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return HPMG_E_NOMEM;
+  }
+}
 
 hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* const* b, int nrhs, double rtol,
                              int maxit, hpmg_solve_info* infos, hipStream_t stream) {
