@@ -6,8 +6,9 @@ DoFs), manufactured u = prod sin(pi x_i), penalty 2(p+1)^2/h, hp V(2,2)
 cycle Q4 -> Q2 -> Q1(32^3) -> 16^3 -> 8^3 -> 4^3 (dense coarsest solve).
 
 One step = the whole hot path once, with inputs resident in HBM:
-  * S fused single-touch smoother sweeps in FP64 and S in FP32, each launch
-    bracketed by HIP events on the launch stream (per-launch duration);
+  * S fused single-touch smoother sweeps in FP64 and S in FP32, one launch
+    each, queued back to back between two HIP events on the launch stream
+    (mean launch duration = elapsed / S);
   * one solve to a 1e-10 relative residual with the FP64 V-cycle inside
     FP64 flexible CG, and one with the FP32 V-cycle inside FP64 flexible CG
     (mixed precision), both from u = 0.
@@ -141,6 +142,10 @@ def run_batched(args):
     us32 = [torch.zeros_like(b) for b in bs32]
     S = args.sweeps
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    # first calls build the tables and tune the persistent grids (untimed)
+    batch.smooth(us, bs, 0, nrhs=R)
+    batch.smooth(us32, bs32, 0, nrhs=R)
+    torch.cuda.synchronize()
 
     def step(record):
         out = {}
@@ -306,18 +311,19 @@ def main():
     us32 = torch.zeros(nd, dtype=torch.float32, device=dev)
     u = torch.zeros(nd, dtype=torch.float64, device=dev)
     S = args.sweeps
-    ev64 = [torch.cuda.Event(enable_timing=True) for _ in range(S + 1)]
-    ev32 = [torch.cuda.Event(enable_timing=True) for _ in range(S + 1)]
+    ev64 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev32 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
     def step(record):
         out = {}
-        # fused sweeps, one launch per call, events on the launch stream
+        # S fused sweeps (one hpmg_sweep call, one launch per sweep) queued
+        # back to back between two events on the launch stream:
+        # mean launch duration = elapsed / S
         for evs, uu, bb in ((ev64, us64, b64), (ev32, us32, b32)):
             g64.project(uu)
             evs[0].record(stream)
-            for i in range(S):
-                g64.sweep(uu, bb, 1)
-                evs[i + 1].record(stream)
+            g64.sweep(uu, bb, S)
+            evs[1].record(stream)
         # time to 1e-10: FP64 cycle, then mixed FP32 cycle
         for name, gs in (("fp64", g64), ("mixed_f32", gmx)):
             u.zero_()
@@ -327,8 +333,8 @@ def main():
             torch.cuda.synchronize()
             out[name] = (time.perf_counter() - t0, info.iterations, st)
         if record:
-            out["sw64"] = [ev64[i].elapsed_time(ev64[i + 1]) * 1e-3 for i in range(S)]
-            out["sw32"] = [ev32[i].elapsed_time(ev32[i + 1]) * 1e-3 for i in range(S)]
+            out["sw64"] = [ev64[0].elapsed_time(ev64[1]) * 1e-3 / S]
+            out["sw32"] = [ev32[0].elapsed_time(ev32[1]) * 1e-3 / S]
         return out
 
     for _ in range(args.warmup):
