@@ -208,7 +208,7 @@ def run_batched(args):
     torch.cuda.synchronize()
     t_seq_mx = time.perf_counter() - t0
     _progress(f"sequential mixed solves {t_seq_mx:.3f} s")
-    grid = batch.grid
+    tuning = batch.tuning
     by64 = R * sum(traffic.sweep_bytes(3, n, p, 8) for n, p in probs)
     by32 = R * sum(traffic.sweep_bytes(3, n, p, 4) for n, p in probs)
     del us32, bs32, batch
@@ -263,7 +263,7 @@ def run_batched(args):
                               "sequential_fp64": its_seq_64},
         "solves_converged": ok,
         "batched_worst_true_rel_residual": worst,
-        "persistent_grid": grid,
+        "autotuned_launch": tuning,
         "setup_s": t_setup,
     }
     print(json.dumps(line), flush=True)
@@ -310,6 +310,8 @@ def main():
     us64 = torch.zeros(nd, dtype=torch.float64, device=dev)
     us32 = torch.zeros(nd, dtype=torch.float32, device=dev)
     u = torch.zeros(nd, dtype=torch.float64, device=dev)
+    solves = ("fp64", "mixed_f32") if vark else ("fp64", "mixed_f32", "mixed_f32_graph")
+    batch1 = None if vark else hp.Batch([gmx])
     S = args.sweeps
     ev64 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev32 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -324,12 +326,18 @@ def main():
             evs[0].record(stream)
             g64.sweep(uu, bb, S)
             evs[1].record(stream)
-        # time to 1e-10: FP64 cycle, then mixed FP32 cycle
-        for name, gs in (("fp64", g64), ("mixed_f32", gmx)):
+        # time to 1e-10: FP64 cycle, then mixed FP32 cycle (single-problem
+        # solver; and, for constant kappa, the batched solver on a batch of
+        # one, whose iteration is a captured graph)
+        for name in solves:
             u.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            info, st = gs.solve(u, b64, rtol=1e-10, maxit=200)
+            if name == "mixed_f32_graph":
+                infos, st = batch1.solve([u], [b64], rtol=1e-10, maxit=200)
+                info = infos[0]
+            else:
+                info, st = (g64 if name == "fp64" else gmx).solve(u, b64, rtol=1e-10, maxit=200)
             torch.cuda.synchronize()
             out[name] = (time.perf_counter() - t0, info.iterations, st)
         if record:
@@ -351,9 +359,9 @@ def main():
     t32 = sum(sw32) / len(sw32)
     by64 = traffic.sweep_bytes(dim, n, p, 8, per_cell_kappa=vark)
     by32 = traffic.sweep_bytes(dim, n, p, 4, per_cell_kappa=vark)
-    tt = {k: min(r[k][0] for r in res) for k in ("fp64", "mixed_f32")}
-    its = {k: res[-1][k][1] for k in ("fp64", "mixed_f32")}
-    ok = all(r[k][2] == 0 for r in res for k in ("fp64", "mixed_f32"))
+    tt = {k: min(r[k][0] for r in res) for k in solves}
+    its = {k: res[-1][k][1] for k in solves}
+    ok = all(r[k][2] == 0 for r in res for k in solves)
 
     # true residual of the last mixed-precision solution (FP64 apply)
     y = torch.empty_like(u)

@@ -184,8 +184,9 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
  * entries, may be NULL) receives per problem the largest iteration count,
  * initial and final true residual over its right-hand sides
  * (residual_history is left zero).  The first call for a given nrhs builds
- * the work lists, picks the persistent grid size by timing the V-cycle of
- * the batch, and captures the iteration graph; later calls with the same
+ * the work lists, picks the persistent grid size and whether to launch
+ * per polynomial degree by timing the V-cycle of the batch (autotuning),
+ * and captures the iteration graph; later calls with the same
  * nrhs reuse them.  Work runs on an internal stream of the batch after the
  * caller's `stream` is synchronised; the call returns when done.
  * HPMG_E_NOT_CONVERGED after maxit iterations, HPMG_E_BREAKDOWN if a
@@ -205,9 +206,13 @@ hpmg_status hpmg_batch_solve(hpmg_batch b, double* const* u, const double* const
 hpmg_status hpmg_batch_smooth(hpmg_batch b, hpmg_dtype dtype, void* const* u, const void* const* rhs,
                               int nsweeps, int nrhs, hipStream_t stream);
 
-/* Persistent grid size (blocks) chosen for the batch's launches by the
- * last hpmg_batch_solve (0 before the first). */
-int hpmg_batch_grid(hpmg_batch b);
+/* Launch configuration the autotuner chose for the batch's current number
+ * of right-hand sides: out[0] persistent grid (blocks) of the V-cycle
+ * launches, out[1] 1 if they run one launch per polynomial degree (else
+ * one launch over all degrees), out[2..3] the same for FP32
+ * hpmg_batch_smooth, out[4..5] for FP64 (0 where not tuned yet).  out: host
+ * array of 6 ints. */
+hpmg_status hpmg_batch_tuning(hpmg_batch b, int* out);
 
 /* Release the batch (not its handles; NULL is ignored). */
 void hpmg_batch_destroy(hpmg_batch b);

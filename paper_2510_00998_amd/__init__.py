@@ -82,8 +82,8 @@ _lib.hpmg_batch_solve.restype = ctypes.c_int
 _lib.hpmg_batch_smooth.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
                                    ctypes.c_int, _vp]
 _lib.hpmg_batch_smooth.restype = ctypes.c_int
-_lib.hpmg_batch_grid.argtypes = [_vp]
-_lib.hpmg_batch_grid.restype = ctypes.c_int
+_lib.hpmg_batch_tuning.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
+_lib.hpmg_batch_tuning.restype = ctypes.c_int
 _lib.hpmg_batch_destroy.argtypes = [_vp]
 _lib.hpmg_batch_destroy.restype = None
 _lib.hpmg_status_string.argtypes = [ctypes.c_int]
@@ -250,8 +250,17 @@ class Batch:
             pass
 
     @property
+    def tuning(self) -> dict:
+        """Autotuned launch configuration (hpmg_batch_tuning)."""
+        out = (ctypes.c_int * 6)()
+        _check(_lib.hpmg_batch_tuning(self._b, out), "hpmg_batch_tuning")
+        return {"vcycle_grid": out[0], "vcycle_split_by_degree": bool(out[1]),
+                "smooth_f32_grid": out[2], "smooth_f32_split_by_degree": bool(out[3]),
+                "smooth_f64_grid": out[4], "smooth_f64_split_by_degree": bool(out[5])}
+
+    @property
     def grid(self) -> int:
-        return int(_lib.hpmg_batch_grid(self._b))
+        return self.tuning["vcycle_grid"]
 
     def smooth(self, us, bs, nsweeps: int, nrhs: int = 1, stream=None):
         """Projection plus nsweeps fused sweeps of every problem (FP64 or FP32 tensors)."""

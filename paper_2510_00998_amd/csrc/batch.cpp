@@ -26,9 +26,29 @@ struct Launch {
   int kind = 0;  // 0: DG float, 1: DG double, 2: Q1 float
   int op = 0;
   const void* args = nullptr;
-  const hpmg::WorkItem* items = nullptr;
+  const hpmg::WorkItem* items = nullptr;  // DG: sorted by degree
   int nitems = 0;
+  // DG: runs of equal degree in `items` (degree, first item, count)
+  std::vector<int3> runs;
 };
+
+// DG launch over `items` (sorted here by degree, stable), uploaded to mem.
+Launch dg_launch(DevMem& mem, int kind, int op, const void* args, std::vector<hpmg::WorkItem> items, hipStream_t s) {
+  std::stable_sort(items.begin(), items.end(),
+                   [](const hpmg::WorkItem& a, const hpmg::WorkItem& b) { return a.w < b.w; });
+  Launch L;
+  L.kind = kind;
+  L.op = op;
+  L.args = args;
+  L.nitems = (int)items.size();
+  if (items.empty()) return L;
+  L.items = mem.upload(items, s);
+  for (int i = 0; i < L.nitems; ++i) {
+    if (L.runs.empty() || L.runs.back().x != items[i].w) L.runs.push_back(int3{items[i].w, i, 0});
+    ++L.runs.back().z;
+  }
+  return L;
+}
 
 }  // namespace
 
@@ -36,11 +56,12 @@ struct Launch {
 // segment tables, launch lists and the captured iteration.
 struct BatchPlan {
   int nrhs = 0;
+  bool split = true;         // one launch per degree (tuned with the grid)
   std::vector<size_t> off0;  // offset of each problem in the workspace vectors
   size_t total = 0;          // their length
   int grid = 0;  // persistent grid (blocks) of the batched launches, 0: not tuned
   DevMem mem;
-  double *r = nullptr, *rold = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   float *r32 = nullptr, *z32 = nullptr;
   double *partial = nullptr, *scal = nullptr;
   int* count = nullptr;
@@ -48,7 +69,7 @@ struct BatchPlan {
   double** seg_u = nullptr;  // device tables of the caller's vectors, set per call
   const double** seg_b = nullptr;
   std::vector<Launch> vcycle, applyp;
-  Launch proj_u, resid_r, resid_q;  // projection of u; b - A u into r or into q
+  Launch proj_u, resid_r, resid_z;  // projection of u; b - A u into r or into z
   hpmg::DGArgs<double>* resid_args = nullptr;
   std::vector<hpmg::DGArgs<double>> resid_args_h;
   hipGraph_t graph = nullptr;
@@ -62,6 +83,7 @@ struct BatchPlan {
     size_t bytes = 0;
     Launch proj, even, odd;
     int grid = 0;
+    bool split = true;
     hipEvent_t copied = nullptr;  // the last staging copy has completed
   } sm[2];
   ~BatchPlan() {
@@ -110,14 +132,8 @@ struct Builder {
   hipStream_t s;
   template <typename T>
   Launch dg(int op, Table<hpmg::DGArgs<T>>& t) {
-    Launch L;
-    L.kind = sizeof(T) == 4 ? 0 : 1;
-    L.op = op;
-    if (t.items.empty()) return L;
-    L.args = b->mem.upload(t.args, s);
-    L.items = b->mem.upload(t.items, s);
-    L.nitems = (int)t.items.size();
-    return L;
+    if (t.items.empty()) return Launch{};
+    return dg_launch(b->mem, sizeof(T) == 4 ? 0 : 1, op, b->mem.upload(t.args, s), t.items, s);
   }
   Launch cg(Table<hpmg::CGArgs<float>>& t) {
     Launch L;
@@ -393,43 +409,53 @@ void build_vcycle(BatchPlan* B, const std::vector<hpmg_handle>& hs, const std::v
   rec(0);
 }
 
-void run_grid(const std::vector<Launch>& v, int grid, hipStream_t s) {
+// split: one launch per degree run (each with its own kernel), else one
+// launch over all degrees
+void run_grid(const std::vector<Launch>& v, int grid, bool split, hipStream_t s) {
   for (const Launch& L : v) {
-    if (L.kind == 0)
-      hpmg::batch_dg<float>(L.op, (const hpmg::DGArgs<float>*)L.args, L.items, L.nitems, grid, s);
-    else if (L.kind == 1)
-      hpmg::batch_dg<double>(L.op, (const hpmg::DGArgs<double>*)L.args, L.items, L.nitems, grid, s);
-    else
+    if (L.nitems == 0) continue;
+    if (L.kind == 2) {
       hpmg::batch_cg<float>((const hpmg::CGArgs<float>*)L.args, L.items, L.nitems, grid, s);
+    } else if (split) {
+      for (const int3& r : L.runs) {
+        if (L.kind == 0)
+          hpmg::batch_dg_n<float>(L.op, r.x, (const hpmg::DGArgs<float>*)L.args, L.items + r.y, r.z, grid, s);
+        else
+          hpmg::batch_dg_n<double>(L.op, r.x, (const hpmg::DGArgs<double>*)L.args, L.items + r.y, r.z, grid, s);
+      }
+    } else if (L.kind == 0) {
+      hpmg::batch_dg<float>(L.op, (const hpmg::DGArgs<float>*)L.args, L.items, L.nitems, grid, s);
+    } else {
+      hpmg::batch_dg<double>(L.op, (const hpmg::DGArgs<double>*)L.args, L.items, L.nitems, grid, s);
+    }
   }
   HIPCHK(hipGetLastError());
 }
 
 void run(BatchPlan* B, const std::vector<Launch>& v, hipStream_t s) {
-  run_grid(v, B->grid > 0 ? B->grid : 1024, s);  // before tuning: a default
+  run_grid(v, B->grid > 0 ? B->grid : 1024, B->split, s);  // before tuning: a default
 }
 
-// One iteration of the flexible CG for every segment.
+// One iteration of the flexible CG for every segment; r32 holds r cast to
+// FP32 (scale s[14]) on entry and on exit.
 void iteration(BatchPlan* B, double rtol2, hipStream_t s) {
   const hpmg::SegTable& t = B->seg;
-  hpmg::bk_cast_down(t, B->r, B->r32, B->scal, s);
-  run(B, B->vcycle, s);
-  hpmg::bk_cast_up(t, B->z32, B->z, B->scal, s);
-  hpmg::bk_dot(t, B->z, B->r, B->rold, B->partial, s);
-  hpmg::bk_finalize(t, 1, B->partial, B->scal, rtol2, s);
-  hpmg::bk_update_p(t, B->z, B->p, B->scal, s);
-  run(B, B->applyp, s);
+  run(B, B->vcycle, s);                                         // z32 = M r32
+  hpmg::bk_dot_z(t, B->z32, B->r, B->q, B->scal, B->partial, s);  // z.r, z.q_old
+  hpmg::bk_finalize(t, 1, B->partial, B->scal, rtol2, s);       // beta, rho
+  hpmg::bk_update_p(t, B->z32, B->p, B->scal, s);               // p = z + beta p
+  run(B, B->applyp, s);                                         // q = A p
   hpmg::bk_dot(t, B->p, B->q, nullptr, B->partial, s);
-  hpmg::bk_finalize(t, 2, B->partial, B->scal, rtol2, s);
-  hpmg::bk_update_ur(t, B->r, B->rold, B->p, B->q, B->scal, B->partial, s);
-  hpmg::bk_finalize(t, 3, B->partial, B->scal, rtol2, s);
+  hpmg::bk_finalize(t, 2, B->partial, B->scal, rtol2, s);       // alpha
+  hpmg::bk_update_ur(t, B->r, B->r32, B->p, B->q, B->scal, B->partial, s);
+  hpmg::bk_finalize(t, 3, B->partial, B->scal, rtol2, s);       // r.r, convergence
   hpmg::bk_count(t, B->scal, B->count, s);
   HIPCHK(hipGetLastError());
 }
 
-// b - A u of the caller's vectors (FP64) into r (into_q = false) or q
-void residual(BatchPlan* B, bool into_q, hipStream_t s) {
-  run(B, {B->proj_u, into_q ? B->resid_q : B->resid_r}, s);
+// b - A u of the caller's vectors (FP64) into r (into_z = false) or z
+void residual(BatchPlan* B, bool into_z, hipStream_t s) {
+  run(B, {B->proj_u, into_z ? B->resid_z : B->resid_r}, s);
 }
 
 // Workspace, segment tables and launch lists for nrhs right-hand sides.
@@ -462,7 +488,6 @@ std::unique_ptr<BatchPlan> make_plan(const std::vector<hpmg_handle>& hs, int nrh
   B->total = tot;
   DevMem& M = B->mem;
   B->r = (double*)M.alloc(tot * sizeof(double));
-  B->rold = (double*)M.alloc(tot * sizeof(double));
   B->z = (double*)M.alloc(tot * sizeof(double));
   B->p = (double*)M.alloc(tot * sizeof(double));
   B->q = (double*)M.alloc(tot * sizeof(double));
@@ -511,54 +536,67 @@ std::unique_ptr<BatchPlan> make_plan(const std::vector<hpmg_handle>& hs, int nrh
   B->applyp.push_back(bld.dg<double>(hpmg::BOP_APPLY, ta));
   // the residual launches share one argument table whose u, b are the
   // caller's, set per call: [0, np) projection of u, [np, 2np) b - A u
-  // into r, [2np, 3np) the same into q
+  // into r, [2np, 3np) the same into z (the true-residual check, which must
+  // leave q, read by the next iteration, intact)
   std::vector<hpmg::DGArgs<double>> all = tpu.args;
   for (int k = 1; k <= 2; ++k)
     for (int j = 0; j < np; ++j) {
       all.push_back(tr.args[j]);
-      all.back().out = (k == 1 ? B->r : B->q) + off0[j];
+      all.back().out = (k == 1 ? B->r : B->z) + off0[j];
     }
   B->resid_args = (hpmg::DGArgs<double>*)M.alloc(all.size() * sizeof(hpmg::DGArgs<double>));
   B->resid_args_h = all;
   auto shifted = [&](int by) {
     std::vector<hpmg::WorkItem> v = tr.items;
     for (auto& w : v) w.x += by;
-    return M.upload(v, s);
+    return v;
   };
-  const int nt = (int)tr.items.size();
-  B->proj_u = Launch{1, hpmg::BOP_PROJECT, B->resid_args, M.upload(tpu.items, s), (int)tpu.items.size()};
-  B->resid_r = Launch{1, hpmg::BOP_RESID, B->resid_args, shifted(np), nt};
-  B->resid_q = Launch{1, hpmg::BOP_RESID, B->resid_args, shifted(2 * np), nt};
+  B->proj_u = dg_launch(M, 1, hpmg::BOP_PROJECT, B->resid_args, tpu.items, s);
+  B->resid_r = dg_launch(M, 1, hpmg::BOP_RESID, B->resid_args, shifted(np), s);
+  B->resid_z = dg_launch(M, 1, hpmg::BOP_RESID, B->resid_args, shifted(2 * np), s);
   HIPCHK(hipStreamSynchronize(s));
   return B;
 }
 
-// Persistent grid size: the fastest of a few candidates on the V-cycle of
-// the batch (run on the current r32).
-int autotune_grid(BatchPlan* B, hipStream_t s) {
-  int best = 1024;
-  double tbest = 1e30;
+// Autotuner: the fastest (grid, split) among the candidates, timed with
+// events on s; work(grid, split, reps) enqueues the timed work.
+template <class F>
+void tune(const std::vector<int>& grids, F work, hipStream_t s, int& grid, bool& split) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (int g : {256, 512, 1024, 2048, 4096}) {
-    B->grid = g;
-    run(B, B->vcycle, s);  // warm-up
-    HIPCHK(hipEventRecord(e0, s));
-    run(B, B->vcycle, s);
-    run(B, B->vcycle, s);
-    HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < tbest) {
-      tbest = ms;
-      best = g;
+  double tbest = 1e30;
+  for (bool sp : {true, false})
+    for (int g : grids) {
+      work(g, sp, 1);  // warm-up
+      HIPCHK(hipEventRecord(e0, s));
+      work(g, sp, 2);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < tbest) {
+        tbest = ms;
+        grid = g;
+        split = sp;
+      }
     }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return best;
+}
+
+// Persistent grid size and degree split of the V-cycle launches, tuned on
+// the V-cycle of the batch (run on the current r32).
+void autotune_vcycle(BatchPlan* B, hipStream_t s) {
+  int grid = 1024;
+  bool split = true;
+  tune({256, 512, 1024, 2048, 4096},
+       [&](int g, bool sp, int reps) {
+         for (int i = 0; i < reps; ++i) run_grid(B->vcycle, g, sp, s);
+       },
+       s, grid, split);
+  B->grid = grid;
+  B->split = split;
 }
 
 template <typename T>
@@ -590,10 +628,10 @@ void stage_smooth(BatchPlan* B, BatchPlan::Smooth& S, int np, T* const* u, const
 }
 
 template <typename T>
-void smooth_launches(BatchPlan::Smooth& S, int nsweeps, int grid, hipStream_t s) {
+void smooth_launches(BatchPlan::Smooth& S, int nsweeps, int grid, bool split, hipStream_t s) {
   std::vector<Launch> v = {S.proj};
   for (int i = 0; i < nsweeps; ++i) v.push_back((i & 1) ? S.odd : S.even);
-  run_grid(v, grid, s);
+  run_grid(v, grid, split, s);
 }
 
 // Tables of hpmg_batch_smooth for dtype T; the persistent grid is tuned on
@@ -629,13 +667,13 @@ void prepare_smooth(BatchPlan* B, const std::vector<hpmg_handle>& hs, hipStream_
   auto shifted = [&](int by) {
     std::vector<hpmg::WorkItem> v = t.items;
     for (auto& w : v) w.x += by;
-    return B->mem.upload(v, s);
+    return v;
   };
   const int ni = (int)t.items.size();
   const int kind = sizeof(T) == 8 ? 1 : 0;
-  S.proj = Launch{kind, hpmg::BOP_PROJECT, S.args, shifted(0), ni};
-  S.even = Launch{kind, hpmg::BOP_SWEEP, S.args, shifted(np), ni};
-  S.odd = Launch{kind, hpmg::BOP_SWEEP, S.args, shifted(2 * np), ni};
+  S.proj = dg_launch(B->mem, kind, hpmg::BOP_PROJECT, S.args, shifted(0), s);
+  S.even = dg_launch(B->mem, kind, hpmg::BOP_SWEEP, S.args, shifted(np), s);
+  S.odd = dg_launch(B->mem, kind, hpmg::BOP_SWEEP, S.args, shifted(2 * np), s);
   // grid: persistent candidates and one block per item
   std::vector<T*> su(np);
   std::vector<const T*> sb(np);
@@ -646,25 +684,8 @@ void prepare_smooth(BatchPlan* B, const std::vector<hpmg_handle>& hs, hipStream_
   hpmg::fill<T>(ws_u<T>(B), B->total, T(0), s);
   hpmg::fill<T>(ws_b<T>(B), B->total, T(0), s);
   stage_smooth<T>(B, S, np, su.data(), sb.data(), s);
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  double tbest = 1e30;
-  for (int g : {1024, 2048, 4096, 8192, ni}) {
-    smooth_launches<T>(S, 1, g, s);  // warm-up
-    HIPCHK(hipEventRecord(e0, s));
-    smooth_launches<T>(S, 4, g, s);
-    HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < tbest) {
-      tbest = ms;
-      S.grid = g;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  tune({1024, 2048, 4096, 8192, ni},
+       [&](int g, bool sp, int reps) { smooth_launches<T>(S, 2 * reps, g, sp, s); }, s, S.grid, S.split);
 }
 
 }  // namespace
@@ -704,7 +725,20 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
 
 void hpmg_batch_destroy(hpmg_batch b) { delete b; }
 
-int hpmg_batch_grid(hpmg_batch b) { return b && b->plan ? b->plan->grid : 0; }
+hpmg_status hpmg_batch_tuning(hpmg_batch b, int* out) {
+  if (!b || !out) {
+    set_last_error("NULL argument");
+    return HPMG_E_INVALID;
+  }
+  const BatchPlan* P = b->plan.get();
+  out[0] = P ? P->grid : 0;
+  out[1] = P ? (int)P->split : 0;
+  for (int k = 0; k < 2; ++k) {
+    out[2 + 2 * k] = P ? P->sm[k].grid : 0;
+    out[3 + 2 * k] = P ? (int)P->sm[k].split : 0;
+  }
+  return HPMG_OK;
+}
 
 hpmg_status hpmg_batch_smooth(hpmg_batch bt, hpmg_dtype dtype, void* const* u, const void* const* b, int nsweeps,
                               int nrhs, hipStream_t stream) {
@@ -729,12 +763,12 @@ hpmg_status hpmg_batch_smooth(hpmg_batch bt, hpmg_dtype dtype, void* const* u, c
       prepare_smooth<double>(B, hs, stream);
       BatchPlan::Smooth& S = B->sm[1];
       stage_smooth<double>(B, S, np, (double* const*)u, (const double* const*)b, stream);
-      smooth_launches<double>(S, nsweeps, S.grid, stream);
+      smooth_launches<double>(S, nsweeps, S.grid, S.split, stream);
     } else {
       prepare_smooth<float>(B, hs, stream);
       BatchPlan::Smooth& S = B->sm[0];
       stage_smooth<float>(B, S, np, (float* const*)u, (const float* const*)b, stream);
-      smooth_launches<float>(S, nsweeps, S.grid, stream);
+      smooth_launches<float>(S, nsweeps, S.grid, S.split, stream);
     }
     return HPMG_OK;
   } catch (const HpmgError& e) {
@@ -791,15 +825,13 @@ hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* cons
       HIPCHK(hipMemcpyAsync(hc, B->count, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
     };
-    // initial residual
+    // initial residual and its FP32 copy
     residual(B, false, s);
     hpmg::bk_dot(B->seg, B->r, B->r, nullptr, B->partial, s);
     hpmg::bk_finalize(B->seg, 4, B->partial, B->scal, rtol2, s);
+    hpmg::bk_cast_down(B->seg, B->r, B->r32, B->scal, s);
     hpmg::bk_count(B->seg, B->scal, B->count, s);
-    if (B->grid == 0) {
-      hpmg::bk_cast_down(B->seg, B->r, B->r32, B->scal, s);
-      B->grid = autotune_grid(B, s);
-    }
+    if (B->grid == 0) autotune_vcycle(B, s);
     // one flexible-CG iteration of every segment, captured once and replayed
     if (!B->exec) {
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -817,9 +849,10 @@ hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* cons
         // true residual of the segments whose recurrence converged; those
         // that miss the tolerance restart from it
         residual(B, true, s);
-        hpmg::bk_dot(B->seg, B->q, B->q, nullptr, B->partial, s);
+        hpmg::bk_dot(B->seg, B->z, B->z, nullptr, B->partial, s);
         hpmg::bk_finalize(B->seg, 5, B->partial, B->scal, rtol2, s);
-        hpmg::bk_select(B->seg, B->q, B->r, B->scal, s);
+        hpmg::bk_select(B->seg, B->z, B->r, B->scal, s);
+        hpmg::bk_cast_down(B->seg, B->r, B->r32, B->scal, s);
         hpmg::bk_count(B->seg, B->scal, B->count, s);
         sync_count();
       }

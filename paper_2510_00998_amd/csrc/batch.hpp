@@ -66,17 +66,21 @@ constexpr int BATCH_SCAL = 16;  // doubles of per-segment scalar state
 
 template <typename T>
 void batch_dg(int op, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
+// The same with one kernel per degree N: items must all have w = N.
+template <typename T>
+void batch_dg_n(int op, int N, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
 template <typename T>
 void batch_cg(const CGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
 
 // Segmented FP64 vector operations of the flexible CG (see batch_kernels.hip).
 void bk_dot(const SegTable& t, const double* x, const double* y, const double* z, double* partial, hipStream_t s);
+void bk_dot_z(const SegTable& t, const float* z32, const double* r, const double* q, const double* scal,
+              double* partial, hipStream_t s);
 void bk_finalize(const SegTable& t, int op, const double* partial, double* scal, double rtol2, hipStream_t s);
-void bk_update_p(const SegTable& t, const double* z, double* p, const double* scal, hipStream_t s);
-void bk_update_ur(const SegTable& t, double* r, double* rold, const double* p, const double* q, const double* scal,
+void bk_update_p(const SegTable& t, const float* z32, double* p, const double* scal, hipStream_t s);
+void bk_update_ur(const SegTable& t, double* r, float* r32, const double* p, const double* q, const double* scal,
                   double* partial, hipStream_t s);
 void bk_cast_down(const SegTable& t, const double* x, float* y, const double* scal, hipStream_t s);
-void bk_cast_up(const SegTable& t, const float* x, double* y, const double* scal, hipStream_t s);
 void bk_count(const SegTable& t, const double* scal, int* count, hipStream_t s);
 void bk_select(const SegTable& t, const double* q, double* r, const double* scal, hipStream_t s);
 

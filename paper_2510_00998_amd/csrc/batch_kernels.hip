@@ -64,6 +64,20 @@ __global__ __launch_bounds__(256) void k_dg_batch(const DGArgs<T>* __restrict__ 
   }
 }
 
+// One degree per launch: the kernel takes only that degree's registers and
+// LDS (items of other degrees are not expected in its list).
+template <typename T, int OP, int N>
+__global__ __launch_bounds__(256) void k_dg_batch_n(const DGArgs<T>* __restrict__ args,
+                                                    const WorkItem* __restrict__ items, int nitems) {
+  __shared__ __attribute__((aligned(16))) char lds[item_lds<T, N, OP>()];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const DGArgs<T> a = args[w.x];
+    dg_item<T, N, OP>(a, w.y, w.z, lds);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
 // ------------------------------------------------------------------ Q1
 __device__ __forceinline__ void vc3(int v, int nv, int& x, int& y, int& z) {
   x = v % nv;
@@ -178,7 +192,7 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
   return s;
 }
 
-// partial[2*chunk + {0,1}] = x.y, x.z over the chunk
+// partial[2*chunk + {0,1}] = x.y, x.z over the chunk (z may be NULL)
 __global__ __launch_bounds__(256) void k_bdot(SegTable t, const double* __restrict__ x, const double* __restrict__ y,
                                               const double* __restrict__ z, double* __restrict__ partial) {
   __shared__ double sh[4];
@@ -201,10 +215,38 @@ __global__ __launch_bounds__(256) void k_bdot(SegTable t, const double* __restri
   }
 }
 
+// Preconditioned residual straight from the FP32 cycle: z = z32 / s[14]
+// (s[14]: scale the cycle's right-hand side was cast with).
+// partial[2*chunk + {0,1}] = z.r, z.q over the chunk.
+__global__ __launch_bounds__(256) void k_bdot_z(SegTable t, const float* __restrict__ z32,
+                                                const double* __restrict__ r, const double* __restrict__ q,
+                                                const double* __restrict__ scal, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
+    const int2 ch = t.chunks[ci];
+    const long long o = t.off[ch.x] + ch.y;
+    const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
+    const double sc = 1.0 / scal[(size_t)ch.x * BATCH_SCAL + 14];
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      const double zi = (double)z32[o + i] * sc;
+      s0 += zi * r[o + i];
+      s1 += zi * q[o + i];
+    }
+    const double t0 = bsum(s0, sh);
+    const double t1 = bsum(s1, sh);
+    if (threadIdx.x == 0) {
+      partial[2 * ci] = t0;
+      partial[2 * ci + 1] = t1;
+    }
+  }
+}
+
 // Per-segment scalar state (BATCH_SCAL doubles): [2] rho, [3] beta,
 // [5] alpha, [6] r.r, [7] 1/||r||, [8] ||r||, [9] ||r0||^2, [10] state
 // (0 iterating, 1 recurrence converged, 2 done, 3 breakdown), [11] restart,
-// [12] last true residual^2, [13] iterations.
+// [12] last true residual^2, [13] iterations, [14] scale of the FP32 copy
+// of r that the next cycle reads.
 __device__ __forceinline__ void set_rr(double* s, double t0) {
   s[6] = t0;
   s[7] = t0 > 0.0 ? 1.0 / sqrt(t0) : 1.0;
@@ -226,15 +268,16 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
   if (threadIdx.x != 0) return;
   double* s = scal + (size_t)sg * BATCH_SCAL;
   const bool finite = t0 == t0 && t0 < 1e300;
-  if (op == 1) {  // beta (flexible: z.(r - r_old) / rho_old)
-    s[3] = (s[11] != 0.0 || s[10] != 0.0) ? 0.0 : (t0 - t1) / s[2];
+  if (op == 1) {  // beta (flexible: z.(r - r_old) / rho_old, r - r_old = -alpha_old q)
+    s[3] = (s[11] != 0.0 || s[10] != 0.0) ? 0.0 : -s[5] * t1 / s[2];
     s[2] = t0;
     s[11] = 0.0;
   } else if (op == 2) {  // alpha
     if (s[10] == 0.0 && !(finite && t0 != 0.0)) s[10] = 3.0;
     s[5] = s[10] != 0.0 ? 0.0 : s[2] / t0;
     if (s[10] == 0.0) s[13] += 1.0;
-  } else if (op == 3) {  // recurrence residual
+  } else if (op == 3) {  // recurrence residual; r32 was written with scale s[7]
+    s[14] = s[7];
     if (s[10] == 0.0) {
       set_rr(s, t0);
       if (!finite)
@@ -242,8 +285,10 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
       else if (t0 <= rtol2 * s[9])
         s[10] = 1.0;
     }
-  } else if (op == 4) {  // initial residual
+  } else if (op == 4) {  // initial residual (cast to FP32 next, with scale s[7])
     set_rr(s, t0);
+    s[14] = s[7];
+    s[5] = 0.0;
     s[9] = t0;
     s[10] = !finite ? 3.0 : (t0 == 0.0 ? 2.0 : 0.0);
     s[11] = 1.0;
@@ -262,21 +307,29 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
         s[11] = 1.0;
       }
     }
+    s[14] = s[7];  // every segment's r is cast to FP32 next with scale s[7]
   }
 }
 
-__global__ __launch_bounds__(256) void k_bupdate_p(SegTable t, const double* __restrict__ z, double* __restrict__ p,
+// p = z + beta p with z = z32 / s[14]
+__global__ __launch_bounds__(256) void k_bupdate_p(SegTable t, const float* __restrict__ z32, double* __restrict__ p,
                                                    const double* __restrict__ scal) {
   for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
     const int2 ch = t.chunks[ci];
     const long long o = t.off[ch.x] + ch.y;
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
-    const double beta = scal[(size_t)ch.x * BATCH_SCAL + 3];
-    for (int i = threadIdx.x; i < len; i += blockDim.x) p[o + i] = beta == 0.0 ? z[o + i] : z[o + i] + beta * p[o + i];
+    const double* sg = scal + (size_t)ch.x * BATCH_SCAL;
+    const double beta = sg[3], sc = 1.0 / sg[14];
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      const double zi = (double)z32[o + i] * sc;
+      p[o + i] = beta == 0.0 ? zi : zi + beta * p[o + i];
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void k_bupdate_ur(SegTable t, double* __restrict__ r, double* __restrict__ rold,
+// u += alpha p, r -= alpha q, r32 = r s[7] (the next cycle's right-hand
+// side), partial[2*chunk] = r.r
+__global__ __launch_bounds__(256) void k_bupdate_ur(SegTable t, double* __restrict__ r, float* __restrict__ r32,
                                                     const double* __restrict__ p, const double* __restrict__ q,
                                                     const double* __restrict__ scal, double* __restrict__ partial) {
   __shared__ double sh[4];
@@ -284,18 +337,18 @@ __global__ __launch_bounds__(256) void k_bupdate_ur(SegTable t, double* __restri
     const int2 ch = t.chunks[ci];
     const long long o = t.off[ch.x] + ch.y;
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
-    const double alpha = scal[(size_t)ch.x * BATCH_SCAL + 5];
+    const double* sg = scal + (size_t)ch.x * BATCH_SCAL;
+    const double alpha = sg[5], sc = sg[7];
     double* u = t.u[ch.x] + ch.y;
     double acc = 0.0;
     for (int i = threadIdx.x; i < len; i += blockDim.x) {
-      const double ri = r[o + i];
-      double rn = ri;
+      double rn = r[o + i];
       if (alpha != 0.0) {
         u[i] += alpha * p[o + i];
-        rn = ri - alpha * q[o + i];
+        rn -= alpha * q[o + i];
         r[o + i] = rn;
       }
-      rold[o + i] = ri;
+      r32[o + i] = (float)(rn * sc);
       acc += rn * rn;
     }
     const double s0 = bsum(acc, sh);
@@ -327,17 +380,6 @@ __global__ __launch_bounds__(256) void k_bcast_down(SegTable t, const double* __
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
     const double sc = scal[(size_t)ch.x * BATCH_SCAL + 7];
     for (int i = threadIdx.x; i < len; i += blockDim.x) y[o + i] = (float)(x[o + i] * sc);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_bcast_up(SegTable t, const float* __restrict__ x, double* __restrict__ y,
-                                                  const double* __restrict__ scal) {
-  for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
-    const int2 ch = t.chunks[ci];
-    const long long o = t.off[ch.x] + ch.y;
-    const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
-    const double sc = scal[(size_t)ch.x * BATCH_SCAL + 8];
-    for (int i = threadIdx.x; i < len; i += blockDim.x) y[o + i] = (double)x[o + i] * sc;
   }
 }
 
@@ -379,6 +421,33 @@ void batch_dg(int op, const DGArgs<T>* args, const WorkItem* items, int nitems, 
   }
 }
 
+template <typename T, int OP>
+void launch_n(int N, const DGArgs<T>* args, const WorkItem* items, int nitems, dim3 g, hipStream_t s) {
+  switch (N) {
+    case 2: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 2>), g, dim3(256), 0, s, args, items, nitems); break;
+    case 3: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 3>), g, dim3(256), 0, s, args, items, nitems); break;
+    case 4: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 4>), g, dim3(256), 0, s, args, items, nitems); break;
+    case 5: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 5>), g, dim3(256), 0, s, args, items, nitems); break;
+    default: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 6>), g, dim3(256), 0, s, args, items, nitems); break;
+  }
+}
+
+template <typename T>
+void batch_dg_n(int op, int N, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s) {
+  const dim3 g(grid_for(nitems, grid));
+  switch (op) {
+    case BOP_SWEEP: launch_n<T, BOP_SWEEP>(N, args, items, nitems, g, s); break;
+    case BOP_SWEEP0: launch_n<T, BOP_SWEEP0>(N, args, items, nitems, g, s); break;
+    case BOP_RESTRICT: launch_n<T, BOP_RESTRICT>(N, args, items, nitems, g, s); break;
+    case BOP_PROLONG: launch_n<T, BOP_PROLONG>(N, args, items, nitems, g, s); break;
+    case BOP_PROJECT: launch_n<T, BOP_PROJECT>(N, args, items, nitems, g, s); break;
+    case BOP_RESID: launch_n<T, BOP_RESID>(N, args, items, nitems, g, s); break;
+    default: launch_n<T, BOP_APPLY>(N, args, items, nitems, g, s); break;
+  }
+}
+template void batch_dg_n<float>(int, int, const DGArgs<float>*, const WorkItem*, int, int, hipStream_t);
+template void batch_dg_n<double>(int, int, const DGArgs<double>*, const WorkItem*, int, int, hipStream_t);
+
 template <typename T>
 void batch_cg(const CGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s) {
   hipLaunchKernelGGL((k_cg_batch<T>), dim3(grid_for(nitems, grid)), dim3(256), 0, s, args, items, nitems);
@@ -392,21 +461,22 @@ template void batch_cg<double>(const CGArgs<double>*, const WorkItem*, int, int,
 void bk_dot(const SegTable& t, const double* x, const double* y, const double* z, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_bdot, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, x, y, z, partial);
 }
+void bk_dot_z(const SegTable& t, const float* z32, const double* r, const double* q, const double* scal,
+              double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_bdot_z, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, z32, r, q, scal, partial);
+}
 void bk_finalize(const SegTable& t, int op, const double* partial, double* scal, double rtol2, hipStream_t s) {
   hipLaunchKernelGGL(k_bfinal, dim3(t.nseg), dim3(64), 0, s, t, op, partial, scal, rtol2);
 }
-void bk_update_p(const SegTable& t, const double* z, double* p, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_bupdate_p, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, z, p, scal);
+void bk_update_p(const SegTable& t, const float* z32, double* p, const double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_bupdate_p, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, z32, p, scal);
 }
-void bk_update_ur(const SegTable& t, double* r, double* rold, const double* p, const double* q, const double* scal,
+void bk_update_ur(const SegTable& t, double* r, float* r32, const double* p, const double* q, const double* scal,
                   double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_bupdate_ur, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, r, rold, p, q, scal, partial);
+  hipLaunchKernelGGL(k_bupdate_ur, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, r, r32, p, q, scal, partial);
 }
 void bk_cast_down(const SegTable& t, const double* x, float* y, const double* scal, hipStream_t s) {
   hipLaunchKernelGGL(k_bcast_down, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, x, y, scal);
-}
-void bk_cast_up(const SegTable& t, const float* x, double* y, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcast_up, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, x, y, scal);
 }
 void bk_count(const SegTable& t, const double* scal, int* count, hipStream_t s) {
   hipLaunchKernelGGL(k_bcount, dim3(1), dim3(256), 0, s, t, scal, count);

@@ -84,5 +84,5 @@ def test_batch_null_arguments_rejected():
     assert lib.hpmg_batch_create(arr, 1, ctypes.byref(out)) == 1  # NULL handle
     assert lib.hpmg_batch_create(arr, 1, None) == 1
     assert lib.hpmg_batch_solve(None, None, None, 1, 1e-10, 10, None, None) == 1
-    assert lib.hpmg_batch_grid(None) == 0
+    assert lib.hpmg_batch_tuning(None, None) == 1
     lib.hpmg_batch_destroy(None)
