@@ -6,12 +6,14 @@ DoFs), manufactured u = prod sin(pi x_i), penalty 2(p+1)^2/h, hp V(2,2)
 cycle Q4 -> Q2 -> Q1(32^3) -> 16^3 -> 8^3 -> 4^3 (dense coarsest solve).
 
 One step = the whole hot path once, with inputs resident in HBM:
-  * S fused single-touch smoother sweeps in FP64 and S in FP32, one launch
-    each, queued back to back between two HIP events on the launch stream
-    (mean launch duration = elapsed / S);
-  * one solve to a 1e-10 relative residual with the FP64 V-cycle inside
-    FP64 flexible CG, and one with the FP32 V-cycle inside FP64 flexible CG
-    (mixed precision), both from u = 0.
+  * S fused single-touch smoother sweeps with FP64, FP32, FP16 and BF16
+    storage (the 16-bit ones compute in FP32), one launch each, queued back to
+    back between two HIP events on the launch stream (mean launch duration =
+    elapsed / S);
+  * solves to a 1e-10 relative residual from u = 0: FP64 flexible CG with the
+    FP64 V-cycle, with the FP32 V-cycle (mixed precision), with the FP32
+    V-cycle on 16-bit finest-level storage (FP16, BF16), and (constant kappa)
+    the batched solver on this one problem (captured iteration graph).
 value = FP64 fused-sweep DoF/s = DoFs / mean sweep launch duration.
 Prints one JSON line (rank 0; this build runs on one GPU only).
 """
@@ -301,27 +303,40 @@ def main():
     t_setup = time.perf_counter()
     g64 = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F64)
     gmx = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F32)
+    g16 = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F16)
+    gb16 = hp.Solver(dim, n, p, kappa, precision=hp.PREC_BF16)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     nd = g64.ndof
     b64 = torch.empty(nd, dtype=torch.float64, device=dev)
     g64.load_vector(fkind, 1.0, b64)
-    b32 = b64.float()
-    us64 = torch.zeros(nd, dtype=torch.float64, device=dev)
-    us32 = torch.zeros(nd, dtype=torch.float32, device=dev)
+    # sweep inputs per storage type; 16-bit b scaled to mean square
+    # lambda = d pi^2 kappa_min (h/N)^d like the solver's 16-bit cycles, so
+    # that the iterates stay in FP16 range
+    import math
+    kmin = kappa if not vark else float(min(kappa))
+    lam = dim * math.pi ** 2 * kmin * (1.0 / (n * (p + 1))) ** dim
+    bscale = float((nd * lam) ** 0.5 / torch.linalg.vector_norm(b64))
+    sweep_in = {}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32), ("f16", torch.float16),
+                     ("bf16", torch.bfloat16)):
+        bb = b64 if dt == torch.float64 else (b64 * (1.0 if dt == torch.float32 else bscale)).to(dt)
+        sweep_in[name] = (torch.zeros(nd, dtype=dt, device=dev), bb,
+                          [torch.cuda.Event(enable_timing=True) for _ in range(2)])
     u = torch.zeros(nd, dtype=torch.float64, device=dev)
-    solves = ("fp64", "mixed_f32") if vark else ("fp64", "mixed_f32", "mixed_f32_graph")
+    solves = ("fp64", "mixed_f32", "mixed_f16", "mixed_bf16")
+    if not vark:
+        solves += ("mixed_f32_graph",)
+    solver_of = {"fp64": g64, "mixed_f32": gmx, "mixed_f16": g16, "mixed_bf16": gb16}
     batch1 = None if vark else hp.Batch([gmx])
     S = args.sweeps
-    ev64 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev32 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
     def step(record):
         out = {}
         # S fused sweeps (one hpmg_sweep call, one launch per sweep) queued
         # back to back between two events on the launch stream:
         # mean launch duration = elapsed / S
-        for evs, uu, bb in ((ev64, us64, b64), (ev32, us32, b32)):
+        for uu, bb, evs in sweep_in.values():
             g64.project(uu)
             evs[0].record(stream)
             g64.sweep(uu, bb, S)
@@ -337,12 +352,13 @@ def main():
                 infos, st = batch1.solve([u], [b64], rtol=1e-10, maxit=200)
                 info = infos[0]
             else:
-                info, st = (g64 if name == "fp64" else gmx).solve(u, b64, rtol=1e-10, maxit=200)
+                info, st = solver_of[name].solve(u, b64, rtol=1e-10, maxit=200, check=False)
             torch.cuda.synchronize()
-            out[name] = (time.perf_counter() - t0, info.iterations, st)
+            out[name] = (time.perf_counter() - t0, info.iterations, st,
+                         info.final_residual / max(info.initial_residual, 1e-300))
         if record:
-            out["sw64"] = [ev64[0].elapsed_time(ev64[1]) * 1e-3 / S]
-            out["sw32"] = [ev32[0].elapsed_time(ev32[1]) * 1e-3 / S]
+            for name, (_, _, evs) in sweep_in.items():
+                out["sw_" + name] = evs[0].elapsed_time(evs[1]) * 1e-3 / S
         return out
 
     for _ in range(args.warmup):
@@ -353,17 +369,20 @@ def main():
     torch.cuda.synchronize()
     T = time.perf_counter() - T0
 
-    sw64 = [x for r in res for x in r["sw64"]]
-    sw32 = [x for r in res for x in r["sw32"]]
-    t64 = sum(sw64) / len(sw64)
-    t32 = sum(sw32) / len(sw32)
-    by64 = traffic.sweep_bytes(dim, n, p, 8, per_cell_kappa=vark)
-    by32 = traffic.sweep_bytes(dim, n, p, 4, per_cell_kappa=vark)
+    tsw = {name: sum(r["sw_" + name] for r in res) / len(res) for name in sweep_in}
+    isz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+    bysw = {name: traffic.sweep_bytes(dim, n, p, isz[name], per_cell_kappa=vark) for name in sweep_in}
+    t64, t32 = tsw["f64"], tsw["f32"]
+    by64, by32 = bysw["f64"], bysw["f32"]
     tt = {k: min(r[k][0] for r in res) for k in solves}
     its = {k: res[-1][k][1] for k in solves}
-    ok = all(r[k][2] == 0 for r in res for k in solves)
+    conv = {k: all(r[k][2] == 0 for r in res) for k in solves}
+    final_rel = {k: res[-1][k][3] for k in solves}
+    ok = all(conv[k] for k in ("fp64", "mixed_f32"))
 
-    # true residual of the last mixed-precision solution (FP64 apply)
+    # true residual of the mixed-precision (FP32 cycle) solution (FP64 apply)
+    u.zero_()
+    gmx.solve(u, b64, rtol=1e-10, maxit=200, check=False)
     y = torch.empty_like(u)
     g64.apply_A(u, y)
     true_rel = float(torch.linalg.vector_norm(b64 - y) / torch.linalg.vector_norm(b64))
@@ -400,14 +419,21 @@ def main():
                      "frac": ach64 / HBM_PEAK_GBS, "traffic": counter_traffic(tkey64),
                      "kernel": f"k_sweep<double,3,{p + 1}> (fused sweep, FP64)",
                      "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64},
-        "sweep_dofs_per_s": {"f64": nd / t64, "f32": nd / t32},
+        "sweep_dofs_per_s": {name: nd / t for name, t in tsw.items()},
         "sweep_roofline_f32": {"achieved": by32 / t32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by32 / t32 / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by32,
                                "traffic": counter_traffic(tkey32),
                                "mean_launch_s": t32},
+        "sweep_roofline_16bit_storage": {
+            name: {"achieved": bysw[name] / tsw[name] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": bysw[name] / tsw[name] / 1e9 / HBM_PEAK_GBS,
+                   "algorithmic_bytes_per_launch": bysw[name], "mean_launch_s": tsw[name]}
+            for name in ("f16", "bf16")},
         "time_to_1e-10_s": tt,
         "solver_iterations": its,
         "solves_converged": ok,
+        "converged_by_solver": conv,
+        "final_rel_residual_by_solver": final_rel,
         "mixed_solution_true_rel_residual": true_rel,
         "setup_s": t_setup,
     }

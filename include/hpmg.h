@@ -46,12 +46,21 @@ typedef enum {
   HPMG_E_UNSUPPORTED = 6    /* valid request this build does not implement */
 } hpmg_status;
 
-typedef enum { HPMG_F64 = 0, HPMG_F32 = 1 } hpmg_dtype;
+/* Element type of the vectors a call reads and writes.  F16 (IEEE binary16)
+ * and BF16 are storage formats of the finest level only: the arithmetic,
+ * the operator tables and the coarser levels are FP32 (16-bit operands,
+ * FP32 accumulation).  hpmg_apply_A takes F64 and F32 only. */
+typedef enum { HPMG_F64 = 0, HPMG_F32 = 1, HPMG_F16 = 2, HPMG_BF16 = 3 } hpmg_dtype;
 
 /* Precision of the multigrid cycle used inside hpmg_solve.  F64: everything
  * in double.  F32: smoother, transfers and coarse levels in float inside the
- * FP64 outer iteration (fine residual, update and coarsest solve in double). */
-typedef enum { HPMG_PREC_F64 = 0, HPMG_PREC_F32 = 1 } hpmg_precision;
+ * FP64 outer iteration (fine residual, update and coarsest solve in double).
+ * F16 / BF16: as F32, with the finest level's cycle vectors and traces stored
+ * in 16 bits (half the bytes of its sweeps); the residual handed to the
+ * cycle is scaled to mean square lambda = dim pi^2 kappa_min (h/(p+1))^dim
+ * before the cast, which keeps it and the cycle's output (about r/lambda)
+ * inside the FP16 range. */
+typedef enum { HPMG_PREC_F64 = 0, HPMG_PREC_F32 = 1, HPMG_PREC_F16 = 2, HPMG_PREC_BF16 = 3 } hpmg_precision;
 
 /* Unit box [0,1]^dim with n[0] cells per axis (n[1], n[2] must equal n[0]).
  * dim in {2, 3}, n >= 2. */
@@ -138,7 +147,9 @@ typedef struct {
 
 /* Solve A u = b to ||b - A u||_2 <= rtol ||b - A u0||_2 (the true residual,
  * recomputed whenever the recurrence converges; the iteration restarts from
- * it if it misses rtol) with flexible CG
+ * it if it misses rtol, at most 3 times per right-hand side: a true residual
+ * still above rtol after that has met the FP64 rounding floor of b - A u and
+ * the call returns HPMG_E_NOT_CONVERGED with final_residual set) with flexible CG
  * preconditioned by one V-cycle (precision from the options) in FP64.  u
  * holds the initial guess on entry.  info may be NULL (host pointer).
  * Returns HPMG_E_NOT_CONVERGED after maxit iterations, HPMG_E_BREAKDOWN on a
@@ -189,8 +200,9 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
  * and captures the iteration graph; later calls with the same
  * nrhs reuse them.  Work runs on an internal stream of the batch after the
  * caller's `stream` is synchronised; the call returns when done.
- * HPMG_E_NOT_CONVERGED after maxit iterations, HPMG_E_BREAKDOWN if a
- * segment met a non-finite value. */
+ * HPMG_E_NOT_CONVERGED after maxit iterations or when a segment's true
+ * residual stays above rtol after 3 restarts (as in hpmg_solve),
+ * HPMG_E_BREAKDOWN if a segment met a non-finite value. */
 hpmg_status hpmg_batch_solve(hpmg_batch b, double* const* u, const double* const* rhs, int nrhs, double rtol,
                              int maxit, hpmg_solve_info* infos, hipStream_t stream);
 

@@ -24,8 +24,13 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 STATUS = {0: "HPMG_OK", 1: "HPMG_E_INVALID", 2: "HPMG_E_NOMEM", 3: "HPMG_E_DEVICE",
           4: "HPMG_E_NOT_CONVERGED", 5: "HPMG_E_BREAKDOWN", 6: "HPMG_E_UNSUPPORTED"}
-F64, F32 = 0, 1
-PREC_F64, PREC_F32 = 0, 1
+F64, F32, F16, BF16 = 0, 1, 2, 3
+PREC_F64, PREC_F32, PREC_F16, PREC_BF16 = 0, 1, 2, 3
+
+
+def _torch_dtype(code):
+    import torch
+    return {F64: torch.float64, F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}[code]
 
 
 class Mesh(ctypes.Structure):
@@ -135,7 +140,7 @@ def _ptr(t, dtype_code=None):
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     if dtype_code is not None:
-        want = torch.float64 if dtype_code == F64 else torch.float32
+        want = _torch_dtype(dtype_code)
         if t.dtype != want:
             raise TypeError(f"expected {want}, got {t.dtype}")
     return ctypes.c_void_p(t.data_ptr())
@@ -143,11 +148,10 @@ def _ptr(t, dtype_code=None):
 
 def _code(t):
     import torch
-    if t.dtype == torch.float64:
-        return F64
-    if t.dtype == torch.float32:
-        return F32
-    raise TypeError(f"unsupported dtype {t.dtype}")
+    codes = {torch.float64: F64, torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return codes[t.dtype]
 
 
 class Solver:

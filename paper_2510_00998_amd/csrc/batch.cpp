@@ -822,7 +822,7 @@ hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* cons
     const double rtol2 = rtol * rtol;
     int* hc = bt->host_count;
     auto sync_count = [&]() {
-      HIPCHK(hipMemcpyAsync(hc, B->count, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hc, B->count, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
     };
     // initial residual and its FP32 copy
@@ -880,8 +880,9 @@ hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* cons
       set_last_error("breakdown (non-finite value or zero curvature) in a batched solve");
       return HPMG_E_BREAKDOWN;
     }
-    if (hc[0] > 0) {
-      set_last_error("maximum number of iterations reached");
+    if (hc[0] > 0 || hc[3] > 0) {
+      set_last_error(hc[3] > 0 ? "true residual stagnates above rtol (FP64 rounding floor of b - A u)"
+                               : "maximum number of iterations reached");
       return HPMG_E_NOT_CONVERGED;
     }
     return HPMG_OK;

@@ -63,6 +63,7 @@ struct SegTable {
 };
 constexpr int BATCH_CHUNK = 16384;
 constexpr int BATCH_SCAL = 16;  // doubles of per-segment scalar state
+constexpr double BATCH_MAX_RESTARTS = 3;  // restarts from the true residual per segment
 
 template <typename T>
 void batch_dg(int op, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);

@@ -244,9 +244,10 @@ __global__ __launch_bounds__(256) void k_bdot_z(SegTable t, const float* __restr
 
 // Per-segment scalar state (BATCH_SCAL doubles): [2] rho, [3] beta,
 // [5] alpha, [6] r.r, [7] 1/||r||, [8] ||r||, [9] ||r0||^2, [10] state
-// (0 iterating, 1 recurrence converged, 2 done, 3 breakdown), [11] restart,
-// [12] last true residual^2, [13] iterations, [14] scale of the FP32 copy
-// of r that the next cycle reads.
+// (0 iterating, 1 recurrence converged, 2 done, 3 breakdown, 4 true residual
+// stagnated above the tolerance), [11] restart, [12] last true residual^2,
+// [13] iterations, [14] scale of the FP32 copy of r that the next cycle
+// reads, [15] restarts so far.
 __device__ __forceinline__ void set_rr(double* s, double t0) {
   s[6] = t0;
   s[7] = t0 > 0.0 ? 1.0 / sqrt(t0) : 1.0;
@@ -294,6 +295,7 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
     s[11] = 1.0;
     s[12] = t0;
     s[13] = 0.0;
+    s[15] = 0.0;
   } else {  // op 5: true residual of the segments whose recurrence converged
     if (s[10] == 1.0) {
       s[12] = t0;
@@ -301,10 +303,13 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
         s[10] = 3.0;
       } else if (t0 <= rtol2 * s[9]) {
         s[10] = 2.0;
+      } else if (s[15] >= BATCH_MAX_RESTARTS) {
+        s[10] = 4.0;  // stagnated at the FP64 rounding floor of b - A u
       } else {  // restart from the true residual
         set_rr(s, t0);
         s[10] = 0.0;
         s[11] = 1.0;
+        s[15] += 1.0;
       }
     }
     s[14] = s[7];  // every segment's r is cast to FP32 next with scale s[7]
@@ -384,23 +389,26 @@ __global__ __launch_bounds__(256) void k_bcast_down(SegTable t, const double* __
 }
 
 // count[0] = segments still iterating or waiting, count[1] = segments
-// waiting for the true residual check, count[2] = segments that broke down
+// waiting for the true residual check, count[2] = segments that broke down,
+// count[3] = segments whose true residual stagnated
 __global__ __launch_bounds__(256) void k_bcount(SegTable t, const double* __restrict__ scal, int* __restrict__ count) {
-  __shared__ int cs[3];
-  if (threadIdx.x < 3) cs[threadIdx.x] = 0;
+  __shared__ int cs[4];
+  if (threadIdx.x < 4) cs[threadIdx.x] = 0;
   __syncthreads();
-  int a = 0, b = 0, c = 0;
+  int a = 0, b = 0, c = 0, d = 0;
   for (int sg = threadIdx.x; sg < t.nseg; sg += blockDim.x) {
     const double st = scal[(size_t)sg * BATCH_SCAL + 10];
     a += st == 0.0 || st == 1.0;
     b += st == 1.0;
     c += st == 3.0;
+    d += st == 4.0;
   }
   atomicAdd(&cs[0], a);
   atomicAdd(&cs[1], b);
   atomicAdd(&cs[2], c);
+  atomicAdd(&cs[3], d);
   __syncthreads();
-  if (threadIdx.x < 3) count[threadIdx.x] = cs[threadIdx.x];
+  if (threadIdx.x < 4) count[threadIdx.x] = cs[threadIdx.x];
 }
 
 inline unsigned grid_for(int n, int cap) { return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap); }

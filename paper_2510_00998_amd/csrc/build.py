@@ -22,12 +22,16 @@ SOURCES = [
     "basis.cpp",
     "hpmg.cpp",
     "cg_kernels.hip",
-    "dg_inst_2d_float.hip",
-    "dg_inst_2d_double.hip",
-    "dg_inst_3d_float.hip",
     "batch_kernels.hip",
     "batch.cpp",
+    "dg_inst_2d_float.hip",
+    "dg_inst_2d_double.hip",
+    "dg_inst_2d_f16.hip",
+    "dg_inst_2d_bf16.hip",
+    "dg_inst_3d_float.hip",
     "dg_inst_3d_double.hip",
+    "dg_inst_3d_f16.hip",
+    "dg_inst_3d_bf16.hip",
 ]
 
 # Packed FP32 instructions are disabled for all device code.

@@ -245,20 +245,24 @@ __global__ __launch_bounds__(256) void k_update_ur(size_t n, double* __restrict_
   }
 }
 
-// y = (float)(x * s[7])  (scaled cast for the FP32 cycle)
-__global__ __launch_bounds__(256) void k_cast_down(size_t n, const double* __restrict__ x, float* __restrict__ y,
-                                                   const double* __restrict__ s) {
-  const double sc = s[7];
+// y = (T)(x * s[7] * mul): scaled cast for a reduced-precision cycle (s[7] =
+// 1/||x||; mul = 1 for FP32, sqrt(n) for 16-bit storage so that the entries
+// have unit mean square)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_down(size_t n, const double* __restrict__ x, T* __restrict__ y,
+                                                   const double* __restrict__ s, double mul) {
+  const double sc = s[7] * mul;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] = (float)(x[i] * sc);
+    y[i] = (T)(float)(x[i] * sc);
 }
 
-// y = (double)x * s[8]
-__global__ __launch_bounds__(256) void k_cast_up(size_t n, const float* __restrict__ x, double* __restrict__ y,
-                                                 const double* __restrict__ s) {
-  const double sc = s[8];
+// y = (double)x * s[8] / mul
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_up(size_t n, const T* __restrict__ x, double* __restrict__ y,
+                                                 const double* __restrict__ s, double mul) {
+  const double sc = s[8] / mul;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] = (double)x[i] * sc;
+    y[i] = (double)(float)x[i] * sc;
 }
 
 inline unsigned nblocks(size_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -340,13 +344,20 @@ void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, (int)g, scal, 3, 0, 0);
 }
 
-void cast_down(size_t n, const double* x, float* y, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_cast_down, dim3(gs_blocks(n)), dim3(256), 0, s, n, x, y, scal);
+template <typename T>
+void cast_down(size_t n, const double* x, T* y, const double* scal, double mul, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast_down<T>), dim3(gs_blocks(n)), dim3(256), 0, s, n, x, y, scal, mul);
 }
-
-void cast_up(size_t n, const float* x, double* y, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_cast_up, dim3(gs_blocks(n)), dim3(256), 0, s, n, x, y, scal);
+template <typename T>
+void cast_up(size_t n, const T* x, double* y, const double* scal, double mul, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast_up<T>), dim3(gs_blocks(n)), dim3(256), 0, s, n, x, y, scal, mul);
 }
+template void cast_down<float>(size_t, const double*, float*, const double*, double, hipStream_t);
+template void cast_down<_Float16>(size_t, const double*, _Float16*, const double*, double, hipStream_t);
+template void cast_down<__bf16>(size_t, const double*, __bf16*, const double*, double, hipStream_t);
+template void cast_up<float>(size_t, const float*, double*, const double*, double, hipStream_t);
+template void cast_up<_Float16>(size_t, const _Float16*, double*, const double*, double, hipStream_t);
+template void cast_up<__bf16>(size_t, const __bf16*, double*, const double*, double, hipStream_t);
 
 #define HPMG_INST(T)                                                                                           \
   template void cg_stencil<T>(int, int, const T*, const T*, const T*, const T*, T*, T, int, int, hipStream_t); \
@@ -358,5 +369,7 @@ void cast_up(size_t n, const float* x, double* y, const double* scal, hipStream_
 HPMG_INST(float)
 HPMG_INST(double)
 #undef HPMG_INST
+template void fill<_Float16>(_Float16*, size_t, _Float16, hipStream_t);
+template void fill<__bf16>(__bf16*, size_t, __bf16, hipStream_t);
 
 }  // namespace hpmg

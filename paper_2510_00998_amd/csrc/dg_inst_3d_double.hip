@@ -1,34 +1,8 @@
-// Instantiation of the DG cell kernels for dim = 3, double.
-#include "dg_kernels_impl.hpp"
-#include "kernels.hpp"
+// Instantiation of the DG cell kernels for dim = 3, storage type double.
+#include "dg_inst.hpp"
 
 namespace hpmg {
-namespace {
-template <int N>
-void run(int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s) {
-  constexpr int NC = nc_next(N);
-  switch (op) {
-    case OP_SWEEP: launch_sweep<double, 3, N>(a, nrhs, flag != 0, s); break;
-    case OP_APPLY: launch_apply<double, 3, N, 0>(a, nrhs, flag != 0, s); break;
-    case OP_RESTRICT: launch_apply<double, 3, N, NC>(a, nrhs, true, s); break;
-    case OP_PROJECT: launch_prolong<double, 3, N, 0>(a, nrhs, s); break;
-    case OP_PROLONG: launch_prolong<double, 3, N, NC>(a, nrhs, s); break;
-    default: break;
-  }
-}
-}  // namespace
-
 bool dg_dispatch3(int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s) {
-  switch (N) {
-    case 2: run<2>(op, a, nrhs, flag, s); return true;
-    case 3: run<3>(op, a, nrhs, flag, s); return true;
-    case 4: run<4>(op, a, nrhs, flag, s); return true;
-    case 5: run<5>(op, a, nrhs, flag, s); return true;
-    case 6: run<6>(op, a, nrhs, flag, s); return true;
-    case 7: run<7>(op, a, nrhs, flag, s); return true;
-    case 8: run<8>(op, a, nrhs, flag, s); return true;
-    case 9: run<9>(op, a, nrhs, flag, s); return true;
-    default: return false;
-  }
+  return inst::dispatch<double, 3>(N, op, a, nrhs, flag, s);
 }
 }  // namespace hpmg

@@ -61,26 +61,45 @@ struct RefOff {
   static constexpr int M = 0, EP0 = N * N, EP1 = N * N + N, E = N * N + 2 * N;
 };
 
+// Storage type T of the cell vectors and traces, compute type CT<T> of the
+// arithmetic, LDS, operator tables and coarse-level vectors: half-precision
+// storage (FP16 or BF16) computes in FP32.
+template <typename T>
+struct Compute {
+  using type = T;
+};
+template <>
+struct Compute<_Float16> {
+  using type = float;
+};
+template <>
+struct Compute<__bf16> {
+  using type = float;
+};
+template <typename T>
+using CT = typename Compute<T>::type;
+
 template <typename T>
 struct DGArgs {
+  using C = CT<T>;
   int n, ncell;
   int vark;            // 0: class tables (constant kappa), 1: per-cell eigendata + kappa
-  T kappa_const;
-  const T* ref;        // RefOff layout
-  const T* eig;        // vark=0: [4 classes][S N^2 | Si N^2 | lam N]; vark=1: [cell][D][S N^2 | lam N]
-  const T* kappa;      // vark=1: per cell
+  C kappa_const;
+  const C* ref;        // RefOff layout
+  const C* eig;        // vark=0: [4 classes][S N^2 | Si N^2 | lam N]; vark=1: [cell][D][S N^2 | lam N]
+  const C* kappa;      // vark=1: per cell
   const unsigned char* bmask;  // per cell: bit 2k+side set if that facet is on the boundary
-  T h_fwd;             // h^(2-d): scales b in the sweep
-  T h_apply;           // h^(d-2): scales A u
-  T sigma_hat;         // sigma * h = sigma0 (p_penalty+1)^2
-  T omega;
+  C h_fwd;             // h^(2-d): scales b in the sweep
+  C h_apply;           // h^(d-2): scales A u
+  C sigma_hat;         // sigma * h = sigma0 (p_penalty+1)^2
+  C omega;
   const T* u_in;       // cell vector
   T* u_out;            // cell vector (may alias u_in)
   const T* b;          // cell vector
   const T* tr_in;      // traces [2D][ncell][2][L]
   T* tr_out;
-  T* out;              // apply: y; resid: r (NC=0) or coarse right-hand side
-  const T* coarse;     // prolong: coarse cell vector (DG) or Q1 interior vertex vector (CG)
+  C* out;              // apply: y; resid: r (NC=0) or coarse right-hand side (next level, compute type)
+  const C* coarse;     // prolong: coarse cell vector (DG) or Q1 interior vertex vector (CG)
   int coarse_cg;       // prolong/restrict partner is Q1 (vertex gather) rather than DG
   long long vstride;   // per right-hand side stride of cell vectors
   long long tstride;   // per right-hand side stride of trace buffers

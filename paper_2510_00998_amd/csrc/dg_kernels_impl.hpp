@@ -98,7 +98,8 @@ struct EigLDS {
 // Stage the eigendata (and, per cell, kappa_F of every facet; 0 on the
 // boundary) of the block's cells.
 template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, T* sE, T* sKF) {
+__device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<T>* sE, CT<T>* sKF) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   const int tid = work_tid<D, N>();
@@ -114,11 +115,11 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, T* 
       const int cl = i / Sh::NF, f = i % Sh::NF;
       const int k = f >> 1, s = f & 1;
       const int c = c0 + cl;
-      T kf = 0;
+      C kf = 0;
       if (!((a.bmask[c] >> f) & 1)) {
         const int st = ipow<D>(a.n, k);
-        const T k0 = a.kappa[c], k1 = a.kappa[s ? c + st : c - st];
-        kf = T(2) * k0 * k1 / (k0 + k1);
+        const C k0 = a.kappa[c], k1 = a.kappa[s ? c + st : c - st];
+        kf = C(2) * k0 * k1 / (k0 + k1);
       }
       sKF[i] = kf;
     }
@@ -127,15 +128,16 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, T* 
 
 // Si = S^T M for every staged (cell, axis) when the data came per cell.
 template <typename T, int D, int N>
-__device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
+__device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, CT<T>* sE) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
-  const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
+  const cptr<C> Mh = as_const(a.ref) + RefOff<N>::M;
   for (int i = work_tid<D, N>(); i < nc * D * NN; i += Sh::NT) {
     const int e = i % NN, ck = i / NN;
     const int r = e / N, col = e % N;
-    const T* S = sE + ck * Sh::EGS;
-    T s = 0;
+    const C* S = sE + ck * Sh::EGS;
+    C s = 0;
 #pragma unroll
     for (int m = 0; m < N; ++m) s += S[m * N + r] * Mh[m * N + col];
     sE[ck * Sh::EGS + NN + e] = s;
@@ -148,11 +150,12 @@ __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, T* sE) {
 // the global class table with scalar loads; otherwise from the LDS copy
 // (LDS = true, after the block staged it) or per lane from global memory.
 template <typename T, int D, int N, bool VARK, bool TR, bool LDS = true>
-__device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const T* sE, int cl, int mask, int k, int off,
-                                         const T (&in)[N], T (&out)[N]) {
+__device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const CT<T>* sE, int cl, int mask, int k, int off,
+                                         const CT<T> (&in)[N], CT<T> (&out)[N]) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   // matrices that fit in about 72 SGPRs take the scalar path
-  constexpr bool SCALAR_OK = N * N * (int)sizeof(T) / 4 <= 72;
+  constexpr bool SCALAR_OK = N * N * (int)sizeof(C) / 4 <= 72;
   if constexpr (VARK) {
     mv<N, TR>(sE + (cl * D + k) * Sh::EGS + off, in, out);
   } else {
@@ -191,14 +194,15 @@ __device__ __forceinline__ int tangential(int k, int pass) {
 // ordered (facet, cell, line) so that a wave mostly sees one facet
 // direction and therefore one matrix.
 template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL>
-__device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int c0, int nc, int pass, T* sNB,
-                                           const T* sE, const T* sKF) {
+__device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int c0, int nc, int pass, CT<T>* sNB,
+                                           const CT<T>* sE, const CT<T>* sKF) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
   constexpr int TL = 2 * L;
   constexpr int LINES = (D == 2) ? 1 : N;
-  const cptr<T> Mh = as_const(a.ref) + RefOff<N>::M;
+  const cptr<C> Mh = as_const(a.ref) + RefOff<N>::M;
   for (int i = work_tid<D, N>(); i < Sh::CPB * Sh::NF * LINES; i += Sh::NT) {
     const int f = i / (Sh::CPB * LINES), rem = i % (Sh::CPB * LINES);
     const int cl = rem / LINES, li = rem % LINES;
@@ -208,19 +212,19 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
     const int t = tangential<D>(k, pass);
     const int st = pass == 0 ? 1 : N;  // node stride along t within the facet
     const int lo = pass == 0 ? N * li : li;
-    T* g = sNB + (cl * Sh::NF + f) * TL + lo;
+    C* g = sNB + (cl * Sh::NF + f) * TL + lo;
     const int mask = a.bmask[c];
-    T x1[N], x2[N], o1[N], o2[N];
+    C x1[N], x2[N], o1[N], o2[N];
     if (pass == 0) {
       if ((mask >> f) & 1) {  // boundary facet: no neighbour, zero flux fields
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          g[j] = T(0);
-          g[L + j] = T(0);
+          g[j] = C(0);
+          g[L + j] = C(0);
         }
         continue;
       }
-      T gv[N], qv[N];
+      C gv[N], qv[N];
       if constexpr (FROM_GLOBAL) {
         const int s = f & 1;
         const int stc = ipow<D>(a.n, k);
@@ -237,15 +241,15 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
           qv[j] = g[L + j];
         }
       }
-      T kf;
+      C kf;
       if constexpr (VARK)
         kf = sKF[cl * Sh::NF + f];
       else
         kf = a.kappa_const;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        x1[j] = kf * (T(0.5) * qv[j] - a.sigma_hat * gv[j]);
-        x2[j] = T(0.5) * kf * gv[j];
+        x1[j] = kf * (C(0.5) * qv[j] - a.sigma_hat * gv[j]);
+        x2[j] = C(0.5) * kf * gv[j];
       }
     } else {
 #pragma unroll
@@ -272,7 +276,8 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
 // Plain copy of the neighbour traces into sNB (variable kappa path, whose
 // facet transform needs the staged per-cell eigendata).
 template <typename T, int D, int N>
-__device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc, T* sNB) {
+__device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int TL = 2 * Sh::L;
   for (int f = 0; f < Sh::NF; ++f) {
@@ -284,7 +289,7 @@ __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const 
       const int cl = i / TL, e = i % TL;
       const int c = c0 + cl;
       const bool bdy = (a.bmask[c] >> f) & 1;
-      sNB[(cl * Sh::NF + f) * TL + e] = bdy ? T(0) : src[(size_t)(c + off) * TL + e];
+      sNB[(cl * Sh::NF + f) * TL + e] = bdy ? C(0) : src[(size_t)(c + off) * TL + e];
     }
   }
 }
@@ -292,7 +297,8 @@ __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const 
 // All facet flux fields of the block in sNB, and the eigendata in sE; ends
 // with a barrier.
 template <typename T, int D, int N, bool VARK>
-__device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int c0, int nc, T* sNB, T* sE, T* sKF) {
+__device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB, CT<T>* sE, CT<T>* sKF) {
+  using C = CT<T>;
   if constexpr (!VARK) {
     facet_pass<T, D, N, false, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
     load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
@@ -315,14 +321,15 @@ __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int
 // r -= lift of facets (k,0) and (k,1): value part at the facet node, normal
 // derivative part along the line (sweep, SIGN = -1) or r += (apply, +1).
 template <typename T, int D, int N, int SIGN>
-__device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int ln, const T* sNB, T (&r)[N]) {
+__device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int ln, const CT<T>* sNB, CT<T> (&r)[N]) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
-  const cptr<T> ep0 = as_const(a.ref) + RefOff<N>::EP0;
-  const cptr<T> ep1 = as_const(a.ref) + RefOff<N>::EP1;
-  const T* f0 = sNB + (cl * Sh::NF + 2 * k) * 2 * L;
-  const T* f1 = f0 + 2 * L;
-  const T v0 = f0[ln], d0 = f0[L + ln], v1 = f1[ln], d1 = f1[L + ln];
+  const cptr<C> ep0 = as_const(a.ref) + RefOff<N>::EP0;
+  const cptr<C> ep1 = as_const(a.ref) + RefOff<N>::EP1;
+  const C* f0 = sNB + (cl * Sh::NF + 2 * k) * 2 * L;
+  const C* f1 = f0 + 2 * L;
+  const C v0 = f0[ln], d0 = f0[L + ln], v1 = f1[ln], d1 = f1[L + ln];
   if constexpr (SIGN < 0) {
     r[0] -= v0;
     r[N - 1] -= v1;
@@ -340,13 +347,14 @@ __device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int
 // straight to the trace buffer for the facets that are not on the boundary.
 template <typename T, int D, int N>
 __device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, int c, int mask, int k, int ln,
-                                                  const T (&u)[N]) {
+                                                  const CT<T> (&u)[N]) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
   constexpr int TL = 2 * L;
-  const cptr<T> ep0 = as_const(a.ref) + RefOff<N>::EP0;
-  const cptr<T> ep1 = as_const(a.ref) + RefOff<N>::EP1;
-  T d0 = 0, d1 = 0;
+  const cptr<C> ep0 = as_const(a.ref) + RefOff<N>::EP0;
+  const cptr<C> ep1 = as_const(a.ref) + RefOff<N>::EP1;
+  C d0 = 0, d1 = 0;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     d0 += ep0[j] * u[j];
@@ -366,13 +374,14 @@ __device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, 
 
 // Traces of the y (and z) lines of the cell vector staged in sU.
 template <typename T, int D, int N>
-__device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, const T* sU, int cl, int c, int mask,
+__device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, const CT<T>* sU, int cl, int c, int mask,
                                                 int ln) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
 #pragma unroll
   for (int k = 1; k < D; ++k) {
     const int base = cl * Sh::NV + line_base<D, N>(k, ln);
-    T u[N];
+    C u[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) u[j] = sU[base + j * line_stride<N>(k)];
     store_line_traces<T, D, N>(a, trout, c, mask, k, ln, u);
@@ -387,20 +396,22 @@ __device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, co
 // LDS bytes of the sweep / apply bodies.
 template <typename T, int D, int N, bool VARK>
 constexpr int cell_lds_bytes() {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
-  return (int)sizeof(T) *
+  return (int)sizeof(C) *
          (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK>::SIZE + (VARK ? Sh::CPB * Sh::NF : 1));
 }
 
 template <typename T, int D, int N, bool UZERO, bool VARK>
 __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, char* lds) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
-  T* sW = (T*)lds;
-  T* sNB = sW + Sh::CPB * Sh::NV;
-  T* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
-  T* sKF = sE + EigLDS<D, N, VARK>::SIZE;
+  C* sW = (C*)lds;
+  C* sNB = sW + Sh::CPB * Sh::NV;
+  C* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
+  C* sKF = sE + EigLDS<D, N, VARK>::SIZE;
 
   const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -412,7 +423,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
   const int mask = a.bmask[c];
 
-  T ul[N], bl[N];
+  C ul[N], bl[N];
   if (act) {
     const T* bs = a.b + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
@@ -440,7 +451,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   for (int k = 0; k < D; ++k) {
     if (act) {
       const int base = cl * Sh::NV + line_base<D, N>(k, ln);
-      T r[N], t[N];
+      C r[N], t[N];
       if (k == 0) {
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = a.h_fwd * bl[j];
@@ -452,15 +463,15 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
       stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, 0, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
-        const T* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
-        const T* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
+        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
+        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
         if constexpr (D == 2) {
-          const T ls = E0[2 * NN + ln];
+          const C ls = E0[2 * NN + ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= recip(ls + E1[2 * NN + j]);
         } else {
-          const T* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
-          const T ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
+          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
+          const C ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= recip(ls + E2[2 * NN + j]);
         }
@@ -480,7 +491,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   for (int k = D - 2; k >= 0; --k) {
     if (act) {
       const int base = cl * Sh::NV + line_base<D, N>(k, ln);
-      T r[N], t[N];
+      C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, 0, r, t);
@@ -488,8 +499,8 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
         T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          const T uo0 = UZERO ? T(0) : ul[j];
-          t[j] = (T(1) - a.omega) * uo0 + a.omega * t[j];
+          const C uo0 = UZERO ? C(0) : ul[j];
+          t[j] = (C(1) - a.omega) * uo0 + a.omega * t[j];
           sW[base + j] = t[j];
           uo[j] = t[j];
         }
@@ -512,19 +523,20 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_sweep(DGArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // y = A u (RESID: r = b - A u), optionally restricted to the next coarser
-// level: NC > 0 gives per cell (E^T x E^T x E^T) r with E the interpolation
+// level: NC > 0 gives per cell (E^C x E^C x E^C) r with E the interpolation
 // from the coarse nodes (DG_q: a coarse cell vector; Q1: the 2^d corner
 // contributions of each cell, summed over cells by the gather kernel).
 // Needs the traces of u in tr_in.
 template <typename T, int D, int N, int NC, bool RESID, bool VARK>
 __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, char* lds) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int L = Sh::L;
-  T* sW = (T*)lds;
-  T* sNB = sW + Sh::CPB * Sh::NV;
-  T* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
-  T* sKF = sE + EigLDS<D, N, VARK>::SIZE;
+  C* sW = (C*)lds;
+  C* sNB = sW + Sh::CPB * Sh::NV;
+  C* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
+  C* sKF = sE + EigLDS<D, N, VARK>::SIZE;
 
   const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -536,7 +548,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
   const int mask = a.bmask[c];
 
-  T ul[N], bl[N];
+  C ul[N], bl[N];
   if (act) {
     const T* us = a.u_in + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
@@ -555,7 +567,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   for (int k = 0; k < D; ++k) {
     if (act) {
       const int base = cl * Sh::NV + line_base<D, N>(k, ln);
-      T r[N], t[N];
+      C r[N], t[N];
       if (k == 0) {
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = ul[j];
@@ -565,15 +577,15 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       }
       stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, NN, r, t);  // Si
       if (k == D - 1) {
-        const T* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
-        const T* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
+        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
+        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
         if constexpr (D == 2) {
-          const T ls = E0[2 * NN + ln];
+          const C ls = E0[2 * NN + ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + E1[2 * NN + j]);
         } else {
-          const T* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
-          const T ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
+          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
+          const C ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + E2[2 * NN + j]);
         }
@@ -591,7 +603,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   for (int k = D - 2; k >= 0; --k) {
     if (act) {
       const int base = cl * Sh::NV + line_base<D, N>(k, ln);
-      T r[N], t[N];
+      C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, NN, r, t);
@@ -603,7 +615,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
           if (RESID) t[j] = bl[j] - t[j];
         }
         if constexpr (NC == 0) {
-          T* dst = a.out + rv + (size_t)c0 * Sh::NV + base0;
+          C* dst = a.out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
           for (int j = 0; j < N; ++j) dst[j] = t[j];
         } else {
@@ -620,19 +632,19 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   if constexpr (NC > 0) {
     // restriction (E^T)^(x d) of the cell residual, one axis per pass; sNB
     // is free once every lift has been read (barrier above)
-    const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
+    const cptr<C> E = as_const(a.ref) + RefOff<N>::E;
     constexpr int NCD = (D == 2) ? NC * NC : NC * NC * NC;
     constexpr int NBS = Sh::NF * 2 * L;  // per-cell stride of sNB
-    T* dst = a.out + (size_t)by * a.cstride + (size_t)c0 * NCD;
+    C* dst = a.out + (size_t)by * a.cstride + (size_t)c0 * NCD;
     // x: sW[cl][..][a] -> sNB[cl][ln][a'] (a' + NC*ln)
     for (int i = tid; i < nc * L; i += Sh::NT) {
       const int c2 = i / L, l2 = i % L;
-      T x[N];
+      C x[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + j + N * l2];
 #pragma unroll
       for (int jc = 0; jc < NC; ++jc) {
-        T s = 0;
+        C s = 0;
 #pragma unroll
         for (int j = 0; j < N; ++j) s += E[j * NC + jc] * x[j];
         sNB[c2 * NBS + jc + NC * l2] = s;
@@ -643,12 +655,12 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       // y: sNB[cl][b][a'] -> dst[a' + NC b']
       for (int i = tid; i < nc * NC; i += Sh::NT) {
         const int c2 = i / NC, ac = i % NC;
-        T x[N];
+        C x[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + NC * j];
 #pragma unroll
         for (int bc = 0; bc < NC; ++bc) {
-          T s = 0;
+          C s = 0;
 #pragma unroll
           for (int j = 0; j < N; ++j) s += E[j * NC + bc] * x[j];
           dst[(size_t)c2 * NCD + ac + NC * bc] = s;
@@ -659,12 +671,12 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       for (int i = tid; i < nc * NC * N; i += Sh::NT) {
         const int c2 = i / (NC * N), rem = i % (NC * N);
         const int ac = rem % NC, cz = rem / NC;
-        T x[N];
+        C x[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + NC * (j + N * cz)];
 #pragma unroll
         for (int bc = 0; bc < NC; ++bc) {
-          T s = 0;
+          C s = 0;
 #pragma unroll
           for (int j = 0; j < N; ++j) s += E[j * NC + bc] * x[j];
           sW[c2 * Sh::NV + ac + NC * (bc + NC * cz)] = s;
@@ -674,12 +686,12 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       // z: sW[cl][c][b'][a'] -> dst[a' + NC b' + NC^2 c']
       for (int i = tid; i < nc * NC * NC; i += Sh::NT) {
         const int c2 = i / (NC * NC), rem = i % (NC * NC);
-        T x[N];
+        C x[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + rem + NC * NC * j];
 #pragma unroll
         for (int ccz = 0; ccz < NC; ++ccz) {
-          T s = 0;
+          C s = 0;
 #pragma unroll
           for (int j = 0; j < N; ++j) s += E[j * NC + ccz] * x[j];
           dst[(size_t)c2 * NCD + rem + NC * NC * ccz] = s;
@@ -702,17 +714,19 @@ __global__ __launch_bounds__(HPMG_MAX_THREADS) void k_apply(DGArgs<T> a) {
 // Section 5.1.1).
 template <typename T, int D, int N, int NC>
 constexpr int prolong_lds_bytes() {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
-  return (int)sizeof(T) * (Sh::CPB * Sh::NV + (NC > 0 ? Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L : 0));
+  return (int)sizeof(C) * (Sh::CPB * Sh::NV + (NC > 0 ? Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L : 0));
 }
 
 template <typename T, int D, int N, int NC>
 __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by, char* lds) {
+  using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int L = Sh::L;
-  T* sU = (T*)lds;
-  T* sW = sU + Sh::CPB * Sh::NV;
-  T* sNB = sW + Sh::CPB * Sh::NV;
+  C* sU = (C*)lds;
+  C* sW = sU + Sh::CPB * Sh::NV;
+  C* sNB = sW + Sh::CPB * Sh::NV;
 
   const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -724,14 +738,14 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
   const int mask = a.bmask[c];
   constexpr int NCD = (NC == 0) ? 0 : ((D == 2) ? NC * NC : NC * NC * NC);
 
-  T u[N];
+  C u[N];
   if (act) {
     const T* us = a.u_in + rv + (size_t)c0 * Sh::NV + cl * Sh::NV + line_base<D, N>(0, ln);
 #pragma unroll
     for (int j = 0; j < N; ++j) u[j] = us[j];
   }
   if constexpr (NC > 0) {
-    const T* cs = a.coarse + (size_t)by * a.cstride;
+    const C* cs = a.coarse + (size_t)by * a.cstride;
     if (!a.coarse_cg) {
       for (int i = tid; i < nc * NCD; i += Sh::NT) sW[(i / NCD) * Sh::NV + i % NCD] = cs[(size_t)c0 * NCD + i];
     } else {
@@ -754,21 +768,21 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
           vid += (v - 1) * mul;
           mul *= nv;
         }
-        sW[c2 * Sh::NV + corner] = inside ? cs[vid] : T(0);
+        sW[c2 * Sh::NV + corner] = inside ? cs[vid] : C(0);
       }
     }
     __syncthreads();
-    const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
+    const cptr<C> E = as_const(a.ref) + RefOff<N>::E;
     if constexpr (D == 3) {
       // z: [c'][b'][a'] -> sNB[cl][c][b'][a'] (a' + NC b' + NC^2 c)
       for (int i = tid; i < nc * NC * NC; i += Sh::NT) {
         const int c2 = i / (NC * NC), rem = i % (NC * NC);
-        T x[NC];
+        C x[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) x[j] = sW[c2 * Sh::NV + rem + NC * NC * j];
 #pragma unroll
         for (int cz = 0; cz < N; ++cz) {
-          T s = 0;
+          C s = 0;
 #pragma unroll
           for (int j = 0; j < NC; ++j) s += E[cz * NC + j] * x[j];
           sNB[c2 * Sh::NF * 2 * L + rem + NC * NC * cz] = s;
@@ -779,12 +793,12 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
       for (int i = tid; i < nc * NC * N; i += Sh::NT) {
         const int c2 = i / (NC * N), rem = i % (NC * N);
         const int ac = rem % NC, cz = rem / NC;
-        T x[NC];
+        C x[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) x[j] = sNB[c2 * Sh::NF * 2 * L + ac + NC * j + NC * NC * cz];
 #pragma unroll
         for (int by = 0; by < N; ++by) {
-          T s = 0;
+          C s = 0;
 #pragma unroll
           for (int j = 0; j < NC; ++j) s += E[by * NC + j] * x[j];
           sW[c2 * Sh::NV + ac + NC * (by + N * cz)] = s;
@@ -795,12 +809,12 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
       // y: [b'][a'] -> sNB[cl][b][a'] -> copy back into sW layout (a' + NC b)
       for (int i = tid; i < nc * NC; i += Sh::NT) {
         const int c2 = i / NC, ac = i % NC;
-        T x[NC];
+        C x[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) x[j] = sW[c2 * Sh::NV + ac + NC * j];
 #pragma unroll
         for (int by = 0; by < N; ++by) {
-          T s = 0;
+          C s = 0;
 #pragma unroll
           for (int j = 0; j < NC; ++j) s += E[by * NC + j] * x[j];
           sNB[c2 * Sh::NF * 2 * L + ac + NC * by] = s;
@@ -820,13 +834,13 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
   if (act) {
     const int base = cl * Sh::NV + line_base<D, N>(0, ln);
     if constexpr (NC > 0) {
-      const cptr<T> E = as_const(a.ref) + RefOff<N>::E;
-      T x[NC];
+      const cptr<C> E = as_const(a.ref) + RefOff<N>::E;
+      C x[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) x[j] = sW[cl * Sh::NV + j + NC * ln];
 #pragma unroll
       for (int ax = 0; ax < N; ++ax) {
-        T s = 0;
+        C s = 0;
 #pragma unroll
         for (int j = 0; j < NC; ++j) s += E[ax * NC + j] * x[j];
         u[ax] += s;

@@ -13,6 +13,7 @@
 #include <stdexcept>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "basis.hpp"
@@ -475,6 +476,9 @@ void vcycle_cg(hpmg_ctx* h, int m, bool uzero, hipStream_t s) {
 // residual + restriction, prolongation + projection, nu_post sweeps.
 template <typename T>
 void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) {
+  // 16-bit storage applies to this level only: the coarser levels run in
+  // the compute type C
+  using C = hpmg::CT<T>;
   DGLevel& L = h->dg[l];
   DGData<T>& d = data<T>(L);
   int cur = 0;
@@ -495,40 +499,69 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) 
   a.tr_in = d.tr[cur];
   a.b = b;
   if (!L.next_cg) {
-    DGLevel& C = h->dg[l + 1];
-    DGData<T>& dc = data<T>(C);
+    DGLevel& Cl = h->dg[l + 1];
+    DGData<C>& dc = data<C>(Cl);
     a.out = dc.b;
-    a.cstride = (long long)C.ndof;
+    a.cstride = (long long)Cl.ndof;
     dg_run(h, hpmg::OP_RESTRICT, a, L.N, 1, 1, s);
-    vcycle_dg<T>(h, l + 1, dc.u, dc.b, true, s);
+    vcycle_dg<C>(h, l + 1, dc.u, dc.b, true, s);
     hpmg::DGArgs<T> pa = dg_args<T>(h, L);
     pa.u_in = u;
     pa.u_out = u;
     pa.tr_out = d.tr[cur];
     pa.coarse = dc.u;
     pa.coarse_cg = 0;
-    pa.cstride = (long long)C.ndof;
+    pa.cstride = (long long)Cl.ndof;
     dg_run(h, hpmg::OP_PROLONG, pa, L.N, 1, 0, s);
   } else {
-    CGLevel& C = h->cg[0];
-    CGData<T>& dc = data<T>(C);
-    a.out = d.contrib;
+    CGLevel& Cg = h->cg[0];
+    CGData<C>& dc = data<C>(Cg);
+    a.out = data<C>(L).contrib;
     a.cstride = (long long)h->ncell << h->dim;
     dg_run(h, hpmg::OP_RESTRICT, a, L.N, 1, 1, s);
-    hpmg::gather_corners<T>(h->dim, h->n, d.contrib, dc.b, s);
-    vcycle_cg<T>(h, 0, true, s);
+    hpmg::gather_corners<C>(h->dim, h->n, data<C>(L).contrib, dc.b, s);
+    vcycle_cg<C>(h, 0, true, s);
     hpmg::DGArgs<T> pa = dg_args<T>(h, L);
     pa.u_in = u;
     pa.u_out = u;
     pa.tr_out = d.tr[cur];
-    pa.coarse = dc.u[C.cur];
+    pa.coarse = dc.u[Cg.cur];
     pa.coarse_cg = 1;
-    pa.cstride = (long long)C.size;
+    pa.cstride = (long long)Cg.size;
     dg_run(h, hpmg::OP_PROLONG, pa, L.N, 1, 0, s);
   }
   for (int i = 0; i < h->opt.nu_post; ++i) {
     sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], false, 1, s);
     cur ^= 1;
+  }
+}
+
+// Finest-level traces of a 16-bit storage type, allocated on first use.
+template <typename T>
+void ensure_traces(hpmg_ctx* h) {
+  DGLevel& L = h->dg[0];
+  DGData<T>& d = data<T>(L);
+  if (d.tr[0]) return;
+  const size_t R = h->opt.max_rhs;
+  for (int k = 0; k < 2; ++k) d.tr[k] = (T*)h->mem.alloc(L.trsize * R * sizeof(T));
+}
+
+// Calls f with a null T* for the storage type of dtype (16-bit traces
+// allocated first).
+template <class F>
+void by_dtype(hpmg_ctx* h, int dtype, F f) {
+  switch (dtype) {
+    case HPMG_F64: f((double*)nullptr); break;
+    case HPMG_F32: f((float*)nullptr); break;
+    case HPMG_F16:
+      ensure_traces<_Float16>(h);
+      f((_Float16*)nullptr);
+      break;
+    case HPMG_BF16:
+      ensure_traces<__bf16>(h);
+      f((__bf16*)nullptr);
+      break;
+    default: throw HpmgError(HPMG_E_INVALID, "bad dtype");
   }
 }
 
@@ -595,7 +628,7 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     require(h->opt.nu_pre >= 0 && h->opt.nu_post >= 0 && h->opt.nu_pre + h->opt.nu_post > 0, "bad nu");
     require(h->opt.coarsest_n >= 2, "coarsest_n must be >= 2");
     require(h->opt.max_rhs >= 1, "max_rhs must be >= 1");
-    require(h->opt.precision == HPMG_PREC_F64 || h->opt.precision == HPMG_PREC_F32, "bad precision");
+    require(h->opt.precision >= HPMG_PREC_F64 && h->opt.precision <= HPMG_PREC_BF16, "bad precision");
     h->dim = mesh->dim;
     h->n = mesh->n[0];
     h->p = p;
@@ -756,20 +789,16 @@ hpmg_status hpmg_smooth(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
     require(h && u && b, "NULL argument");
     require(nrhs >= 1 && nrhs <= h->opt.max_rhs, "nrhs out of range");
     require(nsweeps >= 0, "nsweeps must be >= 0");
-    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    require(dtype >= HPMG_F64 && dtype <= HPMG_BF16, "bad dtype");
     if (nsweeps == 0) return HPMG_OK;
     h->trace_state[dtype] = -1;
-    if (dtype == HPMG_F64) {
-      DGData<double>& d = h->dg[0].d;
-      project<double>(h, 0, (const double*)u, d.tr[0], nrhs, stream);
+    by_dtype(h, dtype, [&](auto tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      DGData<T>& d = data<T>(h->dg[0]);
+      project<T>(h, 0, (const T*)u, d.tr[0], nrhs, stream);
       for (int k = 0; k < nsweeps; ++k)
-        sweep<double>(h, 0, (double*)u, (const double*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
-    } else {
-      DGData<float>& d = h->dg[0].f;
-      project<float>(h, 0, (const float*)u, d.tr[0], nrhs, stream);
-      for (int k = 0; k < nsweeps; ++k)
-        sweep<float>(h, 0, (float*)u, (const float*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
-    }
+        sweep<T>(h, 0, (T*)u, (const T*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
+    });
     h->trace_state[dtype] = nsweeps & 1;
     h->trace_rhs[dtype] = nrhs;
     return HPMG_OK;
@@ -782,12 +811,12 @@ hpmg_status hpmg_project(hpmg_handle h, hpmg_dtype dtype, const void* u, int nrh
   try {
     require(h && u, "NULL argument");
     require(nrhs >= 1 && nrhs <= h->opt.max_rhs, "nrhs out of range");
-    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    require(dtype >= HPMG_F64 && dtype <= HPMG_BF16, "bad dtype");
     h->trace_state[dtype] = -1;
-    if (dtype == HPMG_F64)
-      project<double>(h, 0, (const double*)u, h->dg[0].d.tr[0], nrhs, stream);
-    else
-      project<float>(h, 0, (const float*)u, h->dg[0].f.tr[0], nrhs, stream);
+    by_dtype(h, dtype, [&](auto tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      project<T>(h, 0, (const T*)u, data<T>(h->dg[0]).tr[0], nrhs, stream);
+    });
     h->trace_state[dtype] = 0;
     h->trace_rhs[dtype] = nrhs;
     return HPMG_OK;
@@ -800,21 +829,19 @@ hpmg_status hpmg_sweep(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, 
                        hipStream_t stream) {
   try {
     require(h && u && b, "NULL argument");
-    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    require(dtype >= HPMG_F64 && dtype <= HPMG_BF16, "bad dtype");
     require(nsweeps >= 0, "nsweeps must be >= 0");
     require(h->trace_state[dtype] >= 0, "no current traces: call hpmg_project first");
     require(nrhs == h->trace_rhs[dtype], "nrhs differs from the call that produced the traces");
     int cur = h->trace_state[dtype];
-    for (int k = 0; k < nsweeps; ++k) {
-      if (dtype == HPMG_F64) {
-        DGData<double>& d = h->dg[0].d;
-        sweep<double>(h, 0, (double*)u, (const double*)b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, stream);
-      } else {
-        DGData<float>& d = h->dg[0].f;
-        sweep<float>(h, 0, (float*)u, (const float*)b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, stream);
+    by_dtype(h, dtype, [&](auto tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      DGData<T>& d = data<T>(h->dg[0]);
+      for (int k = 0; k < nsweeps; ++k) {
+        sweep<T>(h, 0, (T*)u, (const T*)b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, stream);
+        cur ^= 1;
       }
-      cur ^= 1;
-    }
+    });
     h->trace_state[dtype] = cur;
     return HPMG_OK;
   } catch (const HpmgError& e) {
@@ -826,17 +853,21 @@ hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
   try {
     require(h && u && b, "NULL argument");
     require(nrhs == 1, "vcycle supports nrhs == 1");
-    require(dtype == HPMG_F64 || dtype == HPMG_F32, "bad dtype");
+    require(dtype >= HPMG_F64 && dtype <= HPMG_BF16, "bad dtype");
     h->trace_state[dtype] = -1;
-    if (dtype == HPMG_F64)
-      vcycle_dg<double>(h, 0, (double*)u, (const double*)b, false, stream);
-    else
-      vcycle_dg<float>(h, 0, (float*)u, (const float*)b, false, stream);
+    by_dtype(h, dtype, [&](auto tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      vcycle_dg<T>(h, 0, (T*)u, (const T*)b, false, stream);
+    });
     return HPMG_OK;
   } catch (const HpmgError& e) {
     return fail(e);
   }
 }
+
+// Restarts from the true residual allowed per right-hand side before a
+// solve that cannot reach rtol in FP64 gives up.
+constexpr int kMaxRestarts = 3;
 
 hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, double rtol, int maxit,
                        hpmg_solve_info* info, hipStream_t stream) {
@@ -849,6 +880,28 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
     const size_t nd = h->ndof;
     DGData<double>& d = h->dg[0].d;
     hpmg_status result = HPMG_OK;
+    bool stagnated = false;
+    // 16-bit cycles: the residual handed to the cycle gets mean square
+    // lambda, lambda = d pi^2 kappa_min (h/N)^d (the smallest eigenvalue of
+    // A for unit-scaled nodal vectors), so that its entries and those of the
+    // correction (about r / lambda for smooth r) stay in FP16 range
+    double kmin = h->kappa_const;
+    if (h->vark) kmin = *std::min_element(h->kappa.begin(), h->kappa.end());
+    const double lam = h->dim * M_PI * M_PI * kmin * std::pow(1.0 / (h->n * (h->p + 1.0)), h->dim);
+    const double rms = std::sqrt((double)nd * lam);
+    if (h->opt.precision == HPMG_PREC_F16) {
+      ensure_traces<_Float16>(h);
+      if (!h->r16) {
+        h->r16 = (_Float16*)h->mem.alloc(nd * sizeof(_Float16));
+        h->z16 = (_Float16*)h->mem.alloc(nd * sizeof(_Float16));
+      }
+    } else if (h->opt.precision == HPMG_PREC_BF16) {
+      ensure_traces<__bf16>(h);
+      if (!h->rb16) {
+        h->rb16 = (__bf16*)h->mem.alloc(nd * sizeof(__bf16));
+        h->zb16 = (__bf16*)h->mem.alloc(nd * sizeof(__bf16));
+      }
+    }
     int its_total = 0;
     double r0_first = 0.0, rfin = 0.0;
     std::vector<double> hist;
@@ -868,12 +921,21 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
       int it = 0;
       bool conv = r0 == 0.0;
       bool restart = true;
+      int restarts = 0;
       while (!conv && it < maxit) {
         // z = M r (one V-cycle, zero initial guess)
         if (h->opt.precision == HPMG_PREC_F32) {
-          hpmg::cast_down(nd, h->r, h->r32, h->scal, stream);
+          hpmg::cast_down<float>(nd, h->r, h->r32, h->scal, 1.0, stream);
           vcycle_dg<float>(h, 0, h->z32, h->r32, true, stream);
-          hpmg::cast_up(nd, h->z32, h->z, h->scal, stream);
+          hpmg::cast_up<float>(nd, h->z32, h->z, h->scal, 1.0, stream);
+        } else if (h->opt.precision == HPMG_PREC_F16) {
+          hpmg::cast_down<_Float16>(nd, h->r, h->r16, h->scal, rms, stream);
+          vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, stream);
+          hpmg::cast_up<_Float16>(nd, h->z16, h->z, h->scal, rms, stream);
+        } else if (h->opt.precision == HPMG_PREC_BF16) {
+          hpmg::cast_down<__bf16>(nd, h->r, h->rb16, h->scal, rms, stream);
+          vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, stream);
+          hpmg::cast_up<__bf16>(nd, h->zb16, h->z, h->scal, rms, stream);
         } else {
           vcycle_dg<double>(h, 0, h->z, h->r, true, stream);
         }
@@ -906,6 +968,12 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
           if (!std::isfinite(rn)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite residual");
           conv = rn <= rtol * r0;
           restart = !conv;
+          // a true residual that stays above rtol after kMaxRestarts
+          // restarts has reached the FP64 rounding floor of b - A u
+          if (!conv && ++restarts > kMaxRestarts) {
+            stagnated = true;
+            break;
+          }
         }
       }
       its_total = std::max(its_total, it);
@@ -919,7 +987,9 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
       for (int i = 0; i < 256; ++i) info->residual_history[i] = i < (int)hist.size() ? hist[i] : 0.0;
       info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    if (result != HPMG_OK) g_last_error = "maximum number of iterations reached";
+    if (result != HPMG_OK)
+      g_last_error = stagnated ? "true residual stagnates above rtol (FP64 rounding floor of b - A u)"
+                               : "maximum number of iterations reached";
     return result;
   } catch (const HpmgError& e) {
     return fail(e);
@@ -928,11 +998,4 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
 
 }  // extern "C"
 
-namespace hpmg {
-bool dg_dispatch(int dim, int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s) {
-  return dim == 2 ? dg_dispatch2(N, op, a, nrhs, flag, s) : dg_dispatch3(N, op, a, nrhs, flag, s);
-}
-bool dg_dispatch(int dim, int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s) {
-  return dim == 2 ? dg_dispatch2(N, op, a, nrhs, flag, s) : dg_dispatch3(N, op, a, nrhs, flag, s);
-}
-}  // namespace hpmg
+

@@ -85,6 +85,10 @@ struct DGLevel {
   size_t ndof = 0, trsize = 0;  // per right-hand side
   DGData<double> d;
   DGData<float> f;
+  // 16-bit storage (finest level only, allocated on first use): traces; the
+  // operator tables and the coarse levels are those of f
+  DGData<_Float16> h16;
+  DGData<__bf16> b16;
 };
 
 template <typename T>
@@ -126,12 +130,14 @@ struct hpmg_ctx {
   // outer solver workspace (FP64) and the FP32 cycle vectors
   double *r = nullptr, *rold = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
   float *r32 = nullptr, *z32 = nullptr;
+  _Float16 *r16 = nullptr, *z16 = nullptr;  // 16-bit cycle vectors (on first use)
+  __bf16 *rb16 = nullptr, *zb16 = nullptr;
   double *partial = nullptr, *scal = nullptr;
   double* host_scal = nullptr;  // pinned
   // which level-0 trace buffer holds the traces of the caller's u after
   // hpmg_project / hpmg_smooth / hpmg_sweep (-1: none), per dtype
-  int trace_state[2] = {-1, -1};
-  int trace_rhs[2] = {0, 0};
+  int trace_state[4] = {-1, -1, -1, -1};
+  int trace_rhs[4] = {0, 0, 0, 0};
   hpmg::detail::DevMem mem;
   ~hpmg_ctx() {
     if (host_scal) (void)hipHostFree(host_scal);
@@ -147,6 +153,10 @@ template <>
 inline DGData<double>& data<double>(DGLevel& l) { return l.d; }
 template <>
 inline DGData<float>& data<float>(DGLevel& l) { return l.f; }
+template <>
+inline DGData<_Float16>& data<_Float16>(DGLevel& l) { return l.h16; }
+template <>
+inline DGData<__bf16>& data<__bf16>(DGLevel& l) { return l.b16; }
 template <typename T>
 CGData<T>& data(CGLevel& l);
 template <>
@@ -154,23 +164,26 @@ inline CGData<double>& data<double>(CGLevel& l) { return l.d; }
 template <>
 inline CGData<float>& data<float>(CGLevel& l) { return l.f; }
 
+// Kernel arguments of level L for storage type T (operator tables in the
+// compute type CT<T>); vectors and traces are set by the caller.
 template <typename T>
 inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
+  using C = hpmg::CT<T>;
   hpmg::DGArgs<T> a{};
-  DGData<T>& d = data<T>(L);
+  DGData<C>& d = data<C>(L);
   a.n = h->n;
   a.ncell = h->ncell;
   a.vark = h->vark ? 1 : 0;
-  a.kappa_const = (T)h->kappa_const;
+  a.kappa_const = (C)h->kappa_const;
   a.ref = d.ref;
   a.eig = d.eig;
   a.kappa = d.kappa;
   a.bmask = h->bmask;
   const double hh = 1.0 / h->n;
-  a.h_fwd = (T)std::pow(hh, 2 - h->dim);
-  a.h_apply = (T)std::pow(hh, h->dim - 2);
-  a.sigma_hat = (T)L.sigma_hat;
-  a.omega = (T)h->opt.omega_dg;
+  a.h_fwd = (C)std::pow(hh, 2 - h->dim);
+  a.h_apply = (C)std::pow(hh, h->dim - 2);
+  a.sigma_hat = (C)L.sigma_hat;
+  a.omega = (C)h->opt.omega_dg;
   a.vstride = (long long)L.ndof;
   a.tstride = (long long)L.trsize;
   return a;

@@ -22,13 +22,20 @@ enum DGOp {
 // NC = floor(p/2)+1 nodes while floor(p/2) >= 2, else Q1 (NC = 2).
 constexpr int nc_next(int N) { return ((N - 1) / 2 >= 2) ? (N - 1) / 2 + 1 : 2; }
 
-// Returns false if (dim, N) has no compiled kernel.
-bool dg_dispatch(int dim, int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s);
-bool dg_dispatch(int dim, int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s);
+// Returns false if (dim, N) has no compiled kernel.  One definition per
+// (dimension, storage type) in dg_inst_<dim>d_<type>.hip.
 bool dg_dispatch2(int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s);
 bool dg_dispatch2(int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch2(int N, int op, const DGArgs<_Float16>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch2(int N, int op, const DGArgs<__bf16>& a, int nrhs, int flag, hipStream_t s);
 bool dg_dispatch3(int N, int op, const DGArgs<double>& a, int nrhs, int flag, hipStream_t s);
 bool dg_dispatch3(int N, int op, const DGArgs<float>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch3(int N, int op, const DGArgs<_Float16>& a, int nrhs, int flag, hipStream_t s);
+bool dg_dispatch3(int N, int op, const DGArgs<__bf16>& a, int nrhs, int flag, hipStream_t s);
+template <typename T>
+inline bool dg_dispatch(int dim, int N, int op, const DGArgs<T>& a, int nrhs, int flag, hipStream_t s) {
+  return dim == 2 ? dg_dispatch2(N, op, a, nrhs, flag, s) : dg_dispatch3(N, op, a, nrhs, flag, s);
+}
 
 template <typename T>
 void cg_stencil(int D, int nv, const T* st, const T* dinv, const T* u, const T* b, T* out, T omega, int mode,
@@ -50,7 +57,9 @@ void krylov_dot(size_t n, const double* x, const double* y, const double* z, dou
 void krylov_update_p(size_t n, const double* z, double* p, const double* scal, hipStream_t s);
 void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double* p, const double* q, double* partial,
                       double* scal, hipStream_t s);
-void cast_down(size_t n, const double* x, float* y, const double* scal, hipStream_t s);
-void cast_up(size_t n, const float* x, double* y, const double* scal, hipStream_t s);
+template <typename T>
+void cast_down(size_t n, const double* x, T* y, const double* scal, double mul, hipStream_t s);
+template <typename T>
+void cast_up(size_t n, const T* x, double* y, const double* scal, double mul, hipStream_t s);
 
 }  // namespace hpmg

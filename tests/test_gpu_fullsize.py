@@ -64,14 +64,18 @@ def test_fullsize_apply_and_sweep_sampled(name):
     g.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("name", ["q4_32cube_const", "q3_64cube_loguniform"])
-def test_fullsize_mixed_solve_residual(name):
-    # the true FP64 residual of the mixed-precision solution meets the
-    # 1e-10 relative tolerance (checked with the parity-tested FP64 apply)
+def test_fullsize_mixed_solve_residual(name, prec):
+    # the true FP64 residual of the mixed-precision solution (FP32 cycle, or
+    # FP32 cycle with 16-bit storage of the finest level) meets the 1e-10
+    # relative tolerance (checked with the parity-tested FP64 apply)
     import paper_2510_00998_amd as hp
     dim, n, p, kf = WORKLOADS[name]
     kappa = kf()
-    g = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F32)
+    pr = {"f32": hp.PREC_F32, "f16": hp.PREC_F16, "bf16": hp.PREC_BF16}[prec]
+    log(f"{name} {prec}")
+    g = hp.Solver(dim, n, p, kappa, precision=pr)
     b = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
     g.load_vector(0, 1.0, b)
     u = torch.zeros_like(b)
@@ -79,6 +83,6 @@ def test_fullsize_mixed_solve_residual(name):
     y = torch.empty_like(u)
     g.apply_A(u, y)
     rel = float(torch.linalg.vector_norm(b - y) / torch.linalg.vector_norm(b))
-    log(f"  {name}: {info.iterations} its, true rel residual {rel:.2e}")
+    log(f"  {name} {prec}: {info.iterations} its, true rel residual {rel:.2e}")
     assert st == 0 and rel <= 2e-10
     g.close()
