@@ -20,6 +20,12 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "hpmg.h")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libhpmg.so not built at {LIB_PATH}; run `python paper_2510_00998_amd/csrc/build.py`")
+# The tensors and streams handed to the library belong to torch's HIP runtime.
+# Loading torch first makes the library's libamdhip64.so.7 dependency resolve
+# to that same, already loaded runtime (one runtime per process); loaded the
+# other way round, the process would hold two HIP runtimes side by side.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 STATUS = {0: "HPMG_OK", 1: "HPMG_E_INVALID", 2: "HPMG_E_NOMEM", 3: "HPMG_E_DEVICE",

@@ -106,22 +106,48 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
   if constexpr (!VARK) {
     for (int i = tid; i < 4 * Sh::EGS; i += Sh::NT) sE[i] = a.eig[i];
   } else {
-    for (int i = tid; i < nc * D * (NN + N); i += Sh::NT) {
-      const int e = i % (NN + N);
-      const int ck = i / (NN + N);
-      sE[ck * Sh::EGS + (e < NN ? e : NN + e)] = a.eig[(size_t)c0 * D * (NN + N) + i];
+    // every load of the thread is issued before the first LDS store (no
+    // load waits on another): eigendata, then kappa of the cell and of its
+    // neighbour across each facet (the neighbour index is clamped into the
+    // mesh so that it needs no boundary test; boundary facets get 0)
+    constexpr int NE = Sh::CPB * D * (NN + N);
+    constexpr int IE = (NE + Sh::NT - 1) / Sh::NT;
+    constexpr int NK = Sh::CPB * Sh::NF;
+    constexpr int IK = (NK + Sh::NT - 1) / Sh::NT;
+    const int ne = nc * D * (NN + N), nk = nc * Sh::NF;
+    C ev[IE], k0[IK], k1[IK];
+    int msk[IK];
+#pragma unroll
+    for (int m = 0; m < IE; ++m) {
+      const int i = tid + m * Sh::NT;
+      ev[m] = i < ne ? a.eig[(size_t)c0 * D * (NN + N) + i] : C(0);
     }
-    for (int i = tid; i < nc * Sh::NF; i += Sh::NT) {
+#pragma unroll
+    for (int m = 0; m < IK; ++m) {
+      const int i = tid + m * Sh::NT;
       const int cl = i / Sh::NF, f = i % Sh::NF;
-      const int k = f >> 1, s = f & 1;
-      const int c = c0 + cl;
-      C kf = 0;
-      if (!((a.bmask[c] >> f) & 1)) {
-        const int st = ipow<D>(a.n, k);
-        const C k0 = a.kappa[c], k1 = a.kappa[s ? c + st : c - st];
-        kf = C(2) * k0 * k1 / (k0 + k1);
+      const int c = c0 + min(cl, nc - 1);
+      const int st = ipow<D>(a.n, f >> 1);
+      const int nb = min(max((f & 1) ? c + st : c - st, 0), a.ncell - 1);
+      msk[m] = a.bmask[c];
+      k0[m] = a.kappa[c];
+      k1[m] = a.kappa[nb];
+    }
+#pragma unroll
+    for (int m = 0; m < IE; ++m) {
+      const int i = tid + m * Sh::NT;
+      if (i < ne) {
+        const int e = i % (NN + N), ck = i / (NN + N);
+        sE[ck * Sh::EGS + (e < NN ? e : NN + e)] = ev[m];
       }
-      sKF[i] = kf;
+    }
+#pragma unroll
+    for (int m = 0; m < IK; ++m) {
+      const int i = tid + m * Sh::NT;
+      if (i < nk) {
+        const int f = i % Sh::NF;
+        sKF[i] = ((msk[m] >> f) & 1) ? C(0) : C(2) * k0[m] * k1[m] / (k0[m] + k1[m]);
+      }
     }
   }
 }
@@ -274,23 +300,37 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
 }
 
 // Plain copy of the neighbour traces into sNB (variable kappa path, whose
-// facet transform needs the staged per-cell eigendata).
+// facet transform needs the staged per-cell eigendata).  Element i of the
+// block is (facet f, cell cl, entry e), i = (f CPB + cl) 2L + e; all loads of
+// a thread are issued before its LDS stores, from neighbour indices clamped
+// into the mesh (boundary facets take zeros).
 template <typename T, int D, int N>
 __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int TL = 2 * Sh::L;
-  for (int f = 0; f < Sh::NF; ++f) {
-    const int k = f >> 1, s = f & 1;
-    const int st = ipow<D>(a.n, k);
-    const int off = s ? st : -st;
-    const T* src = tr + (size_t)(f ^ 1) * a.ncell * TL;
-    for (int i = work_tid<D, N>(); i < nc * TL; i += Sh::NT) {
-      const int cl = i / TL, e = i % TL;
-      const int c = c0 + cl;
-      const bool bdy = (a.bmask[c] >> f) & 1;
-      sNB[(cl * Sh::NF + f) * TL + e] = bdy ? C(0) : src[(size_t)(c + off) * TL + e];
-    }
+  constexpr int NE = Sh::NF * Sh::CPB * TL;
+  constexpr int IT = (NE + Sh::NT - 1) / Sh::NT;
+  const int tid = work_tid<D, N>();
+  C v[IT];
+#pragma unroll
+  for (int m = 0; m < IT; ++m) {
+    const int i = tid + m * Sh::NT;
+    const int f = min(i / (Sh::CPB * TL), Sh::NF - 1), rem = i % (Sh::CPB * TL);
+    const int cl = min(rem / TL, nc - 1), e = rem % TL;
+    const int c = c0 + cl;
+    const int st = ipow<D>(a.n, f >> 1);
+    const int nb = min(max((f & 1) ? c + st : c - st, 0), a.ncell - 1);
+    const bool bdy = (a.bmask[c] >> f) & 1;
+    const C x = tr[((size_t)(f ^ 1) * a.ncell + nb) * TL + e];
+    v[m] = bdy ? C(0) : x;
+  }
+#pragma unroll
+  for (int m = 0; m < IT; ++m) {
+    const int i = tid + m * Sh::NT;
+    const int f = i / (Sh::CPB * TL), rem = i % (Sh::CPB * TL);
+    const int cl = rem / TL, e = rem % TL;
+    if (i < NE && cl < nc) sNB[(cl * Sh::NF + f) * TL + e] = v[m];
   }
 }
 
