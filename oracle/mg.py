@@ -7,9 +7,12 @@ with the readings recorded in the design doc:
 
 * p-coarsening halves p (floor) while the halved degree is >= 2, then goes
   to the continuous Q1 space (zero boundary values) on the same mesh;
-* h-coarsening of Q1 by a factor of two; an odd cell count keeps the last
-  fine vertex as a coarse vertex (one coarse cell of width h), so the coarse
-  spaces stay nested; coarsening stops once n <= 4;
+* h-coarsening of Q1 by a factor of two (option: three, the paper's factor
+  for its 3^k meshes); a cell count that is not a multiple keeps the last
+  fine vertex as a coarse vertex, so the coarse spaces stay nested;
+  coarsening stops once n <= coarsest_n (4);
+* option: p-coarsening straight from DG_p to Q1 in one step (the paper's
+  two-grid hp scheme) instead of halving p;
 * every transfer is nodal interpolation P (coarse function evaluated at the
   fine nodes) and restriction is P^T; every coarse operator is the Galerkin
   product P^T A P;
@@ -44,12 +47,16 @@ class HierarchyOptions:
     sigma0: float = 2.0
     coarsest_n: int = 4
     p_schedule: list = field(default_factory=list)  # explicit DG degrees after the fine one
+    p_coarsening: str = "halve"  # "halve" (gradual) or "direct" (DG_p -> Q1 in one step, Section 5.2)
+    h_factor: int = 2            # Q1 h-coarsening factor (2, or 3 as in the paper's meshes 3^k)
 
 
-def p_levels(p: int, schedule=None):
+def p_levels(p: int, schedule=None, mode: str = "halve"):
     """DG degrees of the hierarchy (fine first); Q1 follows the last entry."""
     if schedule:
         return [p] + [q for q in schedule]
+    if mode == "direct":
+        return [p]
     out = [p]
     q = p // 2
     while q >= 2:
@@ -58,18 +65,19 @@ def p_levels(p: int, schedule=None):
     return out
 
 
-def coarse_vertex_positions(n: int):
-    """Fine vertex indices kept as coarse vertices (factor-2 coarsening)."""
-    pos = list(range(0, n + 1, 2))
+def coarse_vertex_positions(n: int, factor: int = 2):
+    """Fine vertex indices kept as coarse vertices (every factor-th vertex;
+    the last vertex is kept when n is not a multiple of factor)."""
+    pos = list(range(0, n + 1, factor))
     if pos[-1] != n:
         pos.append(n)
     return np.array(pos)
 
 
-def hat_prolongation_1d(n: int):
+def hat_prolongation_1d(n: int, factor: int = 2):
     """1D nodal interpolation from the coarse vertex grid to the fine vertices
     0..n (all vertices, boundary included): P[i, I] = hat_I(x_i)."""
-    pos = coarse_vertex_positions(n)
+    pos = coarse_vertex_positions(n, factor)
     P = np.zeros((n + 1, len(pos)))
     for i in range(n + 1):
         J = np.searchsorted(pos, i)
@@ -83,9 +91,9 @@ def hat_prolongation_1d(n: int):
     return P
 
 
-def cg_prolongation(dim: int, n: int) -> sp.csr_matrix:
+def cg_prolongation(dim: int, n: int, factor: int = 2) -> sp.csr_matrix:
     """Q1 interior vertices of the coarse grid -> interior vertices of n^dim."""
-    P1 = hat_prolongation_1d(n)[1:-1, 1:-1]
+    P1 = hat_prolongation_1d(n, factor)[1:-1, 1:-1]
     return sp.csr_matrix(_kron_dims([P1] * dim))
 
 
@@ -170,7 +178,7 @@ class Hierarchy:
         self.levels = []
         self.P = []  # P[l]: level l+1 -> level l
         A = fine.A.tocsr()
-        degs = p_levels(p, self.opts.p_schedule)
+        degs = p_levels(p, self.opts.p_schedule, self.opts.p_coarsening)
         cur = fine
         for li, q in enumerate(degs):
             blocks = extract_diagonal_blocks(A, (q + 1) ** dim)
@@ -188,10 +196,10 @@ class Hierarchy:
             self.levels.append(Level("cg", A, m))
             if m <= self.opts.coarsest_n:
                 break
-            P = cg_prolongation(dim, m)
+            P = cg_prolongation(dim, m, self.opts.h_factor)
             self.P.append(P)
             A = (P.T @ A @ P).tocsr()
-            m = len(coarse_vertex_positions(m)) - 1
+            m = len(coarse_vertex_positions(m, self.opts.h_factor)) - 1
         last = self.levels[-1]
         self.coarse_chol = sla.cho_factor(last.A.toarray())
 
@@ -251,10 +259,12 @@ class Hierarchy:
             r, z = r_new, z_new
         return u, hist
 
-    def mgmult(self, b, rtol=1e-10, maxit=200, u0=None):
+    def mgmult(self, b, rtol=1e-10, maxit=200, u0=None, exit="unprec"):
         """Stationary multigrid iteration u <- V(u, b) (Algorithm MGMult with a
         V(nu1, nu2) cycle); returns (u, unpreconditioned residual history,
-        preconditioned residual history ||u_k - u_{k-1}||)."""
+        preconditioned residual history ||u_k - u_{k-1}||).  Exit (Section
+        5.1.1): "unprec" once ||b - A u_k|| <= rtol ||b - A u_0||, "prec" once
+        the preconditioned residual ||u_k - u_{k-1}|| <= rtol ||u_1 - u_0||."""
         A = self.levels[0].A
         u = np.zeros_like(b) if u0 is None else u0.copy()
         r0 = np.linalg.norm(b - A @ u)
@@ -264,6 +274,9 @@ class Hierarchy:
             phist.append(np.linalg.norm(un - u))
             u = un
             hist.append(np.linalg.norm(b - A @ u))
-            if hist[-1] <= rtol * r0:
+            if exit == "prec":
+                if phist[-1] <= rtol * phist[0]:
+                    break
+            elif hist[-1] <= rtol * r0:
                 break
         return u, hist, phist

@@ -138,3 +138,88 @@ def test_vcycle_is_h_robust_2d():
         rates.append(len(hist) - 1)
     assert max(rates) - min(rates) <= 3, rates
     assert max(rates) < 40, rates
+
+
+def test_p_schedule_direct():
+    # one-step p-coarsening DG_p -> Q1 (the paper's two-grid hp scheme)
+    for p in range(1, 9):
+        assert p_levels(p, mode="direct") == [p]
+
+
+@pytest.mark.parametrize("n", [3, 9, 10, 11, 27])
+def test_hat_prolongation_factor3_reproduces_linears(n):
+    P = hat_prolongation_1d(n, 3)
+    pos = coarse_vertex_positions(n, 3)
+    assert pos[0] == 0 and pos[-1] == n
+    assert np.all(np.diff(pos) <= 3) and np.all(np.diff(pos) >= 1)
+    assert np.allclose(P @ (pos / n), np.arange(n + 1) / n)
+    assert np.allclose(P.sum(axis=1), 1.0)
+    # a fine vertex between two coarse ones takes weights 1/3, 2/3
+    if n % 3 == 0:
+        assert np.allclose(P[1, :2], [2 / 3, 1 / 3])
+
+
+@pytest.mark.parametrize("dim,n", [(2, 9), (3, 6), (2, 10)])
+def test_cg_galerkin_factor3(dim, n):
+    # P^T A P with factor-3 transfers equals the Q1 stiffness on n/3 cells
+    # (independent Q1 assembly) when 3 divides n; SPD always
+    A = q1_stiffness(dim, n)
+    P = cg_prolongation(dim, n, 3)
+    G = (P.T @ A @ P).toarray()
+    if n % 3 == 0:
+        Q = q1_stiffness(dim, n // 3).toarray()
+        assert np.abs(G - Q).max() < 1e-12 * np.abs(Q).max()
+    assert np.abs(G - G.T).max() < 1e-13 * np.abs(G).max()
+    np.linalg.cholesky(G)
+
+
+def test_direct_hierarchy_levels():
+    H = Hierarchy(2, 9, 4, opts=HierarchyOptions(p_coarsening="direct", h_factor=3, coarsest_n=3))
+    kinds = [(lev.kind, lev.n) for lev in H.levels]
+    assert kinds == [("dg", 9), ("cg", 9), ("cg", 3)]
+
+
+def test_mgmult_histories_match_iteration_matrix():
+    # MGMult is the linear stationary iteration u_k = u_{k-1} + M (b - A u_{k-1})
+    # with M the V-cycle from zero: build M column by column and check both
+    # residual histories and the two exit criteria against matrix powers
+    opts = HierarchyOptions(p_coarsening="direct", h_factor=3, coarsest_n=3, nu_post=0)
+    H = Hierarchy(2, 3, 2, opts=opts)
+    A = H.levels[0].A.toarray()
+    nd = A.shape[0]
+    M = np.stack([H.vcycle(0, np.zeros(nd), e) for e in np.eye(nd)], axis=1)
+    b = synth.random_rhs(nd, seed=71)
+    u = np.zeros(nd)
+    hist, phist = [np.linalg.norm(b)], []
+    for _ in range(12):
+        du = M @ (b - A @ u)
+        u = u + du
+        phist.append(np.linalg.norm(du))
+        hist.append(np.linalg.norm(b - A @ u))
+    _, h2, p2 = H.mgmult(b, rtol=1e-30, maxit=12)
+    assert np.allclose(h2, hist, rtol=1e-9, atol=0)
+    assert np.allclose(p2, phist, rtol=1e-9, atol=0)
+    tol = phist[5] / phist[0] * 1.0000001
+    _, _, p3 = H.mgmult(b, rtol=tol, maxit=50, exit="prec")
+    assert len(p3) == 6
+    tolu = hist[4] / hist[0] * 1.0000001
+    _, h4, _ = H.mgmult(b, rtol=tolu, maxit=50, exit="unprec")
+    assert len(h4) == 5
+
+
+def test_paper_mode_is_h_robust_2d():
+    # one-step p-coarsening, factor-3 h-coarsening, MGMult: cycle counts to
+    # 1e-7 settle as h shrinks (unpreconditioned exit) and do not grow
+    # (preconditioned exit), the paper's robustness result (Section 6)
+    unprec, prec = [], []
+    for n in [9, 27, 81]:
+        opts = HierarchyOptions(p_coarsening="direct", h_factor=3, coarsest_n=3)
+        H = Hierarchy(2, n, 2, opts=opts)
+        _, f = mf.sin_product(2, 2)
+        b = H.fine.load_vector(f)
+        _, hist, _ = H.mgmult(b, rtol=1e-7, maxit=100)
+        _, _, ph = H.mgmult(b, rtol=1e-7, maxit=100, exit="prec")
+        unprec.append(len(hist) - 1)
+        prec.append(len(ph))
+    assert abs(unprec[2] - unprec[1]) <= 1, unprec
+    assert prec[0] >= prec[1] >= prec[2], prec
