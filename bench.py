@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5],
                     help="2: Q4 32^3 kappa=1 (headline); 3: Q3 64^3 log-uniform kappa; "
                          "4: 64 problems x 4 RHS batched; 5: Q5 96^3 log-normal kappa")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="paper-mode cycle counts: 2D, one-step DG_p -> Q1, factor-3 h-coarsening, MGMult to 1e-7")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=6, help="mesh of the oracle's timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -271,12 +273,59 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def run_paper_tables(args):
+    """Cycles of the stationary multigrid iteration (MGMult, FP64) to reduce the
+    unpreconditioned or the preconditioned relative residual by 1e-7, in the
+    paper's 2D setting: unit square, n^2 cells (n = 9 .. 243), p = 2 .. 6,
+    one-step p-coarsening DG_p -> Q1, factor-3 h-coarsening to 3^2, V(2,2),
+    for the sin-product and the two-peak manufactured solutions."""
+    import torch
+
+    import paper_2510_00998_amd as hp
+
+    meshes = (9, 27, 81, 243)
+    degrees = (2, 3, 4, 5, 6)
+    counts = {e: {s: {} for s in ("sin_product", "two_peak")} for e in ("unprec", "prec")}
+    secs = {e: {s: {} for s in ("sin_product", "two_peak")} for e in ("unprec", "prec")}
+    T0 = time.perf_counter()
+    for sol, kind in (("sin_product", 1), ("two_peak", 2)):
+        for n in meshes:
+            for p in degrees:
+                g = hp.Solver(2, n, p, 1.0, p_coarsening=1, h_factor=3, coarsest_n=3, precision=hp.PREC_F64)
+                b = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+                g.load_vector(kind, 2.0, b)
+                for ex in ("unprec", "prec"):
+                    u = torch.zeros_like(b)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    info, st = g.mgmult(u, b, rtol=1e-7, maxit=1000, exit=ex, check=False)
+                    torch.cuda.synchronize()
+                    counts[ex][sol][f"{n}x{n}"] = counts[ex][sol].get(f"{n}x{n}", {})
+                    counts[ex][sol][f"{n}x{n}"][p] = info.iterations if st == 0 else None
+                    secs[ex][sol].setdefault(f"{n}x{n}", {})[p] = time.perf_counter() - t0
+                g.close()
+            _progress(f"{sol} n={n} done")
+    line = {
+        "metric": "paper-mode hp-multigrid cycles to 1e-7 (2D)", "value": None, "unit": "cycles",
+        "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+        "config": {"workload": "2D Poisson, SIPG Q_p on n^2 cells, manufactured sin(2 pi x)sin(2 pi y) and two-peak "
+                               "solutions, MGMult with V(2,2) (omega_DG 0.7, omega_CG 2/3), one-step DG_p -> Q1, "
+                               "factor-3 h-coarsening to 3^2, FP64",
+                   "meshes": list(meshes), "degrees": list(degrees)},
+        "cycles": counts, "seconds": secs, "total_s": time.perf_counter() - T0,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "requested_gpus": args.gpus}))
         sys.exit(2)
+    if args.paper_tables:
+        run_paper_tables(args)
+        return
     if args.config == 4:
         run_batched(args)
         return

@@ -80,6 +80,9 @@ typedef struct {
   int coarsest_n;     /* stop h-coarsening once n <= coarsest_n (default 4) */
   int precision;      /* hpmg_precision of the cycle inside hpmg_solve (default F32) */
   int max_rhs;        /* largest nrhs any call will use (default 1) */
+  int p_coarsening;   /* 0: halve p while >= 2, then Q1 (default); 1: DG_p -> Q1 in one step
+                         (the paper's two-grid hp scheme, Section 5.2) */
+  int h_factor;       /* Q1 h-coarsening factor, 2 (default) or 3 (the paper's 3^k meshes) */
 } hpmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -99,8 +102,11 @@ size_t hpmg_ndof(hpmg_handle h);
 
 /* Load vector b_i = int f phi_i ((p+3)-point Gauss per direction) for a
  * built-in f: kind 0: f = params[0] (constant); kind 1: f = -Laplace of
- * prod_i sin(params[0] pi x_i) (i.e. dim params[0]^2 pi^2 prod sin); b is a
- * device FP64 vector of hpmg_ndof entries.  Paper: Section 2.3.1, b(v). */
+ * prod_i sin(params[0] pi x_i) (i.e. dim params[0]^2 pi^2 prod sin); kind 2
+ * (dim 2 only): f = -Laplace of the two-peak solution of Section 6
+ * (x(1-x)y(1-y)(2 e1 - e2), Gaussians e_i centred at (0.3, 0.4) and
+ * (0.8, 0.6) with widths 0.2 and 0.1; params unused); b is a device FP64
+ * vector of hpmg_ndof entries.  Paper: Section 2.3.1, b(v). */
 hpmg_status hpmg_load_vector(hpmg_handle h, int kind, const double* params, double* b,
                              hipStream_t stream);
 
@@ -158,6 +164,18 @@ typedef struct {
 hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, double rtol,
                        int maxit, hpmg_solve_info* info, hipStream_t stream);
 
+/* Stationary multigrid iteration u <- V(u, b) in FP64 (Algorithm MGMult with
+ * the handle's V(nu_pre, nu_post) cycle; with precision F32/F16/BF16 each
+ * step is u <- u + V(0, b - A u) with the reduced-precision cycle), from the
+ * initial guess in u, until the relative residual of kind `exit_kind` is
+ * <= rtol: 0 = unpreconditioned ||b - A u_k||_2 / ||b - A u_0||_2, 1 =
+ * preconditioned ||u_k - u_{k-1}||_2 / ||u_1 - u_0||_2 (Section 5.1.1).
+ * info->iterations = cycles done, residual_history[k] = relative residual of
+ * that kind after cycle k+1 (first 256), final_residual = true ||b - A u||_2.
+ * nrhs = 1.  HPMG_E_NOT_CONVERGED after maxit cycles. */
+hpmg_status hpmg_mgmult(hpmg_handle h, double* u, const double* b, double rtol, int maxit, int exit_kind,
+                        hpmg_solve_info* info, hipStream_t stream);
+
 /* Release every resource of the handle (NULL is ignored). */
 void hpmg_destroy(hpmg_handle h);
 
@@ -179,8 +197,8 @@ typedef struct hpmg_batch_ctx* hpmg_batch; /* opaque, owned by the library */
 /* Group `count` handles into a batch (*out; release with
  * hpmg_batch_destroy).  The handles must stay alive while the batch is
  * used, must be distinct, and must all be 3D with constant kappa,
- * 1 <= p <= 5, nu_pre >= 1 and equal nu_pre, nu_post (HPMG_E_INVALID
- * otherwise).  The batch uses the handles' level data and workspaces:
+ * 1 <= p <= 5, nu_pre >= 1, equal nu_pre, nu_post and the default p- and
+ * h-coarsening (HPMG_E_INVALID otherwise).  The batch uses the handles' level data and workspaces:
  * calls on a handle must not overlap a batch solve that contains it, and a
  * batch solve invalidates the handle's trace state (as hpmg_solve does). */
 hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out);

@@ -51,7 +51,8 @@ class Coeff(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("sigma0", ctypes.c_double), ("omega_dg", ctypes.c_double), ("omega_cg", ctypes.c_double),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("coarsest_n", ctypes.c_int),
-                ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int), ("p_coarsening", ctypes.c_int),
+                ("h_factor", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -83,6 +84,9 @@ _lib.hpmg_vcycle.restype = ctypes.c_int
 _lib.hpmg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(SolveInfo), _vp]
 _lib.hpmg_solve.restype = ctypes.c_int
+_lib.hpmg_mgmult.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                             ctypes.POINTER(SolveInfo), _vp]
+_lib.hpmg_mgmult.restype = ctypes.c_int
 _lib.hpmg_destroy.argtypes = [_vp]
 _lib.hpmg_destroy.restype = None
 _lib.hpmg_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]
@@ -198,6 +202,7 @@ class Solver:
             pass
 
     def load_vector(self, kind: int, param: float, b, stream=None):
+        """kind 0: f = param; 1: f = -Laplace prod sin(param pi x_i); 2 (2D): the two-peak f."""
         prm = (ctypes.c_double * 1)(param)
         _check(_lib.hpmg_load_vector(self._h, kind, prm, _ptr(b, F64), _stream(stream)), "hpmg_load_vector")
         return b
@@ -226,6 +231,15 @@ class Solver:
         c = _code(u)
         _check(_lib.hpmg_vcycle(self._h, c, _ptr(u, c), _ptr(b, c), nrhs, _stream(stream)), "hpmg_vcycle")
         return u
+
+    def mgmult(self, u, b, rtol: float = 1e-7, maxit: int = 500, exit: str = "unprec", stream=None, check=True):
+        """Stationary multigrid iteration (hpmg_mgmult); exit "unprec" or "prec"."""
+        info = SolveInfo()
+        st = _lib.hpmg_mgmult(self._h, _ptr(u, F64), _ptr(b, F64), rtol, maxit, 0 if exit == "unprec" else 1,
+                              ctypes.byref(info), _stream(stream))
+        if check:
+            _check(st, "hpmg_mgmult")
+        return info, st
 
     def solve(self, u, b, rtol: float = 1e-10, maxit: int = 200, nrhs: int = 1, stream=None, check=True):
         info = SolveInfo()

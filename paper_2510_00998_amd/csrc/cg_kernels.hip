@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict_
 // b_c = P^T r_f with the tensor-product 1D transfer: coarse interior index I
 // gathers up to three fine interior indices ridx[3I..3I+2] with weights rw.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, const int* __restrict__ ridx,
+__global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, int rk, const int* __restrict__ ridx,
                                                      const T* __restrict__ rw, const T* __restrict__ rf,
                                                      T* __restrict__ bc) {
   const int total = (D == 2) ? nvc * nvc : nvc * nvc * nvc;
@@ -60,18 +60,18 @@ __global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, const int
   int x[3];
   vcoords<D>(v, nvc, x);
   T s = 0;
-  for (int c = 0; c < (D == 3 ? 3 : 1); ++c) {
-    const int iz = (D == 3) ? ridx[3 * x[2] + c] : 0;
-    const T wz = (D == 3) ? rw[3 * x[2] + c] : T(1);
+  for (int c = 0; c < (D == 3 ? rk : 1); ++c) {
+    const int iz = (D == 3) ? ridx[rk * x[2] + c] : 0;
+    const T wz = (D == 3) ? rw[rk * x[2] + c] : T(1);
     if (iz < 0) continue;
-    for (int b2 = 0; b2 < 3; ++b2) {
-      const int iy = ridx[3 * x[1] + b2];
+    for (int b2 = 0; b2 < rk; ++b2) {
+      const int iy = ridx[rk * x[1] + b2];
       if (iy < 0) continue;
-      const T wy = rw[3 * x[1] + b2];
-      for (int a2 = 0; a2 < 3; ++a2) {
-        const int ix = ridx[3 * x[0] + a2];
+      const T wy = rw[rk * x[1] + b2];
+      for (int a2 = 0; a2 < rk; ++a2) {
+        const int ix = ridx[rk * x[0] + a2];
         if (ix < 0) continue;
-        s += wz * wy * rw[3 * x[0] + a2] * rf[ix + nvf * (iy + nvf * iz)];
+        s += wz * wy * rw[rk * x[0] + a2] * rf[ix + nvf * (iy + nvf * iz)];
       }
     }
   }
@@ -213,6 +213,12 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   }
 }
 
+// y += a x
+__global__ __launch_bounds__(256) void k_axpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
 // p = z + beta p (p = z when beta == 0: the first iteration never reads
 // the previous search direction)
 __global__ __launch_bounds__(256) void k_update_p(size_t n, const double* __restrict__ z, double* __restrict__ p,
@@ -286,12 +292,12 @@ void cg_stencil(int D, int nv, const T* st, const T* dinv, const T* u, const T* 
 }
 
 template <typename T>
-void cg_restrict(int D, int nvf, int nvc, const int* ridx, const T* rw, const T* rf, T* bc, hipStream_t s) {
+void cg_restrict(int D, int nvf, int nvc, int rk, const int* ridx, const T* rw, const T* rf, T* bc, hipStream_t s) {
   const size_t total = (D == 2) ? (size_t)nvc * nvc : (size_t)nvc * nvc * nvc;
   if (D == 2)
-    hipLaunchKernelGGL((k_cg_restrict<T, 2>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
+    hipLaunchKernelGGL((k_cg_restrict<T, 2>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, rk, ridx, rw, rf, bc);
   else
-    hipLaunchKernelGGL((k_cg_restrict<T, 3>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
+    hipLaunchKernelGGL((k_cg_restrict<T, 3>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, rk, ridx, rw, rf, bc);
 }
 
 template <typename T>
@@ -333,6 +339,10 @@ void krylov_dot(size_t n, const double* x, const double* y, const double* z, dou
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, (int)g, scal, op, a0, first);
 }
 
+void axpy(size_t n, double a, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(gs_blocks(n)), dim3(256), 0, s, n, a, x, y);
+}
+
 void krylov_update_p(size_t n, const double* z, double* p, const double* scal, hipStream_t s) {
   hipLaunchKernelGGL(k_update_p, dim3(gs_blocks(n)), dim3(256), 0, s, n, z, p, scal);
 }
@@ -361,7 +371,7 @@ template void cast_up<__bf16>(size_t, const __bf16*, double*, const double*, dou
 
 #define HPMG_INST(T)                                                                                           \
   template void cg_stencil<T>(int, int, const T*, const T*, const T*, const T*, T*, T, int, int, hipStream_t); \
-  template void cg_restrict<T>(int, int, int, const int*, const T*, const T*, T*, hipStream_t);                \
+  template void cg_restrict<T>(int, int, int, int, const int*, const T*, const T*, T*, hipStream_t);           \
   template void cg_prolong<T>(int, int, int, const int*, const T*, const T*, T*, hipStream_t);                 \
   template void gather_corners<T>(int, int, const T*, T*, hipStream_t);                                        \
   template void dense_solve<T>(int, const double*, const T*, T*, hipStream_t);                                 \

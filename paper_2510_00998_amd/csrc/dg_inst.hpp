@@ -16,6 +16,8 @@ void run(int op, const DGArgs<T>& a, int nrhs, int flag, hipStream_t s) {
     case OP_RESTRICT: launch_apply<T, D, N, NC>(a, nrhs, true, s); break;
     case OP_PROJECT: launch_prolong<T, D, N, 0>(a, nrhs, s); break;
     case OP_PROLONG: launch_prolong<T, D, N, NC>(a, nrhs, s); break;
+    case OP_RESTRICT_Q1: launch_apply<T, D, N, 2>(a, nrhs, true, s); break;
+    case OP_PROLONG_Q1: launch_prolong<T, D, N, 2>(a, nrhs, s); break;
     default: break;
   }
 }

@@ -223,9 +223,11 @@ std::vector<double> q1_stencil(int D, int n, const std::vector<double>& kap) {
 
 // 1D interpolation from the coarse vertex grid (every other fine vertex, the
 // last fine vertex always kept) to the fine vertices 0..n.
-std::vector<int> coarse_positions(int n) {
+// Fine vertices kept as coarse vertices: every f-th, plus the last one when
+// f does not divide n.
+std::vector<int> coarse_positions(int n, int f) {
   std::vector<int> pos;
-  for (int i = 0; i <= n; i += 2) pos.push_back(i);
+  for (int i = 0; i <= n; i += f) pos.push_back(i);
   if (pos.back() != n) pos.push_back(n);
   return pos;
 }
@@ -234,8 +236,8 @@ struct Transfer1D {
   std::vector<std::vector<std::pair<int, double>>> parents;  // fine vertex -> (coarse vertex, weight)
 };
 
-Transfer1D transfer_1d(int n) {
-  std::vector<int> pos = coarse_positions(n);
+Transfer1D transfer_1d(int n, int f) {
+  std::vector<int> pos = coarse_positions(n, f);
   Transfer1D T;
   T.parents.resize(n + 1);
   for (int i = 0; i <= n; ++i) {
@@ -253,9 +255,9 @@ Transfer1D transfer_1d(int n) {
 }
 
 // Galerkin coarse stencil P^T A P with the tensor-product 1D transfer.
-std::vector<double> rap(int D, int n, const std::vector<double>& st, int nc) {
+std::vector<double> rap(int D, int n, const std::vector<double>& st, int nc, int f) {
   const int nv = n - 1, nvc = nc - 1, NS = nstencil(D);
-  Transfer1D T1 = transfer_1d(n);
+  Transfer1D T1 = transfer_1d(n, f);
   std::vector<double> out((size_t)ipow(nvc, D) * NS, 0.0);
   const size_t nvt = (size_t)ipow(nv, D);
   for (size_t v = 0; v < nvt; ++v) {
@@ -368,12 +370,15 @@ void build_cg_levels(hpmg_ctx* h, hipStream_t s) {
       break;
     }
     // transfer to the next coarser grid
-    std::vector<int> pos = coarse_positions(m);
+    const int hf = h->opt.h_factor;
+    std::vector<int> pos = coarse_positions(m, hf);
     const int mc = (int)pos.size() - 1;
     const int nvc = mc - 1;
-    Transfer1D T1 = transfer_1d(m);
-    std::vector<int> ridx((size_t)nvc * 3, -1), pidx((size_t)L.nv * 2, -1);
-    std::vector<double> rw((size_t)nvc * 3, 0.0), pw((size_t)L.nv * 2, 0.0);
+    Transfer1D T1 = transfer_1d(m, hf);
+    const int RK = 2 * hf - 1;  // fine vertices within reach of a coarse hat
+    L.rk = RK;
+    std::vector<int> ridx((size_t)nvc * RK, -1), pidx((size_t)L.nv * 2, -1);
+    std::vector<double> rw((size_t)nvc * RK, 0.0), pw((size_t)L.nv * 2, 0.0);
     std::vector<int> cnt(nvc, 0);
     for (int i = 1; i < m; ++i) {  // fine interior vertex i
       int k = 0;
@@ -382,8 +387,9 @@ void build_cg_levels(hpmg_ctx* h, hipStream_t s) {
           pidx[(size_t)(i - 1) * 2 + k] = pr.first - 1;
           pw[(size_t)(i - 1) * 2 + k] = pr.second;
           const int I = pr.first - 1;
-          ridx[(size_t)I * 3 + cnt[I]] = i - 1;
-          rw[(size_t)I * 3 + cnt[I]] = pr.second;
+          require(cnt[I] < RK, "internal: restriction stencil wider than 2 factor - 1");
+          ridx[(size_t)I * RK + cnt[I]] = i - 1;
+          rw[(size_t)I * RK + cnt[I]] = pr.second;
           ++cnt[I];
         }
         ++k;
@@ -395,7 +401,7 @@ void build_cg_levels(hpmg_ctx* h, hipStream_t s) {
     L.f.rw = h->mem.upload(cast_vec<float>(rw), s);
     L.d.pw = h->mem.upload(pw, s);
     L.f.pw = h->mem.upload(cast_vec<float>(pw), s);
-    st = rap(D, m, st, mc);
+    st = rap(D, m, st, mc, hf);
     h->cg.push_back(L);
     m = mc;
   }
@@ -460,7 +466,7 @@ void vcycle_cg(hpmg_ctx* h, int m, bool uzero, hipStream_t s) {
   hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, d.u[cur], d.b, d.r, w, 1, 0, s);
   CGLevel& C = h->cg[m + 1];
   CGData<T>& dc = data<T>(C);
-  hpmg::cg_restrict<T>(D, L.nv, C.nv, L.ridx, d.rw, d.r, dc.b, s);
+  hpmg::cg_restrict<T>(D, L.nv, C.nv, L.rk, L.ridx, d.rw, d.r, dc.b, s);
   vcycle_cg<T>(h, m + 1, true, s);
   hpmg::cg_prolong<T>(D, L.nv, C.nv, L.pidx, d.pw, dc.u[C.cur], d.u[cur], s);
   for (int i = 0; i < h->opt.nu_post; ++i) {
@@ -518,7 +524,7 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) 
     CGData<C>& dc = data<C>(Cg);
     a.out = data<C>(L).contrib;
     a.cstride = (long long)h->ncell << h->dim;
-    dg_run(h, hpmg::OP_RESTRICT, a, L.N, 1, 1, s);
+    dg_run(h, hpmg::OP_RESTRICT_Q1, a, L.N, 1, 1, s);
     hpmg::gather_corners<C>(h->dim, h->n, data<C>(L).contrib, dc.b, s);
     vcycle_cg<C>(h, 0, true, s);
     hpmg::DGArgs<T> pa = dg_args<T>(h, L);
@@ -528,7 +534,7 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) 
     pa.coarse = dc.u[Cg.cur];
     pa.coarse_cg = 1;
     pa.cstride = (long long)Cg.size;
-    dg_run(h, hpmg::OP_PROLONG, pa, L.N, 1, 0, s);
+    dg_run(h, hpmg::OP_PROLONG_Q1, pa, L.N, 1, 0, s);
   }
   for (int i = 0; i < h->opt.nu_post; ++i) {
     sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], false, 1, s);
@@ -573,6 +579,75 @@ hpmg_status fail(const HpmgError& e) {
 }  // namespace
 
 // ====================================================================== ABI
+namespace {
+
+// Restarts from the true residual allowed per right-hand side before a
+// solve that cannot reach rtol in FP64 gives up.
+constexpr int kMaxRestarts = 3;
+
+// Workspace of the reduced-precision cycles (on first use) and the scale of
+// the residual handed to a 16-bit cycle (see hpmg_solve).
+double lowp_setup(hpmg_ctx* h) {
+  const size_t nd = h->ndof;
+  if (h->opt.precision == HPMG_PREC_F16) {
+    ensure_traces<_Float16>(h);
+    if (!h->r16) {
+      h->r16 = (_Float16*)h->mem.alloc(nd * sizeof(_Float16));
+      h->z16 = (_Float16*)h->mem.alloc(nd * sizeof(_Float16));
+    }
+  } else if (h->opt.precision == HPMG_PREC_BF16) {
+    ensure_traces<__bf16>(h);
+    if (!h->rb16) {
+      h->rb16 = (__bf16*)h->mem.alloc(nd * sizeof(__bf16));
+      h->zb16 = (__bf16*)h->mem.alloc(nd * sizeof(__bf16));
+    }
+  }
+  // 16-bit cycles: the residual handed to the cycle gets mean square
+  // lambda, lambda = d pi^2 kappa_min (h/N)^d (the smallest eigenvalue of
+  // A for unit-scaled nodal vectors), so that its entries and those of the
+  // correction (about r / lambda for smooth r) stay in FP16 range
+  double kmin = h->kappa_const;
+  if (h->vark) kmin = *std::min_element(h->kappa.begin(), h->kappa.end());
+  const double lam = h->dim * M_PI * M_PI * kmin * std::pow(1.0 / (h->n * (h->p + 1.0)), h->dim);
+  return std::sqrt((double)nd * lam);
+}
+
+// z = M r: one V-cycle from zero in the handle's cycle precision (r, z FP64;
+// scal[7], scal[8] = 1/||r||, ||r|| must be current for the reduced ones).
+void precondition(hpmg_ctx* h, double rms, hipStream_t stream) {
+  const size_t nd = h->ndof;
+  if (h->opt.precision == HPMG_PREC_F32) {
+    hpmg::cast_down<float>(nd, h->r, h->r32, h->scal, 1.0, stream);
+    vcycle_dg<float>(h, 0, h->z32, h->r32, true, stream);
+    hpmg::cast_up<float>(nd, h->z32, h->z, h->scal, 1.0, stream);
+  } else if (h->opt.precision == HPMG_PREC_F16) {
+    hpmg::cast_down<_Float16>(nd, h->r, h->r16, h->scal, rms, stream);
+    vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, stream);
+    hpmg::cast_up<_Float16>(nd, h->z16, h->z, h->scal, rms, stream);
+  } else if (h->opt.precision == HPMG_PREC_BF16) {
+    hpmg::cast_down<__bf16>(nd, h->r, h->rb16, h->scal, rms, stream);
+    vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, stream);
+    hpmg::cast_up<__bf16>(nd, h->zb16, h->z, h->scal, rms, stream);
+  } else {
+    vcycle_dg<double>(h, 0, h->z, h->r, true, stream);
+  }
+}
+
+// r = b - A u (FP64) and scal[6..8] = ||r||^2, 1/||r||, ||r||; returns ||r||.
+double fp64_residual(hpmg_ctx* h, const double* u, const double* b, hipStream_t stream) {
+  DGData<double>& d = h->dg[0].d;
+  project<double>(h, 0, u, d.tr[0], 1, stream);
+  apply<double>(h, 0, u, d.tr[0], b, h->r, 1, stream);
+  hpmg::krylov_dot(h->ndof, h->r, h->r, nullptr, h->partial, h->scal, 3, 0, 0, stream);
+  HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const double rn = std::sqrt(h->host_scal[6]);
+  if (!std::isfinite(rn)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite residual");
+  return rn;
+}
+
+}  // namespace
+
 extern "C" {
 
 void hpmg_default_options(hpmg_options* o) {
@@ -585,6 +660,8 @@ void hpmg_default_options(hpmg_options* o) {
   o->coarsest_n = 4;
   o->precision = HPMG_PREC_F32;
   o->max_rhs = 1;
+  o->p_coarsening = 0;
+  o->h_factor = 2;
 }
 
 const char* hpmg_status_string(hpmg_status s) {
@@ -629,6 +706,8 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     require(h->opt.coarsest_n >= 2, "coarsest_n must be >= 2");
     require(h->opt.max_rhs >= 1, "max_rhs must be >= 1");
     require(h->opt.precision >= HPMG_PREC_F64 && h->opt.precision <= HPMG_PREC_BF16, "bad precision");
+    require(h->opt.p_coarsening == 0 || h->opt.p_coarsening == 1, "p_coarsening must be 0 or 1");
+    require(h->opt.h_factor == 2 || h->opt.h_factor == 3, "h_factor must be 2 or 3");
     h->dim = mesh->dim;
     h->n = mesh->n[0];
     h->p = p;
@@ -661,7 +740,8 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     }
     // DG levels: p, floor(p/2), ... while >= 2, then Q1
     std::vector<int> degs = {p};
-    for (int q = p / 2; q >= 2; q /= 2) degs.push_back(q);
+    if (h->opt.p_coarsening == 0)
+      for (int q = p / 2; q >= 2; q /= 2) degs.push_back(q);
     const double sigma_hat = h->opt.sigma0 * (p + 1.0) * (p + 1.0);
     std::vector<hpmg::Basis1D> bases;
     for (int q : degs) bases.push_back(hpmg::make_basis(q));
@@ -672,7 +752,7 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
       L.N = degs[l] + 1;
       L.next_cg = (l + 1 == degs.size());
       L.NC = L.next_cg ? 2 : degs[l + 1] + 1;
-      require(L.NC == hpmg::nc_next(L.N), "internal: p schedule mismatch");
+      require(L.next_cg || L.NC == hpmg::nc_next(L.N), "internal: p schedule mismatch");
       L.sigma_hat = sigma_hat;
       build_dg_level(h.get(), L, bases[l], L.next_cg ? nullptr : &bases[l + 1], stream);
       const size_t R = h->opt.max_rhs;
@@ -720,8 +800,9 @@ void hpmg_destroy(hpmg_handle h) { delete h; }
 hpmg_status hpmg_load_vector(hpmg_handle h, int kind, const double* params, double* b, hipStream_t stream) {
   try {
     require(h && b, "NULL argument");
-    require(kind == 0 || kind == 1, "kind must be 0 or 1");
-    require(params != nullptr, "params is NULL");
+    require(kind >= 0 && kind <= 2, "kind must be 0, 1 or 2");
+    require(kind == 2 || params != nullptr, "params is NULL");
+    require(kind != 2 || h->dim == 2, "kind 2 (two-peak) is two-dimensional");
     const int D = h->dim, n = h->n, N = h->p + 1;
     const double hh = 1.0 / n;
     hpmg::Basis1D B = hpmg::make_basis(h->p);
@@ -729,6 +810,46 @@ hpmg_status hpmg_load_vector(hpmg_handle h, int kind, const double* params, doub
     hpmg::gauss_legendre(h->p + 3, xq, wq);
     std::vector<double> V = hpmg::interp_matrix(xq, B.xi);
     const int nq = (int)xq.size();
+    if (kind == 2) {
+      // f = -Laplace u2, u2 = P G, P = x(1-x)y(1-y), G = 2 e1 - e2,
+      // e = exp(-|x - x0|^2 / (2 s^2)):  Laplace u2 = G Laplace P
+      // + 2 grad P . grad G + P Laplace G, grad e = -(x - x0) e / s^2,
+      // Laplace e = (|x - x0|^2 / s^4 - 2 / s^2) e
+      auto f2 = [](double x, double y) {
+        const double cx[2] = {0.3, 0.8}, cy[2] = {0.4, 0.6}, sg[2] = {0.2, 0.1}, wt[2] = {2.0, -1.0};
+        double G = 0.0, Gx = 0.0, Gy = 0.0, LG = 0.0;
+        for (int i = 0; i < 2; ++i) {
+          const double dx = x - cx[i], dy = y - cy[i], s2 = sg[i] * sg[i];
+          const double r2 = dx * dx + dy * dy;
+          const double e = std::exp(-r2 / (2.0 * s2));
+          G += wt[i] * e;
+          Gx += wt[i] * (-dx / s2) * e;
+          Gy += wt[i] * (-dy / s2) * e;
+          LG += wt[i] * (r2 / (s2 * s2) - 2.0 / s2) * e;
+        }
+        const double px = x * (1.0 - x), py = y * (1.0 - y);
+        const double P = px * py, Px = (1.0 - 2.0 * x) * py, Py = px * (1.0 - 2.0 * y);
+        const double LP = -2.0 * (py + px);
+        return -(G * LP + 2.0 * (Px * Gx + Py * Gy) + P * LG);
+      };
+      std::vector<double> out(h->ndof);
+      const int nd2 = N * N;
+      for (int c = 0; c < h->ncell; ++c) {
+        const int cx = c % n, cy = c / n;
+        for (int i = 0; i < nd2; ++i) {
+          const int a = i % N, bb = i / N;
+          double v = 0.0;
+          for (int qy = 0; qy < nq; ++qy)
+            for (int qx = 0; qx < nq; ++qx)
+              v += wq[qx] * wq[qy] * f2((cx + xq[qx]) * hh, (cy + xq[qy]) * hh) * V[(size_t)qx * N + a] *
+                   V[(size_t)qy * N + bb];
+          out[(size_t)c * nd2 + i] = v * hh * hh;
+        }
+      }
+      HIPCHK(hipMemcpyAsync(b, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      return HPMG_OK;
+    }
     // separable f: f = coef * prod_k g(x_k); per axis and cell coordinate,
     // G[x][a] = h int g l_a over the cell
     double coef;
@@ -865,10 +986,6 @@ hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
   }
 }
 
-// Restarts from the true residual allowed per right-hand side before a
-// solve that cannot reach rtol in FP64 gives up.
-constexpr int kMaxRestarts = 3;
-
 hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, double rtol, int maxit,
                        hpmg_solve_info* info, hipStream_t stream) {
   try {
@@ -881,27 +998,7 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
     DGData<double>& d = h->dg[0].d;
     hpmg_status result = HPMG_OK;
     bool stagnated = false;
-    // 16-bit cycles: the residual handed to the cycle gets mean square
-    // lambda, lambda = d pi^2 kappa_min (h/N)^d (the smallest eigenvalue of
-    // A for unit-scaled nodal vectors), so that its entries and those of the
-    // correction (about r / lambda for smooth r) stay in FP16 range
-    double kmin = h->kappa_const;
-    if (h->vark) kmin = *std::min_element(h->kappa.begin(), h->kappa.end());
-    const double lam = h->dim * M_PI * M_PI * kmin * std::pow(1.0 / (h->n * (h->p + 1.0)), h->dim);
-    const double rms = std::sqrt((double)nd * lam);
-    if (h->opt.precision == HPMG_PREC_F16) {
-      ensure_traces<_Float16>(h);
-      if (!h->r16) {
-        h->r16 = (_Float16*)h->mem.alloc(nd * sizeof(_Float16));
-        h->z16 = (_Float16*)h->mem.alloc(nd * sizeof(_Float16));
-      }
-    } else if (h->opt.precision == HPMG_PREC_BF16) {
-      ensure_traces<__bf16>(h);
-      if (!h->rb16) {
-        h->rb16 = (__bf16*)h->mem.alloc(nd * sizeof(__bf16));
-        h->zb16 = (__bf16*)h->mem.alloc(nd * sizeof(__bf16));
-      }
-    }
+    const double rms = lowp_setup(h);
     int its_total = 0;
     double r0_first = 0.0, rfin = 0.0;
     std::vector<double> hist;
@@ -924,21 +1021,7 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
       int restarts = 0;
       while (!conv && it < maxit) {
         // z = M r (one V-cycle, zero initial guess)
-        if (h->opt.precision == HPMG_PREC_F32) {
-          hpmg::cast_down<float>(nd, h->r, h->r32, h->scal, 1.0, stream);
-          vcycle_dg<float>(h, 0, h->z32, h->r32, true, stream);
-          hpmg::cast_up<float>(nd, h->z32, h->z, h->scal, 1.0, stream);
-        } else if (h->opt.precision == HPMG_PREC_F16) {
-          hpmg::cast_down<_Float16>(nd, h->r, h->r16, h->scal, rms, stream);
-          vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, stream);
-          hpmg::cast_up<_Float16>(nd, h->z16, h->z, h->scal, rms, stream);
-        } else if (h->opt.precision == HPMG_PREC_BF16) {
-          hpmg::cast_down<__bf16>(nd, h->r, h->rb16, h->scal, rms, stream);
-          vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, stream);
-          hpmg::cast_up<__bf16>(nd, h->zb16, h->z, h->scal, rms, stream);
-        } else {
-          vcycle_dg<double>(h, 0, h->z, h->r, true, stream);
-        }
+        precondition(h, rms, stream);
         // beta, rho = z.r ; p = z + beta p
         hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart ? 1 : 0, stream);
         restart = false;
@@ -991,6 +1074,52 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
       g_last_error = stagnated ? "true residual stagnates above rtol (FP64 rounding floor of b - A u)"
                                : "maximum number of iterations reached";
     return result;
+  } catch (const HpmgError& e) {
+    return fail(e);
+  }
+}
+
+hpmg_status hpmg_mgmult(hpmg_handle h, double* u, const double* b, double rtol, int maxit, int exit_kind,
+                        hpmg_solve_info* info, hipStream_t stream) {
+  try {
+    require(h && u && b, "NULL argument");
+    require(rtol > 0.0 && maxit >= 1, "bad rtol/maxit");
+    require(exit_kind == 0 || exit_kind == 1, "exit_kind must be 0 or 1");
+    const auto t0 = std::chrono::steady_clock::now();
+    h->trace_state[0] = h->trace_state[1] = h->trace_state[2] = h->trace_state[3] = -1;
+    const double rms = lowp_setup(h);
+    // u_k = u_{k-1} + M (b - A u_{k-1}) equals the in-place cycle V(u_{k-1}, b)
+    // for the linear V-cycle; z = M r is the preconditioned residual
+    double rn = fp64_residual(h, u, b, stream);
+    const double r0 = rn;
+    double p1 = 0.0;
+    std::vector<double> hist;
+    int it = 0;
+    bool conv = r0 == 0.0;
+    while (!conv && it < maxit) {
+      precondition(h, rms, stream);
+      hpmg::krylov_dot(h->ndof, h->z, h->z, nullptr, h->partial, h->scal, 0, 10, 0, stream);
+      hpmg::axpy(h->ndof, 1.0, h->z, u, stream);
+      rn = fp64_residual(h, u, b, stream);  // synchronises; scal[10] = ||z||^2
+      const double pz = std::sqrt(h->host_scal[10]);
+      ++it;
+      if (it == 1) p1 = pz;
+      const double rel = exit_kind == 0 ? rn / r0 : (p1 > 0.0 ? pz / p1 : 0.0);
+      hist.push_back(rel);
+      conv = rel <= rtol;
+    }
+    if (info) {
+      info->iterations = it;
+      info->initial_residual = r0;
+      info->final_residual = rn;
+      for (int i = 0; i < 256; ++i) info->residual_history[i] = i < (int)hist.size() ? hist[i] : 0.0;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!conv) {
+      g_last_error = "maximum number of cycles reached";
+      return HPMG_E_NOT_CONVERGED;
+    }
+    return HPMG_OK;
   } catch (const HpmgError& e) {
     return fail(e);
   }

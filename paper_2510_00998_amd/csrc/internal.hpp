@@ -106,7 +106,8 @@ struct CGLevel {
   int n = 0, nv = 0;
   size_t size = 0;
   int cur = 0;                // which of u[0], u[1] holds the iterate
-  int* ridx = nullptr;        // [nvc][3]
+  int rk = 3;                 // fine vertices per coarse vertex in the restriction (2 factor - 1)
+  int* ridx = nullptr;        // [nvc][rk]
   int* pidx = nullptr;        // [nv][2]
   CGData<double> d;
   CGData<float> f;

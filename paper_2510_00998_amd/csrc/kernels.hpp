@@ -15,7 +15,9 @@ enum DGOp {
   OP_APPLY = 1,       // y = A u (flag: 1 -> r = b - A u)
   OP_RESTRICT = 2,    // r = b - A u restricted to the next coarser level
   OP_PROJECT = 3,     // traces of u
-  OP_PROLONG = 4      // u += P e, then traces of u
+  OP_PROLONG = 4,     // u += P e, then traces of u
+  OP_RESTRICT_Q1 = 5, // OP_RESTRICT to Q1 corner contributions from any degree (one-step p-coarsening)
+  OP_PROLONG_Q1 = 6   // OP_PROLONG from Q1 to any degree
 };
 
 // Next coarser level of a DG level with N nodes per direction: DG with
@@ -41,7 +43,7 @@ template <typename T>
 void cg_stencil(int D, int nv, const T* st, const T* dinv, const T* u, const T* b, T* out, T omega, int mode,
                 int uzero, hipStream_t s);
 template <typename T>
-void cg_restrict(int D, int nvf, int nvc, const int* ridx, const T* rw, const T* rf, T* bc, hipStream_t s);
+void cg_restrict(int D, int nvf, int nvc, int rk, const int* ridx, const T* rw, const T* rf, T* bc, hipStream_t s);
 template <typename T>
 void cg_prolong(int D, int nvf, int nvc, const int* pidx, const T* pw, const T* ec, T* uf, hipStream_t s);
 template <typename T>
@@ -55,6 +57,7 @@ constexpr int KRYLOV_RED_BLOCKS = 1024;
 void krylov_dot(size_t n, const double* x, const double* y, const double* z, double* partial, double* scal, int op,
                 int a0, int first, hipStream_t s);
 void krylov_update_p(size_t n, const double* z, double* p, const double* scal, hipStream_t s);
+void axpy(size_t n, double a, const double* x, double* y, hipStream_t s);
 void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double* p, const double* q, double* partial,
                       double* scal, hipStream_t s);
 template <typename T>

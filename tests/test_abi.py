@@ -43,7 +43,8 @@ def test_setup_rejects_invalid(kw):
 
 def test_setup_rejects_bad_options():
     for field, val in [("omega_dg", 0.0), ("omega_dg", 1.5), ("omega_cg", -1.0), ("sigma0", 0.0),
-                       ("coarsest_n", 1), ("max_rhs", 0), ("precision", 7)]:
+                       ("coarsest_n", 1), ("max_rhs", 0), ("precision", 7), ("p_coarsening", 2),
+                       ("h_factor", 4), ("h_factor", 1)]:
         opt = hp.default_options()
         setattr(opt, field, val)
         st, _ = _setup(opt=opt)
@@ -64,6 +65,7 @@ def test_null_handle_rejected():
     assert lib.hpmg_smooth(None, 0, None, None, 1, 1, None) == 1
     assert lib.hpmg_vcycle(None, 0, None, None, 1, None) == 1
     assert lib.hpmg_solve(None, None, None, 1, 1e-10, 10, None, None) == 1
+    assert lib.hpmg_mgmult(None, None, None, 1e-7, 10, 0, None, None) == 1
     assert lib.hpmg_ndof(None) == 0
     lib.hpmg_destroy(None)
 
