@@ -58,6 +58,23 @@ def counter_traffic(key):
     return float(vals[key])
 
 
+def measured_copy_bandwidth(torch, dev, stream, mib=1024, reps=10):
+    """Read + write bytes per second of a plain device-to-device copy of
+    `mib` MiB (the achievable streaming rate, beside the datasheet peak)."""
+    a = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, c
+    return 2 * mib * 1024 * 1024 / t / 1e9
+
+
 def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -442,6 +459,7 @@ def main():
         for _ in range(3):
             c.copy_(a)
         torch.cuda.synchronize()
+    copy_gbs = measured_copy_bandwidth(torch, dev, stream)
 
     ach64 = by64 / t64 / 1e9
     headline = args.config == 2
@@ -467,7 +485,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach64 / HBM_PEAK_GBS, "traffic": counter_traffic(tkey64),
                      "kernel": f"k_sweep<double,3,{p + 1}> (fused sweep, FP64)",
-                     "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64},
+                     "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64,
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": ach64 / copy_gbs},
         "sweep_dofs_per_s": {name: nd / t for name, t in tsw.items()},
         "sweep_roofline_f32": {"achieved": by32 / t32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by32 / t32 / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by32,
