@@ -15,8 +15,8 @@
  * Conventions (all entry points):
  *  - Vectors are DEVICE pointers owned by the caller, cell-major: cell
  *    c = cx + n*cy (+ n^2*cz), local node i = a + N*b (+ N^2*c), N = p+1,
- *    x fastest, Gauss-Lobatto nodes.  `nrhs` right-hand sides are stacked
- *    back to back ([rhs][dof]).
+ *    x fastest, Gauss-Lobatto nodes (Gauss-Legendre with options.basis =
+ *    1).  `nrhs` right-hand sides are stacked back to back ([rhs][dof]).
  *  - All work is enqueued on `stream` (0 = the null stream).  Only
  *    hpmg_solve synchronises the stream (it reads one 8-byte norm per
  *    iteration back to the host).
@@ -83,6 +83,8 @@ typedef struct {
   int p_coarsening;   /* 0: halve p while >= 2, then Q1 (default); 1: DG_p -> Q1 in one step
                          (the paper's two-grid hp scheme, Section 5.2) */
   int h_factor;       /* Q1 h-coarsening factor, 2 (default) or 3 (the paper's 3^k meshes) */
+  int basis;          /* DG nodes: 0 Gauss-Lobatto (default), 1 Gauss-Legendre (diagonal mass, dense
+                         facet value functionals; Section 4.1 remark on the two bases) */
 } hpmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -197,8 +199,8 @@ typedef struct hpmg_batch_ctx* hpmg_batch; /* opaque, owned by the library */
 /* Group `count` handles into a batch (*out; release with
  * hpmg_batch_destroy).  The handles must stay alive while the batch is
  * used, must be distinct, and must all be 3D with constant kappa,
- * 1 <= p <= 5, nu_pre >= 1, equal nu_pre, nu_post and the default p- and
- * h-coarsening (HPMG_E_INVALID otherwise).  The batch uses the handles' level data and workspaces:
+ * 1 <= p <= 5, nu_pre >= 1, equal nu_pre, nu_post, the default p- and
+ * h-coarsening and the Gauss-Lobatto basis (HPMG_E_INVALID otherwise).  The batch uses the handles' level data and workspaces:
  * calls on a handle must not overlap a batch solve that contains it, and a
  * batch solve invalidates the handle's trace state (as hpmg_solve does). */
 hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out);

@@ -49,6 +49,7 @@ class HierarchyOptions:
     p_schedule: list = field(default_factory=list)  # explicit DG degrees after the fine one
     p_coarsening: str = "halve"  # "halve" (gradual) or "direct" (DG_p -> Q1 in one step, Section 5.2)
     h_factor: int = 2            # Q1 h-coarsening factor (2, or 3 as in the paper's meshes 3^k)
+    basis: str = "gll"           # DG nodes: "gll" (Gauss-Lobatto) or "gl" (Gauss-Legendre)
 
 
 def p_levels(p: int, schedule=None, mode: str = "halve"):
@@ -98,9 +99,10 @@ def cg_prolongation(dim: int, n: int, factor: int = 2) -> sp.csr_matrix:
 
 
 def dg_to_dg_prolongation(fine: SIPG, q: int) -> sp.csr_matrix:
-    """Nodal interpolation Q_q -> Q_p on every cell (same mesh)."""
-    from .basis import gll_nodes
-    E, _ = lagrange_1d(gll_nodes(q), fine.nodes1d)  # E[a, a'] = l^q_{a'}(xi^p_a)
+    """Nodal interpolation Q_q -> Q_p on every cell (same mesh, same node family)."""
+    from .basis import gl_nodes, gll_nodes
+    coarse_nodes = gll_nodes(q) if fine.basis == "gll" else gl_nodes(q)
+    E, _ = lagrange_1d(coarse_nodes, fine.nodes1d)  # E[a, a'] = l^q_{a'}(xi^p_a)
     Pc = _kron_dims([E] * fine.dim)
     return sp.csr_matrix(sp.kron(sp.identity(fine.ncell), sp.csr_matrix(Pc)))
 
@@ -173,7 +175,7 @@ class Hierarchy:
     def __init__(self, dim, n, p, kappa=None, opts: HierarchyOptions | None = None):
         self.opts = opts or HierarchyOptions()
         self.dim = dim
-        fine = SIPG(dim, n, p, kappa, sigma0=self.opts.sigma0)
+        fine = SIPG(dim, n, p, kappa, sigma0=self.opts.sigma0, basis=self.opts.basis)
         self.fine = fine
         self.levels = []
         self.P = []  # P[l]: level l+1 -> level l
@@ -184,7 +186,7 @@ class Hierarchy:
             blocks = extract_diagonal_blocks(A, (q + 1) ** dim)
             self.levels.append(Level("dg", A, n, q, blocks))
             if li + 1 < len(degs):
-                nxt = SIPG(dim, n, degs[li + 1], kappa, p_penalty=p, sigma0=self.opts.sigma0)
+                nxt = SIPG(dim, n, degs[li + 1], kappa, p_penalty=p, sigma0=self.opts.sigma0, basis=self.opts.basis)
                 P = dg_to_dg_prolongation(cur, degs[li + 1])
                 cur = nxt
             else:

@@ -1,6 +1,7 @@
 // Host-side 1D reference data (see basis.hpp).
 //
 // Gauss-Lobatto nodes: interior nodes are the roots of P_p', found by Newton
+// (Gauss-Legendre nodes: the roots of P_{p+1}, by the same recurrence)
 // iteration in long double from Chebyshev-Lobatto guesses, using the
 // Legendre recurrence and the Legendre differential equation for P_p''.
 // Lagrange values use the barycentric formula, the nodal differentiation
@@ -78,12 +79,17 @@ std::vector<double> interp_matrix(const std::vector<double>& xf, const std::vect
   return E;
 }
 
-Basis1D make_basis(int p) {
+Basis1D make_basis(int p, bool gl) {
   Basis1D B;
   B.p = p;
+  B.gl = gl;
   const int N = p + 1;
   B.N = N;
-  // nodes on [-1,1]
+  if (gl) {
+    std::vector<double> w;
+    gauss_legendre(N, B.xi, w);
+  }
+  // Gauss-Lobatto nodes on [-1,1]
   std::vector<long double> t(N);
   const long double pi = 3.141592653589793238462643383279502884L;
   t[0] = -1.0L;
@@ -101,10 +107,12 @@ Basis1D make_basis(int p) {
     }
     t[j] = x;
   }
-  B.xi.resize(N);
-  for (int j = 0; j < N; ++j) B.xi[j] = (double)(0.5L * (t[j] + 1.0L));
-  B.xi[0] = 0.0;
-  B.xi[p] = 1.0;
+  if (!gl) {
+    B.xi.resize(N);
+    for (int j = 0; j < N; ++j) B.xi[j] = (double)(0.5L * (t[j] + 1.0L));
+    B.xi[0] = 0.0;
+    B.xi[p] = 1.0;
+  }
   // barycentric weights and differentiation matrix at the nodes
   std::vector<long double> bw(N, 1.0L);
   for (int j = 0; j < N; ++j)
@@ -142,11 +150,20 @@ Basis1D make_basis(int p) {
           s += (long double)B.Dn[a * N + i] * B.M[a * N + b] * B.Dn[b * N + j];
       B.K[(size_t)i * N + j] = (double)s;
     }
-  B.ep0.resize(N);
-  B.ep1.resize(N);
+  // values at the end points, and the derivatives there: l_j' has degree
+  // p-1, so l_j'(x) = sum_a l_a(x) l_j'(xi_a)
+  B.e0 = interp_matrix({0.0}, B.xi);
+  B.e1 = interp_matrix({1.0}, B.xi);
+  B.ep0.assign(N, 0.0);
+  B.ep1.assign(N, 0.0);
   for (int j = 0; j < N; ++j) {
-    B.ep0[j] = -B.Dn[0 * N + j];
-    B.ep1[j] = B.Dn[(size_t)p * N + j];
+    long double d0 = 0.0L, d1 = 0.0L;
+    for (int a = 0; a < N; ++a) {
+      d0 += (long double)B.e0[a] * B.Dn[(size_t)a * N + j];
+      d1 += (long double)B.e1[a] * B.Dn[(size_t)a * N + j];
+    }
+    B.ep0[j] = (double)(-d0);
+    B.ep1[j] = (double)d1;
   }
   return B;
 }

@@ -706,8 +706,8 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
       require(!h->vark, "batched solver supports constant kappa");
       require(h->p + 1 >= hpmg::BATCH_NMIN && h->p + 1 <= hpmg::BATCH_NMAX, "batched solver supports 1 <= p <= 5");
       require(h->opt.nu_pre >= 1, "batched solver needs nu_pre >= 1");
-      require(h->opt.p_coarsening == 0 && h->opt.h_factor == 2,
-              "batched solver supports the default p- and h-coarsening");
+      require(h->opt.p_coarsening == 0 && h->opt.h_factor == 2 && h->opt.basis == 0,
+              "batched solver supports the default p- and h-coarsening and basis");
       require(h->opt.nu_pre == hs[0]->opt.nu_pre && h->opt.nu_post == hs[0]->opt.nu_post,
               "all problems of a batch need the same nu_pre, nu_post");
       B->hs.push_back(h);

@@ -54,11 +54,14 @@ struct DGShape {
 //   [0, N^2)            Mhat (1D mass on [0,1], symmetric)
 //   [N^2, N^2+N)        ep0: outward normal derivative functional at x=0
 //   [N^2+N, N^2+2N)     ep1: same at x=1
-//   [N^2+2N, ...)       E: interpolation to the fine nodes from the next
+//   [N^2+2N, N^2+3N)    ev0: value functional at x=0 (used with gl)
+//   [N^2+3N, N^2+4N)    ev1: value functional at x=1
+//   [N^2+4N, ...)       E: interpolation to the fine nodes from the next
 //                       coarser nodes, E[a*NC + j] (only when NC > 0)
 template <int N>
 struct RefOff {
-  static constexpr int M = 0, EP0 = N * N, EP1 = N * N + N, E = N * N + 2 * N;
+  static constexpr int M = 0, EP0 = N * N, EP1 = N * N + N, EV0 = N * N + 2 * N, EV1 = N * N + 3 * N,
+                       E = N * N + 4 * N;
 };
 
 // Storage type T of the cell vectors and traces, compute type CT<T> of the
@@ -84,6 +87,7 @@ struct DGArgs {
   using C = CT<T>;
   int n, ncell;
   int vark;            // 0: class tables (constant kappa), 1: per-cell eigendata + kappa
+  int gl;              // 0: Gauss-Lobatto nodes (facet values are the end nodes), 1: Gauss-Legendre
   C kappa_const;
   const C* ref;        // RefOff layout
   const C* eig;        // vark=0: [4 classes][S N^2 | Si N^2 | lam N]; vark=1: [cell][D][S N^2 | lam N]

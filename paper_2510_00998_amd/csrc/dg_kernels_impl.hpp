@@ -370,17 +370,18 @@ __device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int
   const C* f0 = sNB + (cl * Sh::NF + 2 * k) * 2 * L;
   const C* f1 = f0 + 2 * L;
   const C v0 = f0[ln], d0 = f0[L + ln], v1 = f1[ln], d1 = f1[L + ln];
-  if constexpr (SIGN < 0) {
-    r[0] -= v0;
-    r[N - 1] -= v1;
+  constexpr C sg = SIGN < 0 ? C(-1) : C(1);
+  if (a.gl) {  // value functionals are dense (Gauss-Legendre nodes)
+    const cptr<C> ev0 = as_const(a.ref) + RefOff<N>::EV0;
+    const cptr<C> ev1 = as_const(a.ref) + RefOff<N>::EV1;
 #pragma unroll
-    for (int j = 0; j < N; ++j) r[j] -= ep0[j] * d0 + ep1[j] * d1;
+    for (int j = 0; j < N; ++j) r[j] += sg * (ev0[j] * v0 + ev1[j] * v1);
   } else {
-    r[0] += v0;
-    r[N - 1] += v1;
-#pragma unroll
-    for (int j = 0; j < N; ++j) r[j] += ep0[j] * d0 + ep1[j] * d1;
+    r[0] += sg * v0;
+    r[N - 1] += sg * v1;
   }
+#pragma unroll
+  for (int j = 0; j < N; ++j) r[j] += sg * (ep0[j] * d0 + ep1[j] * d1);
 }
 
 // Traces (value, outward normal derivative) of a line along axis k, stored
@@ -394,20 +395,31 @@ __device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, 
   constexpr int TL = 2 * L;
   const cptr<C> ep0 = as_const(a.ref) + RefOff<N>::EP0;
   const cptr<C> ep1 = as_const(a.ref) + RefOff<N>::EP1;
-  C d0 = 0, d1 = 0;
+  C d0 = 0, d1 = 0, g0 = u[0], g1 = u[N - 1];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     d0 += ep0[j] * u[j];
     d1 += ep1[j] * u[j];
   }
+  if (a.gl) {  // value functionals are dense (Gauss-Legendre nodes)
+    const cptr<C> ev0 = as_const(a.ref) + RefOff<N>::EV0;
+    const cptr<C> ev1 = as_const(a.ref) + RefOff<N>::EV1;
+    g0 = 0;
+    g1 = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      g0 += ev0[j] * u[j];
+      g1 += ev1[j] * u[j];
+    }
+  }
   if (!((mask >> (2 * k)) & 1)) {
     T* t0 = trout + ((size_t)(2 * k) * a.ncell + c) * TL;
-    t0[ln] = u[0];
+    t0[ln] = g0;
     t0[L + ln] = d0;
   }
   if (!((mask >> (2 * k + 1)) & 1)) {
     T* t1 = trout + ((size_t)(2 * k + 1) * a.ncell + c) * TL;
-    t1[ln] = u[N - 1];
+    t1[ln] = g1;
     t1[L + ln] = d1;
   }
 }

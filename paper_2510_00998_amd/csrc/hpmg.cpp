@@ -52,13 +52,11 @@ void axis_operator(const hpmg::Basis1D& B, double kK, double kF0, bool bdy0, dou
     const double kF = s ? kF1 : kF0;
     const double c1 = bdy ? -kK : -0.5 * kF;
     const double c2 = bdy ? 2.0 * sigma_hat * kK : sigma_hat * kF;
-    const int ie = s ? N - 1 : 0;
+    const std::vector<double>& e = s ? B.e1 : B.e0;
     const std::vector<double>& ep = s ? B.ep1 : B.ep0;
-    for (int j = 0; j < N; ++j) {
-      L[(size_t)ie * N + j] += c1 * ep[j];
-      L[(size_t)j * N + ie] += c1 * ep[j];
-    }
-    L[(size_t)ie * N + ie] += c2;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j)
+        L[(size_t)i * N + j] += c1 * (e[i] * ep[j] + ep[i] * e[j]) + c2 * e[i] * e[j];
   }
 }
 
@@ -80,6 +78,8 @@ void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg:
   ref.insert(ref.end(), B.M.begin(), B.M.end());
   ref.insert(ref.end(), B.ep0.begin(), B.ep0.end());
   ref.insert(ref.end(), B.ep1.begin(), B.ep1.end());
+  ref.insert(ref.end(), B.e0.begin(), B.e0.end());
+  ref.insert(ref.end(), B.e1.begin(), B.e1.end());
   if (Bnext) {
     std::vector<double> E = hpmg::interp_matrix(B.xi, Bnext->xi);
     ref.insert(ref.end(), E.begin(), E.end());
@@ -662,6 +662,7 @@ void hpmg_default_options(hpmg_options* o) {
   o->max_rhs = 1;
   o->p_coarsening = 0;
   o->h_factor = 2;
+  o->basis = 0;
 }
 
 const char* hpmg_status_string(hpmg_status s) {
@@ -708,6 +709,7 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     require(h->opt.precision >= HPMG_PREC_F64 && h->opt.precision <= HPMG_PREC_BF16, "bad precision");
     require(h->opt.p_coarsening == 0 || h->opt.p_coarsening == 1, "p_coarsening must be 0 or 1");
     require(h->opt.h_factor == 2 || h->opt.h_factor == 3, "h_factor must be 2 or 3");
+    require(h->opt.basis == 0 || h->opt.basis == 1, "basis must be 0 (Gauss-Lobatto) or 1 (Gauss-Legendre)");
     h->dim = mesh->dim;
     h->n = mesh->n[0];
     h->p = p;
@@ -744,7 +746,7 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
       for (int q = p / 2; q >= 2; q /= 2) degs.push_back(q);
     const double sigma_hat = h->opt.sigma0 * (p + 1.0) * (p + 1.0);
     std::vector<hpmg::Basis1D> bases;
-    for (int q : degs) bases.push_back(hpmg::make_basis(q));
+    for (int q : degs) bases.push_back(hpmg::make_basis(q, h->opt.basis == 1));
     h->dg.resize(degs.size());
     for (size_t l = 0; l < degs.size(); ++l) {
       DGLevel& L = h->dg[l];
@@ -805,7 +807,7 @@ hpmg_status hpmg_load_vector(hpmg_handle h, int kind, const double* params, doub
     require(kind != 2 || h->dim == 2, "kind 2 (two-peak) is two-dimensional");
     const int D = h->dim, n = h->n, N = h->p + 1;
     const double hh = 1.0 / n;
-    hpmg::Basis1D B = hpmg::make_basis(h->p);
+    hpmg::Basis1D B = hpmg::make_basis(h->p, h->opt.basis == 1);
     std::vector<double> xq, wq;
     hpmg::gauss_legendre(h->p + 3, xq, wq);
     std::vector<double> V = hpmg::interp_matrix(xq, B.xi);

@@ -185,6 +185,7 @@ inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
   a.h_apply = (C)std::pow(hh, h->dim - 2);
   a.sigma_hat = (C)L.sigma_hat;
   a.omega = (C)h->opt.omega_dg;
+  a.gl = h->opt.basis;
   a.vstride = (long long)L.ndof;
   a.tstride = (long long)L.trsize;
   return a;

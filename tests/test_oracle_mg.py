@@ -223,3 +223,15 @@ def test_paper_mode_is_h_robust_2d():
         prec.append(len(ph))
     assert abs(unprec[2] - unprec[1]) <= 1, unprec
     assert prec[0] >= prec[1] >= prec[2], prec
+
+
+def test_gauss_legendre_hierarchy_solves():
+    # MG-PCG with Gauss-Legendre nodes on every DG level reaches the direct
+    # solution; the V-cycle contracts as with Gauss-Lobatto nodes
+    for basis in ("gll", "gl"):
+        H = Hierarchy(2, 6, 4, synth.kappa_log_uniform(2, 6, seed=9), opts=HierarchyOptions(basis=basis))
+        b = synth.random_rhs(H.fine.ndof, seed=10)
+        u, hist = H.solve(b, rtol=1e-10, maxit=100)
+        ref = spla.spsolve(H.levels[0].A.tocsc(), b)
+        assert np.abs(u - ref).max() <= 1e-8 * np.abs(ref).max()
+        assert len(hist) - 1 < 40

@@ -149,3 +149,41 @@ def test_block_rows_match_assembled(dim, n, p):
     cells = np.array([0, 1, s.ncell // 2, s.ncell - 1])
     y = (s.A @ u).reshape(s.ncell, s.nd)
     assert np.allclose(s.apply_rows(cells, u), y[cells], rtol=0, atol=1e-12 * np.abs(y).max())
+
+
+def _to_nodes(s_from, u, nodes_to):
+    """Nodal values of the DG function u (basis of s_from) at other nodes, per cell."""
+    from oracle.basis import lagrange_1d
+    from oracle.sipg import _kron_dims
+    E, _ = lagrange_1d(s_from.nodes1d, nodes_to)
+    T = _kron_dims([E] * s_from.dim)
+    return (u.reshape(s_from.ncell, -1) @ T.T).ravel()
+
+
+@pytest.mark.parametrize("dim,n,p,varkappa", [(2, 4, 3, False), (2, 3, 4, True), (3, 2, 2, True)])
+def test_gauss_legendre_basis_gives_the_same_discrete_solution(dim, n, p, varkappa):
+    # Gauss-Lobatto and Gauss-Legendre nodes span the same Q_p space and the
+    # bilinear form does not depend on the basis: the Galerkin solutions are
+    # the same function (Section 4.1 remark on the two node families)
+    kappa = synth.kappa_log_uniform(dim, n, seed=17) if varkappa else None
+    _, f = mf.sin_product(dim, 1)
+    s1 = SIPG(dim, n, p, kappa, basis="gll")
+    s2 = SIPG(dim, n, p, kappa, basis="gl")
+    u1 = spla.spsolve(s1.A.tocsc(), s1.load_vector(f))
+    u2 = spla.spsolve(s2.A.tocsc(), s2.load_vector(f))
+    u1_at_gl = _to_nodes(s1, u1, s2.nodes1d)
+    assert np.abs(u1_at_gl - u2).max() <= 1e-11 * np.abs(u2).max()
+    A2 = s2.A.toarray()
+    assert np.abs(A2 - A2.T).max() <= 1e-14 * np.abs(A2).max()
+    np.linalg.cholesky(A2)
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 3, 2), (3, 2, 3)])
+def test_gauss_legendre_mass_is_diagonal_and_bubble_reproduced(dim, n, p):
+    from oracle.basis import gl_nodes, ref_matrices_1d
+    M, _ = ref_matrices_1d(p, gl_nodes(p))
+    assert np.abs(M - np.diag(np.diag(M))).max() <= 1e-15
+    u, f = mf.bubble(dim)
+    s = SIPG(dim, n, p, basis="gl")
+    uh = spla.spsolve(s.A.tocsc(), s.load_vector(f))
+    assert np.abs(uh - s.interpolate(u)).max() <= 1e-11
