@@ -302,32 +302,34 @@ def run_paper_tables(args):
 
     meshes = (9, 27, 81, 243)
     degrees = (2, 3, 4, 5, 6)
-    counts = {e: {s: {} for s in ("sin_product", "two_peak")} for e in ("unprec", "prec")}
-    secs = {e: {s: {} for s in ("sin_product", "two_peak")} for e in ("unprec", "prec")}
+    bases = ("gll", "gl")
+    counts = {bs: {e: {s: {} for s in ("sin_product", "two_peak")} for e in ("unprec", "prec")} for bs in bases}
+    secs = {bs: {e: {s: {} for s in ("sin_product", "two_peak")} for e in ("unprec", "prec")} for bs in bases}
     T0 = time.perf_counter()
-    for sol, kind in (("sin_product", 1), ("two_peak", 2)):
-        for n in meshes:
-            for p in degrees:
-                g = hp.Solver(2, n, p, 1.0, p_coarsening=1, h_factor=3, coarsest_n=3, precision=hp.PREC_F64)
-                b = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
-                g.load_vector(kind, 2.0, b)
-                for ex in ("unprec", "prec"):
-                    u = torch.zeros_like(b)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    info, st = g.mgmult(u, b, rtol=1e-7, maxit=1000, exit=ex, check=False)
-                    torch.cuda.synchronize()
-                    counts[ex][sol][f"{n}x{n}"] = counts[ex][sol].get(f"{n}x{n}", {})
-                    counts[ex][sol][f"{n}x{n}"][p] = info.iterations if st == 0 else None
-                    secs[ex][sol].setdefault(f"{n}x{n}", {})[p] = time.perf_counter() - t0
-                g.close()
-            _progress(f"{sol} n={n} done")
+    for bi, bs in enumerate(bases):
+        for sol, kind in (("sin_product", 1), ("two_peak", 2)):
+            for n in meshes:
+                for p in degrees:
+                    g = hp.Solver(2, n, p, 1.0, p_coarsening=1, h_factor=3, coarsest_n=3, precision=hp.PREC_F64,
+                                  basis=bi)
+                    b = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+                    g.load_vector(kind, 2.0, b)
+                    for ex in ("unprec", "prec"):
+                        u = torch.zeros_like(b)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        info, st = g.mgmult(u, b, rtol=1e-7, maxit=1000, exit=ex, check=False)
+                        torch.cuda.synchronize()
+                        counts[bs][ex][sol].setdefault(f"{n}x{n}", {})[p] = info.iterations if st == 0 else None
+                        secs[bs][ex][sol].setdefault(f"{n}x{n}", {})[p] = time.perf_counter() - t0
+                    g.close()
+                _progress(f"{bs} {sol} n={n} done")
     line = {
         "metric": "paper-mode hp-multigrid cycles to 1e-7 (2D)", "value": None, "unit": "cycles",
         "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-        "config": {"workload": "2D Poisson, SIPG Q_p on n^2 cells, manufactured sin(2 pi x)sin(2 pi y) and two-peak "
-                               "solutions, MGMult with V(2,2) (omega_DG 0.7, omega_CG 2/3), one-step DG_p -> Q1, "
-                               "factor-3 h-coarsening to 3^2, FP64",
+        "config": {"workload": "2D Poisson, SIPG Q_p on n^2 cells (Gauss-Lobatto and Gauss-Legendre nodes), "
+                               "manufactured sin(2 pi x)sin(2 pi y) and two-peak solutions, MGMult with V(2,2) "
+                               "(omega_DG 0.7, omega_CG 2/3), one-step DG_p -> Q1, factor-3 h-coarsening to 3^2, FP64",
                    "meshes": list(meshes), "degrees": list(degrees)},
         "cycles": counts, "seconds": secs, "total_s": time.perf_counter() - T0,
     }
@@ -390,6 +392,11 @@ def main():
         sweep_in[name] = (torch.zeros(nd, dtype=dt, device=dev), bb,
                           [torch.cuda.Event(enable_timing=True) for _ in range(2)])
     u = torch.zeros(nd, dtype=torch.float64, device=dev)
+    # the same sweep with Gauss-Legendre nodes (dense facet value functionals)
+    ggl = hp.Solver(dim, n, p, kappa, basis=1)
+    gl_in = {name: (torch.zeros(nd, dtype=dt, device=dev), b64.to(dt),
+                    [torch.cuda.Event(enable_timing=True) for _ in range(2)])
+             for name, dt in (("f64", torch.float64), ("f32", torch.float32))}
     solves = ("fp64", "mixed_f32", "mixed_f16", "mixed_bf16")
     if not vark:
         solves += ("mixed_f32_graph",)
@@ -402,11 +409,12 @@ def main():
         # S fused sweeps (one hpmg_sweep call, one launch per sweep) queued
         # back to back between two events on the launch stream:
         # mean launch duration = elapsed / S
-        for uu, bb, evs in sweep_in.values():
-            g64.project(uu)
-            evs[0].record(stream)
-            g64.sweep(uu, bb, S)
-            evs[1].record(stream)
+        for gs, ins in ((g64, sweep_in), (ggl, gl_in)):
+            for uu, bb, evs in ins.values():
+                gs.project(uu)
+                evs[0].record(stream)
+                gs.sweep(uu, bb, S)
+                evs[1].record(stream)
         # time to 1e-10: FP64 cycle, then mixed FP32 cycle (single-problem
         # solver; and, for constant kappa, the batched solver on a batch of
         # one, whose iteration is a captured graph)
@@ -425,6 +433,8 @@ def main():
         if record:
             for name, (_, _, evs) in sweep_in.items():
                 out["sw_" + name] = evs[0].elapsed_time(evs[1]) * 1e-3 / S
+            for name, (_, _, evs) in gl_in.items():
+                out["swgl_" + name] = evs[0].elapsed_time(evs[1]) * 1e-3 / S
         return out
 
     for _ in range(args.warmup):
@@ -488,6 +498,8 @@ def main():
                      "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64,
                      "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": ach64 / copy_gbs},
         "sweep_dofs_per_s": {name: nd / t for name, t in tsw.items()},
+        "sweep_dofs_per_s_gauss_legendre": {name: nd / (sum(r["swgl_" + name] for r in res) / len(res))
+                                            for name in gl_in},
         "sweep_roofline_f32": {"achieved": by32 / t32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by32 / t32 / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by32,
                                "traffic": counter_traffic(tkey32),
