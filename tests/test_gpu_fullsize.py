@@ -86,3 +86,40 @@ def test_fullsize_mixed_solve_residual(name, prec):
     log(f"  {name} {prec}: {info.iterations} its, true rel residual {rel:.2e}")
     assert st == 0 and rel <= 2e-10
     g.close()
+
+
+def test_fullsize_batched_workload():
+    # the 64 problems x 4 RHS batched workload at full size (as the bench runs
+    # it): every segment's true FP64 residual (parity-tested apply) meets the
+    # tolerance, and the oracle's own residual on the smallest problems
+    import paper_2510_00998_amd as hp
+    probs = synth.batched_problem_list()
+    R = 4
+    solvers = [hp.Solver(3, n, p, 1.0, max_rhs=R) for n, p in probs]
+    batch = hp.Batch(solvers)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1004)
+    bs = [torch.randn(R * s.ndof, dtype=torch.float64, device="cuda", generator=gen) for s in solvers]
+    us = [torch.zeros_like(b) for b in bs]
+    infos, st = batch.solve(us, bs, rtol=1e-10, maxit=200, nrhs=R)
+    log(f"batched 64x4: status {st}, max iterations {max(i.iterations for i in infos)}")
+    assert st == 0
+    worst = 0.0
+    for s, u, b in zip(solvers, us, bs):
+        y = torch.empty_like(u)
+        s.apply_A(u, y, nrhs=R)
+        for r in range(R):
+            sl = slice(r * s.ndof, (r + 1) * s.ndof)
+            worst = max(worst, float(torch.linalg.vector_norm(b[sl] - y[sl]) / torch.linalg.vector_norm(b[sl])))
+    log(f"  worst true relative residual {worst:.2e}")
+    assert worst <= 2e-10
+    small = sorted(range(len(probs)), key=lambda j: solvers[j].ndof)[:2]
+    for j in small:
+        n, p = probs[j]
+        A = SIPG(3, n, p).A
+        u, b = to_host(us[j]), to_host(bs[j])
+        nd = solvers[j].ndof
+        rr = max(np.linalg.norm(b[r * nd:(r + 1) * nd] - A @ u[r * nd:(r + 1) * nd]) /
+                 np.linalg.norm(b[r * nd:(r + 1) * nd]) for r in range(R))
+        log(f"  problem {j} (n={n}, p={p}): oracle residual {rr:.2e}")
+        assert rr <= 2e-10
