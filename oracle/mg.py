@@ -50,6 +50,9 @@ class HierarchyOptions:
     p_coarsening: str = "halve"  # "halve" (gradual) or "direct" (DG_p -> Q1 in one step, Section 5.2)
     h_factor: int = 2            # Q1 h-coarsening factor (2, or 3 as in the paper's meshes 3^k)
     basis: str = "gll"           # DG nodes: "gll" (Gauss-Lobatto) or "gl" (Gauss-Legendre)
+    block: str = "exact"         # block-Jacobi block: "exact" A_{K<-K}, or "interior": the block of an
+                                 # interior cell for every cell (Section 4, technique approximate
+                                 # boundary operators; constant kappa, n >= 3)
 
 
 def p_levels(p: int, schedule=None, mode: str = "halve"):
@@ -184,6 +187,11 @@ class Hierarchy:
         cur = fine
         for li, q in enumerate(degs):
             blocks = extract_diagonal_blocks(A, (q + 1) ** dim)
+            if self.opts.block == "interior":
+                if n < 3:
+                    raise ValueError("the interior-block smoother needs an interior cell (n >= 3)")
+                inner = sum(n ** k for k in range(dim))  # cell (1, 1[, 1])
+                blocks = np.broadcast_to(blocks[inner], blocks.shape).copy()
             self.levels.append(Level("dg", A, n, q, blocks))
             if li + 1 < len(degs):
                 nxt = SIPG(dim, n, degs[li + 1], kappa, p_penalty=p, sigma0=self.opts.sigma0, basis=self.opts.basis)
