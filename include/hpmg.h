@@ -17,9 +17,9 @@
  *    c = cx + n*cy (+ n^2*cz), local node i = a + N*b (+ N^2*c), N = p+1,
  *    x fastest, Gauss-Lobatto nodes (Gauss-Legendre with options.basis =
  *    1).  `nrhs` right-hand sides are stacked back to back ([rhs][dof]).
- *  - All work is enqueued on `stream` (0 = the null stream).  Only
- *    hpmg_solve synchronises the stream (it reads one 8-byte norm per
- *    iteration back to the host).
+ *  - All work is enqueued on `stream` (0 = the null stream).  The solvers
+ *    (hpmg_solve, hpmg_mgmult, hpmg_batch_solve) synchronise it and read a
+ *    few scalars per iteration back to the host.
  *  - No function throws; each returns a status.  A message describing the
  *    last failure of the calling thread is available from hpmg_last_error.
  *  - Right-hand sides are load vectors b_i = int f phi_i, not samples of f.
@@ -161,8 +161,11 @@ typedef struct {
  * preconditioned by one V-cycle (precision from the options) in FP64.  u
  * holds the initial guess on entry.  info may be NULL (host pointer).
  * Returns HPMG_E_NOT_CONVERGED after maxit iterations, HPMG_E_BREAKDOWN on a
- * non-finite residual.  Paper: Section 5 (MGMult, exit criterion), with the
- * unpreconditioned residual as exit test. */
+ * non-finite residual.  The caller's stream is synchronised first; the
+ * iteration (one outer step, captured once per handle and cycle precision as
+ * a HIP graph) then runs on an internal stream of the handle, and the call
+ * returns when u holds the result.  Paper: Section 5 (MGMult, exit
+ * criterion), with the unpreconditioned residual as exit test. */
 hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, double rtol,
                        int maxit, hpmg_solve_info* info, hipStream_t stream);
 

@@ -646,6 +646,22 @@ double fp64_residual(hpmg_ctx* h, const double* u, const double* b, hipStream_t 
   return rn;
 }
 
+// One outer FCG iteration on the internal vectors (ug, r, rold, pv, q, z)
+// enqueued on s, ending with the copy of the scalars to the pinned host
+// buffer; restart = 1 takes beta = 0.
+void fcg_iteration(hpmg_ctx* h, double rms, int restart, hipStream_t s) {
+  const size_t nd = h->ndof;
+  DGData<double>& d = h->dg[0].d;
+  precondition(h, rms, s);  // z = M r
+  hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart, s);
+  hpmg::krylov_update_p(nd, h->z, h->pv, h->scal, s);
+  project<double>(h, 0, h->pv, d.tr[0], 1, s);  // q = A p
+  apply<double>(h, 0, h->pv, d.tr[0], nullptr, h->q, 1, s);
+  hpmg::krylov_dot(nd, h->pv, h->q, nullptr, h->partial, h->scal, 2, 0, 0, s);
+  hpmg::krylov_update_ur(nd, h->ug, h->r, h->rold, h->pv, h->q, h->partial, h->scal, s);
+  HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
 }  // namespace
 
 extern "C" {
@@ -995,46 +1011,50 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
     require(nrhs >= 1, "nrhs must be >= 1");
     require(rtol > 0.0 && maxit >= 1, "bad rtol/maxit");
     const auto t0 = std::chrono::steady_clock::now();
-    h->trace_state[0] = h->trace_state[1] = -1;
+    h->trace_state[0] = h->trace_state[1] = h->trace_state[2] = h->trace_state[3] = -1;
     const size_t nd = h->ndof;
-    DGData<double>& d = h->dg[0].d;
     hpmg_status result = HPMG_OK;
     bool stagnated = false;
     const double rms = lowp_setup(h);
+    // the iteration runs as a captured graph on an internal stream, on an
+    // internal copy of u (so that one capture serves every call)
+    if (!h->gs) HIPCHK(hipStreamCreateWithFlags(&h->gs, hipStreamNonBlocking));
+    if (!h->ug) h->ug = (double*)h->mem.alloc(nd * sizeof(double));
+    hipStream_t gs = h->gs;
+    if (h->graph_prec != h->opt.precision) {
+      for (int i = 0; i < 2; ++i) {
+        if (h->gexec[i]) (void)hipGraphExecDestroy(h->gexec[i]);
+        if (h->graph[i]) (void)hipGraphDestroy(h->graph[i]);
+        h->gexec[i] = nullptr;
+        h->graph[i] = nullptr;
+      }
+      for (int i = 0; i < 2; ++i) {
+        HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        fcg_iteration(h, rms, i, gs);
+        HIPCHK(hipStreamEndCapture(gs, &h->graph[i]));
+        HIPCHK(hipGraphInstantiate(&h->gexec[i], h->graph[i], nullptr, nullptr, 0));
+      }
+      h->graph_prec = h->opt.precision;
+    }
+    HIPCHK(hipStreamSynchronize(stream));  // the caller's writes of u, b are done
     int its_total = 0;
     double r0_first = 0.0, rfin = 0.0;
     std::vector<double> hist;
     for (int rhs = 0; rhs < nrhs; ++rhs) {
       double* ur = u + (size_t)rhs * nd;
       const double* br = b + (size_t)rhs * nd;
-      // r = b - A u
-      project<double>(h, 0, ur, d.tr[0], 1, stream);
-      apply<double>(h, 0, ur, d.tr[0], br, h->r, 1, stream);
-      hpmg::krylov_dot(nd, h->r, h->r, nullptr, h->partial, h->scal, 3, 0, 0, stream);
-      HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipStreamSynchronize(stream));
-      const double r0 = std::sqrt(h->host_scal[6]);
-      if (!std::isfinite(r0)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite initial residual");
+      HIPCHK(hipMemcpyAsync(h->ug, ur, nd * sizeof(double), hipMemcpyDeviceToDevice, gs));
+      const double r0 = fp64_residual(h, h->ug, br, gs);  // r = b - A u
       if (rhs == 0) r0_first = r0;
       double rn = r0;
       int it = 0;
       bool conv = r0 == 0.0;
-      bool restart = true;
+      int restart = 1;
       int restarts = 0;
       while (!conv && it < maxit) {
-        // z = M r (one V-cycle, zero initial guess)
-        precondition(h, rms, stream);
-        // beta, rho = z.r ; p = z + beta p
-        hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart ? 1 : 0, stream);
-        restart = false;
-        hpmg::krylov_update_p(nd, h->z, h->pv, h->scal, stream);
-        // q = A p ; alpha = rho / p.q
-        project<double>(h, 0, h->pv, d.tr[0], 1, stream);
-        apply<double>(h, 0, h->pv, d.tr[0], nullptr, h->q, 1, stream);
-        hpmg::krylov_dot(nd, h->pv, h->q, nullptr, h->partial, h->scal, 2, 0, 0, stream);
-        hpmg::krylov_update_ur(nd, ur, h->r, h->rold, h->pv, h->q, h->partial, h->scal, stream);
-        HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        HIPCHK(hipGraphLaunch(h->gexec[restart], gs));
+        HIPCHK(hipStreamSynchronize(gs));
+        restart = 0;
         ++it;
         rn = std::sqrt(h->host_scal[6]);
         if (!std::isfinite(rn)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite residual");
@@ -1044,15 +1064,9 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
           // the recurrence residual drifts from b - A u in finite precision:
           // accept only if the true residual meets the tolerance, else
           // restart the iteration from it
-          project<double>(h, 0, ur, d.tr[0], 1, stream);
-          apply<double>(h, 0, ur, d.tr[0], br, h->r, 1, stream);
-          hpmg::krylov_dot(nd, h->r, h->r, nullptr, h->partial, h->scal, 3, 0, 0, stream);
-          HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
-          HIPCHK(hipStreamSynchronize(stream));
-          rn = std::sqrt(h->host_scal[6]);
-          if (!std::isfinite(rn)) throw HpmgError(HPMG_E_BREAKDOWN, "non-finite residual");
+          rn = fp64_residual(h, h->ug, br, gs);
           conv = rn <= rtol * r0;
-          restart = !conv;
+          restart = conv ? 0 : 1;
           // a true residual that stays above rtol after kMaxRestarts
           // restarts has reached the FP64 rounding floor of b - A u
           if (!conv && ++restarts > kMaxRestarts) {
@@ -1061,6 +1075,8 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
           }
         }
       }
+      HIPCHK(hipMemcpyAsync(ur, h->ug, nd * sizeof(double), hipMemcpyDeviceToDevice, gs));
+      HIPCHK(hipStreamSynchronize(gs));
       its_total = std::max(its_total, it);
       rfin = std::max(rfin, rn);
       if (!conv) result = HPMG_E_NOT_CONVERGED;

@@ -140,7 +140,20 @@ struct hpmg_ctx {
   int trace_state[4] = {-1, -1, -1, -1};
   int trace_rhs[4] = {0, 0, 0, 0};
   hpmg::detail::DevMem mem;
+  // hpmg_solve: one outer iteration captured as a HIP graph (index: restart
+  // flag) for the cycle precision graph_prec, replayed on the internal
+  // stream gs on the internal solution vector ug
+  hipStream_t gs = nullptr;
+  double* ug = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int graph_prec = -1;
   ~hpmg_ctx() {
+    for (int i = 0; i < 2; ++i) {
+      if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+    }
+    if (gs) (void)hipStreamDestroy(gs);
     if (host_scal) (void)hipHostFree(host_scal);
   }
 };
