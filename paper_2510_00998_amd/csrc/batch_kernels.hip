@@ -97,13 +97,26 @@ __device__ void cg_item(const CGArgs<T>& a, int blk, int rhs) {
     if (v >= nv * nv * nv) return;
     T au = 0;
     if (!a.uzero) {
+      // point-major stencil; clamped neighbour indices (an absent
+      // neighbour has a zero stencil entry), independent loads
+      const int total = nv * nv * nv;
       int x, y, z;
       vc3(v, nv, x, y, z);
-      for (int s = 0; s < 27; ++s) {
-        const int X = x + s % 3 - 1, Y = y + (s / 3) % 3 - 1, Z = z + s / 9 - 1;
-        if (X < 0 || X >= nv || Y < 0 || Y >= nv || Z < 0 || Z >= nv) continue;
-        au += a.st[(size_t)v * 27 + s] * u[X + nv * (Y + nv * Z)];
+      int cx[3], cy[3], cz[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        cx[d] = min(max(x + d - 1, 0), nv - 1);
+        cy[d] = min(max(y + d - 1, 0), nv - 1) * nv;
+        cz[d] = min(max(z + d - 1, 0), nv - 1) * nv * nv;
       }
+      T sv[27], uv[27];
+#pragma unroll
+      for (int s = 0; s < 27; ++s) {
+        sv[s] = a.st[(size_t)s * total + v];
+        uv[s] = u[cx[s % 3] + cy[(s / 3) % 3] + cz[s / 9]];
+      }
+#pragma unroll
+      for (int s = 0; s < 27; ++s) au += sv[s] * uv[s];
     }
     if (a.op == CGOP_JACOBI)
       out[v] = (a.uzero ? T(0) : u[v]) + a.omega * a.dinv[v] * (b[v] - au);
@@ -114,40 +127,51 @@ __device__ void cg_item(const CGArgs<T>& a, int blk, int rhs) {
     if (v >= nvc * nvc * nvc) return;
     int x, y, z;
     vc3(v, nvc, x, y, z);
-    T s = 0;
-    for (int c = 0; c < 3; ++c) {
-      const int iz = a.idx[3 * z + c];
-      if (iz < 0) continue;
-      for (int bb = 0; bb < 3; ++bb) {
-        const int iy = a.idx[3 * y + bb];
-        if (iy < 0) continue;
-        for (int aa = 0; aa < 3; ++aa) {
-          const int ix = a.idx[3 * x + aa];
-          if (ix < 0) continue;
-          s += a.w[3 * z + c] * a.w[3 * y + bb] * a.w[3 * x + aa] * in[ix + nvf * (iy + nvf * iz)];
-        }
-      }
+    // empty parent slots (index < 0) take index 0 with weight 0
+    int ix[3], iy[3], iz[3];
+    T wx[3], wy[3], wz[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int jx = a.idx[3 * x + k], jy = a.idx[3 * y + k], jz = a.idx[3 * z + k];
+      ix[k] = max(jx, 0);
+      iy[k] = max(jy, 0);
+      iz[k] = max(jz, 0);
+      wx[k] = jx < 0 ? T(0) : a.w[3 * x + k];
+      wy[k] = jy < 0 ? T(0) : a.w[3 * y + k];
+      wz[k] = jz < 0 ? T(0) : a.w[3 * z + k];
     }
+    T s = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa) s += wz[c] * wy[bb] * wx[aa] * in[ix[aa] + nvf * (iy[bb] + nvf * iz[c])];
     out[v] = s;
   } else if (a.op == CGOP_PROLONG) {
     const int nvf = a.nv, nvc = a.nvc;
     if (v >= nvf * nvf * nvf) return;
     int x, y, z;
     vc3(v, nvf, x, y, z);
-    T s = 0;
-    for (int c = 0; c < 2; ++c) {
-      const int iz = a.idx[2 * z + c];
-      if (iz < 0) continue;
-      for (int bb = 0; bb < 2; ++bb) {
-        const int iy = a.idx[2 * y + bb];
-        if (iy < 0) continue;
-        for (int aa = 0; aa < 2; ++aa) {
-          const int ix = a.idx[2 * x + aa];
-          if (ix < 0) continue;
-          s += a.w[2 * z + c] * a.w[2 * y + bb] * a.w[2 * x + aa] * in[ix + nvc * (iy + nvc * iz)];
-        }
-      }
+    int ix[2], iy[2], iz[2];
+    T wx[2], wy[2], wz[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int jx = a.idx[2 * x + k], jy = a.idx[2 * y + k], jz = a.idx[2 * z + k];
+      ix[k] = max(jx, 0);
+      iy[k] = max(jy, 0);
+      iz[k] = max(jz, 0);
+      wx[k] = jx < 0 ? T(0) : a.w[2 * x + k];
+      wy[k] = jy < 0 ? T(0) : a.w[2 * y + k];
+      wz[k] = jz < 0 ? T(0) : a.w[2 * z + k];
     }
+    T s = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) s += wz[c] * wy[bb] * wx[aa] * in[ix[aa] + nvc * (iy[bb] + nvc * iz[c])];
     out[v] += s;
   } else if (a.op == CGOP_GATHER) {
     const int n = a.n, nv = n - 1;

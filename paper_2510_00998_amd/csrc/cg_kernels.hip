@@ -19,6 +19,11 @@ __device__ __forceinline__ void vcoords(int v, int nv, int (&x)[3]) {
 
 // out = u + omega Dinv (b - A u)   (mode 0; u = 0 if uzero)
 // out = b - A u                    (mode 1)
+// The stencil is stored point-major, st[s * nv^d + v], so that a wave reads
+// each stencil point of its vertices with one coalesced load.  Neighbour
+// indices are clamped into the grid instead of skipped: the stencil entry of
+// a neighbour outside the interior is zero, and the loads of a thread are
+// independent of each other (issued back to back).
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict__ st, const T* __restrict__ dinv,
                                                     const T* __restrict__ u, const T* __restrict__ b,
@@ -31,14 +36,21 @@ __global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict_
   if (!uzero) {
     int x[3];
     vcoords<D>(v, nv, x);
+    int cx[3], cy[3], cz[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      cx[d] = min(max(x[0] + d - 1, 0), nv - 1);
+      cy[d] = min(max(x[1] + d - 1, 0), nv - 1) * nv;
+      cz[d] = (D == 3) ? min(max(x[2] + d - 1, 0), nv - 1) * nv * nv : 0;
+    }
+    T sv[NS], uv[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = (D == 3) ? s / 9 - 1 : 0;
-      const int X = x[0] + dx, Y = x[1] + dy, Z = x[2] + dz;
-      if (X < 0 || X >= nv || Y < 0 || Y >= nv || (D == 3 && (Z < 0 || Z >= nv))) continue;
-      const int w = X + nv * (Y + nv * Z);
-      au += st[(size_t)v * NS + s] * u[w];
+      sv[s] = st[(size_t)s * total + v];
+      uv[s] = u[cx[s % 3] + cy[(s / 3) % 3] + cz[(D == 3) ? s / 9 : 1]];
     }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) au += sv[s] * uv[s];
   }
   if (mode == 0) {
     const T u0 = uzero ? T(0) : u[v];
@@ -48,10 +60,24 @@ __global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict_
   }
 }
 
+// Fine interior indices and weights of a coarse vertex along one axis
+// (RK slots; an empty slot, index < 0, becomes index 0 with weight 0).
+template <typename T, int RK>
+__device__ __forceinline__ void axis_parents(const int* __restrict__ idx, const T* __restrict__ w, int x, int (&i)[RK],
+                                             T (&wt)[RK]) {
+#pragma unroll
+  for (int a = 0; a < RK; ++a) {
+    const int k = idx[RK * x + a];
+    i[a] = k < 0 ? 0 : k;
+    wt[a] = k < 0 ? T(0) : w[RK * x + a];
+  }
+}
+
 // b_c = P^T r_f with the tensor-product 1D transfer: coarse interior index I
-// gathers up to three fine interior indices ridx[3I..3I+2] with weights rw.
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, int rk, const int* __restrict__ ridx,
+// gathers up to RK = 2f - 1 fine interior indices ridx[RK I ..] per axis with
+// weights rw (f = 2 or 3: the coarsening factor).
+template <typename T, int D, int RK>
+__global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, const int* __restrict__ ridx,
                                                      const T* __restrict__ rw, const T* __restrict__ rf,
                                                      T* __restrict__ bc) {
   const int total = (D == 2) ? nvc * nvc : nvc * nvc * nvc;
@@ -59,22 +85,24 @@ __global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, int rk, c
   if (v >= total) return;
   int x[3];
   vcoords<D>(v, nvc, x);
-  T s = 0;
-  for (int c = 0; c < (D == 3 ? rk : 1); ++c) {
-    const int iz = (D == 3) ? ridx[rk * x[2] + c] : 0;
-    const T wz = (D == 3) ? rw[rk * x[2] + c] : T(1);
-    if (iz < 0) continue;
-    for (int b2 = 0; b2 < rk; ++b2) {
-      const int iy = ridx[rk * x[1] + b2];
-      if (iy < 0) continue;
-      const T wy = rw[rk * x[1] + b2];
-      for (int a2 = 0; a2 < rk; ++a2) {
-        const int ix = ridx[rk * x[0] + a2];
-        if (ix < 0) continue;
-        s += wz * wy * rw[rk * x[0] + a2] * rf[ix + nvf * (iy + nvf * iz)];
-      }
-    }
+  constexpr int RZ = (D == 3) ? RK : 1;
+  int ix[RK], iy[RK], iz[RK];
+  T wx[RK], wy[RK], wz[RK];
+  axis_parents<T, RK>(ridx, rw, x[0], ix, wx);
+  axis_parents<T, RK>(ridx, rw, x[1], iy, wy);
+  if constexpr (D == 3) {
+    axis_parents<T, RK>(ridx, rw, x[2], iz, wz);
+  } else {
+    iz[0] = 0;
+    wz[0] = T(1);
   }
+  T s = 0;
+#pragma unroll
+  for (int c = 0; c < RZ; ++c)
+#pragma unroll
+    for (int b2 = 0; b2 < RK; ++b2)
+#pragma unroll
+      for (int a2 = 0; a2 < RK; ++a2) s += wz[c] * wy[b2] * wx[a2] * rf[ix[a2] + nvf * (iy[b2] + nvf * iz[c])];
   bc[v] = s;
 }
 
@@ -89,22 +117,24 @@ __global__ __launch_bounds__(256) void k_cg_prolong(int nvf, int nvc, const int*
   if (v >= total) return;
   int x[3];
   vcoords<D>(v, nvf, x);
-  T s = 0;
-  for (int c = 0; c < (D == 3 ? 2 : 1); ++c) {
-    const int iz = (D == 3) ? pidx[2 * x[2] + c] : 0;
-    const T wz = (D == 3) ? pw[2 * x[2] + c] : T(1);
-    if (iz < 0) continue;
-    for (int b2 = 0; b2 < 2; ++b2) {
-      const int iy = pidx[2 * x[1] + b2];
-      if (iy < 0) continue;
-      const T wy = pw[2 * x[1] + b2];
-      for (int a2 = 0; a2 < 2; ++a2) {
-        const int ix = pidx[2 * x[0] + a2];
-        if (ix < 0) continue;
-        s += wz * wy * pw[2 * x[0] + a2] * ec[ix + nvc * (iy + nvc * iz)];
-      }
-    }
+  constexpr int RZ = (D == 3) ? 2 : 1;
+  int ix[2], iy[2], iz[2];
+  T wx[2], wy[2], wz[2];
+  axis_parents<T, 2>(pidx, pw, x[0], ix, wx);
+  axis_parents<T, 2>(pidx, pw, x[1], iy, wy);
+  if constexpr (D == 3) {
+    axis_parents<T, 2>(pidx, pw, x[2], iz, wz);
+  } else {
+    iz[0] = 0;
+    wz[0] = T(1);
   }
+  T s = 0;
+#pragma unroll
+  for (int c = 0; c < RZ; ++c)
+#pragma unroll
+    for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+      for (int a2 = 0; a2 < 2; ++a2) s += wz[c] * wy[b2] * wx[a2] * ec[ix[a2] + nvc * (iy[b2] + nvc * iz[c])];
   uf[v] += s;
 }
 
@@ -181,6 +211,38 @@ __global__ __launch_bounds__(256) void k_dot2(size_t n, const double* __restrict
   }
 }
 
+// Low-precision z of a mixed cycle, read as z_i = (double) zl_i * sc.
+template <typename T>
+__device__ __forceinline__ double lowz(const T* __restrict__ zl, size_t i, double sc) {
+  return (double)(float)zl[i] * sc;
+}
+__device__ __forceinline__ double lowz_scale(const double* __restrict__ s, int scaled, double mul) {
+  return scaled ? s[8] / mul : 1.0;
+}
+
+// partials of z.r and z.rold with z read from the cycle's own vector (no
+// FP64 copy of z is formed)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot2z(size_t n, const T* __restrict__ zl, const double* __restrict__ s,
+                                               int scaled, double mul, const double* __restrict__ r,
+                                               const double* __restrict__ rold, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const double sc = lowz_scale(s, scaled, mul);
+  double s0 = 0.0, s1 = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double zi = lowz(zl, i, sc);
+    s0 += zi * r[i];
+    s1 += zi * rold[i];
+  }
+  double t0 = block_sum(s0, sh);
+  __syncthreads();
+  double t1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = t0;
+    partial[RED_BLOCKS + blockIdx.x] = t1;
+  }
+}
+
 // Sum the partials into slots and apply the scalar step of the flexible CG:
 //  op 0: s[a0] = sum0
 //  op 1: beta: s[3] = first ? 0 : (sum0 - sum1)/s[2]; s[2] = sum0 (rho)
@@ -228,11 +290,24 @@ __global__ __launch_bounds__(256) void k_update_p(size_t n, const double* __rest
     p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
 }
 
-// u += alpha p; r_old = r; r -= alpha q; partial r.r
+// p = z + beta p with z read from the cycle's low-precision vector
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_pz(size_t n, const T* __restrict__ zl, double* __restrict__ p,
+                                                   const double* __restrict__ s, int scaled, double mul) {
+  const double beta = s[3];
+  const double sc = lowz_scale(s, scaled, mul);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double zi = lowz(zl, i, sc);
+    p[i] = beta == 0.0 ? zi : zi + beta * p[i];
+  }
+}
+
+// u += alpha p; r_old = r; r -= alpha q; partial r.r; r32 = (float) r when
+// given (the unscaled FP32 copy that the next FP32 cycle reads)
 __global__ __launch_bounds__(256) void k_update_ur(size_t n, double* __restrict__ u, double* __restrict__ r,
                                                    double* __restrict__ rold, const double* __restrict__ p,
                                                    const double* __restrict__ q, const double* __restrict__ s,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, float* __restrict__ r32) {
   __shared__ double sh[4];
   const double alpha = s[5];
   double acc = 0.0;
@@ -242,6 +317,7 @@ __global__ __launch_bounds__(256) void k_update_ur(size_t n, double* __restrict_
     rold[i] = ri;
     const double rn = ri - alpha * q[i];
     r[i] = rn;
+    if (r32) r32[i] = (float)rn;
     acc += rn * rn;
   }
   const double t = block_sum(acc, sh);
@@ -253,11 +329,11 @@ __global__ __launch_bounds__(256) void k_update_ur(size_t n, double* __restrict_
 
 // y = (T)(x * s[7] * mul): scaled cast for a reduced-precision cycle (s[7] =
 // 1/||x||; mul = 1 for FP32, sqrt(n) for 16-bit storage so that the entries
-// have unit mean square)
+// have unit mean square); s = null: y = (T)(x * mul)
 template <typename T>
 __global__ __launch_bounds__(256) void k_cast_down(size_t n, const double* __restrict__ x, T* __restrict__ y,
                                                    const double* __restrict__ s, double mul) {
-  const double sc = s[7] * mul;
+  const double sc = s ? s[7] * mul : mul;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = (T)(float)(x[i] * sc);
 }
@@ -294,10 +370,15 @@ void cg_stencil(int D, int nv, const T* st, const T* dinv, const T* u, const T* 
 template <typename T>
 void cg_restrict(int D, int nvf, int nvc, int rk, const int* ridx, const T* rw, const T* rf, T* bc, hipStream_t s) {
   const size_t total = (D == 2) ? (size_t)nvc * nvc : (size_t)nvc * nvc * nvc;
-  if (D == 2)
-    hipLaunchKernelGGL((k_cg_restrict<T, 2>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, rk, ridx, rw, rf, bc);
+  const dim3 g(nblocks(total));
+  if (D == 2 && rk == 3)
+    hipLaunchKernelGGL((k_cg_restrict<T, 2, 3>), g, dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
+  else if (D == 2)
+    hipLaunchKernelGGL((k_cg_restrict<T, 2, 5>), g, dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
+  else if (rk == 3)
+    hipLaunchKernelGGL((k_cg_restrict<T, 3, 3>), g, dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
   else
-    hipLaunchKernelGGL((k_cg_restrict<T, 3>), dim3(nblocks(total)), dim3(256), 0, s, nvf, nvc, rk, ridx, rw, rf, bc);
+    hipLaunchKernelGGL((k_cg_restrict<T, 3, 5>), g, dim3(256), 0, s, nvf, nvc, ridx, rw, rf, bc);
 }
 
 template <typename T>
@@ -348,11 +429,32 @@ void krylov_update_p(size_t n, const double* z, double* p, const double* scal, h
 }
 
 void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double* p, const double* q, double* partial,
-                      double* scal, hipStream_t s) {
+                      double* scal, float* r32, hipStream_t s) {
   const unsigned g = gs_blocks(n);
-  hipLaunchKernelGGL(k_update_ur, dim3(g), dim3(256), 0, s, n, u, r, rold, p, q, scal, partial);
+  hipLaunchKernelGGL(k_update_ur, dim3(g), dim3(256), 0, s, n, u, r, rold, p, q, scal, partial, r32);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, (int)g, scal, 3, 0, 0);
 }
+
+template <typename T>
+void krylov_dot_lowz(size_t n, const T* zl, int scaled, double mul, const double* r, const double* rold,
+                     double* partial, double* scal, int first, hipStream_t s) {
+  const unsigned g = gs_blocks(n);
+  hipLaunchKernelGGL((k_dot2z<T>), dim3(g), dim3(256), 0, s, n, zl, scal, scaled, mul, r, rold, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, (int)g, scal, 1, 0, first);
+}
+template <typename T>
+void krylov_update_p_lowz(size_t n, const T* zl, int scaled, double mul, double* p, const double* scal,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_update_pz<T>), dim3(gs_blocks(n)), dim3(256), 0, s, n, zl, p, scal, scaled, mul);
+}
+#define HPMG_LOWZ(T)                                                                                            \
+  template void krylov_dot_lowz<T>(size_t, const T*, int, double, const double*, const double*, double*, double*, \
+                                   int, hipStream_t);                                                           \
+  template void krylov_update_p_lowz<T>(size_t, const T*, int, double, double*, const double*, hipStream_t);
+HPMG_LOWZ(float)
+HPMG_LOWZ(_Float16)
+HPMG_LOWZ(__bf16)
+#undef HPMG_LOWZ
 
 template <typename T>
 void cast_down(size_t n, const double* x, T* y, const double* scal, double mul, hipStream_t s) {

@@ -37,9 +37,6 @@ namespace hpmg {
 #define HPMG_CPB3D_N 0
 #define HPMG_CPB3D 0
 #endif
-#ifndef HPMG_MAX_THREADS
-#define HPMG_MAX_THREADS 256
-#endif
 template <int D, int N>
 struct DGShape {
   static constexpr int L = (D == 2) ? N : N * N;  // lines per cell = nodes per facet
@@ -47,6 +44,7 @@ struct DGShape {
   static constexpr int NF = 2 * D;                // facets per cell
   static constexpr int CPB = (D == 3 && N == HPMG_CPB3D_N) ? HPMG_CPB3D : ((256 / L) > 0 ? (256 / L) : 1);
   static constexpr int NT = CPB * L;
+  static constexpr int BLOCK = (NT + 63) / 64 * 64;  // launch bound: whole waves
   static constexpr int EGS = 2 * N * N + N;       // S, Si, lambda of one direction
 };
 

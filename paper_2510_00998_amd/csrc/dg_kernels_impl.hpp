@@ -568,7 +568,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
 }
 
 template <typename T, int D, int N, bool UZERO, bool VARK>
-__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_sweep(DGArgs<T> a) {
+__global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_sweep(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
   sweep_body<T, D, N, UZERO, VARK>(a, blockIdx.x, blockIdx.y, lds);
 }
@@ -754,7 +754,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
 }
 
 template <typename T, int D, int N, int NC, bool RESID, bool VARK>
-__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_apply(DGArgs<T> a) {
+__global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_apply(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
   apply_body<T, D, N, NC, RESID, VARK>(a, blockIdx.x, blockIdx.y, lds);
 }
@@ -910,7 +910,7 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
 }
 
 template <typename T, int D, int N, int NC>
-__global__ __launch_bounds__(HPMG_MAX_THREADS) void k_prolong(DGArgs<T> a) {
+__global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_prolong(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[prolong_lds_bytes<T, D, N, NC>()];
   prolong_body<T, D, N, NC>(a, blockIdx.x, blockIdx.y, lds);
 }

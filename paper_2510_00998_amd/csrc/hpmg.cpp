@@ -309,8 +309,12 @@ void build_cg_levels(hpmg_ctx* h, hipStream_t s) {
     const int NS = nstencil(D);
     std::vector<double> dinv(L.size);
     for (size_t v = 0; v < L.size; ++v) dinv[v] = 1.0 / st[v * NS + NS / 2];
-    L.d.st = h->mem.upload(st, s);
-    L.f.st = h->mem.upload(cast_vec<float>(st), s);
+    // device copy point-major: st[s * size + v]
+    std::vector<double> stp(st.size());
+    for (size_t v = 0; v < L.size; ++v)
+      for (int k = 0; k < NS; ++k) stp[(size_t)k * L.size + v] = st[v * NS + k];
+    L.d.st = h->mem.upload(stp, s);
+    L.f.st = h->mem.upload(cast_vec<float>(stp), s);
     L.d.dinv = h->mem.upload(dinv, s);
     L.f.dinv = h->mem.upload(cast_vec<float>(dinv), s);
     const size_t R = h->opt.max_rhs;
@@ -646,19 +650,46 @@ double fp64_residual(hpmg_ctx* h, const double* u, const double* b, hipStream_t 
   return rn;
 }
 
-// One outer FCG iteration on the internal vectors (ug, r, rold, pv, q, z)
-// enqueued on s, ending with the copy of the scalars to the pinned host
-// buffer; restart = 1 takes beta = 0.
+// One outer FCG iteration on the internal vectors (ug, r, rold, pv, q and
+// the cycle's z) enqueued on s, ending with the copy of the scalars to the
+// pinned host buffer; restart = 1 takes beta = 0.  A reduced-precision
+// cycle's z is read where it lies (the dots and the update of p convert it);
+// the FP32 cycle takes r unscaled, cast by the previous iteration's update
+// (after a restart: by a cast here), the 16-bit cycles take r scaled to
+// mean square lambda.
 void fcg_iteration(hpmg_ctx* h, double rms, int restart, hipStream_t s) {
   const size_t nd = h->ndof;
   DGData<double>& d = h->dg[0].d;
-  precondition(h, rms, s);  // z = M r
-  hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart, s);
-  hpmg::krylov_update_p(nd, h->z, h->pv, h->scal, s);
+  float* r32_next = nullptr;
+  switch (h->opt.precision) {
+    case HPMG_PREC_F32:
+      if (restart) hpmg::cast_down<float>(nd, h->r, h->r32, nullptr, 1.0, s);
+      vcycle_dg<float>(h, 0, h->z32, h->r32, true, s);
+      hpmg::krylov_dot_lowz<float>(nd, h->z32, 0, 1.0, h->r, h->rold, h->partial, h->scal, restart, s);
+      hpmg::krylov_update_p_lowz<float>(nd, h->z32, 0, 1.0, h->pv, h->scal, s);
+      r32_next = h->r32;
+      break;
+    case HPMG_PREC_F16:
+      hpmg::cast_down<_Float16>(nd, h->r, h->r16, h->scal, rms, s);
+      vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, s);
+      hpmg::krylov_dot_lowz<_Float16>(nd, h->z16, 1, rms, h->r, h->rold, h->partial, h->scal, restart, s);
+      hpmg::krylov_update_p_lowz<_Float16>(nd, h->z16, 1, rms, h->pv, h->scal, s);
+      break;
+    case HPMG_PREC_BF16:
+      hpmg::cast_down<__bf16>(nd, h->r, h->rb16, h->scal, rms, s);
+      vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, s);
+      hpmg::krylov_dot_lowz<__bf16>(nd, h->zb16, 1, rms, h->r, h->rold, h->partial, h->scal, restart, s);
+      hpmg::krylov_update_p_lowz<__bf16>(nd, h->zb16, 1, rms, h->pv, h->scal, s);
+      break;
+    default:
+      vcycle_dg<double>(h, 0, h->z, h->r, true, s);
+      hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart, s);
+      hpmg::krylov_update_p(nd, h->z, h->pv, h->scal, s);
+  }
   project<double>(h, 0, h->pv, d.tr[0], 1, s);  // q = A p
   apply<double>(h, 0, h->pv, d.tr[0], nullptr, h->q, 1, s);
   hpmg::krylov_dot(nd, h->pv, h->q, nullptr, h->partial, h->scal, 2, 0, 0, s);
-  hpmg::krylov_update_ur(nd, h->ug, h->r, h->rold, h->pv, h->q, h->partial, h->scal, s);
+  hpmg::krylov_update_ur(nd, h->ug, h->r, h->rold, h->pv, h->q, h->partial, h->scal, r32_next, s);
   HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
 }
 

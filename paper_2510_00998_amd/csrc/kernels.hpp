@@ -58,8 +58,18 @@ void krylov_dot(size_t n, const double* x, const double* y, const double* z, dou
                 int a0, int first, hipStream_t s);
 void krylov_update_p(size_t n, const double* z, double* p, const double* scal, hipStream_t s);
 void axpy(size_t n, double a, const double* x, double* y, hipStream_t s);
+// r32 (nullable): also store (float) r for the next FP32 cycle
 void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double* p, const double* q, double* partial,
-                      double* scal, hipStream_t s);
+                      double* scal, float* r32, hipStream_t s);
+// As krylov_dot (op 1) and krylov_update_p with z = zl * (scaled ? scal[8] / mul : 1),
+// read from a reduced-precision cycle's output.
+template <typename T>
+void krylov_dot_lowz(size_t n, const T* zl, int scaled, double mul, const double* r, const double* rold,
+                     double* partial, double* scal, int first, hipStream_t s);
+template <typename T>
+void krylov_update_p_lowz(size_t n, const T* zl, int scaled, double mul, double* p, const double* scal,
+                          hipStream_t s);
+// y = x * scal[7] * mul (scal null: y = x * mul)
 template <typename T>
 void cast_down(size_t n, const double* x, T* y, const double* scal, double mul, hipStream_t s);
 template <typename T>
