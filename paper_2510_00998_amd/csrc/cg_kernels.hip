@@ -19,19 +19,16 @@ __device__ __forceinline__ void vcoords(int v, int nv, int (&x)[3]) {
 
 // out = u + omega Dinv (b - A u)   (mode 0; u = 0 if uzero)
 // out = b - A u                    (mode 1)
-// The stencil is stored point-major, st[s * nv^d + v], so that a wave reads
-// each stencil point of its vertices with one coalesced load.  Neighbour
-// indices are clamped into the grid instead of skipped: the stencil entry of
-// a neighbour outside the interior is zero, and the loads of a thread are
-// independent of each other (issued back to back).
+// at vertex v (total = nv^d).  The stencil is stored point-major,
+// st[s * nv^d + v], so that a wave reads each stencil point of its vertices
+// with one coalesced load.  Neighbour indices are clamped into the grid
+// instead of skipped: the stencil entry of a neighbour outside the interior
+// is zero, and the loads of a thread are independent of each other.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict__ st, const T* __restrict__ dinv,
-                                                    const T* __restrict__ u, const T* __restrict__ b,
-                                                    T* __restrict__ out, T omega, int mode, int uzero) {
+__device__ __forceinline__ T cg_stencil_at(int v, int nv, int total, const T* __restrict__ st,
+                                           const T* __restrict__ dinv, const T* __restrict__ u,
+                                           const T* __restrict__ b, T omega, int mode, int uzero) {
   constexpr int NS = (D == 2) ? 9 : 27;
-  const int total = (D == 2) ? nv * nv : nv * nv * nv;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= total) return;
   T au = 0;
   if (!uzero) {
     int x[3];
@@ -54,10 +51,19 @@ __global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict_
   }
   if (mode == 0) {
     const T u0 = uzero ? T(0) : u[v];
-    out[v] = u0 + omega * dinv[v] * (b[v] - au);
-  } else {
-    out[v] = b[v] - au;
+    return u0 + omega * dinv[v] * (b[v] - au);
   }
+  return b[v] - au;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cg_stencil(int nv, const T* __restrict__ st, const T* __restrict__ dinv,
+                                                    const T* __restrict__ u, const T* __restrict__ b,
+                                                    T* __restrict__ out, T omega, int mode, int uzero) {
+  const int total = (D == 2) ? nv * nv : nv * nv * nv;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= total) return;
+  out[v] = cg_stencil_at<T, D>(v, nv, total, st, dinv, u, b, omega, mode, uzero);
 }
 
 // Fine interior indices and weights of a coarse vertex along one axis
@@ -73,16 +79,12 @@ __device__ __forceinline__ void axis_parents(const int* __restrict__ idx, const 
   }
 }
 
-// b_c = P^T r_f with the tensor-product 1D transfer: coarse interior index I
+// (P^T r_f)_v with the tensor-product 1D transfer: coarse interior index v
 // gathers up to RK = 2f - 1 fine interior indices ridx[RK I ..] per axis with
 // weights rw (f = 2 or 3: the coarsening factor).
 template <typename T, int D, int RK>
-__global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, const int* __restrict__ ridx,
-                                                     const T* __restrict__ rw, const T* __restrict__ rf,
-                                                     T* __restrict__ bc) {
-  const int total = (D == 2) ? nvc * nvc : nvc * nvc * nvc;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= total) return;
+__device__ __forceinline__ T cg_restrict_at(int v, int nvf, int nvc, const int* __restrict__ ridx,
+                                            const T* __restrict__ rw, const T* __restrict__ rf) {
   int x[3];
   vcoords<D>(v, nvc, x);
   constexpr int RZ = (D == 3) ? RK : 1;
@@ -103,18 +105,24 @@ __global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, const int
     for (int b2 = 0; b2 < RK; ++b2)
 #pragma unroll
       for (int a2 = 0; a2 < RK; ++a2) s += wz[c] * wy[b2] * wx[a2] * rf[ix[a2] + nvf * (iy[b2] + nvf * iz[c])];
-  bc[v] = s;
+  return s;
 }
 
-// u_f += P e_c: fine interior index i interpolates from up to two coarse
-// interior indices pidx[2i..2i+1] with weights pw.
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cg_prolong(int nvf, int nvc, const int* __restrict__ pidx,
-                                                    const T* __restrict__ pw, const T* __restrict__ ec,
-                                                    T* __restrict__ uf) {
-  const int total = (D == 2) ? nvf * nvf : nvf * nvf * nvf;
+template <typename T, int D, int RK>
+__global__ __launch_bounds__(256) void k_cg_restrict(int nvf, int nvc, const int* __restrict__ ridx,
+                                                     const T* __restrict__ rw, const T* __restrict__ rf,
+                                                     T* __restrict__ bc) {
+  const int total = (D == 2) ? nvc * nvc : nvc * nvc * nvc;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= total) return;
+  bc[v] = cg_restrict_at<T, D, RK>(v, nvf, nvc, ridx, rw, rf);
+}
+
+// (P e_c)_v: fine interior index v interpolates from up to two coarse
+// interior indices pidx[2v..2v+1] per axis with weights pw.
+template <typename T, int D>
+__device__ __forceinline__ T cg_prolong_at(int v, int nvf, int nvc, const int* __restrict__ pidx,
+                                           const T* __restrict__ pw, const T* __restrict__ ec) {
   int x[3];
   vcoords<D>(v, nvf, x);
   constexpr int RZ = (D == 3) ? 2 : 1;
@@ -135,7 +143,18 @@ __global__ __launch_bounds__(256) void k_cg_prolong(int nvf, int nvc, const int*
     for (int b2 = 0; b2 < 2; ++b2)
 #pragma unroll
       for (int a2 = 0; a2 < 2; ++a2) s += wz[c] * wy[b2] * wx[a2] * ec[ix[a2] + nvc * (iy[b2] + nvc * iz[c])];
-  uf[v] += s;
+  return s;
+}
+
+// u_f += P e_c
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cg_prolong(int nvf, int nvc, const int* __restrict__ pidx,
+                                                    const T* __restrict__ pw, const T* __restrict__ ec,
+                                                    T* __restrict__ uf) {
+  const int total = (D == 2) ? nvf * nvf : nvf * nvf * nvf;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= total) return;
+  uf[v] += cg_prolong_at<T, D>(v, nvf, nvc, pidx, pw, ec);
 }
 
 // Q1 right-hand side from the per-cell corner contributions of the
@@ -161,16 +180,87 @@ __global__ __launch_bounds__(256) void k_gather_corners(int n, const T* __restri
   bcg[v] = s;
 }
 
-// x = Ainv b on the coarsest level (dense FP64 inverse from a Cholesky
-// factorisation done at setup).
+// (Ainv b)_i on the coarsest level (dense FP64 inverse from a Cholesky
+// factorisation done at setup), four independent loads in flight.
+template <typename T>
+__device__ __forceinline__ T dense_at(int i, int m, const double* __restrict__ Ainv, const T* __restrict__ b) {
+  const double* row = Ainv + (size_t)i * m;
+  double s = 0.0;
+  int j = 0;
+  for (; j + 4 <= m; j += 4) {
+    const double a0 = row[j], a1 = row[j + 1], a2 = row[j + 2], a3 = row[j + 3];
+    const double b0 = (double)b[j], b1 = (double)b[j + 1], b2 = (double)b[j + 2], b3 = (double)b[j + 3];
+    s += a0 * b0;
+    s += a1 * b1;
+    s += a2 * b2;
+    s += a3 * b3;
+  }
+  for (; j < m; ++j) s += row[j] * (double)b[j];
+  return (T)s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_solve(int m, const double* __restrict__ Ainv, const T* __restrict__ b,
                                                      T* __restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  double s = 0.0;
-  for (int j = 0; j < m; ++j) s += Ainv[(size_t)i * m + j] * (double)b[j];
-  x[i] = (T)s;
+  x[i] = dense_at<T>(i, m, Ainv, b);
+}
+
+// The Q1 V-cycle below a level in one workgroup: every level from lv[0]
+// down is small (a few thousand vertices), so the workgroup's barriers
+// replace kernel boundaries between the Jacobi, residual, restriction,
+// coarsest-solve and prolongation steps.  Same steps, order and per-vertex
+// arithmetic as the level-by-level launches; every level is entered with a
+// zero initial guess, so after the pre-smoothing u[nu_pre & 1] holds the
+// iterate and after the post-smoothing u[(nu_pre + nu_post) & 1].
+template <typename T, int D, int RK>
+__global__ __launch_bounds__(1024) void k_cg_vcycle_block(CGBlockArgs<T> a) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int cpre = a.nu_pre & 1;
+  for (int l = 0; l + 1 < a.nlev; ++l) {
+    const CGBlockLevel<T>& L = a.lv[l];
+    const int total = (D == 2) ? L.nv * L.nv : L.nv * L.nv * L.nv;
+    int c = 0, zero = 1;
+    for (int i = 0; i < a.nu_pre; ++i) {
+      for (int v = tid; v < total; v += nt)
+        L.u[c ^ 1][v] = cg_stencil_at<T, D>(v, L.nv, total, L.st, L.dinv, L.u[c], L.b, a.omega, 0, zero);
+      __syncthreads();
+      c ^= 1;
+      zero = 0;
+    }
+    if (zero) {
+      for (int v = tid; v < total; v += nt) L.u[c][v] = T(0);
+      __syncthreads();
+    }
+    for (int v = tid; v < total; v += nt)
+      L.r[v] = cg_stencil_at<T, D>(v, L.nv, total, L.st, L.dinv, L.u[c], L.b, a.omega, 1, 0);
+    __syncthreads();
+    const CGBlockLevel<T>& C = a.lv[l + 1];
+    const int totc = (D == 2) ? C.nv * C.nv : C.nv * C.nv * C.nv;
+    for (int v = tid; v < totc; v += nt) C.b[v] = cg_restrict_at<T, D, RK>(v, L.nv, C.nv, L.ridx, L.rw, L.r);
+    __syncthreads();
+  }
+  {
+    const CGBlockLevel<T>& L = a.lv[a.nlev - 1];
+    for (int i = tid; i < a.m; i += nt) L.u[0][i] = dense_at<T>(i, a.m, a.Ainv, L.b);
+    __syncthreads();
+  }
+  for (int l = a.nlev - 2; l >= 0; --l) {
+    const CGBlockLevel<T>& L = a.lv[l];
+    const CGBlockLevel<T>& C = a.lv[l + 1];
+    const int total = (D == 2) ? L.nv * L.nv : L.nv * L.nv * L.nv;
+    const T* ec = C.u[l + 2 == a.nlev ? 0 : (a.nu_pre + a.nu_post) & 1];
+    int c = cpre;
+    for (int v = tid; v < total; v += nt) L.u[c][v] += cg_prolong_at<T, D>(v, L.nv, C.nv, L.pidx, L.pw, ec);
+    __syncthreads();
+    for (int i = 0; i < a.nu_post; ++i) {
+      for (int v = tid; v < total; v += nt)
+        L.u[c ^ 1][v] = cg_stencil_at<T, D>(v, L.nv, total, L.st, L.dinv, L.u[c], L.b, a.omega, 0, 0);
+      __syncthreads();
+      c ^= 1;
+    }
+  }
 }
 
 template <typename T>
@@ -406,6 +496,19 @@ void dense_solve(int m, const double* Ainv, const T* b, T* x, hipStream_t s) {
 }
 
 template <typename T>
+void cg_vcycle_block(int D, int rk, const CGBlockArgs<T>& a, hipStream_t s) {
+  const dim3 g(1), t(1024);
+  if (D == 2 && rk == 3)
+    hipLaunchKernelGGL((k_cg_vcycle_block<T, 2, 3>), g, t, 0, s, a);
+  else if (D == 2)
+    hipLaunchKernelGGL((k_cg_vcycle_block<T, 2, 5>), g, t, 0, s, a);
+  else if (rk == 3)
+    hipLaunchKernelGGL((k_cg_vcycle_block<T, 3, 3>), g, t, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_cg_vcycle_block<T, 3, 5>), g, t, 0, s, a);
+}
+
+template <typename T>
 void fill(T* x, size_t n, T v, hipStream_t s) {
   unsigned g = nblocks(n);
   if (g > 8192) g = 8192;
@@ -477,6 +580,7 @@ template void cast_up<__bf16>(size_t, const __bf16*, double*, const double*, dou
   template void cg_prolong<T>(int, int, int, const int*, const T*, const T*, T*, hipStream_t);                 \
   template void gather_corners<T>(int, int, const T*, T*, hipStream_t);                                        \
   template void dense_solve<T>(int, const double*, const T*, T*, hipStream_t);                                 \
+  template void cg_vcycle_block<T>(int, int, const CGBlockArgs<T>&, hipStream_t);                              \
   template void fill<T>(T*, size_t, T, hipStream_t);
 HPMG_INST(float)
 HPMG_INST(double)

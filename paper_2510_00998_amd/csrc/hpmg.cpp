@@ -456,6 +456,27 @@ void vcycle_cg(hpmg_ctx* h, int m, bool uzero, hipStream_t s) {
     return;
   }
   const T w = (T)h->opt.omega_cg;
+  const int nlev = (int)h->cg.size() - m;
+  if (uzero && L.size <= (size_t)hpmg::CG_BLOCK_MAX_VERTICES && nlev <= hpmg::CG_BLOCK_MAX_LEVELS) {
+    // this level and all coarser ones are small: the rest of the cycle in
+    // one workgroup
+    hpmg::CGBlockArgs<T> a{};
+    a.nlev = nlev;
+    a.nu_pre = h->opt.nu_pre;
+    a.nu_post = h->opt.nu_post;
+    a.m = h->coarse_m;
+    a.omega = w;
+    a.Ainv = h->coarse_inv;
+    for (int k = 0; k < nlev; ++k) {
+      CGLevel& Lk = h->cg[m + k];
+      CGData<T>& dk = data<T>(Lk);
+      a.lv[k] = {Lk.nv, dk.st, dk.dinv, {dk.u[0], dk.u[1]}, dk.b, dk.r, Lk.ridx, dk.rw, Lk.pidx, dk.pw};
+      Lk.cur = k + 1 == nlev ? 0 : (h->opt.nu_pre + h->opt.nu_post) & 1;
+    }
+    hpmg::cg_vcycle_block<T>(D, L.rk, a, s);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   int cur = 0;
   bool zero = uzero;
   for (int i = 0; i < h->opt.nu_pre; ++i) {

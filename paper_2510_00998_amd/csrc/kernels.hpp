@@ -53,6 +53,34 @@ void dense_solve(int m, const double* Ainv, const T* b, T* x, hipStream_t s);
 template <typename T>
 void fill(T* x, size_t n, T v, hipStream_t s);
 
+// The Q1 V-cycle from level lv[0] (entered with a zero initial guess, its
+// right-hand side in lv[0].b) down to the coarsest level lv[nlev - 1]
+// (dense solve with Ainv, m unknowns), in one workgroup.
+constexpr int CG_BLOCK_MAX_LEVELS = 8;
+constexpr int CG_BLOCK_MAX_VERTICES = 512;  // largest level taken by the one-workgroup cycle
+template <typename T>
+struct CGBlockLevel {
+  int nv;
+  const T* st;
+  const T* dinv;
+  T* u[2];
+  T* b;
+  T* r;
+  const int* ridx;  // restriction to the next level (RK slots per coarse vertex and axis)
+  const T* rw;
+  const int* pidx;  // prolongation from the next level (2 slots per vertex and axis)
+  const T* pw;
+};
+template <typename T>
+struct CGBlockArgs {
+  int nlev, nu_pre, nu_post, m;
+  T omega;
+  const double* Ainv;
+  CGBlockLevel<T> lv[CG_BLOCK_MAX_LEVELS];
+};
+template <typename T>
+void cg_vcycle_block(int D, int rk, const CGBlockArgs<T>& a, hipStream_t s);
+
 constexpr int KRYLOV_RED_BLOCKS = 1024;
 void krylov_dot(size_t n, const double* x, const double* y, const double* z, double* partial, double* scal, int op,
                 int a0, int first, hipStream_t s);
