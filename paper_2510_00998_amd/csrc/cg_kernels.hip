@@ -365,6 +365,16 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   }
 }
 
+// alpha = rho / p.q from the per-block shares of p.q: s[5] = s[2] / sum
+__global__ __launch_bounds__(256) void k_finalize_alpha(const double* __restrict__ partial, int n,
+                                                        double* __restrict__ s) {
+  __shared__ double sh[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += partial[i];
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) s[5] = s[2] / t;
+}
+
 // y += a x
 __global__ __launch_bounds__(256) void k_axpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -521,6 +531,10 @@ void krylov_dot(size_t n, const double* x, const double* y, const double* z, dou
   const unsigned g = gs_blocks(n);
   hipLaunchKernelGGL(k_dot2, dim3(g), dim3(256), 0, s, n, x, y, z, partial);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, (int)g, scal, op, a0, first);
+}
+
+void krylov_alpha(const double* partial, int n, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_alpha, dim3(1), dim3(256), 0, s, partial, n, scal);
 }
 
 void axpy(size_t n, double a, const double* x, double* y, hipStream_t s) {

@@ -37,12 +37,16 @@ namespace hpmg {
 #define HPMG_CPB3D_N 0
 #define HPMG_CPB3D 0
 #endif
+__host__ __device__ constexpr int cells_per_block(int D, int N) {
+  return (D == 3 && N == HPMG_CPB3D_N) ? HPMG_CPB3D
+                                       : ((256 / (D == 2 ? N : N * N)) > 0 ? (256 / (D == 2 ? N : N * N)) : 1);
+}
 template <int D, int N>
 struct DGShape {
   static constexpr int L = (D == 2) ? N : N * N;  // lines per cell = nodes per facet
   static constexpr int NV = L * N;                // nodes per cell
   static constexpr int NF = 2 * D;                // facets per cell
-  static constexpr int CPB = (D == 3 && N == HPMG_CPB3D_N) ? HPMG_CPB3D : ((256 / L) > 0 ? (256 / L) : 1);
+  static constexpr int CPB = cells_per_block(D, N);
   static constexpr int NT = CPB * L;
   static constexpr int BLOCK = (NT + 63) / 64 * 64;  // launch bound: whole waves
   static constexpr int EGS = 2 * N * N + N;       // S, Si, lambda of one direction
@@ -106,6 +110,17 @@ struct DGArgs {
   long long vstride;   // per right-hand side stride of cell vectors
   long long tstride;   // per right-hand side stride of trace buffers
   long long cstride;   // per right-hand side stride of coarse vectors
+  // Fusions of the outer FP64 Krylov iteration into the finest-level
+  // kernels (one right-hand side, NC = 0, T = double):
+  //   kry = 1 (projection): first p = z + beta p in place (u_in = u_out = p),
+  //     z of type zkind (hpmg_dtype code) at zlow, read as
+  //     z * (zscaled ? kscal[8] / kmul : 1), beta = kscal[3]
+  //   kdot = 1 (apply, y = A p): kpartial[block] = the block's share of p.y
+  int kry = 0, kdot = 0, zkind = 0, zscaled = 0;
+  const void* zlow = nullptr;
+  const double* kscal = nullptr;
+  double kmul = 1.0;
+  double* kpartial = nullptr;
 };
 
 template <typename T, int D, int N> void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s);

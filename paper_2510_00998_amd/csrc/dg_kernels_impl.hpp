@@ -13,6 +13,8 @@
 // Seven barriers; the facet traces are written by each cell for its own
 // interior facets and read once by the neighbour in the next sweep.
 #pragma once
+#include <type_traits>
+
 #include "dg_kernels.hpp"
 
 namespace hpmg {
@@ -440,6 +442,29 @@ __device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, co
   }
 }
 
+// z_j of the Krylov projection (see DGArgs::kry), read by its storage type.
+__device__ __forceinline__ double krylov_z(const DGArgs<double>& a, size_t i, double sc) {
+  switch (a.zkind) {
+    case 1: return (double)((const float*)a.zlow)[i] * sc;
+    case 2: return (double)(float)((const _Float16*)a.zlow)[i] * sc;
+    case 3: return (double)(float)((const __bf16*)a.zlow)[i] * sc;
+    default: return ((const double*)a.zlow)[i] * sc;
+  }
+}
+
+// Sum of v over the block, written by thread 0 to out (sh: one double per wave).
+__device__ __forceinline__ void block_partial(double v, double* sh, double* out) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) s += sh[i];
+    *out = s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fused block-Jacobi sweep.  UZERO: u is identically zero on entry (first
 // sweep of a coarse-level smoothing with zero initial guess): u and the
@@ -612,6 +637,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
     }
   }
   flux_fields<T, D, N, VARK>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+  double pdot = 0.0;  // share of p.(A p) (kdot)
 
   // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
   // lifts added right after each axis is transformed back.
@@ -670,6 +696,10 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
           C* dst = a.out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
           for (int j = 0; j < N; ++j) dst[j] = t[j];
+          if constexpr (std::is_same<T, double>::value && !RESID) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) pdot += ul[j] * t[j];
+          }
         } else {
 #pragma unroll
           for (int j = 0; j < N; ++j) sW[base + j] = t[j];
@@ -680,6 +710,12 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       }
     }
     if (k > 0 || NC > 0) __syncthreads();
+  }
+  if constexpr (std::is_same<T, double>::value && NC == 0 && !RESID) {
+    if (a.kdot) {
+      __shared__ double sh[16];
+      block_partial(pdot, sh, a.kpartial + bx);
+    }
   }
   if constexpr (NC > 0) {
     // restriction (E^T)^(x d) of the cell residual, one axis per pass; sNB
@@ -792,9 +828,24 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
 
   C u[N];
   if (act) {
-    const T* us = a.u_in + rv + (size_t)c0 * Sh::NV + cl * Sh::NV + line_base<D, N>(0, ln);
+    const size_t off = rv + (size_t)c0 * Sh::NV + cl * Sh::NV + line_base<D, N>(0, ln);
+    const T* us = a.u_in + off;
 #pragma unroll
     for (int j = 0; j < N; ++j) u[j] = us[j];
+    if constexpr (std::is_same<T, double>::value && NC == 0) {
+      if (a.kry) {  // p = z + beta p, in place
+        const double beta = a.kscal[3];
+        const double sc = a.zscaled ? a.kscal[8] / a.kmul : 1.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const double zj = krylov_z(a, off + j, sc);
+          u[j] = beta == 0.0 ? zj : zj + beta * u[j];
+        }
+        T* uo = a.u_out + off;
+#pragma unroll
+        for (int j = 0; j < N; ++j) uo[j] = u[j];
+      }
+    }
   }
   if constexpr (NC > 0) {
     const C* cs = a.coarse + (size_t)by * a.cstride;

@@ -674,42 +674,72 @@ double fp64_residual(hpmg_ctx* h, const double* u, const double* b, hipStream_t 
 // One outer FCG iteration on the internal vectors (ug, r, rold, pv, q and
 // the cycle's z) enqueued on s, ending with the copy of the scalars to the
 // pinned host buffer; restart = 1 takes beta = 0.  A reduced-precision
-// cycle's z is read where it lies (the dots and the update of p convert it);
-// the FP32 cycle takes r unscaled, cast by the previous iteration's update
-// (after a restart: by a cast here), the 16-bit cycles take r scaled to
-// mean square lambda.
+// cycle's z is read where it lies (the dots convert it, and the projection
+// kernel forms p = z + beta p while it projects p onto its traces); the FP32
+// cycle takes r unscaled, cast by the previous iteration's update (after a
+// restart: by a cast here), the 16-bit cycles take r scaled to mean square
+// lambda.  The apply q = A p leaves per-block shares of p.q for alpha.
 void fcg_iteration(hpmg_ctx* h, double rms, int restart, hipStream_t s) {
   const size_t nd = h->ndof;
-  DGData<double>& d = h->dg[0].d;
+  DGLevel& L0 = h->dg[0];
+  DGData<double>& d = L0.d;
   float* r32_next = nullptr;
+  const void* zl = h->z;
+  int zkind = HPMG_F64, scaled = 0;
+  double mul = 1.0;
   switch (h->opt.precision) {
     case HPMG_PREC_F32:
       if (restart) hpmg::cast_down<float>(nd, h->r, h->r32, nullptr, 1.0, s);
       vcycle_dg<float>(h, 0, h->z32, h->r32, true, s);
       hpmg::krylov_dot_lowz<float>(nd, h->z32, 0, 1.0, h->r, h->rold, h->partial, h->scal, restart, s);
-      hpmg::krylov_update_p_lowz<float>(nd, h->z32, 0, 1.0, h->pv, h->scal, s);
       r32_next = h->r32;
+      zl = h->z32;
+      zkind = HPMG_F32;
       break;
     case HPMG_PREC_F16:
       hpmg::cast_down<_Float16>(nd, h->r, h->r16, h->scal, rms, s);
       vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, s);
       hpmg::krylov_dot_lowz<_Float16>(nd, h->z16, 1, rms, h->r, h->rold, h->partial, h->scal, restart, s);
-      hpmg::krylov_update_p_lowz<_Float16>(nd, h->z16, 1, rms, h->pv, h->scal, s);
+      zl = h->z16;
+      zkind = HPMG_F16;
+      scaled = 1;
+      mul = rms;
       break;
     case HPMG_PREC_BF16:
       hpmg::cast_down<__bf16>(nd, h->r, h->rb16, h->scal, rms, s);
       vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, s);
       hpmg::krylov_dot_lowz<__bf16>(nd, h->zb16, 1, rms, h->r, h->rold, h->partial, h->scal, restart, s);
-      hpmg::krylov_update_p_lowz<__bf16>(nd, h->zb16, 1, rms, h->pv, h->scal, s);
+      zl = h->zb16;
+      zkind = HPMG_BF16;
+      scaled = 1;
+      mul = rms;
       break;
     default:
       vcycle_dg<double>(h, 0, h->z, h->r, true, s);
       hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart, s);
-      hpmg::krylov_update_p(nd, h->z, h->pv, h->scal, s);
   }
-  project<double>(h, 0, h->pv, d.tr[0], 1, s);  // q = A p
-  apply<double>(h, 0, h->pv, d.tr[0], nullptr, h->q, 1, s);
-  hpmg::krylov_dot(nd, h->pv, h->q, nullptr, h->partial, h->scal, 2, 0, 0, s);
+  // p = z + beta p and its traces in one pass
+  hpmg::DGArgs<double> pa = dg_args<double>(h, L0);
+  pa.u_in = h->pv;
+  pa.u_out = h->pv;
+  pa.tr_out = d.tr[0];
+  pa.kry = 1;
+  pa.zkind = zkind;
+  pa.zlow = zl;
+  pa.zscaled = scaled;
+  pa.kscal = h->scal;
+  pa.kmul = mul;
+  dg_run(h, hpmg::OP_PROJECT, pa, L0.N, 1, 0, s);
+  // q = A p with the per-block shares of p.q, then alpha
+  hpmg::DGArgs<double> aa = dg_args<double>(h, L0);
+  aa.u_in = h->pv;
+  aa.tr_in = d.tr[0];
+  aa.out = h->q;
+  aa.kdot = 1;
+  aa.kpartial = h->kpartial;
+  dg_run(h, hpmg::OP_APPLY, aa, L0.N, 1, 0, s);
+  const int cpb = hpmg::cells_per_block(h->dim, L0.N);
+  hpmg::krylov_alpha(h->kpartial, (h->ncell + cpb - 1) / cpb, h->scal, s);
   hpmg::krylov_update_ur(nd, h->ug, h->r, h->rold, h->pv, h->q, h->partial, h->scal, r32_next, s);
   HIPCHK(hipMemcpyAsync(h->host_scal, h->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
 }
@@ -850,6 +880,7 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     h->r32 = (float*)h->mem.alloc(nd * sizeof(float));
     h->z32 = (float*)h->mem.alloc(nd * sizeof(float));
     h->partial = (double*)h->mem.alloc(2 * hpmg::KRYLOV_RED_BLOCKS * sizeof(double));
+    h->kpartial = (double*)h->mem.alloc((size_t)h->ncell * sizeof(double));
     h->scal = (double*)h->mem.alloc(16 * sizeof(double));
     HIPCHK(hipHostMalloc((void**)&h->host_scal, 16 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipStreamSynchronize(stream));

@@ -134,6 +134,7 @@ struct hpmg_ctx {
   _Float16 *r16 = nullptr, *z16 = nullptr;  // 16-bit cycle vectors (on first use)
   __bf16 *rb16 = nullptr, *zb16 = nullptr;
   double *partial = nullptr, *scal = nullptr;
+  double* kpartial = nullptr;  // per-block shares of p.q (one per finest-level cell at most)
   double* host_scal = nullptr;  // pinned
   // which level-0 trace buffer holds the traces of the caller's u after
   // hpmg_project / hpmg_smooth / hpmg_sweep (-1: none), per dtype

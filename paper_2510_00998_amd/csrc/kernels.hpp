@@ -85,6 +85,8 @@ constexpr int KRYLOV_RED_BLOCKS = 1024;
 void krylov_dot(size_t n, const double* x, const double* y, const double* z, double* partial, double* scal, int op,
                 int a0, int first, hipStream_t s);
 void krylov_update_p(size_t n, const double* z, double* p, const double* scal, hipStream_t s);
+// scal[5] = scal[2] / (sum of partial[0..n)): alpha from per-block shares of p.q
+void krylov_alpha(const double* partial, int n, double* scal, hipStream_t s);
 void axpy(size_t n, double a, const double* x, double* y, hipStream_t s);
 // r32 (nullable): also store (float) r for the next FP32 cycle
 void krylov_update_ur(size_t n, double* u, double* r, double* rold, const double* p, const double* q, double* partial,
