@@ -78,6 +78,15 @@ __device__ __forceinline__ float recip(float d) {
   return __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
 }
 
+// Load scheme of the neighbour traces in the constant-kappa sweep: issued
+// all at once (facet_pass0_const) except for the FP64 degree-4 sweep, which
+// measured faster with the traces read item after item (the apply kernels
+// always issue them at once).
+template <typename T, int N>
+constexpr bool batched_trace_loads() {
+  return !(sizeof(T) == 8 && N == 5);
+}
+
 // Thread index within the block's NT working threads; threads beyond NT
 // (a batched launch uses one block size for every degree) get an index past
 // every work range, so they only take part in the barriers.
@@ -96,6 +105,17 @@ template <int D, int N, bool VARK>
 struct EigLDS {
   static constexpr int SIZE = VARK ? DGShape<D, N>::CPB * D * DGShape<D, N>::EGS : 4 * DGShape<D, N>::EGS;
 };
+
+// Boundary masks of the block's cells in LDS, right after the kappa_F
+// entries (read by the facet passes that follow a barrier).
+template <int D, int N, bool VARK, typename C>
+__device__ __forceinline__ int* mask_lds(C* sKF) {
+  return (int*)(sKF + (VARK ? DGShape<D, N>::CPB * DGShape<D, N>::NF : 1));
+}
+template <int D, int N, bool VARK, typename C>
+__device__ __forceinline__ const int* mask_lds(const C* sKF) {
+  return (const int*)(sKF + (VARK ? DGShape<D, N>::CPB * DGShape<D, N>::NF : 1));
+}
 
 // Stage the eigendata (and, per cell, kappa_F of every facet; 0 on the
 // boundary) of the block's cells.
@@ -217,11 +237,11 @@ __device__ __forceinline__ int tangential(int k, int pass) {
 // T_f = G_t1 x G_t2 over the tangential axes with G_t = Si_t for t < k
 // (axes already transformed when facet k is processed) and Mhat otherwise.
 // sNB[cl][f][F1|F2][L].  Pass 0 reads the neighbour traces (FROM_GLOBAL:
-// straight from the trace buffer, else from the plain LDS copy) and
-// transforms along t1; pass 1 transforms along t2 (3D).  Work items are
+// straight from the trace buffer, item after item; else from the plain LDS
+// copy) and transforms along t1; pass 1 transforms along t2 (3D).  Work items are
 // ordered (facet, cell, line) so that a wave mostly sees one facet
 // direction and therefore one matrix.
-template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL>
+template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL = false>
 __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int c0, int nc, int pass, CT<T>* sNB,
                                            const CT<T>* sE, const CT<T>* sKF) {
   using C = CT<T>;
@@ -241,7 +261,7 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
     const int st = pass == 0 ? 1 : N;  // node stride along t within the facet
     const int lo = pass == 0 ? N * li : li;
     C* g = sNB + (cl * Sh::NF + f) * TL + lo;
-    const int mask = a.bmask[c];
+    const int mask = FROM_GLOBAL ? a.bmask[c] : mask_lds<D, N, VARK>(sKF)[cl];
     C x1[N], x2[N], o1[N], o2[N];
     if (pass == 0) {
       if ((mask >> f) & 1) {  // boundary facet: no neighbour, zero flux fields
@@ -301,6 +321,97 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
   }
 }
 
+// Pass 0 for constant kappa with every global load of the thread issued
+// before the first use of any of them: the class tables, the boundary masks
+// of its items' cells and the neighbour traces (neighbour index clamped into
+// the mesh, boundary facets zeroed by a select afterwards), so that the
+// block waits for memory once.  Stages the class tables in sE.
+template <typename T, int D, int N>
+__device__ __forceinline__ void facet_pass0_const(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB,
+                                                  CT<T>* sE, int* sMask) {
+  using C = CT<T>;
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  constexpr int L = Sh::L;
+  constexpr int TL = 2 * L;
+  constexpr int LINES = (D == 2) ? 1 : N;
+  constexpr int ITEMS = Sh::CPB * Sh::NF * LINES;
+  constexpr int IT = (ITEMS + Sh::NT - 1) / Sh::NT;
+  constexpr int NE = 4 * Sh::EGS;
+  constexpr int IE = (NE + Sh::NT - 1) / Sh::NT;
+  const int tid = work_tid<D, N>();
+  const cptr<C> Mh = as_const(a.ref) + RefOff<N>::M;
+  C ev[IE];
+#pragma unroll
+  for (int m = 0; m < IE; ++m) {
+    const int i = tid + m * Sh::NT;
+    ev[m] = i < NE ? a.eig[i] : C(0);
+  }
+  // no branches around the loads: an item past the block's work reads the
+  // first word of the trace buffer (one cache line for all such lanes)
+  C gv[IT][N], qv[IT][N];
+  int msk[IT];
+#pragma unroll
+  for (int m = 0; m < IT; ++m) {
+    const int i = tid + m * Sh::NT;
+    const int f = min(i / (Sh::CPB * LINES), Sh::NF - 1), rem = i % (Sh::CPB * LINES);
+    const int cl = rem / LINES, li = rem % LINES;
+    const bool valid = i < ITEMS && cl < nc;
+    const int c = c0 + (valid ? cl : 0);
+    const int stc = ipow<D>(a.n, f >> 1);
+    const int nb = min(max((f & 1) ? c + stc : c - stc, 0), a.ncell - 1);
+    const T* src = valid ? tr + ((size_t)(f ^ 1) * a.ncell + nb) * TL + N * li : tr;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      gv[m][j] = src[j];
+      qv[m][j] = src[L + j];
+    }
+    msk[m] = a.bmask[c];
+  }
+  const int cmask = a.bmask[c0 + min(tid, nc - 1)];
+  // keep every use of the loaded values below this point, so that the
+  // compiler does not wait for one item's data before issuing the next loads
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int m = 0; m < IE; ++m) {
+    const int i = tid + m * Sh::NT;
+    if (i < NE) sE[i] = ev[m];
+  }
+  if (tid < nc) sMask[tid] = cmask;
+#pragma unroll
+  for (int m = 0; m < IT; ++m) {
+    const int i = tid + m * Sh::NT;
+    const int f = i / (Sh::CPB * LINES), rem = i % (Sh::CPB * LINES);
+    const int cl = rem / LINES, li = rem % LINES;
+    if (!(i < ITEMS && cl < nc)) continue;
+    const int k = f >> 1;
+    const int t = tangential<D>(k, 0);
+    const bool bdy = (msk[m] >> f) & 1;
+    const C kf = a.kappa_const;
+    C x1[N], x2[N], o1[N], o2[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const C g = bdy ? C(0) : gv[m][j];
+      const C q = bdy ? C(0) : qv[m][j];
+      x1[j] = kf * (C(0.5) * q - a.sigma_hat * g);
+      x2[j] = C(0.5) * kf * g;
+    }
+    if (t < k) {
+      stage_mv<T, D, N, false, false, false>(a, sE, cl, msk[m], t, NN, x1, o1);
+      stage_mv<T, D, N, false, false, false>(a, sE, cl, msk[m], t, NN, x2, o2);
+    } else {
+      mv<N, false>(Mh, x1, o1);
+      mv<N, false>(Mh, x2, o2);
+    }
+    C* g = sNB + (cl * Sh::NF + f) * TL + N * li;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      g[j] = o1[j];
+      g[L + j] = o2[j];
+    }
+  }
+}
+
 // Plain copy of the neighbour traces into sNB (variable kappa path, whose
 // facet transform needs the staged per-cell eigendata).  Element i of the
 // block is (facet f, cell cl, entry e), i = (f CPB + cl) 2L + e; all loads of
@@ -336,26 +447,32 @@ __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const 
   }
 }
 
-// All facet flux fields of the block in sNB, and the eigendata in sE; ends
-// with a barrier.
-template <typename T, int D, int N, bool VARK>
+// All facet flux fields of the block in sNB, the eigendata in sE and the
+// boundary masks of the block's cells in LDS; ends with a barrier.
+template <typename T, int D, int N, bool VARK, bool AT_ONCE = true>
 __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB, CT<T>* sE, CT<T>* sKF) {
-  using C = CT<T>;
-  if constexpr (!VARK) {
+  int* sMask = mask_lds<D, N, VARK>(sKF);
+  const int tid = work_tid<D, N>();
+  if constexpr (!VARK && AT_ONCE) {
+    facet_pass0_const<T, D, N>(a, tr, c0, nc, sNB, sE, sMask);
+    __syncthreads();
+  } else if constexpr (!VARK) {
     facet_pass<T, D, N, false, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
     load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
+    if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
     __syncthreads();
   } else {
     copy_neighbour_traces<T, D, N>(a, tr, c0, nc, sNB);
     load_eig<T, D, N, true>(a, c0, nc, sE, sKF);
+    if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
     __syncthreads();
     make_si<T, D, N>(a, nc, sE);
     __syncthreads();
-    facet_pass<T, D, N, true, false>(a, tr, c0, nc, 0, sNB, sE, sKF);
+    facet_pass<T, D, N, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
     __syncthreads();
   }
   if constexpr (D == 3) {
-    facet_pass<T, D, N, VARK, false>(a, tr, c0, nc, 1, sNB, sE, sKF);
+    facet_pass<T, D, N, VARK>(a, tr, c0, nc, 1, sNB, sE, sKF);
     __syncthreads();
   }
 }
@@ -476,7 +593,8 @@ constexpr int cell_lds_bytes() {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
   return (int)sizeof(C) *
-         (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK>::SIZE + (VARK ? Sh::CPB * Sh::NF : 1));
+         (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK>::SIZE + (VARK ? Sh::CPB * Sh::NF : 1)) +
+         (int)sizeof(int) * Sh::CPB;
 }
 
 template <typename T, int D, int N, bool UZERO, bool VARK>
@@ -512,7 +630,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
     }
   }
   if (!UZERO) {
-    flux_fields<T, D, N, VARK>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+    flux_fields<T, D, N, VARK, batched_trace_loads<T, N>()>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   } else {
     load_eig<T, D, N, VARK>(a, c0, nc, sE, sKF);
     __syncthreads();
@@ -789,8 +907,15 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   }
 }
 
+// Apply holds u, b and the neighbour traces in registers at once; for the
+// FP64 degree-4 instances at most 128 VGPRs (four waves per SIMD, no spills).
+template <typename T, int N>
+constexpr int apply_waves_per_eu() {
+  return (sizeof(T) == 8 && N <= 5) ? 4 : 1;
+}
 template <typename T, int D, int N, int NC, bool RESID, bool VARK>
-__global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_apply(DGArgs<T> a) {
+__global__ __launch_bounds__((DGShape<D, N>::BLOCK))
+__attribute__((amdgpu_waves_per_eu(apply_waves_per_eu<T, N>()))) void k_apply(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
   apply_body<T, D, N, NC, RESID, VARK>(a, blockIdx.x, blockIdx.y, lds);
 }
