@@ -60,6 +60,63 @@ __device__ __forceinline__ void mv(P G, const T (&in)[N], T (&out)[N]) {
   }
 }
 
+// Even-odd forms of the products with the interior-class matrices, whose
+// columns (S) or rows (Si = S^T Mhat) are mirror-even for the first
+// (N+1)/2 and mirror-odd for the last N/2 indices: entry A(i, c) is G[i N + c]
+// (S) or G[c N + i] (SI, i.e. Si accessed transposed), and
+// A(N-1-i, c) = +-A(i, c).  Forward: out[c] = sum_i A(i, c) in[i], from the
+// mirror sums and differences of in.  Inverse: out[i] = sum_c A(i, c) in[c],
+// as even part +- odd part.  About half the multiply-adds of mv.
+template <int N, bool SI, typename T, typename P>
+__device__ __forceinline__ T eo_at(P G, int i, int c) {
+  return SI ? G[c * N + i] : G[i * N + c];
+}
+template <int N, bool SI, typename T, typename P>
+__device__ __forceinline__ void mv_fwd_eo(P G, const T (&in)[N], T (&out)[N]) {
+  constexpr int H = N / 2, NE = (N + 1) / 2;
+  T e[H], o[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    e[i] = in[i] + in[N - 1 - i];
+    o[i] = in[i] - in[N - 1 - i];
+  }
+#pragma unroll
+  for (int c = 0; c < NE; ++c) {
+    T s = (N & 1) ? eo_at<N, SI, T>(G, H, c) * in[H] : T(0);
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += eo_at<N, SI, T>(G, i, c) * e[i];
+    out[c] = s;
+  }
+#pragma unroll
+  for (int c = NE; c < N; ++c) {
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) s += eo_at<N, SI, T>(G, i, c) * o[i];
+    out[c] = s;
+  }
+}
+template <int N, bool SI, typename T, typename P>
+__device__ __forceinline__ void mv_inv_eo(P G, const T (&in)[N], T (&out)[N]) {
+  constexpr int H = N / 2, NE = (N + 1) / 2;
+  T ev[NE], od[H > 0 ? H : 1];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    ev[i] = 0;
+#pragma unroll
+    for (int c = 0; c < NE; ++c) ev[i] += eo_at<N, SI, T>(G, i, c) * in[c];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    od[i] = 0;
+#pragma unroll
+    for (int c = NE; c < N; ++c) od[i] += eo_at<N, SI, T>(G, i, c) * in[c];
+  }
+  // out written in ascending order (as mv does), so that the stores of the
+  // alternative paths of stage_mv coincide index by index
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = i < H ? ev[i] + od[i] : (i == H && (N & 1) ? ev[H] : ev[N - 1 - i] - od[N - 1 - i]);
+}
+
 template <int D>
 __device__ __forceinline__ int ipow(int n, int k) {
   return k == 0 ? 1 : (k == 1 ? n : n * n);
@@ -197,11 +254,12 @@ __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, CT<T>* sE) {
 // lane of the wave needs the same boundary class the record is read from
 // the global class table with scalar loads; otherwise from the LDS copy
 // (LDS = true, after the block staged it) or per lane from global memory.
-template <typename T, int D, int N, bool VARK, bool TR, bool LDS = true>
-__device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const CT<T>* sE, int cl, int mask, int k, int off,
+template <typename T, int D, int N, bool VARK, bool TR, bool SIM, bool LDS = true>
+__device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const CT<T>* sE, int cl, int mask, int k,
                                          const CT<T> (&in)[N], CT<T> (&out)[N]) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
+  constexpr int off = SIM ? N * N : 0;  // S or Si within the S | Si | lambda record
   // matrices that fit in about 72 SGPRs take the scalar path
   constexpr bool SCALAR_OK = N * N * (int)sizeof(C) / 4 <= 72;
   if constexpr (VARK) {
@@ -214,7 +272,15 @@ __device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const CT<T>* sE, in
       c0 = __builtin_amdgcn_readfirstlane(cls);
       uni = __all(cls == c0);
     }
-    if (uni)
+    // interior class in FP32 arithmetic (bound by vector-ALU issue): even-odd
+    // forms; FP64 (bound by memory latency) keeps the plain products
+    if (uni && sizeof(C) == 4 && c0 == 0) {
+      const cptr<C> G = as_const(a.eig) + off;
+      if constexpr (TR != SIM)
+        mv_fwd_eo<N, SIM>(G, in, out);
+      else
+        mv_inv_eo<N, SIM>(G, in, out);
+    } else if (uni)
       mv<N, TR>(as_const(a.eig) + c0 * Sh::EGS + off, in, out);
     else if constexpr (LDS)
       mv<N, TR>(sE + cls * Sh::EGS + off, in, out);
@@ -307,8 +373,8 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
       }
     }
     if (t < k) {
-      stage_mv<T, D, N, VARK, false, !FROM_GLOBAL>(a, sE, cl, mask, t, NN, x1, o1);
-      stage_mv<T, D, N, VARK, false, !FROM_GLOBAL>(a, sE, cl, mask, t, NN, x2, o2);
+      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, mask, t, x1, o1);
+      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, mask, t, x2, o2);
     } else {
       mv<N, false>(Mh, x1, o1);
       mv<N, false>(Mh, x2, o2);
@@ -397,8 +463,8 @@ __device__ __forceinline__ void facet_pass0_const(const DGArgs<T>& a, const T* t
       x2[j] = C(0.5) * kf * g;
     }
     if (t < k) {
-      stage_mv<T, D, N, false, false, false>(a, sE, cl, msk[m], t, NN, x1, o1);
-      stage_mv<T, D, N, false, false, false>(a, sE, cl, msk[m], t, NN, x2, o2);
+      stage_mv<T, D, N, false, false, true, false>(a, sE, cl, msk[m], t, x1, o1);
+      stage_mv<T, D, N, false, false, true, false>(a, sE, cl, msk[m], t, x2, o2);
     } else {
       mv<N, false>(Mh, x1, o1);
       mv<N, false>(Mh, x2, o2);
@@ -655,7 +721,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
       if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
-      stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, 0, r, t);  // S^T
+      stage_mv<T, D, N, VARK, true, false>(a, sE, cl, mask, k, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
         const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
@@ -670,7 +736,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= recip(ls + E2[2 * NN + j]);
         }
-        stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, 0, t, r);  // S
+        stage_mv<T, D, N, VARK, false, false>(a, sE, cl, mask, k, t, r);  // S
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
       }
@@ -689,7 +755,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
       C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, 0, r, t);
+      stage_mv<T, D, N, VARK, false, false>(a, sE, cl, mask, k, r, t);
       if (k == 0) {
         T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
@@ -771,7 +837,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
-      stage_mv<T, D, N, VARK, false>(a, sE, cl, mask, k, NN, r, t);  // Si
+      stage_mv<T, D, N, VARK, false, true>(a, sE, cl, mask, k, r, t);  // Si
       if (k == D - 1) {
         const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
         const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
@@ -785,7 +851,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + E2[2 * NN + j]);
         }
-        stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, NN, t, r);  // Si^T
+        stage_mv<T, D, N, VARK, true, true>(a, sE, cl, mask, k, t, r);  // Si^T
         add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, r);
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
@@ -802,7 +868,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, true>(a, sE, cl, mask, k, NN, r, t);
+      stage_mv<T, D, N, VARK, true, true>(a, sE, cl, mask, k, r, t);
       add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, t);
       if (k == 0) {
 #pragma unroll

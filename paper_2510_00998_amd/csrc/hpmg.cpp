@@ -68,6 +68,59 @@ void eig_of(const hpmg::Basis1D& B, const std::vector<double>& L, double* S, dou
       throw HpmgError(HPMG_E_INVALID, "cell block is not positive definite (penalty too small?)");
 }
 
+// Eigendata of a 1D operator that commutes with the node mirror i -> N-1-i
+// (interior class with constant kappa: the Gauss-Lobatto and Gauss-Legendre
+// nodes are symmetric about 1/2, so Mhat, Khat and the two-facet terms are
+// centro-symmetric).  Its M-orthonormal eigenvectors split into mirror-even
+// and mirror-odd ones; each group is solved in its own subspace, so that
+// S = [even columns (N+1)/2 | odd columns N/2] holds the parity exactly:
+// S[N-1-i][c] = S[i][c] for even c and -S[i][c] for odd c (bitwise, rows i
+// and N-1-i are computed from identical data).  The kernels use this split
+// to apply S, S^T, Si and Si^T with about half the multiply-adds.
+void eig_even_odd(const hpmg::Basis1D& B, const std::vector<double>& L, double* S, double* lam) {
+  const int N = B.N, H = N / 2, NE = (N + 1) / 2;
+  const double r2 = std::sqrt(0.5);
+  std::fill(S, S + (size_t)N * N, 0.0);
+  for (int par = 0; par < 2; ++par) {
+    const int m = par == 0 ? NE : H;  // subspace dimension
+    if (m == 0) continue;
+    // basis Q (N x m) of the even (par 0) or odd (par 1) vectors
+    std::vector<double> Q((size_t)N * m, 0.0);
+    for (int j = 0; j < H; ++j) {
+      Q[(size_t)j * m + j] = r2;
+      Q[(size_t)(N - 1 - j) * m + j] = par == 0 ? r2 : -r2;
+    }
+    if (par == 0 && (N & 1)) Q[(size_t)H * m + H] = 1.0;
+    std::vector<double> Lr((size_t)m * m), Mr((size_t)m * m), Sr((size_t)m * m), lr(m);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) {
+        long double sl = 0.0L, sm = 0.0L;
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) {
+            const long double q = (long double)Q[(size_t)i * m + a] * Q[(size_t)j * m + b];
+            sl += q * L[(size_t)i * N + j];
+            sm += q * B.M[(size_t)i * N + j];
+          }
+        Lr[(size_t)a * m + b] = (double)sl;
+        Mr[(size_t)a * m + b] = (double)sm;
+      }
+    if (!hpmg::gen_sym_eig(Lr.data(), Mr.data(), m, Sr.data(), lr.data()))
+      throw HpmgError(HPMG_E_DEVICE, "mass matrix not positive definite");
+    const int c0 = par == 0 ? 0 : NE;
+    for (int c = 0; c < m; ++c) {
+      lam[c0 + c] = lr[c];
+      for (int i = 0; i < N; ++i) {
+        long double acc = 0.0L;
+        for (int a = 0; a < m; ++a) acc += (long double)Q[(size_t)i * m + a] * Sr[(size_t)a * m + c];
+        S[(size_t)i * N + c0 + c] = (double)acc;
+      }
+    }
+  }
+  for (int i = 0; i < N; ++i)
+    if (!(lam[i] > 0.0) || !std::isfinite(lam[i]))
+      throw HpmgError(HPMG_E_INVALID, "cell block is not positive definite (penalty too small?)");
+}
+
 void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg::Basis1D* Bnext,
                     hipStream_t s) {
   const int N = B.N, NN = N * N, D = h->dim;
@@ -106,13 +159,25 @@ void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg:
       double* S = &tab[(size_t)cls * EGS];
       double* Si = S + NN;
       double* lam = S + 2 * NN;
-      eig_of(B, Lm, S, lam);
+      if (cls == 0)
+        eig_even_odd(B, Lm, S, lam);
+      else
+        eig_of(B, Lm, S, lam);
       for (int r = 0; r < N; ++r)
         for (int c = 0; c < N; ++c) {
           double acc = 0.0;
           for (int m = 0; m < N; ++m) acc += S[m * N + r] * B.M[m * N + c];
           Si[r * N + c] = acc;
         }
+      if (cls == 0) {
+        // Si = S^T Mhat inherits the parity of the columns of S along its
+        // rows; make it exact (the two halves were summed in different order)
+        for (int r = 0; r < N; ++r) {
+          const double sg = r < (N + 1) / 2 ? 1.0 : -1.0;
+          for (int c = 0; c < N / 2; ++c) Si[r * N + N - 1 - c] = sg * Si[r * N + c];
+          if ((N & 1) && sg < 0) Si[r * N + N / 2] = 0.0;
+        }
+      }
     }
     L.d.eig = h->mem.upload(tab, s);
     L.f.eig = h->mem.upload(cast_vec<float>(tab), s);
