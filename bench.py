@@ -401,6 +401,20 @@ def main():
     if not vark:
         solves += ("mixed_f32_graph",)
     solver_of = {"fp64": g64, "mixed_f32": gmx, "mixed_f16": g16, "mixed_bf16": gb16}
+    # variable kappa: the same sweeps and mixed solve with the block inverse
+    # rebuilt in every traversal from kappa (no stored per-cell eigendata)
+    rc_in = {}
+    t_setup_rc = None
+    if vark:
+        t0 = time.perf_counter()
+        grc = hp.Solver(dim, n, p, kappa, block_recompute=1)
+        torch.cuda.synchronize()
+        t_setup_rc = time.perf_counter() - t0
+        rc_in = {name: (torch.zeros(nd, dtype=dt, device=dev), b64.to(dt),
+                        [torch.cuda.Event(enable_timing=True) for _ in range(2)])
+                 for name, dt in (("f64", torch.float64), ("f32", torch.float32))}
+        solves += ("mixed_f32_block_recompute",)
+        solver_of["mixed_f32_block_recompute"] = grc
     batch1 = None if vark else hp.Batch([gmx])
     S = args.sweeps
 
@@ -409,7 +423,7 @@ def main():
         # S fused sweeps (one hpmg_sweep call, one launch per sweep) queued
         # back to back between two events on the launch stream:
         # mean launch duration = elapsed / S
-        for gs, ins in ((g64, sweep_in), (ggl, gl_in)):
+        for gs, ins in ((g64, sweep_in), (ggl, gl_in)) + (((grc, rc_in),) if vark else ()):
             for uu, bb, evs in ins.values():
                 gs.project(uu)
                 evs[0].record(stream)
@@ -435,6 +449,8 @@ def main():
                 out["sw_" + name] = evs[0].elapsed_time(evs[1]) * 1e-3 / S
             for name, (_, _, evs) in gl_in.items():
                 out["swgl_" + name] = evs[0].elapsed_time(evs[1]) * 1e-3 / S
+            for name, (_, _, evs) in rc_in.items():
+                out["swrc_" + name] = evs[0].elapsed_time(evs[1]) * 1e-3 / S
         return out
 
     for _ in range(args.warmup):
@@ -517,6 +533,16 @@ def main():
         "mixed_solution_true_rel_residual": true_rel,
         "setup_s": t_setup,
     }
+    if vark:
+        trc = {name: sum(r["swrc_" + name] for r in res) / len(res) for name in rc_in}
+        byrc = {name: traffic.sweep_bytes(dim, n, p, isz[name], per_cell_kappa=True, block_recompute=True)
+                for name in rc_in}
+        line["block_recompute"] = {
+            "setup_s": t_setup_rc,
+            "sweep_dofs_per_s": {name: nd / t for name, t in trc.items()},
+            "sweep_mean_launch_s": trc,
+            "sweep_roofline_frac": {name: byrc[name] / trc[name] / 1e9 / HBM_PEAK_GBS for name in rc_in},
+            "algorithmic_bytes_per_launch": byrc}
     if not args.no_cpu_baseline and headline:
         line["cpu_baseline"] = cpu_baseline(dim, p, args.cpu_n)
     print(json.dumps(line), flush=True)

@@ -85,6 +85,13 @@ typedef struct {
   int h_factor;       /* Q1 h-coarsening factor, 2 (default) or 3 (the paper's 3^k meshes) */
   int basis;          /* DG nodes: 0 Gauss-Lobatto (default), 1 Gauss-Legendre (diagonal mass, dense
                          facet value functionals; Section 4.1 remark on the two bases) */
+  int block_recompute; /* variable kappa only: 0 (default) precompute the fast-diagonalisation data of
+                         every cell block at setup and stream it in each traversal; 1 rebuild it in
+                         every traversal from kappa (a Jacobi eigensolve per cell and axis inside the
+                         kernels), the paper's "recompute the block inverse per cell" variant that
+                         mimics inhomogeneous problems (Section 6 experiments).  Same operator and
+                         iterates up to rounding; setup skips the per-cell eigendata.  Setting it with
+                         constant kappa is HPMG_E_INVALID. */
 } hpmg_options;
 
 /* Fill *opt with the defaults listed above. */

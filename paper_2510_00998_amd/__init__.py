@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
     _fields_ = [("sigma0", ctypes.c_double), ("omega_dg", ctypes.c_double), ("omega_cg", ctypes.c_double),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("coarsest_n", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int), ("p_coarsening", ctypes.c_int),
-                ("h_factor", ctypes.c_int), ("basis", ctypes.c_int)]
+                ("h_factor", ctypes.c_int), ("basis", ctypes.c_int), ("block_recompute", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

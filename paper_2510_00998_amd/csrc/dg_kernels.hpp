@@ -94,6 +94,8 @@ struct DGArgs {
   const C* ref;        // RefOff layout
   const C* eig;        // vark=0: [4 classes][S N^2 | Si N^2 | lam N]; vark=1: [cell][D][S N^2 | lam N]
   const C* kappa;      // vark=1: per cell
+  const C* rk;         // vark=1 with the block recomputed in each traversal: [Khat | C^-1] (Mhat = C C^T),
+                       // eig unused; nullptr: eig holds the precomputed per-cell data
   const unsigned char* bmask;  // per cell: bit 2k+side set if that facet is on the boundary
   C h_fwd;             // h^(2-d): scales b in the sweep
   C h_apply;           // h^(d-2): scales A u

@@ -163,15 +163,21 @@ struct EigLDS {
   static constexpr int SIZE = VARK ? DGShape<D, N>::CPB * D * DGShape<D, N>::EGS : 4 * DGShape<D, N>::EGS;
 };
 
-// Boundary masks of the block's cells in LDS, right after the kappa_F
-// entries (read by the facet passes that follow a barrier).
+// LDS after the staged eigendata: kappa_F per (cell, facet) (variable
+// kappa; one unused entry otherwise), kappa_K per cell (variable kappa),
+// then the boundary masks of the block's cells (read by the facet passes
+// that follow a barrier).
+template <int D, int N, bool VARK>
+constexpr int kappa_lds_entries() {
+  return VARK ? DGShape<D, N>::CPB * (DGShape<D, N>::NF + 1) : 1;
+}
 template <int D, int N, bool VARK, typename C>
 __device__ __forceinline__ int* mask_lds(C* sKF) {
-  return (int*)(sKF + (VARK ? DGShape<D, N>::CPB * DGShape<D, N>::NF : 1));
+  return (int*)(sKF + kappa_lds_entries<D, N, VARK>());
 }
 template <int D, int N, bool VARK, typename C>
 __device__ __forceinline__ const int* mask_lds(const C* sKF) {
-  return (const int*)(sKF + (VARK ? DGShape<D, N>::CPB * DGShape<D, N>::NF : 1));
+  return (const int*)(sKF + kappa_lds_entries<D, N, VARK>());
 }
 
 // Stage the eigendata (and, per cell, kappa_F of every facet; 0 on the
@@ -196,10 +202,11 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
     const int ne = nc * D * (NN + N), nk = nc * Sh::NF;
     C ev[IE], k0[IK], k1[IK];
     int msk[IK];
+    const bool stored = a.rk == nullptr;  // else rebuilt by recompute_eig
 #pragma unroll
     for (int m = 0; m < IE; ++m) {
       const int i = tid + m * Sh::NT;
-      ev[m] = i < ne ? a.eig[(size_t)c0 * D * (NN + N) + i] : C(0);
+      ev[m] = (stored && i < ne) ? a.eig[(size_t)c0 * D * (NN + N) + i] : C(0);
     }
 #pragma unroll
     for (int m = 0; m < IK; ++m) {
@@ -215,7 +222,7 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
 #pragma unroll
     for (int m = 0; m < IE; ++m) {
       const int i = tid + m * Sh::NT;
-      if (i < ne) {
+      if (stored && i < ne) {
         const int e = i % (NN + N), ck = i / (NN + N);
         sE[ck * Sh::EGS + (e < NN ? e : NN + e)] = ev[m];
       }
@@ -226,8 +233,127 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
       if (i < nk) {
         const int f = i % Sh::NF;
         sKF[i] = ((msk[m] >> f) & 1) ? C(0) : C(2) * k0[m] * k1[m] / (k0[m] + k1[m]);
+        if (f == 0) sKF[Sh::CPB * Sh::NF + i / Sh::NF] = k0[m];  // kappa_K
       }
     }
+  }
+}
+
+// Fast-diagonalisation data of every staged (cell, axis), rebuilt from kappa
+// (block_recompute; the paper's variant that forms the block inverse anew in
+// each cell and traversal).  One thread per (cell, axis), working in the
+// cell's own S | Si | lambda record in LDS:
+//   L   = kappa_K Khat + sum_s [c1_s (e_s ep_s^T + ep_s e_s^T) + c2_s e_s e_s^T]
+//         (c1, c2) = (-kappa_F/2, sigma_hat kappa_F) interior, (-kappa_K,
+//         2 sigma_hat kappa_K) on the boundary (a boundary facet has kappa_F 0)
+//   A   = W L W^T with W = C^-1, Mhat = C C^T (symmetric), in the Si slot
+//   cyclic Jacobi rotations A <- J^T A J, V <- V J (V in the S slot) until A
+//   is diagonal to working precision (a fixed number of sweeps)
+//   lambda = diag(A), S = W^T V, so that L S = Mhat S diag(lambda), S^T Mhat S = I.
+template <typename T, int D, int N>
+__device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>* sE, const CT<T>* sKF) {
+  using C = CT<T>;
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  constexpr int SWEEPS = sizeof(C) == 8 ? 8 : 6;
+  const C* sKK = sKF + Sh::CPB * Sh::NF;
+  const cptr<C> Kh = as_const(a.rk);
+  const cptr<C> Wi = as_const(a.rk) + NN;
+  const cptr<C> ev0 = as_const(a.ref) + RefOff<N>::EV0;
+  const cptr<C> ev1 = as_const(a.ref) + RefOff<N>::EV1;
+  const cptr<C> ep0 = as_const(a.ref) + RefOff<N>::EP0;
+  const cptr<C> ep1 = as_const(a.ref) + RefOff<N>::EP1;
+  for (int t = work_tid<D, N>(); t < nc * D; t += Sh::NT) {
+    const int cl = t / D, k = t % D;
+    C* V = sE + t * Sh::EGS;
+    C* A = V + NN;
+    C* lam = V + 2 * NN;
+    const C kK = sKK[cl];
+    const C kF0 = sKF[cl * Sh::NF + 2 * k], kF1 = sKF[cl * Sh::NF + 2 * k + 1];
+    const bool b0 = kF0 == C(0), b1 = kF1 == C(0);
+    const C c10 = b0 ? -kK : C(-0.5) * kF0, c20 = a.sigma_hat * (b0 ? C(2) * kK : kF0);
+    const C c11 = b1 ? -kK : C(-0.5) * kF1, c21 = a.sigma_hat * (b1 ? C(2) * kK : kF1);
+#pragma unroll 1
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        A[i * N + j] = kK * Kh[i * N + j] + c10 * (ev0[i] * ep0[j] + ep0[i] * ev0[j]) + c20 * ev0[i] * ev0[j] +
+                       c11 * (ev1[i] * ep1[j] + ep1[i] * ev1[j]) + c21 * ev1[i] * ev1[j];
+    // V <- W L (W lower triangular, so the sums stop at the diagonal), then
+    // A <- V W^T, symmetrised
+#pragma unroll 1
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        C s = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) s += (m <= i ? Wi[i * N + m] : C(0)) * A[m * N + j];
+        V[i * N + j] = s;
+      }
+#pragma unroll 1
+    for (int i = 0; i < N; ++i)
+#pragma unroll 1
+      for (int j = 0; j <= i; ++j) {
+        C s = 0, r = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          s += (m <= j ? V[i * N + m] * Wi[j * N + m] : C(0));
+          r += (m <= i ? V[j * N + m] * Wi[i * N + m] : C(0));
+        }
+        A[i * N + j] = A[j * N + i] = C(0.5) * (s + r);
+      }
+#pragma unroll
+    for (int i = 0; i < NN; ++i) V[i] = (i % (N + 1) == 0) ? C(1) : C(0);
+#pragma unroll 1
+    for (int sw = 0; sw < SWEEPS; ++sw) {
+#pragma unroll 1
+      for (int p = 0; p < N - 1; ++p) {
+#pragma unroll 1
+        for (int q = p + 1; q < N; ++q) {
+          const C apq = A[p * N + q];
+          if (apq == C(0)) continue;
+          const C tau = (A[q * N + q] - A[p * N + p]) / (C(2) * apq);
+          const C at = tau < C(0) ? -tau : tau;
+          // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), without overflow
+          const C root = at > C(1) ? at * __builtin_sqrt(C(1) + (C(1) / at) * (C(1) / at)) : __builtin_sqrt(C(1) + at * at);
+          const C tt = (tau < C(0) ? C(-1) : C(1)) / (at + root);
+          const C cs = C(1) / __builtin_sqrt(C(1) + tt * tt), sn = tt * cs;
+#pragma unroll
+          for (int r = 0; r < N; ++r) {  // columns p, q
+            const C x = A[r * N + p], y = A[r * N + q];
+            A[r * N + p] = cs * x - sn * y;
+            A[r * N + q] = sn * x + cs * y;
+          }
+#pragma unroll
+          for (int r = 0; r < N; ++r) {  // rows p, q
+            const C x = A[p * N + r], y = A[q * N + r];
+            A[p * N + r] = cs * x - sn * y;
+            A[q * N + r] = sn * x + cs * y;
+          }
+          A[p * N + q] = A[q * N + p] = C(0);
+#pragma unroll
+          for (int r = 0; r < N; ++r) {
+            const C x = V[r * N + p], y = V[r * N + q];
+            V[r * N + p] = cs * x - sn * y;
+            V[r * N + q] = sn * x + cs * y;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) lam[c] = A[c * N + c];
+    // S = W^T V (into the Si slot, then back to the S slot)
+#pragma unroll 1
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        C s = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) s += (m >= i ? Wi[m * N + i] : C(0)) * V[m * N + c];
+        A[i * N + c] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < NN; ++i) V[i] = A[i];
   }
 }
 
@@ -532,6 +658,10 @@ __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int
     load_eig<T, D, N, true>(a, c0, nc, sE, sKF);
     if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
     __syncthreads();
+    if (a.rk) {
+      recompute_eig<T, D, N>(a, nc, sE, sKF);
+      __syncthreads();
+    }
     make_si<T, D, N>(a, nc, sE);
     __syncthreads();
     facet_pass<T, D, N, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
@@ -659,7 +789,7 @@ constexpr int cell_lds_bytes() {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
   return (int)sizeof(C) *
-         (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK>::SIZE + (VARK ? Sh::CPB * Sh::NF : 1)) +
+         (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK>::SIZE + kappa_lds_entries<D, N, VARK>()) +
          (int)sizeof(int) * Sh::CPB;
 }
 
@@ -701,6 +831,10 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
     load_eig<T, D, N, VARK>(a, c0, nc, sE, sKF);
     __syncthreads();
     if constexpr (VARK) {
+      if (a.rk) {
+        recompute_eig<T, D, N>(a, nc, sE, sKF);
+        __syncthreads();
+      }
       make_si<T, D, N>(a, nc, sE);
       __syncthreads();
     }

@@ -181,6 +181,37 @@ void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg:
     }
     L.d.eig = h->mem.upload(tab, s);
     L.f.eig = h->mem.upload(cast_vec<float>(tab), s);
+  } else if (h->opt.block_recompute) {
+    // the kernels rebuild S, lambda per cell and axis from kappa: they need
+    // Khat and W = C^-1 with Mhat = C C^T (then W L W^T is symmetric and its
+    // eigenvectors V give S = W^T V)
+    std::vector<double> tab((size_t)2 * NN, 0.0);
+    std::copy(B.K.begin(), B.K.end(), tab.begin());
+    std::vector<long double> Cm((size_t)NN, 0.0L), Wm((size_t)NN, 0.0L);
+    for (int j = 0; j < N; ++j) {
+      long double sd = B.M[(size_t)j * N + j];
+      for (int k = 0; k < j; ++k) sd -= Cm[(size_t)j * N + k] * Cm[(size_t)j * N + k];
+      if (!(sd > 0.0L)) throw HpmgError(HPMG_E_DEVICE, "mass matrix not positive definite");
+      Cm[(size_t)j * N + j] = std::sqrt(sd);
+      for (int i = j + 1; i < N; ++i) {
+        long double t = B.M[(size_t)i * N + j];
+        for (int k = 0; k < j; ++k) t -= Cm[(size_t)i * N + k] * Cm[(size_t)j * N + k];
+        Cm[(size_t)i * N + j] = t / Cm[(size_t)j * N + j];
+      }
+    }
+    for (int j = 0; j < N; ++j) {
+      Wm[(size_t)j * N + j] = 1.0L / Cm[(size_t)j * N + j];
+      for (int i = j + 1; i < N; ++i) {
+        long double t = 0.0L;
+        for (int k = j; k < i; ++k) t += Cm[(size_t)i * N + k] * Wm[(size_t)k * N + j];
+        Wm[(size_t)i * N + j] = -t / Cm[(size_t)i * N + i];
+      }
+    }
+    for (int i = 0; i < NN; ++i) tab[(size_t)NN + i] = (double)Wm[i];
+    L.d.rk = h->mem.upload(tab, s);
+    L.f.rk = h->mem.upload(cast_vec<float>(tab), s);
+    L.d.kappa = h->mem.upload(h->kappa, s);
+    L.f.kappa = h->mem.upload(cast_vec<float>(h->kappa), s);
   } else {
     const int W = NN + N;
     std::vector<double> tab((size_t)h->ncell * D * W);
@@ -826,6 +857,7 @@ void hpmg_default_options(hpmg_options* o) {
   o->p_coarsening = 0;
   o->h_factor = 2;
   o->basis = 0;
+  o->block_recompute = 0;
 }
 
 const char* hpmg_status_string(hpmg_status s) {
@@ -886,6 +918,8 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
       require(coeff->kappa_const > 0.0 && std::isfinite(coeff->kappa_const), "kappa_const must be positive");
       h->kappa_const = coeff->kappa_const;
     }
+    require(h->opt.block_recompute == 0 || (h->opt.block_recompute == 1 && h->vark),
+            "block_recompute must be 0, or 1 with a per-cell kappa");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     {

@@ -71,6 +71,7 @@ template <typename T>
 struct DGData {
   T* ref = nullptr;
   T* eig = nullptr;
+  T* rk = nullptr;       // block_recompute: [Khat | C^-1], Mhat = C C^T
   T* kappa = nullptr;
   T* u = nullptr;        // coarse levels only
   T* b = nullptr;        // coarse levels only
@@ -192,6 +193,7 @@ inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
   a.kappa_const = (C)h->kappa_const;
   a.ref = d.ref;
   a.eig = d.eig;
+  a.rk = d.rk;
   a.kappa = d.kappa;
   a.bmask = h->bmask;
   const double hh = 1.0 / h->n;

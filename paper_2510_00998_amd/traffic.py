@@ -34,17 +34,19 @@ def interior_facets(d: int, n: int) -> int:
     return d * n ** (d - 1) * (n - 1)
 
 
-def sweep_bytes(d: int, n: int, p: int, itemsize: int, per_cell_kappa: bool = False) -> int:
+def sweep_bytes(d: int, n: int, p: int, itemsize: int, per_cell_kappa: bool = False,
+                block_recompute: bool = False) -> int:
     """Exact algorithmic bytes of one fused sweep launch on the n^d mesh:
     3 cell vectors, plus 2 sides x 2 fields x (p+1)^(d-1) trace values per
     interior facet read once and written once (boundary facets carry no
     traces), plus per-cell eigendata d((p+1)^2 + (p+1)) and kappa when the
-    coefficient varies per cell."""
+    coefficient varies per cell (kappa alone when the kernels rebuild the
+    eigendata in each traversal)."""
     N = p + 1
     ncell = n ** d
     words = 3 * ncell * N ** d + interior_facets(d, n) * 2 * 2 * N ** (d - 1) * 2
     if per_cell_kappa:
-        words += ncell * (d * (N * N + N) + 1)
+        words += ncell * (1 if block_recompute else d * (N * N + N) + 1)
     return words * itemsize
 
 

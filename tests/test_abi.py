@@ -44,7 +44,8 @@ def test_setup_rejects_invalid(kw):
 def test_setup_rejects_bad_options():
     for field, val in [("omega_dg", 0.0), ("omega_dg", 1.5), ("omega_cg", -1.0), ("sigma0", 0.0),
                        ("coarsest_n", 1), ("max_rhs", 0), ("precision", 7), ("p_coarsening", 2),
-                       ("h_factor", 4), ("h_factor", 1)]:
+                       ("h_factor", 4), ("h_factor", 1), ("block_recompute", 2),
+                       ("block_recompute", 1)]:  # the last: recompute with constant kappa
         opt = hp.default_options()
         setattr(opt, field, val)
         st, _ = _setup(opt=opt)
