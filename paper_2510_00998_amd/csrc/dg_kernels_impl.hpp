@@ -248,7 +248,7 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
 //         2 sigma_hat kappa_K) on the boundary (a boundary facet has kappa_F 0)
 //   A   = W L W^T with W = C^-1, Mhat = C C^T (symmetric), in the Si slot
 //   cyclic Jacobi rotations A <- J^T A J, V <- V J (V in the S slot) until A
-//   is diagonal to working precision (a fixed number of sweeps)
+//   is diagonal to working precision (at most 8 sweeps in FP64, 6 in FP32)
 //   lambda = diag(A), S = W^T V, so that L S = Mhat S diag(lambda), S^T Mhat S = I.
 template <typename T, int D, int N>
 __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>* sE, const CT<T>* sKF) {
@@ -306,6 +306,15 @@ __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>*
     for (int i = 0; i < NN; ++i) V[i] = (i % (N + 1) == 0) ? C(1) : C(0);
 #pragma unroll 1
     for (int sw = 0; sw < SWEEPS; ++sw) {
+      // stop once the off-diagonal part is below working precision
+      C off = 0, dg = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        dg += A[i * N + i] * A[i * N + i];
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) off += A[i * N + j] * A[i * N + j];
+      }
+      if (off <= (sizeof(C) == 8 ? C(1e-30) : C(1e-14)) * dg) break;
 #pragma unroll 1
       for (int p = 0; p < N - 1; ++p) {
 #pragma unroll 1
