@@ -3,7 +3,7 @@
 Written from the paper's Section 5 (Algorithms CoarseGridCorrection and
 MGMult; the h-multigrid V-cycle of Section 5.2) and Section 2.3.2
 (block-Jacobi, eq. block-Jacobi-IP) / Section 2.4 (point-Jacobi on CG_1),
-with the readings recorded in the design doc:
+with these readings where the paper is silent or ambiguous:
 
 * p-coarsening halves p (floor) while the halved degree is >= 2, then goes
   to the continuous Q1 space (zero boundary values) on the same mesh;

@@ -1,6 +1,7 @@
 """Assembled SIPG operator for the oracle (test infrastructure only).
 
-Discretisation (paper Section 2, with the readings listed in the design doc):
+Discretisation (paper Section 2, with these readings where the paper is silent
+or ambiguous):
 
 * mesh: unit box [0,1]^d, n cells per axis, h = 1/n (Section 2.1, uniform
   instead of 3-partitioned); cell index c = cx + n*cy (+ n^2*cz);
