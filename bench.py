@@ -15,7 +15,7 @@ One step = the whole hot path once, with inputs resident in HBM:
     V-cycle on 16-bit finest-level storage (FP16, BF16), and (constant kappa)
     the batched solver on this one problem (captured iteration graph).
 value = FP64 fused-sweep DoF/s = DoFs / mean sweep launch duration.
-Prints one JSON line (rank 0; this build runs on one GPU only).
+Prints one JSON line (rank 0; the library runs on one GPU only).
 """
 from __future__ import annotations
 
@@ -339,7 +339,7 @@ def run_paper_tables(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on exactly one GPU; --gpus must be 1",
                           "requested_gpus": args.gpus}))
         sys.exit(2)
     if args.paper_tables:

@@ -43,7 +43,7 @@ typedef enum {
   HPMG_E_DEVICE = 3,        /* a HIP call failed (no device, launch failure, ...) */
   HPMG_E_NOT_CONVERGED = 4, /* hpmg_solve reached maxit before rtol */
   HPMG_E_BREAKDOWN = 5,     /* non-finite value met in hpmg_solve (e.g. NaN in b) */
-  HPMG_E_UNSUPPORTED = 6    /* valid request this build does not implement */
+  HPMG_E_UNSUPPORTED = 6    /* valid request the library does not implement */
 } hpmg_status;
 
 /* Element type of the vectors a call reads and writes.  F16 (IEEE binary16)
