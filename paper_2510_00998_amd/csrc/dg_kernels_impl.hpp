@@ -241,8 +241,7 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
 
 // Fast-diagonalisation data of every staged (cell, axis), rebuilt from kappa
 // (block_recompute; the paper's variant that forms the block inverse anew in
-// each cell and traversal).  One thread per (cell, axis), working in the
-// cell's own S | Si | lambda record in LDS:
+// each cell and traversal), in the cell's own S | Si | lambda record in LDS:
 //   L   = kappa_K Khat + sum_s [c1_s (e_s ep_s^T + ep_s e_s^T) + c2_s e_s e_s^T]
 //         (c1, c2) = (-kappa_F/2, sigma_hat kappa_F) interior, (-kappa_K,
 //         2 sigma_hat kappa_K) on the boundary (a boundary facet has kappa_F 0)
@@ -250,12 +249,27 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
 //   cyclic Jacobi rotations A <- J^T A J, V <- V J (V in the S slot) until A
 //   is diagonal to working precision (at most 8 sweeps in FP64, 6 in FP32)
 //   lambda = diag(A), S = W^T V, so that L S = Mhat S diag(lambda), S^T Mhat S = I.
+// N lanes of one wave share a (cell, axis): lane r owns row r of every
+// product and entry r of the two columns and rows each rotation changes;
+// the rotation angle is formed redundantly by the N lanes.  The lanes of a
+// problem are in one wave, whose LDS accesses complete in program order, so
+// a wavefront-scope fence between the phases orders them.
 template <typename T, int D, int N>
 __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>* sE, const CT<T>* sKF) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   constexpr int SWEEPS = sizeof(C) == 8 ? 8 : 6;
+  // the block has NT threads (not always whole waves): its last wave hosts
+  // only the problems whose N lanes all exist
+  constexpr int TPW = 64 / N;  // problems per full wave
+  constexpr int NWT = (Sh::NT + 63) / 64;
+  constexpr int CLAST = (Sh::NT - 64 * (NWT - 1)) / N < TPW ? (Sh::NT - 64 * (NWT - 1)) / N : TPW;
+  constexpr int CAP = (NWT - 1) * TPW + CLAST;  // problems per round of the block
+  static_assert(CAP > 0, "no wave can host a problem");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane % N, slot = lane / N;
+  const int cap_w = wave == NWT - 1 ? CLAST : TPW;
   const C* sKK = sKF + Sh::CPB * Sh::NF;
   const cptr<C> Kh = as_const(a.rk);
   const cptr<C> Wi = as_const(a.rk) + NN;
@@ -263,9 +277,15 @@ __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>*
   const cptr<C> ev1 = as_const(a.ref) + RefOff<N>::EV1;
   const cptr<C> ep0 = as_const(a.ref) + RefOff<N>::EP0;
   const cptr<C> ep1 = as_const(a.ref) + RefOff<N>::EP1;
-  for (int t = work_tid<D, N>(); t < nc * D; t += Sh::NT) {
-    const int cl = t / D, k = t % D;
-    C* V = sE + t * Sh::EGS;
+  const auto wave_sync = []() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); };
+  // rounds of CAP problems; every lane of the block runs the same rounds
+  for (int R = 0; R * CAP < nc * D; ++R) {
+    const int t = R * CAP + wave * TPW + slot;
+    const bool act = slot < cap_w && t < nc * D;
+    if (__all(!act)) continue;  // nothing for this wave in this round
+    const int tt = act ? t : R * CAP;  // idle lanes shadow a valid problem, writing nothing
+    const int cl = tt / D, k = tt % D;
+    C* V = sE + tt * Sh::EGS;
     C* A = V + NN;
     C* lam = V + 2 * NN;
     const C kK = sKK[cl];
@@ -273,40 +293,59 @@ __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>*
     const bool b0 = kF0 == C(0), b1 = kF1 == C(0);
     const C c10 = b0 ? -kK : C(-0.5) * kF0, c20 = a.sigma_hat * (b0 ? C(2) * kK : kF0);
     const C c11 = b1 ? -kK : C(-0.5) * kF1, c21 = a.sigma_hat * (b1 ? C(2) * kK : kF1);
-#pragma unroll 1
-    for (int i = 0; i < N; ++i)
+    // row r of L, of W L (into V), of A = (W L) W^T
+    C row[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j)
-        A[i * N + j] = kK * Kh[i * N + j] + c10 * (ev0[i] * ep0[j] + ep0[i] * ev0[j]) + c20 * ev0[i] * ev0[j] +
-                       c11 * (ev1[i] * ep1[j] + ep1[i] * ev1[j]) + c21 * ev1[i] * ev1[j];
-    // V <- W L (W lower triangular, so the sums stop at the diagonal), then
-    // A <- V W^T, symmetrised
-#pragma unroll 1
-    for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      row[j] = kK * Kh[r * N + j] + c10 * (ev0[r] * ep0[j] + ep0[r] * ev0[j]) + c20 * ev0[r] * ev0[j] +
+               c11 * (ev1[r] * ep1[j] + ep1[r] * ev1[j]) + c21 * ev1[r] * ev1[j];
+    if (act) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        C s = 0;
+      for (int j = 0; j < N; ++j) A[r * N + j] = row[j];
+    }
+    wave_sync();
 #pragma unroll
-        for (int m = 0; m < N; ++m) s += (m <= i ? Wi[i * N + m] : C(0)) * A[m * N + j];
-        V[i * N + j] = s;
-      }
-#pragma unroll 1
-    for (int i = 0; i < N; ++i)
-#pragma unroll 1
-      for (int j = 0; j <= i; ++j) {
-        C s = 0, r = 0;
+    for (int j = 0; j < N; ++j) {
+      C s = 0;
 #pragma unroll
-        for (int m = 0; m < N; ++m) {
-          s += (m <= j ? V[i * N + m] * Wi[j * N + m] : C(0));
-          r += (m <= i ? V[j * N + m] * Wi[i * N + m] : C(0));
-        }
-        A[i * N + j] = A[j * N + i] = C(0.5) * (s + r);
-      }
+      for (int m = 0; m < N; ++m) s += Wi[r * N + m] * A[m * N + j];  // W lower triangular: zeros above
+      row[j] = s;
+    }
+    wave_sync();
+    if (act) {
 #pragma unroll
-    for (int i = 0; i < NN; ++i) V[i] = (i % (N + 1) == 0) ? C(1) : C(0);
+      for (int j = 0; j < N; ++j) V[r * N + j] = row[j];
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      C s = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) s += V[r * N + m] * Wi[j * N + m];
+      row[j] = s;
+    }
+    wave_sync();
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) A[r * N + j] = row[j];
+#pragma unroll
+      for (int j = 0; j < N; ++j) V[r * N + j] = j == r ? C(1) : C(0);
+    }
+    wave_sync();
+    // symmetrise: A <- (A + A^T) / 2
+#pragma unroll
+    for (int j = 0; j < N; ++j) row[j] = C(0.5) * (A[r * N + j] + A[j * N + r]);
+    wave_sync();
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) A[r * N + j] = row[j];
+    }
+    wave_sync();
+    bool done = false;
 #pragma unroll 1
     for (int sw = 0; sw < SWEEPS; ++sw) {
-      // stop once the off-diagonal part is below working precision
+      // stop once the off-diagonal part is below working precision (every
+      // lane of a problem forms the same sums)
       C off = 0, dg = 0;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -314,55 +353,66 @@ __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>*
 #pragma unroll
         for (int j = i + 1; j < N; ++j) off += A[i * N + j] * A[i * N + j];
       }
-      if (off <= (sizeof(C) == 8 ? C(1e-30) : C(1e-14)) * dg) break;
+      done = done || off <= (sizeof(C) == 8 ? C(1e-30) : C(1e-14)) * dg;
+      if (__all(done)) break;  // every problem of the wave has converged
 #pragma unroll 1
       for (int p = 0; p < N - 1; ++p) {
 #pragma unroll 1
         for (int q = p + 1; q < N; ++q) {
           const C apq = A[p * N + q];
-          if (apq == C(0)) continue;
-          const C tau = (A[q * N + q] - A[p * N + p]) / (C(2) * apq);
-          const C at = tau < C(0) ? -tau : tau;
-          // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), without overflow
-          const C root = at > C(1) ? at * __builtin_sqrt(C(1) + (C(1) / at) * (C(1) / at)) : __builtin_sqrt(C(1) + at * at);
-          const C tt = (tau < C(0) ? C(-1) : C(1)) / (at + root);
-          const C cs = C(1) / __builtin_sqrt(C(1) + tt * tt), sn = tt * cs;
-#pragma unroll
-          for (int r = 0; r < N; ++r) {  // columns p, q
-            const C x = A[r * N + p], y = A[r * N + q];
+          const bool rot = !done && apq != C(0);
+          C cs = C(1), sn = C(0);
+          if (rot) {
+            const C tau = (A[q * N + q] - A[p * N + p]) / (C(2) * apq);
+            const C at = tau < C(0) ? -tau : tau;
+            // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), without overflow
+            const C root =
+                at > C(1) ? at * __builtin_sqrt(C(1) + (C(1) / at) * (C(1) / at)) : __builtin_sqrt(C(1) + at * at);
+            const C tn = (tau < C(0) ? C(-1) : C(1)) / (at + root);
+            cs = C(1) / __builtin_sqrt(C(1) + tn * tn);
+            sn = tn * cs;
+          }
+          wave_sync();
+          // columns p, q: entry r
+          const C x = A[r * N + p], y = A[r * N + q];
+          wave_sync();
+          if (act && rot) {
             A[r * N + p] = cs * x - sn * y;
             A[r * N + q] = sn * x + cs * y;
           }
-#pragma unroll
-          for (int r = 0; r < N; ++r) {  // rows p, q
-            const C x = A[p * N + r], y = A[q * N + r];
-            A[p * N + r] = cs * x - sn * y;
-            A[q * N + r] = sn * x + cs * y;
+          wave_sync();
+          // rows p, q: entry r
+          const C xr = A[p * N + r], yr = A[q * N + r];
+          const C vx = V[r * N + p], vy = V[r * N + q];
+          wave_sync();
+          if (act && rot) {
+            A[p * N + r] = cs * xr - sn * yr;
+            A[q * N + r] = sn * xr + cs * yr;
+            V[r * N + p] = cs * vx - sn * vy;
+            V[r * N + q] = sn * vx + cs * vy;
           }
-          A[p * N + q] = A[q * N + p] = C(0);
-#pragma unroll
-          for (int r = 0; r < N; ++r) {
-            const C x = V[r * N + p], y = V[r * N + q];
-            V[r * N + p] = cs * x - sn * y;
-            V[r * N + q] = sn * x + cs * y;
-          }
+          wave_sync();
+          if (act && rot && r == 0) A[p * N + q] = A[q * N + p] = C(0);
+          wave_sync();
         }
       }
     }
+    // lambda = diag(A); S = W^T V, row r: S[r][c] = sum_{m >= r} W[m][r] V[m][c]
+    const C lr = A[r * N + r];
 #pragma unroll
-    for (int c = 0; c < N; ++c) lam[c] = A[c * N + c];
-    // S = W^T V (into the Si slot, then back to the S slot)
-#pragma unroll 1
-    for (int i = 0; i < N; ++i)
+    for (int c = 0; c < N; ++c) {
+      C s = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        C s = 0;
+      for (int m = 0; m < N; ++m) s += Wi[m * N + r] * V[m * N + c];
+      row[c] = s;
+    }
+    wave_sync();
+    if (act) {
+      lam[r] = lr;
 #pragma unroll
-        for (int m = 0; m < N; ++m) s += (m >= i ? Wi[m * N + i] : C(0)) * V[m * N + c];
-        A[i * N + c] = s;
-      }
-#pragma unroll
-    for (int i = 0; i < NN; ++i) V[i] = A[i];
+      for (int c = 0; c < N; ++c) V[r * N + c] = row[c];
+    }
+    wave_sync();
   }
 }
 

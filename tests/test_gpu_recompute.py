@@ -15,10 +15,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 CASES = [
-    # dim, n, p: several blocks, a ragged last block, p up to 8 (N = 9)
+    # dim, n, p: several blocks, full blocks and a ragged last block, p up to
+    # 8 (N = 9); 3D degree 2 has a partial last wave in a full block
     (2, 7, 3),
+    (2, 6, 2),
     (2, 3, 8),
     (3, 3, 1),
+    (3, 5, 2),
     (3, 4, 3),
     (3, 5, 4),
     (3, 3, 5),
@@ -64,7 +67,7 @@ def test_recompute_apply_and_sweeps(dim, n, p):
         assert e_or <= tol_s and e_rs <= 10 * tol_x
 
 
-@pytest.mark.parametrize("dim,n,p", [(2, 7, 3), (3, 4, 3), (3, 3, 5)])
+@pytest.mark.parametrize("dim,n,p", [(2, 7, 3), (3, 4, 3), (3, 3, 5), (3, 5, 4)])
 def test_recompute_vcycle_and_solve(dim, n, p):
     log(f"recompute vcycle/solve dim={dim} n={n} p={p}")
     H = Hierarchy(dim, n, p, _kappa(dim, n))
