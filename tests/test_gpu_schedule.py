@@ -1,0 +1,97 @@
+"""Schedule invariance, solver status paths and discretisation error.
+
+* The block-Jacobi sweep reads only old traces (two trace buffers), so its
+  result cannot depend on which block processes which cells or in what
+  order: repeated sweeps, right-hand sides processed by different blocks of
+  one launch, and the batched driver's persistent work-list launches must
+  agree bit for bit in FP64 (a trace race would break this).
+* solve reports HPMG_E_NOT_CONVERGED when maxit is too small and
+  HPMG_E_BREAKDOWN for a non-finite right-hand side.
+* The solver's solution has the discretisation error of the exact discrete
+  solution (the oracle's direct solve) for a manufactured solution.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import SIPG, manufactured as mf
+from tests.gpu_common import log, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _kappa(dim, n, kind):
+    return 1.5 if kind == "const" else synth.kappa_log_uniform(dim, n, seed=400)
+
+
+@pytest.mark.parametrize("n,p,kind", [(6, 4, "const"), (5, 3, "var"), (7, 2, "const"), (4, 5, "var")])
+def test_sweep_is_schedule_invariant(n, p, kind):
+    import paper_2510_00998_amd as hp
+    log(f"schedule invariance n={n} p={p} kappa={kind}")
+    g = hp.Solver(3, n, p, _kappa(3, n, kind), max_rhs=2)
+    u0 = synth.random_vector(g.ndof, seed=41)
+    b = synth.random_rhs(g.ndof, seed=42)
+    for dt in (torch.float64, torch.float32):
+        runs = []
+        for _ in range(2):
+            u = to_dev(u0, dt)
+            g.smooth(u, to_dev(b, dt), 3)
+            runs.append(u)
+        assert torch.equal(runs[0], runs[1])
+        # two identical right-hand sides: the second is swept by other blocks
+        u2 = to_dev(np.concatenate([u0, u0]), dt)
+        g.smooth(u2, to_dev(np.concatenate([b, b]), dt), 3, nrhs=2)
+        assert torch.equal(u2[:g.ndof], u2[g.ndof:])
+        assert torch.equal(u2[:g.ndof], runs[0])
+    if kind == "const":
+        # the batched driver's persistent launches: other block-to-cell maps
+        h2 = hp.Solver(3, n, p, _kappa(3, n, kind))
+        bt = hp.Batch([g, h2])
+        us = [to_dev(u0, torch.float64), to_dev(u0, torch.float64)]
+        bs = [to_dev(b, torch.float64), to_dev(b, torch.float64)]
+        bt.smooth(us, bs, 3)
+        ref = to_dev(u0, torch.float64)
+        g.smooth(ref, to_dev(b, torch.float64), 3)
+        d = max(float((x - ref).abs().max()) for x in us)
+        log(f"  batched vs single-problem FP64 sweeps: max |diff| {d:.3e}")
+        assert torch.equal(us[0], us[1])
+        assert d <= 1e-14 * float(ref.abs().max())
+
+
+def test_solve_status_paths():
+    import paper_2510_00998_amd as hp
+    g = hp.Solver(3, 4, 3, 1.0)
+    b = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+    g.load_vector(1, 1.0, b)
+    u = torch.zeros_like(b)
+    info, st = g.solve(u, b, rtol=1e-10, maxit=1, check=False)
+    log(f"maxit=1: status {hp.STATUS[st]}, {info.iterations} iteration(s)")
+    assert st == 4 and info.iterations == 1
+    bn = b.clone()
+    bn[7] = float("nan")
+    u.zero_()
+    _, st = g.solve(u, bn, rtol=1e-10, maxit=50, check=False)
+    log(f"NaN in b: status {hp.STATUS[st]}")
+    assert st == 5
+
+
+@pytest.mark.parametrize("dim,n,p,prec", [(2, 16, 2, 1), (2, 16, 2, 0), (3, 4, 4, 1)])
+def test_solve_has_the_discretisation_error(dim, n, p, prec):
+    import paper_2510_00998_amd as hp
+    s = SIPG(dim, n, p)
+    uex, f = mf.sin_product(dim, 1)
+    b = s.load_vector(f)
+    ud = spla.spsolve(s.A.tocsc(), b)
+    e_direct = s.l2_error(ud, uex)
+    g = hp.Solver(dim, n, p, 1.0, precision=prec)
+    bd = to_dev(b, torch.float64)
+    x = torch.zeros_like(bd)
+    info, st = g.solve(x, bd, rtol=1e-10, maxit=100)
+    e_gpu = s.l2_error(to_host(x), uex)
+    log(f"dim={dim} n={n} p={p} cycle precision {prec}: L2 error GPU {e_gpu:.6e}, direct {e_direct:.6e}, "
+        f"{info.iterations} its")
+    assert st == 0
+    assert abs(e_gpu - e_direct) <= 0.01 * e_direct
