@@ -969,8 +969,16 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   if (act) store_yz_traces<T, D, N>(a, trout, sW, cl, c, mask, ln);
 }
 
+// At least two waves per SIMD for the 3D FP64 degree 7 and 8 sweeps: left to
+// itself the compiler keeps a whole 1D matrix (too large for scalar
+// registers) in vector registers and reaches 256 VGPRs (one wave per SIMD).
+template <typename T, int D, int N>
+constexpr int sweep_waves_per_eu() {
+  return (D == 3 && sizeof(CT<T>) == 8 && N >= 8) ? 2 : 1;
+}
 template <typename T, int D, int N, bool UZERO, bool VARK>
-__global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_sweep(DGArgs<T> a) {
+__global__ __launch_bounds__((DGShape<D, N>::BLOCK))
+__attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, D, N>()))) void k_sweep(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
   sweep_body<T, D, N, UZERO, VARK>(a, blockIdx.x, blockIdx.y, lds);
 }
