@@ -148,7 +148,9 @@ hpmg_status hpmg_sweep(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, 
 
 /* One V(nu_pre, nu_post) cycle of the hp-multigrid in place on u
  * (Algorithm MGMult body with CoarseGridCorrection; gradual p-coarsening,
- * Q1, h-coarsening, dense coarsest solve). */
+ * Q1, h-coarsening, dense coarsest solve).  One right-hand side: nrhs other
+ * than 1 returns HPMG_E_INVALID (hpmg_solve takes several right-hand sides
+ * one after another; hpmg_batch_solve cycles them together). */
 hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nrhs,
                         hipStream_t stream);
 
@@ -172,7 +174,8 @@ typedef struct {
  * iteration (one outer step, captured once per handle and cycle precision as
  * a HIP graph) then runs on an internal stream of the handle, and the call
  * returns when u holds the result.  Paper: Section 5 (MGMult, exit
- * criterion), with the unpreconditioned residual as exit test. */
+ * criterion), with the unpreconditioned residual as exit test.  nrhs > 1
+ * solves the stacked right-hand sides one after another (info: the last). */
 hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, double rtol,
                        int maxit, hpmg_solve_info* info, hipStream_t stream);
 

@@ -95,3 +95,52 @@ def test_solve_has_the_discretisation_error(dim, n, p, prec):
         f"{info.iterations} its")
     assert st == 0
     assert abs(e_gpu - e_direct) <= 0.01 * e_direct
+
+
+@pytest.mark.parametrize("dim,n,p,kind", [(3, 5, 3, "var"), (2, 7, 4, "const"), (3, 4, 2, "const")])
+def test_distinct_columns_match_single_rhs(dim, n, p, kind):
+    """nrhs = 2 with different columns: every column of apply and smooth
+    equals the one-column call on that column (a wrong per-column stride of
+    the cell vectors or traces mixes the columns), every column of the FP64
+    solve reaches the tolerance, and the one-column V-cycle rejects nrhs = 2."""
+    import paper_2510_00998_amd as hp
+    log(f"distinct columns dim={dim} n={n} p={p} kappa={kind}")
+    g = hp.Solver(dim, n, p, _kappa(dim, n, kind), max_rhs=2)
+    N = g.ndof
+    u0 = [synth.random_vector(N, seed=51), synth.random_vector(N, seed=52)]
+    b = [synth.random_rhs(N, seed=53), synth.random_rhs(N, seed=54)]
+    for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
+        for op in ("apply", "smooth"):
+            two = to_dev(np.concatenate(u0), dt)
+            rhs2 = to_dev(np.concatenate(b), dt)
+            out2 = torch.empty_like(two)
+            if op == "apply":
+                g.apply_A(two, out2, nrhs=2)
+            else:
+                g.smooth(two, rhs2, 3, nrhs=2)
+                out2 = two
+            for j in range(2):
+                one = to_dev(u0[j], dt)
+                out1 = torch.empty_like(one)
+                if op == "apply":
+                    g.apply_A(one, out1)
+                else:
+                    g.smooth(one, to_dev(b[j], dt), 3)
+                    out1 = one
+                col = out2[j * N:(j + 1) * N]
+                err = float((col.double() - out1.double()).abs().max() / out1.double().abs().max())
+                log(f"  {op} {str(dt)[6:]} column {j}: rel diff {err:.2e}")
+                assert err <= tol, (op, dt, j, err)
+    two = to_dev(np.concatenate(u0), torch.float64)
+    with pytest.raises(hp.HpmgError, match="HPMG_E_INVALID"):
+        g.vcycle(two, to_dev(np.concatenate(b), torch.float64), nrhs=2)
+    u = torch.zeros(2 * N, dtype=torch.float64, device="cuda")
+    bd = to_dev(np.concatenate(b), torch.float64)
+    info, st = g.solve(u, bd, rtol=1e-10, nrhs=2)
+    r = torch.empty_like(u)
+    g.apply_A(u, r, nrhs=2)
+    for j in range(2):
+        sl = slice(j * N, (j + 1) * N)
+        rel = float(torch.linalg.norm(bd[sl] - r[sl]) / torch.linalg.norm(bd[sl]))
+        log(f"  solve column {j}: true relative residual {rel:.2e}")
+        assert rel <= 2e-10, (j, rel)
