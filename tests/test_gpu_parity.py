@@ -24,6 +24,8 @@ CASES = [
     (3, 4, 4, "const"),
     (3, 3, 5, "var"),
     (3, 2, 7, "const"),
+    (3, 3, 6, "const"),
+    (3, 2, 8, "var"),
 ]
 
 
