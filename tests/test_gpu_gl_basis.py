@@ -19,6 +19,8 @@ CASES = [
     (3, 3, 2, "var"),
     (3, 4, 4, "const"),
     (3, 3, 5, "var"),
+    (3, 3, 1, "const"),
+    (3, 2, 8, "var"),
 ]
 
 

@@ -20,6 +20,8 @@ CASES = [
     (3, 4, 3, "var"),
     (3, 4, 4, "const"),
     (3, 3, 5, "var"),
+    (3, 3, 1, "var"),
+    (3, 2, 8, "const"),
 ]
 
 # Relative max-norm tolerances.  Every sweep stores u and its traces once in
