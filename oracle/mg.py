@@ -18,7 +18,10 @@ with these readings where the paper is silent or ambiguous:
   product P^T A P;
 * V(nu1, nu2) cycle, block-Jacobi with the exact diagonal blocks A_{K<-K}
   (dense Cholesky) on DG levels, point-Jacobi with diag(A) on Q1 levels,
-  dense Cholesky on the coarsest level;
+  dense Cholesky on the coarsest level; the DG and the Q1 levels have their
+  own smoothing counts, so that the DG level can run Algorithm MGMult's nu
+  pre- and zero post-smoothing steps while the Q1 h-multigrid of Section 5.2
+  pre- and post-smooths;
 * solve: multigrid-preconditioned (flexible) CG in FP64 to a relative
   unpreconditioned residual ||b - A u|| <= rtol ||b - A u0||.
 
@@ -42,8 +45,10 @@ from .sipg import SIPG, _kron_dims
 class HierarchyOptions:
     omega_dg: float = 0.7
     omega_cg: float = 2.0 / 3.0
-    nu_pre: int = 2
-    nu_post: int = 2
+    nu_pre: int = 2              # block-Jacobi steps before / after the coarse correction on DG levels
+    nu_post: int = 2             # (Algorithm MGMult: nu_pre = nu, nu_post = 0)
+    nu_pre_cg: int | None = None   # point-Jacobi steps on Q1 levels (Section 5.2: pre-smoothing, then a
+    nu_post_cg: int | None = None  # few post-smoothing steps); None: the DG counts
     sigma0: float = 2.0
     coarsest_n: int = 4
     p_schedule: list = field(default_factory=list)  # explicit DG degrees after the fine one
@@ -214,6 +219,14 @@ class Hierarchy:
         self.coarse_chol = sla.cho_factor(last.A.toarray())
 
     # ------------------------------------------------------------- smoothers
+    def smoothing_counts(self, l):
+        """(pre, post) smoothing steps on level l."""
+        o = self.opts
+        if self.levels[l].kind == "dg":
+            return o.nu_pre, o.nu_post
+        return (o.nu_pre if o.nu_pre_cg is None else o.nu_pre_cg,
+                o.nu_post if o.nu_post_cg is None else o.nu_post_cg)
+
     def smooth(self, l, u, b, nsweeps):
         lev = self.levels[l]
         for _ in range(nsweeps):
@@ -225,15 +238,17 @@ class Hierarchy:
         return u
 
     def vcycle(self, l, u, b):
-        """One V(nu1, nu2) cycle on level l starting from u."""
+        """One V-cycle on level l starting from u: pre-smoothing, coarse
+        correction (one V-cycle on the next level from zero), post-smoothing."""
         if l == len(self.levels) - 1:
             return sla.cho_solve(self.coarse_chol, b)
-        u = self.smooth(l, u, b, self.opts.nu_pre)
+        pre, post = self.smoothing_counts(l)
+        u = self.smooth(l, u, b, pre)
         r = b - self.levels[l].A @ u
         P = self.P[l]
         e = self.vcycle(l + 1, np.zeros(P.shape[1]), P.T @ r)
         u = u + P @ e
-        return self.smooth(l, u, b, self.opts.nu_post)
+        return self.smooth(l, u, b, post)
 
     def precondition(self, r):
         return self.vcycle(0, np.zeros_like(r), r)
