@@ -438,17 +438,17 @@ void run(BatchPlan* B, const std::vector<Launch>& v, hipStream_t s) {
 
 // One iteration of the flexible CG for every segment; r32 holds r cast to
 // FP32 (scale s[14]) on entry and on exit.
-void iteration(BatchPlan* B, double rtol2, hipStream_t s) {
+void iteration(BatchPlan* B, hipStream_t s) {
   const hpmg::SegTable& t = B->seg;
   run(B, B->vcycle, s);                                         // z32 = M r32
   hpmg::bk_dot_z(t, B->z32, B->r, B->q, B->scal, B->partial, s);  // z.r, z.q_old
-  hpmg::bk_finalize(t, 1, B->partial, B->scal, rtol2, s);       // beta, rho
+  hpmg::bk_finalize(t, 1, B->partial, B->scal, 0.0, s);         // beta, rho
   hpmg::bk_update_p(t, B->z32, B->p, B->scal, s);               // p = z + beta p
   run(B, B->applyp, s);                                         // q = A p
   hpmg::bk_dot(t, B->p, B->q, nullptr, B->partial, s);
-  hpmg::bk_finalize(t, 2, B->partial, B->scal, rtol2, s);       // alpha
+  hpmg::bk_finalize(t, 2, B->partial, B->scal, 0.0, s);         // alpha
   hpmg::bk_update_ur(t, B->r, B->r32, B->p, B->q, B->scal, B->partial, s);
-  hpmg::bk_finalize(t, 3, B->partial, B->scal, rtol2, s);       // r.r, convergence
+  hpmg::bk_finalize(t, 3, B->partial, B->scal, 0.0, s);         // r.r, convergence (rtol^2 from scal)
   hpmg::bk_count(t, B->scal, B->count, s);
   HIPCHK(hipGetLastError());
 }
@@ -837,7 +837,7 @@ hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* cons
     // one flexible-CG iteration of every segment, captured once and replayed
     if (!B->exec) {
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      iteration(B, rtol2, s);
+      iteration(B, s);
       HIPCHK(hipStreamEndCapture(s, &B->graph));
       HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     }

@@ -266,7 +266,10 @@ __global__ __launch_bounds__(256) void k_bdot_z(SegTable t, const float* __restr
   }
 }
 
-// Per-segment scalar state (BATCH_SCAL doubles): [2] rho, [3] beta,
+// Per-segment scalar state (BATCH_SCAL doubles): [0] rtol^2 of the current
+// solve (written by op 4, which runs outside the captured iteration, so a
+// replayed graph tests against the tolerance of the call that replays it),
+// [2] rho, [3] beta,
 // [5] alpha, [6] r.r, [7] 1/||r||, [8] ||r||, [9] ||r0||^2, [10] state
 // (0 iterating, 1 recurrence converged, 2 done, 3 breakdown, 4 true residual
 // stagnated above the tolerance), [11] restart, [12] last true residual^2,
@@ -307,10 +310,11 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
       set_rr(s, t0);
       if (!finite)
         s[10] = 3.0;
-      else if (t0 <= rtol2 * s[9])
+      else if (t0 <= s[0] * s[9])
         s[10] = 1.0;
     }
   } else if (op == 4) {  // initial residual (cast to FP32 next, with scale s[7])
+    s[0] = rtol2;
     set_rr(s, t0);
     s[14] = s[7];
     s[5] = 0.0;
@@ -325,7 +329,7 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
       s[12] = t0;
       if (!finite) {
         s[10] = 3.0;
-      } else if (t0 <= rtol2 * s[9]) {
+      } else if (t0 <= s[0] * s[9]) {
         s[10] = 2.0;
       } else if (s[15] >= BATCH_MAX_RESTARTS) {
         s[10] = 4.0;  // stagnated at the FP64 rounding floor of b - A u

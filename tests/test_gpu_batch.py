@@ -187,3 +187,29 @@ def test_batch_smooth_matches_oracle(nsweeps):
         batch.smooth(ud2, bd, nsweeps, nrhs=nrhs)
         for j in range(len(PROBLEMS)):
             assert rel_err(to_host(ud2[j]), refs[j]) <= tol
+
+
+def test_batch_reuse_with_a_different_tolerance():
+    """The captured iteration reads the tolerance of the current call: a solve
+    at 1e-6 followed by one at 1e-10 on the same batch reaches 1e-10 (true
+    residual) without spurious restarts."""
+    problems = [(4, 2), (3, 3)]
+    solvers, batch = _batch(problems, max_rhs=1)
+    bh, bs = [], []
+    for j, s in enumerate(solvers):
+        b = _rhs(j, s.ndof, 1, base=SEED + 7)
+        bh.append(b)
+        bs.append(to_dev(b, torch.float64))
+    for rtol in (1e-6, 1e-10, 1e-6):
+        us = [torch.zeros(s.ndof, dtype=torch.float64, device="cuda") for s in solvers]
+        log(f"batch reuse: rtol={rtol}")
+        infos, st = batch.solve(us, bs, rtol=rtol, maxit=200, nrhs=1)
+        assert st == 0
+        for j, ((n, p), s) in enumerate(zip(problems, solvers)):
+            A = SIPG(3, n, p, KAPPA).A
+            x = to_host(us[j])
+            rr = np.linalg.norm(bh[j] - A @ x) / np.linalg.norm(bh[j])
+            log(f"  n={n} p={p}: its {infos[j].iterations} oracle residual {rr:.3e}")
+            assert rr <= 2 * rtol
+            if rtol == 1e-6:
+                assert rr > 1e-9  # stopped at the loose tolerance, not at the previous call's
