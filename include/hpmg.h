@@ -191,6 +191,30 @@ hpmg_status hpmg_solve(hpmg_handle h, double* u, const double* b, int nrhs, doub
 hpmg_status hpmg_mgmult(hpmg_handle h, double* u, const double* b, double rtol, int maxit, int exit_kind,
                         hpmg_solve_info* info, hipStream_t stream);
 
+/* Size in bytes of the static device array that hpmg_smooth_noalloc keeps its
+ * trace buffers in (one array per GPU, held until the process ends). */
+#define HPMG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* hpmg_smooth without any device allocation, for callers that cannot
+ * allocate device memory during the call (code under HIP stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * result as hpmg_smooth (same kernels: the results are identical), but the
+ * two ping-pong trace buffers live in a file-scope device array of
+ * HPMG_NOALLOC_SCRATCH_BYTES bytes whose address hpmg_setup resolved for the
+ * handle's device, instead of in memory owned by the handle; no hipMalloc,
+ * hipFree or other allocating call is made (the 16-bit types included, for
+ * which hpmg_smooth allocates traces on first use).  The handle's device must
+ * be current.  Returns HPMG_E_INVALID when 2 x the traces of nrhs right-hand
+ * sides (2 dim n^dim (p+1)^(dim-1) values each, in dtype, rounded up to 256
+ * bytes) exceed the array.  Every call on one GPU shares that GPU's array and
+ * leaves its last contents there; the projection writes every trace a sweep
+ * reads, so nothing needs clearing, but calls that overlap in time on one GPU
+ * (different streams, threads or handles) race on the array and must be
+ * serialised by the caller.  The handle's own trace state is invalidated (as
+ * u changes), so hpmg_sweep needs a new hpmg_project afterwards. */
+hpmg_status hpmg_smooth_noalloc(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nsweeps, int nrhs,
+                                hipStream_t stream);
+
 /* Release every resource of the handle (NULL is ignored). */
 void hpmg_destroy(hpmg_handle h);
 

@@ -75,6 +75,8 @@ _lib.hpmg_apply_A.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]
 _lib.hpmg_apply_A.restype = ctypes.c_int
 _lib.hpmg_smooth.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
 _lib.hpmg_smooth.restype = ctypes.c_int
+_lib.hpmg_smooth_noalloc.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
+_lib.hpmg_smooth_noalloc.restype = ctypes.c_int
 _lib.hpmg_project.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp]
 _lib.hpmg_project.restype = ctypes.c_int
 _lib.hpmg_sweep.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]
@@ -216,6 +218,14 @@ class Solver:
         c = _code(u)
         _check(_lib.hpmg_smooth(self._h, c, _ptr(u, c), _ptr(b, c), nsweeps, nrhs, _stream(stream)), "hpmg_smooth")
         return u
+
+    def smooth_noalloc(self, u, b, nsweeps: int, nrhs: int = 1, stream=None, check=True):
+        """hpmg_smooth_noalloc: hpmg_smooth with the traces in the static scratch array."""
+        c = _code(u)
+        st = _lib.hpmg_smooth_noalloc(self._h, c, _ptr(u, c), _ptr(b, c), nsweeps, nrhs, _stream(stream))
+        if check:
+            _check(st, "hpmg_smooth_noalloc")
+        return st
 
     def project(self, u, nrhs: int = 1, stream=None):
         c = _code(u)

@@ -24,6 +24,7 @@ SOURCES = [
     "cg_kernels.hip",
     "batch_kernels.hip",
     "batch.cpp",
+    "noalloc.hip",
     "dg_inst_2d_float.hip",
     "dg_inst_2d_double.hip",
     "dg_inst_2d_f16.hip",

@@ -922,6 +922,8 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
             "block_recompute must be 0, or 1 with a per-cell kappa");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
+    h->dev = dev;
+    init_noalloc_scratch(dev);
     {
       std::vector<unsigned char> m(h->ncell);
       const int n = h->n;

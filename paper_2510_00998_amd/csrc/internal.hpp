@@ -15,6 +15,10 @@ namespace detail {
 
 void set_last_error(const std::string& m);
 
+// Resolves the device address of the static scratch array of
+// hpmg_smooth_noalloc for device `dev` (current), once per device.
+void init_noalloc_scratch(int dev);
+
 
 
 struct HpmgError : std::runtime_error {
@@ -119,6 +123,7 @@ struct CGLevel {
 
 struct hpmg_ctx {
   int dim = 0, n = 0, p = 0, ncell = 0;
+  int dev = -1;  // HIP device the handle was set up on
   bool vark = false;
   double kappa_const = 1.0;
   std::vector<double> kappa;
