@@ -75,8 +75,9 @@ typedef struct {
   double sigma0;      /* penalty sigma = sigma0 (p+1)^2 / h on interior facets, 2 sigma on boundary facets (default 2) */
   double omega_dg;    /* block-Jacobi relaxation on DG levels, 0 < omega <= 1 (default 0.7) */
   double omega_cg;    /* point-Jacobi relaxation on Q1 levels (default 2/3) */
-  int nu_pre;         /* smoothing steps before the coarse correction (default 2) */
-  int nu_post;        /* smoothing steps after it (default 2) */
+  int nu_pre;         /* block-Jacobi steps on DG levels before the coarse correction (default 2) */
+  int nu_post;        /* block-Jacobi steps on DG levels after it (default 2; Algorithm MGMult of
+                         Section 5.1: nu_pre = nu, nu_post = 0) */
   int coarsest_n;     /* stop h-coarsening once n <= coarsest_n (default 4) */
   int precision;      /* hpmg_precision of the cycle inside hpmg_solve (default F32) */
   int max_rhs;        /* largest nrhs any call will use (default 1) */
@@ -92,6 +93,21 @@ typedef struct {
                          mimics inhomogeneous problems (Section 6 experiments).  Same operator and
                          iterates up to rounding; setup skips the per-cell eigendata.  Setting it with
                          constant kappa is HPMG_E_INVALID. */
+  int nu_pre_cg;      /* point-Jacobi steps on Q1 levels before their coarse correction (-1, the
+                         default: nu_pre); the h-multigrid of Section 5.2 pre- and post-smooths */
+  int nu_post_cg;     /* point-Jacobi steps on Q1 levels after it (-1, the default: nu_post) */
+  int block_variant;  /* block-Jacobi block on DG levels: 0 (default) the exact cell block A_{K<-K};
+                         1 the block of an interior cell for every cell (Section 4.1, technique
+                         approximate boundary operators: one stored block inverse; the operator A and
+                         the fixed point are unchanged).  1 needs constant kappa and n >= 3. */
+  int p_schedule[8];  /* explicit degrees of the p-coarse DG levels after the finest one, strictly
+                         decreasing, each >= 2, terminated by 0 (Q1 follows the last); p_schedule[0]
+                         = 0 (the default) takes the schedule from p_coarsening */
+  void* (*alloc)(size_t bytes, void* ctx); /* device allocator for every buffer the handle (and a batch
+                         of handles) holds, NULL (default): hipMalloc.  Must return memory of the
+                         current device aligned to 256 bytes, or NULL on failure (HPMG_E_NOMEM). */
+  void (*free)(void* ptr, void* ctx);      /* releases what alloc returned (hpmg_destroy, batch destroy) */
+  void* alloc_ctx;    /* passed to alloc and free */
 } hpmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -146,11 +162,12 @@ hpmg_status hpmg_project(hpmg_handle h, hpmg_dtype dtype, const void* u, int nrh
 hpmg_status hpmg_sweep(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nsweeps, int nrhs,
                        hipStream_t stream);
 
-/* One V(nu_pre, nu_post) cycle of the hp-multigrid in place on u
- * (Algorithm MGMult body with CoarseGridCorrection; gradual p-coarsening,
- * Q1, h-coarsening, dense coarsest solve).  One right-hand side: nrhs other
- * than 1 returns HPMG_E_INVALID (hpmg_solve takes several right-hand sides
- * one after another; hpmg_batch_solve cycles them together). */
+/* One V-cycle of the hp-multigrid in place on u (Algorithm MGMult body with
+ * CoarseGridCorrection; nu_pre / nu_post block-Jacobi steps on the DG
+ * levels, nu_pre_cg / nu_post_cg point-Jacobi steps on the Q1 levels,
+ * p-coarsening, Q1, h-coarsening, dense coarsest solve) for each of the nrhs
+ * stacked right-hand sides (1 <= nrhs <= max_rhs): the DG levels run every
+ * column in one launch per traversal, the Q1 levels column after column. */
 hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nrhs,
                         hipStream_t stream);
 
@@ -236,8 +253,10 @@ typedef struct hpmg_batch_ctx* hpmg_batch; /* opaque, owned by the library */
 /* Group `count` handles into a batch (*out; release with
  * hpmg_batch_destroy).  The handles must stay alive while the batch is
  * used, must be distinct, and must all be 3D with constant kappa,
- * 1 <= p <= 5, nu_pre >= 1, equal nu_pre, nu_post, the default p- and
- * h-coarsening and the Gauss-Lobatto basis (HPMG_E_INVALID otherwise).  The batch uses the handles' level data and workspaces:
+ * 1 <= p <= 5, nu_pre >= 1, equal smoothing counts (DG and Q1), the
+ * default p- and h-coarsening, the Gauss-Lobatto basis and the exact block
+ * (HPMG_E_INVALID otherwise).  The batch's own workspace comes from the
+ * first handle's allocator (options.alloc).  The batch uses the handles' level data and workspaces:
  * calls on a handle must not overlap a batch solve that contains it, and a
  * batch solve invalidates the handle's trace state (as hpmg_solve does). */
 hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out);

@@ -48,11 +48,18 @@ class Coeff(ctypes.Structure):
                 ("kappa", ctypes.POINTER(ctypes.c_double))]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("sigma0", ctypes.c_double), ("omega_dg", ctypes.c_double), ("omega_cg", ctypes.c_double),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("coarsest_n", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_rhs", ctypes.c_int), ("p_coarsening", ctypes.c_int),
-                ("h_factor", ctypes.c_int), ("basis", ctypes.c_int), ("block_recompute", ctypes.c_int)]
+                ("h_factor", ctypes.c_int), ("basis", ctypes.c_int), ("block_recompute", ctypes.c_int),
+                ("nu_pre_cg", ctypes.c_int), ("nu_post_cg", ctypes.c_int), ("block_variant", ctypes.c_int),
+                ("p_schedule", ctypes.c_int * 8), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -169,12 +176,37 @@ def _code(t):
 class Solver:
     """One SIPG problem -div(kappa grad u) = f on [0,1]^dim (hpmg_setup)."""
 
-    def __init__(self, dim: int, n: int, p: int, kappa=1.0, stream=None, **options):
+    def __init__(self, dim: int, n: int, p: int, kappa=1.0, stream=None, allocator=None, **options):
+        """options: fields of hpmg_options (p_schedule as a sequence of degrees);
+        allocator: optional (alloc(nbytes) -> device pointer int, free(pointer))
+        pair through which the library obtains every device buffer of the
+        handle (e.g. torch's caching allocator); kept alive with the solver."""
         opt = default_options()
         for k, v in options.items():
-            if not hasattr(opt, k):
+            if not hasattr(opt, k) or k in ("alloc", "free", "alloc_ctx"):
                 raise KeyError(f"unknown option {k}")
-            setattr(opt, k, v)
+            if k == "p_schedule":
+                sched = list(v) + [0] * (8 - len(v))
+                if len(sched) > 8:
+                    raise ValueError("p_schedule holds at most 7 degrees")
+                opt.p_schedule = (ctypes.c_int * 8)(*sched)
+            else:
+                setattr(opt, k, v)
+        self._alloc_cbs = None
+        if allocator is not None:
+            fa, ff = allocator
+
+            def _a(nbytes, _ctx):
+                try:
+                    return int(fa(int(nbytes)))
+                except Exception:
+                    return None
+
+            def _f(ptr, _ctx):
+                ff(int(ptr))
+
+            self._alloc_cbs = (ALLOC_FN(_a), FREE_FN(_f))
+            opt.alloc, opt.free = self._alloc_cbs
         mesh = Mesh(dim, (ctypes.c_int * 3)(n, n, n))
         self._kappa_buf = None
         if np.isscalar(kappa):

@@ -185,6 +185,8 @@ void build_vcycle(BatchPlan* B, const std::vector<hpmg_handle>& hs, const std::v
     lmax = std::max(lmax, ps[j].ndg + ps[j].ncg);
   }
   const hpmg_options& O = hs[0]->opt;
+  const int cg_pre = O.nu_pre_cg >= 0 ? O.nu_pre_cg : O.nu_pre;
+  const int cg_post = O.nu_post_cg >= 0 ? O.nu_post_cg : O.nu_post;
   // level-l vectors of problem j
   auto dg_u = [&](int j, int l) -> float* { return l == 0 ? B->z32 + off0[j] : hs[j]->dg[l].f.u; };
   auto dg_b = [&](int j, int l) -> float* { return l == 0 ? B->r32 + off0[j] : hs[j]->dg[l].f.b; };
@@ -219,12 +221,13 @@ void build_vcycle(BatchPlan* B, const std::vector<hpmg_handle>& hs, const std::v
       Launch L = bld.cg(t);
       if (L.nitems) out.push_back(L);
     }
-    // pre-smoothing
-    for (int i = 0; i < O.nu_pre; ++i) {
+    // pre-smoothing (DG and Q1 levels each take their own count)
+    for (int i = 0; i < std::max(O.nu_pre, cg_pre); ++i) {
       Table<hpmg::DGArgs<float>> td;
       Table<hpmg::CGArgs<float>> tc;
       for (int j : P) {
         hpmg_ctx* h = hs[j];
+        if (is_dg(j) ? i >= O.nu_pre : i >= cg_pre) continue;
         if (is_dg(j)) {
           DGLevel& L = h->dg[l];
           int& cur = ps[j].dgcur[l];
@@ -366,11 +369,12 @@ void build_vcycle(BatchPlan* B, const std::vector<hpmg_handle>& hs, const std::v
       if (L2.nitems) out.push_back(L2);
     }
     // post-smoothing
-    for (int i = 0; i < O.nu_post; ++i) {
+    for (int i = 0; i < std::max(O.nu_post, cg_post); ++i) {
       Table<hpmg::DGArgs<float>> td;
       Table<hpmg::CGArgs<float>> tc;
       for (int j : P) {
         if (coarsest(j)) continue;
+        if (is_dg(j) ? i >= O.nu_post : i >= cg_post) continue;
         hpmg_ctx* h = hs[j];
         if (is_dg(j)) {
           DGLevel& L = h->dg[l];
@@ -461,6 +465,10 @@ void residual(BatchPlan* B, bool into_z, hipStream_t s) {
 // Workspace, segment tables and launch lists for nrhs right-hand sides.
 std::unique_ptr<BatchPlan> make_plan(const std::vector<hpmg_handle>& hs, int nrhs, hipStream_t s) {
   std::unique_ptr<BatchPlan> B(new BatchPlan());
+  // the batch workspace comes from the first handle's allocator
+  B->mem.alloc_fn = hs[0]->opt.alloc;
+  B->mem.free_fn = hs[0]->opt.free;
+  B->mem.ctx = hs[0]->opt.alloc_ctx;
   B->nrhs = nrhs;
   const int np = (int)hs.size(), R = nrhs;
   // segments: one per (problem, right-hand side), [problem][rhs][dof] in
@@ -706,10 +714,12 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
       require(!h->vark, "batched solver supports constant kappa");
       require(h->p + 1 >= hpmg::BATCH_NMIN && h->p + 1 <= hpmg::BATCH_NMAX, "batched solver supports 1 <= p <= 5");
       require(h->opt.nu_pre >= 1, "batched solver needs nu_pre >= 1");
-      require(h->opt.p_coarsening == 0 && h->opt.h_factor == 2 && h->opt.basis == 0,
-              "batched solver supports the default p- and h-coarsening and basis");
-      require(h->opt.nu_pre == hs[0]->opt.nu_pre && h->opt.nu_post == hs[0]->opt.nu_post,
-              "all problems of a batch need the same nu_pre, nu_post");
+      require(h->opt.p_coarsening == 0 && h->opt.p_schedule[0] == 0 && h->opt.h_factor == 2 &&
+                  h->opt.basis == 0 && h->opt.block_variant == 0,
+              "batched solver supports the default p- and h-coarsening, basis and block");
+      require(h->opt.nu_pre == hs[0]->opt.nu_pre && h->opt.nu_post == hs[0]->opt.nu_post &&
+                  h->opt.nu_pre_cg == hs[0]->opt.nu_pre_cg && h->opt.nu_post_cg == hs[0]->opt.nu_post_cg,
+              "all problems of a batch need the same smoothing counts");
       B->hs.push_back(h);
     }
     HIPCHK(hipStreamCreateWithFlags(&B->st, hipStreamNonBlocking));

@@ -18,6 +18,12 @@ void run(int op, const DGArgs<T>& a, int nrhs, int flag, hipStream_t s) {
     case OP_PROLONG: launch_prolong<T, D, N, NC>(a, nrhs, s); break;
     case OP_RESTRICT_Q1: launch_apply<T, D, N, 2>(a, nrhs, true, s); break;
     case OP_PROLONG_Q1: launch_prolong<T, D, N, 2>(a, nrhs, s); break;
+    case OP_RESTRICT_DYN:
+      if constexpr (N >= 4) launch_apply<T, D, N, -1>(a, nrhs, true, s);
+      break;
+    case OP_PROLONG_DYN:
+      if constexpr (N >= 4) launch_prolong<T, D, N, -1>(a, nrhs, s);
+      break;
     default: break;
   }
 }

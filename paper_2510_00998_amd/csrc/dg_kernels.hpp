@@ -119,6 +119,17 @@ struct DGArgs {
   //     z * (zscaled ? kscal[8] / kmul : 1), beta = kscal[3]
   //   kdot = 1 (apply, y = A p): kpartial[block] = the block's share of p.y
   int kry = 0, kdot = 0, zkind = 0, zscaled = 0;
+  // Interior-block smoother (constant kappa; Section 4.1 technique
+  // approximate boundary operators): ivar = 1 takes the block of an interior
+  // cell (class 0 along every axis) as the block-Jacobi block D~ of every
+  // cell.  The operator stays A: a boundary facet contributes the lift of
+  // the cell's own traces with the sign reversed, i.e. (D~ - A_{K<-K}) u
+  // (the difference of the two 1D operators is the boundary-facet term,
+  // kappa/2 (e ep^T + ep e^T) - sigma_hat kappa e e^T), so that the sweep
+  // computes u + omega D~^-1 (b - A u) and the apply A u.  Traces are then
+  // stored on boundary facets too.
+  int ivar = 0;
+  int ncd = 0;         // nodes per direction of the coarse DG level (transfers with a run-time degree)
   const void* zlow = nullptr;
   const double* kscal = nullptr;
   double kmul = 1.0;

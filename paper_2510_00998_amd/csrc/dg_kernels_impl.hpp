@@ -513,9 +513,11 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
     const int lo = pass == 0 ? N * li : li;
     C* g = sNB + (cl * Sh::NF + f) * TL + lo;
     const int mask = FROM_GLOBAL ? a.bmask[c] : mask_lds<D, N, VARK>(sKF)[cl];
+    const int smask = a.ivar ? 0 : mask;  // boundary classes of the block solve
     C x1[N], x2[N], o1[N], o2[N];
     if (pass == 0) {
-      if ((mask >> f) & 1) {  // boundary facet: no neighbour, zero flux fields
+      const bool bdy = (mask >> f) & 1;
+      if (bdy && !(FROM_GLOBAL && a.ivar)) {  // boundary facet: no neighbour, zero flux fields
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           g[j] = C(0);
@@ -527,11 +529,15 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
       if constexpr (FROM_GLOBAL) {
         const int s = f & 1;
         const int stc = ipow<D>(a.n, k);
-        const T* src = tr + ((size_t)(f ^ 1) * a.ncell + (s ? c + stc : c - stc)) * TL + lo;
+        // interior-block smoother: a boundary facet reads the cell's own
+        // traces, negated
+        const T* src = bdy ? tr + ((size_t)f * a.ncell + c) * TL + lo
+                           : tr + ((size_t)(f ^ 1) * a.ncell + (s ? c + stc : c - stc)) * TL + lo;
+        const C sg = bdy ? C(-1) : C(1);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          gv[j] = src[j];
-          qv[j] = src[L + j];
+          gv[j] = sg * (C)src[j];
+          qv[j] = sg * (C)src[L + j];
         }
       } else {
 #pragma unroll
@@ -558,8 +564,8 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
       }
     }
     if (t < k) {
-      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, mask, t, x1, o1);
-      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, mask, t, x2, o2);
+      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, smask, t, x1, o1);
+      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, smask, t, x2, o2);
     } else {
       mv<N, false>(Mh, x1, o1);
       mv<N, false>(Mh, x2, o2);
@@ -705,7 +711,13 @@ __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int
   int* sMask = mask_lds<D, N, VARK>(sKF);
   const int tid = work_tid<D, N>();
   if constexpr (!VARK && AT_ONCE) {
-    facet_pass0_const<T, D, N>(a, tr, c0, nc, sNB, sE, sMask);
+    if (a.ivar) {  // interior-block smoother: item after item (boundary facets read own traces)
+      facet_pass<T, D, N, false, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
+      load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
+      if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
+    } else {
+      facet_pass0_const<T, D, N>(a, tr, c0, nc, sNB, sE, sMask);
+    }
     __syncthreads();
   } else if constexpr (!VARK) {
     facet_pass<T, D, N, false, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
@@ -786,12 +798,12 @@ __device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, 
       g1 += ev1[j] * u[j];
     }
   }
-  if (!((mask >> (2 * k)) & 1)) {
+  if (a.ivar || !((mask >> (2 * k)) & 1)) {
     T* t0 = trout + ((size_t)(2 * k) * a.ncell + c) * TL;
     t0[ln] = g0;
     t0[L + ln] = d0;
   }
-  if (!((mask >> (2 * k + 1)) & 1)) {
+  if (a.ivar || !((mask >> (2 * k + 1)) & 1)) {
     T* t1 = trout + ((size_t)(2 * k + 1) * a.ncell + c) * TL;
     t1[ln] = g1;
     t1[L + ln] = d1;
@@ -872,6 +884,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
   const int mask = a.bmask[c];
+  const int smask = a.ivar ? 0 : mask;  // boundary classes of the block solve
 
   C ul[N], bl[N];
   if (act) {
@@ -914,22 +927,22 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
       if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
-      stage_mv<T, D, N, VARK, true, false>(a, sE, cl, mask, k, r, t);  // S^T
+      stage_mv<T, D, N, VARK, true, false>(a, sE, cl, smask, k, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
-        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
-        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
+        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(smask, 0) * Sh::EGS;
+        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(smask, 1) * Sh::EGS;
         if constexpr (D == 2) {
           const C ls = E0[2 * NN + ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= recip(ls + E1[2 * NN + j]);
         } else {
-          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
+          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(smask, 2) * Sh::EGS;
           const C ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= recip(ls + E2[2 * NN + j]);
         }
-        stage_mv<T, D, N, VARK, false, false>(a, sE, cl, mask, k, t, r);  // S
+        stage_mv<T, D, N, VARK, false, false>(a, sE, cl, smask, k, t, r);  // S
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
       }
@@ -948,7 +961,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
       C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, false, false>(a, sE, cl, mask, k, r, t);
+      stage_mv<T, D, N, VARK, false, false>(a, sE, cl, smask, k, r, t);
       if (k == 0) {
         T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
@@ -1009,6 +1022,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
   const int mask = a.bmask[c];
+  const int smask = a.ivar ? 0 : mask;  // boundary classes of the block solve
 
   C ul[N], bl[N];
   if (act) {
@@ -1038,21 +1052,21 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
-      stage_mv<T, D, N, VARK, false, true>(a, sE, cl, mask, k, r, t);  // Si
+      stage_mv<T, D, N, VARK, false, true>(a, sE, cl, smask, k, r, t);  // Si
       if (k == D - 1) {
-        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(mask, 0) * Sh::EGS;
-        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(mask, 1) * Sh::EGS;
+        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(smask, 0) * Sh::EGS;
+        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(smask, 1) * Sh::EGS;
         if constexpr (D == 2) {
           const C ls = E0[2 * NN + ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + E1[2 * NN + j]);
         } else {
-          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(mask, 2) * Sh::EGS;
+          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(smask, 2) * Sh::EGS;
           const C ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + E2[2 * NN + j]);
         }
-        stage_mv<T, D, N, VARK, true, true>(a, sE, cl, mask, k, t, r);  // Si^T
+        stage_mv<T, D, N, VARK, true, true>(a, sE, cl, smask, k, t, r);  // Si^T
         add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, r);
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
@@ -1069,7 +1083,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, true, true>(a, sE, cl, mask, k, r, t);
+      stage_mv<T, D, N, VARK, true, true>(a, sE, cl, smask, k, r, t);
       add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, t);
       if (k == 0) {
 #pragma unroll
@@ -1094,7 +1108,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
         for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
       }
     }
-    if (k > 0 || NC > 0) __syncthreads();
+    if (k > 0 || NC != 0) __syncthreads();
   }
   if constexpr (std::is_same<T, double>::value && NC == 0 && !RESID) {
     if (a.kdot) {
@@ -1102,72 +1116,83 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       block_partial(pdot, sh, a.kpartial + bx);
     }
   }
-  if constexpr (NC > 0) {
+  if constexpr (NC != 0) {
     // restriction (E^T)^(x d) of the cell residual, one axis per pass; sNB
-    // is free once every lift has been read (barrier above)
+    // is free once every lift has been read (barrier above).  NC < 0: the
+    // coarse node count ncr comes at run time (a.ncd <= N), loops run to N.
+    constexpr int NCB = NC > 0 ? NC : N;
+    const int ncr = NC > 0 ? NC : a.ncd;
     const cptr<C> E = as_const(a.ref) + RefOff<N>::E;
-    constexpr int NCD = (D == 2) ? NC * NC : NC * NC * NC;
+    const int NCD = (D == 2) ? ncr * ncr : ncr * ncr * ncr;
     constexpr int NBS = Sh::NF * 2 * L;  // per-cell stride of sNB
     C* dst = a.out + (size_t)by * a.cstride + (size_t)c0 * NCD;
-    // x: sW[cl][..][a] -> sNB[cl][ln][a'] (a' + NC*ln)
+    // x: sW[cl][..][a] -> sNB[cl][ln][a'] (a' + ncr*ln)
     for (int i = tid; i < nc * L; i += Sh::NT) {
       const int c2 = i / L, l2 = i % L;
       C x[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + j + N * l2];
 #pragma unroll
-      for (int jc = 0; jc < NC; ++jc) {
-        C s = 0;
+      for (int jc = 0; jc < NCB; ++jc) {
+        if (jc < ncr) {
+          C s = 0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) s += E[j * NC + jc] * x[j];
-        sNB[c2 * NBS + jc + NC * l2] = s;
+          for (int j = 0; j < N; ++j) s += E[j * ncr + jc] * x[j];
+          sNB[c2 * NBS + jc + ncr * l2] = s;
+        }
       }
     }
     __syncthreads();
     if constexpr (D == 2) {
-      // y: sNB[cl][b][a'] -> dst[a' + NC b']
-      for (int i = tid; i < nc * NC; i += Sh::NT) {
-        const int c2 = i / NC, ac = i % NC;
+      // y: sNB[cl][b][a'] -> dst[a' + ncr b']
+      for (int i = tid; i < nc * ncr; i += Sh::NT) {
+        const int c2 = i / ncr, ac = i % ncr;
         C x[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + NC * j];
+        for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + ncr * j];
 #pragma unroll
-        for (int bc = 0; bc < NC; ++bc) {
-          C s = 0;
+        for (int bc = 0; bc < NCB; ++bc) {
+          if (bc < ncr) {
+            C s = 0;
 #pragma unroll
-          for (int j = 0; j < N; ++j) s += E[j * NC + bc] * x[j];
-          dst[(size_t)c2 * NCD + ac + NC * bc] = s;
+            for (int j = 0; j < N; ++j) s += E[j * ncr + bc] * x[j];
+            dst[(size_t)c2 * NCD + ac + ncr * bc] = s;
+          }
         }
       }
     } else {
-      // y: sNB[cl][c][b][a'] (a' + NC(b + N c)) -> sW[cl][c][b'][a'] (a' + NC(b' + NC c))
-      for (int i = tid; i < nc * NC * N; i += Sh::NT) {
-        const int c2 = i / (NC * N), rem = i % (NC * N);
-        const int ac = rem % NC, cz = rem / NC;
+      // y: sNB[cl][c][b][a'] (a' + ncr(b + N c)) -> sW[cl][c][b'][a'] (a' + ncr(b' + ncr c))
+      for (int i = tid; i < nc * ncr * N; i += Sh::NT) {
+        const int c2 = i / (ncr * N), rem = i % (ncr * N);
+        const int ac = rem % ncr, cz = rem / ncr;
         C x[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + NC * (j + N * cz)];
+        for (int j = 0; j < N; ++j) x[j] = sNB[c2 * NBS + ac + ncr * (j + N * cz)];
 #pragma unroll
-        for (int bc = 0; bc < NC; ++bc) {
-          C s = 0;
+        for (int bc = 0; bc < NCB; ++bc) {
+          if (bc < ncr) {
+            C s = 0;
 #pragma unroll
-          for (int j = 0; j < N; ++j) s += E[j * NC + bc] * x[j];
-          sW[c2 * Sh::NV + ac + NC * (bc + NC * cz)] = s;
+            for (int j = 0; j < N; ++j) s += E[j * ncr + bc] * x[j];
+            sW[c2 * Sh::NV + ac + ncr * (bc + ncr * cz)] = s;
+          }
         }
       }
       __syncthreads();
-      // z: sW[cl][c][b'][a'] -> dst[a' + NC b' + NC^2 c']
-      for (int i = tid; i < nc * NC * NC; i += Sh::NT) {
-        const int c2 = i / (NC * NC), rem = i % (NC * NC);
+      // z: sW[cl][c][b'][a'] -> dst[a' + ncr b' + ncr^2 c']
+      for (int i = tid; i < nc * ncr * ncr; i += Sh::NT) {
+        const int c2 = i / (ncr * ncr), rem = i % (ncr * ncr);
         C x[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + rem + NC * NC * j];
+        for (int j = 0; j < N; ++j) x[j] = sW[c2 * Sh::NV + rem + ncr * ncr * j];
 #pragma unroll
-        for (int ccz = 0; ccz < NC; ++ccz) {
-          C s = 0;
+        for (int ccz = 0; ccz < NCB; ++ccz) {
+          if (ccz < ncr) {
+            C s = 0;
 #pragma unroll
-          for (int j = 0; j < N; ++j) s += E[j * NC + ccz] * x[j];
-          dst[(size_t)c2 * NCD + rem + NC * NC * ccz] = s;
+            for (int j = 0; j < N; ++j) s += E[j * ncr + ccz] * x[j];
+            dst[(size_t)c2 * NCD + rem + ncr * ncr * ccz] = s;
+          }
         }
       }
     }
@@ -1196,7 +1221,7 @@ template <typename T, int D, int N, int NC>
 constexpr int prolong_lds_bytes() {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
-  return (int)sizeof(C) * (Sh::CPB * Sh::NV + (NC > 0 ? Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L : 0));
+  return (int)sizeof(C) * (Sh::CPB * Sh::NV + (NC != 0 ? Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L : 0));
 }
 
 template <typename T, int D, int N, int NC>
@@ -1216,7 +1241,11 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
   const bool act = tid < Sh::NT && cl < nc;
   const int c = c0 + (act ? cl : 0);
   const int mask = a.bmask[c];
-  constexpr int NCD = (NC == 0) ? 0 : ((D == 2) ? NC * NC : NC * NC * NC);
+  // NC < 0: coarse node count ncr at run time (a.ncd <= N); loops run to
+  // NCB = N with the entries past ncr skipped
+  constexpr int NCB = NC > 0 ? NC : (NC < 0 ? N : 1);
+  const int ncr = NC >= 0 ? NC : a.ncd;
+  const int NCD = (NC == 0) ? 0 : ((D == 2) ? ncr * ncr : ncr * ncr * ncr);
 
   C u[N];
   if (act) {
@@ -1239,7 +1268,7 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
       }
     }
   }
-  if constexpr (NC > 0) {
+  if constexpr (NC != 0) {
     const C* cs = a.coarse + (size_t)by * a.cstride;
     if (!a.coarse_cg) {
       for (int i = tid; i < nc * NCD; i += Sh::NT) sW[(i / NCD) * Sh::NV + i % NCD] = cs[(size_t)c0 * NCD + i];
@@ -1270,54 +1299,54 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
     const cptr<C> E = as_const(a.ref) + RefOff<N>::E;
     if constexpr (D == 3) {
       // z: [c'][b'][a'] -> sNB[cl][c][b'][a'] (a' + NC b' + NC^2 c)
-      for (int i = tid; i < nc * NC * NC; i += Sh::NT) {
-        const int c2 = i / (NC * NC), rem = i % (NC * NC);
-        C x[NC];
+      for (int i = tid; i < nc * ncr * ncr; i += Sh::NT) {
+        const int c2 = i / (ncr * ncr), rem = i % (ncr * ncr);
+        C x[NCB];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) x[j] = sW[c2 * Sh::NV + rem + NC * NC * j];
+        for (int j = 0; j < NCB; ++j) x[j] = j >= ncr ? C(0) : sW[c2 * Sh::NV + rem + ncr * ncr * min(j, ncr - 1)];
 #pragma unroll
         for (int cz = 0; cz < N; ++cz) {
           C s = 0;
 #pragma unroll
-          for (int j = 0; j < NC; ++j) s += E[cz * NC + j] * x[j];
-          sNB[c2 * Sh::NF * 2 * L + rem + NC * NC * cz] = s;
+          for (int j = 0; j < NCB; ++j) s += E[cz * ncr + min(j, ncr - 1)] * x[j];  // x[j] = 0 past ncr
+          sNB[c2 * Sh::NF * 2 * L + rem + ncr * ncr * cz] = s;
         }
       }
       __syncthreads();
       // y: sNB[c][b'][a'] -> sW[cl][c][b][a'] (a' + NC b + NC N c)
-      for (int i = tid; i < nc * NC * N; i += Sh::NT) {
-        const int c2 = i / (NC * N), rem = i % (NC * N);
-        const int ac = rem % NC, cz = rem / NC;
-        C x[NC];
+      for (int i = tid; i < nc * ncr * N; i += Sh::NT) {
+        const int c2 = i / (ncr * N), rem = i % (ncr * N);
+        const int ac = rem % ncr, cz = rem / ncr;
+        C x[NCB];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) x[j] = sNB[c2 * Sh::NF * 2 * L + ac + NC * j + NC * NC * cz];
+        for (int j = 0; j < NCB; ++j) x[j] = j >= ncr ? C(0) : sNB[c2 * Sh::NF * 2 * L + ac + ncr * min(j, ncr - 1) + ncr * ncr * cz];
 #pragma unroll
         for (int by = 0; by < N; ++by) {
           C s = 0;
 #pragma unroll
-          for (int j = 0; j < NC; ++j) s += E[by * NC + j] * x[j];
-          sW[c2 * Sh::NV + ac + NC * (by + N * cz)] = s;
+          for (int j = 0; j < NCB; ++j) s += E[by * ncr + min(j, ncr - 1)] * x[j];  // x[j] = 0 past ncr
+          sW[c2 * Sh::NV + ac + ncr * (by + N * cz)] = s;
         }
       }
       __syncthreads();
     } else {
       // y: [b'][a'] -> sNB[cl][b][a'] -> copy back into sW layout (a' + NC b)
-      for (int i = tid; i < nc * NC; i += Sh::NT) {
-        const int c2 = i / NC, ac = i % NC;
-        C x[NC];
+      for (int i = tid; i < nc * ncr; i += Sh::NT) {
+        const int c2 = i / ncr, ac = i % ncr;
+        C x[NCB];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) x[j] = sW[c2 * Sh::NV + ac + NC * j];
+        for (int j = 0; j < NCB; ++j) x[j] = j >= ncr ? C(0) : sW[c2 * Sh::NV + ac + ncr * min(j, ncr - 1)];
 #pragma unroll
         for (int by = 0; by < N; ++by) {
           C s = 0;
 #pragma unroll
-          for (int j = 0; j < NC; ++j) s += E[by * NC + j] * x[j];
-          sNB[c2 * Sh::NF * 2 * L + ac + NC * by] = s;
+          for (int j = 0; j < NCB; ++j) s += E[by * ncr + min(j, ncr - 1)] * x[j];  // x[j] = 0 past ncr
+          sNB[c2 * Sh::NF * 2 * L + ac + ncr * by] = s;
         }
       }
       __syncthreads();
-      for (int i = tid; i < nc * NC * N; i += Sh::NT) {
-        const int c2 = i / (NC * N), rem = i % (NC * N);
+      for (int i = tid; i < nc * ncr * N; i += Sh::NT) {
+        const int c2 = i / (ncr * N), rem = i % (ncr * N);
         sW[c2 * Sh::NV + rem] = sNB[c2 * Sh::NF * 2 * L + rem];
       }
       __syncthreads();
@@ -1328,16 +1357,16 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
   T* trout = a.tr_out + rt;
   if (act) {
     const int base = cl * Sh::NV + line_base<D, N>(0, ln);
-    if constexpr (NC > 0) {
+    if constexpr (NC != 0) {
       const cptr<C> E = as_const(a.ref) + RefOff<N>::E;
-      C x[NC];
+      C x[NCB];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) x[j] = sW[cl * Sh::NV + j + NC * ln];
+      for (int j = 0; j < NCB; ++j) x[j] = j >= ncr ? C(0) : sW[cl * Sh::NV + min(j, ncr - 1) + ncr * ln];
 #pragma unroll
       for (int ax = 0; ax < N; ++ax) {
         C s = 0;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) s += E[ax * NC + j] * x[j];
+        for (int j = 0; j < NCB; ++j) s += E[ax * ncr + min(j, ncr - 1)] * x[j];  // x[j] = 0 past ncr
         u[ax] += s;
       }
       T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base;

@@ -540,34 +540,47 @@ void apply(hpmg_ctx* h, int l, const T* u, const T* tr, const T* b, T* out, int 
   dg_run(h, hpmg::OP_APPLY, a, L.N, nrhs, b ? 1 : 0, s);
 }
 
+// Smoothing steps on the Q1 levels (their own counts, or the DG ones).
+int cg_nu_pre(const hpmg_ctx* h) { return h->opt.nu_pre_cg >= 0 ? h->opt.nu_pre_cg : h->opt.nu_pre; }
+int cg_nu_post(const hpmg_ctx* h) { return h->opt.nu_post_cg >= 0 ? h->opt.nu_post_cg : h->opt.nu_post; }
+
+// The Q1 part of a V-cycle for right-hand side `col` (the level vectors
+// hold max_rhs columns of L.size entries each).
 template <typename T>
-void vcycle_cg(hpmg_ctx* h, int m, bool uzero, hipStream_t s) {
+void vcycle_cg(hpmg_ctx* h, int m, bool uzero, int col, hipStream_t s) {
   CGLevel& L = h->cg[m];
   CGData<T>& d = data<T>(L);
   const int D = h->dim;
+  const size_t o = (size_t)col * L.size;
+  T* u[2] = {d.u[0] + o, d.u[1] + o};
+  T* b = d.b + o;
+  T* r = d.r + o;
   if (m + 1 == (int)h->cg.size()) {
-    hpmg::dense_solve<T>(h->coarse_m, h->coarse_inv, d.b, d.u[0], s);
+    hpmg::dense_solve<T>(h->coarse_m, h->coarse_inv, b, u[0], s);
     L.cur = 0;
     HIPCHK(hipGetLastError());
     return;
   }
   const T w = (T)h->opt.omega_cg;
+  const int npre = cg_nu_pre(h), npost = cg_nu_post(h);
   const int nlev = (int)h->cg.size() - m;
   if (uzero && L.size <= (size_t)hpmg::CG_BLOCK_MAX_VERTICES && nlev <= hpmg::CG_BLOCK_MAX_LEVELS) {
     // this level and all coarser ones are small: the rest of the cycle in
     // one workgroup
     hpmg::CGBlockArgs<T> a{};
     a.nlev = nlev;
-    a.nu_pre = h->opt.nu_pre;
-    a.nu_post = h->opt.nu_post;
+    a.nu_pre = npre;
+    a.nu_post = npost;
     a.m = h->coarse_m;
     a.omega = w;
     a.Ainv = h->coarse_inv;
     for (int k = 0; k < nlev; ++k) {
       CGLevel& Lk = h->cg[m + k];
       CGData<T>& dk = data<T>(Lk);
-      a.lv[k] = {Lk.nv, dk.st, dk.dinv, {dk.u[0], dk.u[1]}, dk.b, dk.r, Lk.ridx, dk.rw, Lk.pidx, dk.pw};
-      Lk.cur = k + 1 == nlev ? 0 : (h->opt.nu_pre + h->opt.nu_post) & 1;
+      const size_t ok = (size_t)col * Lk.size;
+      a.lv[k] = {Lk.nv, dk.st, dk.dinv, {dk.u[0] + ok, dk.u[1] + ok}, dk.b + ok, dk.r + ok, Lk.ridx, dk.rw,
+                 Lk.pidx, dk.pw};
+      Lk.cur = k + 1 == nlev ? 0 : (npre + npost) & 1;
     }
     hpmg::cg_vcycle_block<T>(D, L.rk, a, s);
     HIPCHK(hipGetLastError());
@@ -575,34 +588,37 @@ void vcycle_cg(hpmg_ctx* h, int m, bool uzero, hipStream_t s) {
   }
   int cur = 0;
   bool zero = uzero;
-  for (int i = 0; i < h->opt.nu_pre; ++i) {
-    hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, d.u[cur], d.b, d.u[cur ^ 1], w, 0, zero ? 1 : 0, s);
+  for (int i = 0; i < npre; ++i) {
+    hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, u[cur], b, u[cur ^ 1], w, 0, zero ? 1 : 0, s);
     cur ^= 1;
     zero = false;
   }
   if (zero) {
-    hpmg::fill<T>(d.u[cur], L.size, T(0), s);
+    hpmg::fill<T>(u[cur], L.size, T(0), s);
     zero = false;
   }
-  hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, d.u[cur], d.b, d.r, w, 1, 0, s);
+  hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, u[cur], b, r, w, 1, 0, s);
   CGLevel& C = h->cg[m + 1];
   CGData<T>& dc = data<T>(C);
-  hpmg::cg_restrict<T>(D, L.nv, C.nv, L.rk, L.ridx, d.rw, d.r, dc.b, s);
-  vcycle_cg<T>(h, m + 1, true, s);
-  hpmg::cg_prolong<T>(D, L.nv, C.nv, L.pidx, d.pw, dc.u[C.cur], d.u[cur], s);
-  for (int i = 0; i < h->opt.nu_post; ++i) {
-    hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, d.u[cur], d.b, d.u[cur ^ 1], w, 0, 0, s);
+  const size_t oc = (size_t)col * C.size;
+  hpmg::cg_restrict<T>(D, L.nv, C.nv, L.rk, L.ridx, d.rw, r, dc.b + oc, s);
+  vcycle_cg<T>(h, m + 1, true, col, s);
+  hpmg::cg_prolong<T>(D, L.nv, C.nv, L.pidx, d.pw, dc.u[C.cur] + oc, u[cur], s);
+  for (int i = 0; i < npost; ++i) {
+    hpmg::cg_stencil<T>(D, L.nv, d.st, d.dinv, u[cur], b, u[cur ^ 1], w, 0, 0, s);
     cur ^= 1;
   }
   L.cur = cur;
   HIPCHK(hipGetLastError());
 }
 
-// One V-cycle on DG level l; u, b are the level's vectors (for l = 0 the
-// caller's).  Traversals on the level: [projection], nu_pre sweeps,
-// residual + restriction, prolongation + projection, nu_post sweeps.
+// One V-cycle on DG level l for nrhs stacked right-hand sides; u, b are the
+// level's vectors (for l = 0 the caller's).  Traversals on the level:
+// [projection], nu_pre sweeps, residual + restriction, prolongation +
+// projection, nu_post sweeps (each one launch over all columns); the Q1
+// levels run column after column.
 template <typename T>
-void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) {
+void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, int nrhs, hipStream_t s) {
   // 16-bit storage applies to this level only: the coarser levels run in
   // the compute type C
   using C = hpmg::CT<T>;
@@ -611,12 +627,12 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) 
   int cur = 0;
   bool zero = uzero;
   if (zero && h->opt.nu_pre == 0) {
-    hpmg::fill<T>(u, L.ndof, T(0), s);
+    hpmg::fill<T>(u, L.ndof * nrhs, T(0), s);
     zero = false;
   }
-  if (!zero) project<T>(h, l, u, d.tr[0], 1, s);
+  if (!zero) project<T>(h, l, u, d.tr[0], nrhs, s);
   for (int i = 0; i < h->opt.nu_pre; ++i) {
-    sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], zero, 1, s);
+    sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], zero, nrhs, s);
     cur ^= 1;
     zero = false;
   }
@@ -630,8 +646,9 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) 
     DGData<C>& dc = data<C>(Cl);
     a.out = dc.b;
     a.cstride = (long long)Cl.ndof;
-    dg_run(h, hpmg::OP_RESTRICT, a, L.N, 1, 1, s);
-    vcycle_dg<C>(h, l + 1, dc.u, dc.b, true, s);
+    a.ncd = Cl.N;
+    dg_run(h, L.dyn_nc ? hpmg::OP_RESTRICT_DYN : hpmg::OP_RESTRICT, a, L.N, nrhs, 1, s);
+    vcycle_dg<C>(h, l + 1, dc.u, dc.b, true, nrhs, s);
     hpmg::DGArgs<T> pa = dg_args<T>(h, L);
     pa.u_in = u;
     pa.u_out = u;
@@ -639,15 +656,19 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) 
     pa.coarse = dc.u;
     pa.coarse_cg = 0;
     pa.cstride = (long long)Cl.ndof;
-    dg_run(h, hpmg::OP_PROLONG, pa, L.N, 1, 0, s);
+    pa.ncd = Cl.N;
+    dg_run(h, L.dyn_nc ? hpmg::OP_PROLONG_DYN : hpmg::OP_PROLONG, pa, L.N, nrhs, 0, s);
   } else {
     CGLevel& Cg = h->cg[0];
     CGData<C>& dc = data<C>(Cg);
+    const size_t nct = (size_t)h->ncell << h->dim;
     a.out = data<C>(L).contrib;
-    a.cstride = (long long)h->ncell << h->dim;
-    dg_run(h, hpmg::OP_RESTRICT_Q1, a, L.N, 1, 1, s);
-    hpmg::gather_corners<C>(h->dim, h->n, data<C>(L).contrib, dc.b, s);
-    vcycle_cg<C>(h, 0, true, s);
+    a.cstride = (long long)nct;
+    dg_run(h, hpmg::OP_RESTRICT_Q1, a, L.N, nrhs, 1, s);
+    for (int c = 0; c < nrhs; ++c) {
+      hpmg::gather_corners<C>(h->dim, h->n, data<C>(L).contrib + c * nct, dc.b + c * Cg.size, s);
+      vcycle_cg<C>(h, 0, true, c, s);
+    }
     hpmg::DGArgs<T> pa = dg_args<T>(h, L);
     pa.u_in = u;
     pa.u_out = u;
@@ -655,10 +676,10 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, hipStream_t s) 
     pa.coarse = dc.u[Cg.cur];
     pa.coarse_cg = 1;
     pa.cstride = (long long)Cg.size;
-    dg_run(h, hpmg::OP_PROLONG_Q1, pa, L.N, 1, 0, s);
+    dg_run(h, hpmg::OP_PROLONG_Q1, pa, L.N, nrhs, 0, s);
   }
   for (int i = 0; i < h->opt.nu_post; ++i) {
-    sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], false, 1, s);
+    sweep<T>(h, l, u, b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, s);
     cur ^= 1;
   }
 }
@@ -739,18 +760,18 @@ void precondition(hpmg_ctx* h, double rms, hipStream_t stream) {
   const size_t nd = h->ndof;
   if (h->opt.precision == HPMG_PREC_F32) {
     hpmg::cast_down<float>(nd, h->r, h->r32, h->scal, 1.0, stream);
-    vcycle_dg<float>(h, 0, h->z32, h->r32, true, stream);
+    vcycle_dg<float>(h, 0, h->z32, h->r32, true, 1, stream);
     hpmg::cast_up<float>(nd, h->z32, h->z, h->scal, 1.0, stream);
   } else if (h->opt.precision == HPMG_PREC_F16) {
     hpmg::cast_down<_Float16>(nd, h->r, h->r16, h->scal, rms, stream);
-    vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, stream);
+    vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, 1, stream);
     hpmg::cast_up<_Float16>(nd, h->z16, h->z, h->scal, rms, stream);
   } else if (h->opt.precision == HPMG_PREC_BF16) {
     hpmg::cast_down<__bf16>(nd, h->r, h->rb16, h->scal, rms, stream);
-    vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, stream);
+    vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, 1, stream);
     hpmg::cast_up<__bf16>(nd, h->zb16, h->z, h->scal, rms, stream);
   } else {
-    vcycle_dg<double>(h, 0, h->z, h->r, true, stream);
+    vcycle_dg<double>(h, 0, h->z, h->r, true, 1, stream);
   }
 }
 
@@ -786,7 +807,7 @@ void fcg_iteration(hpmg_ctx* h, double rms, int restart, hipStream_t s) {
   switch (h->opt.precision) {
     case HPMG_PREC_F32:
       if (restart) hpmg::cast_down<float>(nd, h->r, h->r32, nullptr, 1.0, s);
-      vcycle_dg<float>(h, 0, h->z32, h->r32, true, s);
+      vcycle_dg<float>(h, 0, h->z32, h->r32, true, 1, s);
       hpmg::krylov_dot_lowz<float>(nd, h->z32, 0, 1.0, h->r, h->rold, h->partial, h->scal, restart, s);
       r32_next = h->r32;
       zl = h->z32;
@@ -794,7 +815,7 @@ void fcg_iteration(hpmg_ctx* h, double rms, int restart, hipStream_t s) {
       break;
     case HPMG_PREC_F16:
       hpmg::cast_down<_Float16>(nd, h->r, h->r16, h->scal, rms, s);
-      vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, s);
+      vcycle_dg<_Float16>(h, 0, h->z16, h->r16, true, 1, s);
       hpmg::krylov_dot_lowz<_Float16>(nd, h->z16, 1, rms, h->r, h->rold, h->partial, h->scal, restart, s);
       zl = h->z16;
       zkind = HPMG_F16;
@@ -803,7 +824,7 @@ void fcg_iteration(hpmg_ctx* h, double rms, int restart, hipStream_t s) {
       break;
     case HPMG_PREC_BF16:
       hpmg::cast_down<__bf16>(nd, h->r, h->rb16, h->scal, rms, s);
-      vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, s);
+      vcycle_dg<__bf16>(h, 0, h->zb16, h->rb16, true, 1, s);
       hpmg::krylov_dot_lowz<__bf16>(nd, h->zb16, 1, rms, h->r, h->rold, h->partial, h->scal, restart, s);
       zl = h->zb16;
       zkind = HPMG_BF16;
@@ -811,7 +832,7 @@ void fcg_iteration(hpmg_ctx* h, double rms, int restart, hipStream_t s) {
       mul = rms;
       break;
     default:
-      vcycle_dg<double>(h, 0, h->z, h->r, true, s);
+      vcycle_dg<double>(h, 0, h->z, h->r, true, 1, s);
       hpmg::krylov_dot(nd, h->z, h->r, h->rold, h->partial, h->scal, 1, 0, restart, s);
   }
   // p = z + beta p and its traces in one pass
@@ -858,6 +879,13 @@ void hpmg_default_options(hpmg_options* o) {
   o->h_factor = 2;
   o->basis = 0;
   o->block_recompute = 0;
+  o->nu_pre_cg = -1;
+  o->nu_post_cg = -1;
+  o->block_variant = 0;
+  for (int i = 0; i < 8; ++i) o->p_schedule[i] = 0;
+  o->alloc = nullptr;
+  o->free = nullptr;
+  o->alloc_ctx = nullptr;
 }
 
 const char* hpmg_status_string(hpmg_status s) {
@@ -905,6 +933,12 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     require(h->opt.p_coarsening == 0 || h->opt.p_coarsening == 1, "p_coarsening must be 0 or 1");
     require(h->opt.h_factor == 2 || h->opt.h_factor == 3, "h_factor must be 2 or 3");
     require(h->opt.basis == 0 || h->opt.basis == 1, "basis must be 0 (Gauss-Lobatto) or 1 (Gauss-Legendre)");
+    require(h->opt.nu_pre_cg >= -1 && h->opt.nu_post_cg >= -1, "nu_pre_cg / nu_post_cg must be >= -1");
+    require(h->opt.block_variant == 0 || h->opt.block_variant == 1, "block_variant must be 0 or 1");
+    require((h->opt.alloc == nullptr) == (h->opt.free == nullptr), "alloc and free must be given together");
+    h->mem.alloc_fn = h->opt.alloc;
+    h->mem.free_fn = h->opt.free;
+    h->mem.ctx = h->opt.alloc_ctx;
     h->dim = mesh->dim;
     h->n = mesh->n[0];
     h->p = p;
@@ -920,6 +954,16 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     }
     require(h->opt.block_recompute == 0 || (h->opt.block_recompute == 1 && h->vark),
             "block_recompute must be 0, or 1 with a per-cell kappa");
+    require(h->opt.block_variant == 0 || (!h->vark && h->n >= 3),
+            "block_variant 1 (interior block) needs constant kappa and n >= 3");
+    for (int i = 0, prev = p; i < 8 && h->opt.p_schedule[i] != 0; prev = h->opt.p_schedule[i], ++i)
+      require(h->opt.p_schedule[i] >= 2 && h->opt.p_schedule[i] < prev,
+              "p_schedule must be strictly decreasing, each entry in [2, p)");
+    {
+      const int npre = h->opt.nu_pre_cg >= 0 ? h->opt.nu_pre_cg : h->opt.nu_pre;
+      const int npost = h->opt.nu_post_cg >= 0 ? h->opt.nu_post_cg : h->opt.nu_post;
+      require(npre + npost > 0 || h->n <= h->opt.coarsest_n, "the Q1 levels need at least one smoothing step");
+    }
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     h->dev = dev;
@@ -939,10 +983,14 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
       }
       h->bmask = h->mem.upload(m, stream);
     }
-    // DG levels: p, floor(p/2), ... while >= 2, then Q1
+    // DG levels: p, then the explicit schedule, or floor(p/2), ... while
+    // >= 2 (p_coarsening 0), or none (1); then Q1
     std::vector<int> degs = {p};
-    if (h->opt.p_coarsening == 0)
+    if (h->opt.p_schedule[0] != 0) {
+      for (int i = 0; i < 8 && h->opt.p_schedule[i] != 0; ++i) degs.push_back(h->opt.p_schedule[i]);
+    } else if (h->opt.p_coarsening == 0) {
       for (int q = p / 2; q >= 2; q /= 2) degs.push_back(q);
+    }
     const double sigma_hat = h->opt.sigma0 * (p + 1.0) * (p + 1.0);
     std::vector<hpmg::Basis1D> bases;
     for (int q : degs) bases.push_back(hpmg::make_basis(q, h->opt.basis == 1));
@@ -953,7 +1001,9 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
       L.N = degs[l] + 1;
       L.next_cg = (l + 1 == degs.size());
       L.NC = L.next_cg ? 2 : degs[l + 1] + 1;
-      require(L.next_cg || L.NC == hpmg::nc_next(L.N), "internal: p schedule mismatch");
+      // transfers to a DG level other than the halved degree take the
+      // kernels with a run-time coarse degree
+      L.dyn_nc = !L.next_cg && L.NC != hpmg::nc_next(L.N);
       L.sigma_hat = sigma_hat;
       build_dg_level(h.get(), L, bases[l], L.next_cg ? nullptr : &bases[l + 1], stream);
       const size_t R = h->opt.max_rhs;
@@ -1175,12 +1225,12 @@ hpmg_status hpmg_sweep(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, 
 hpmg_status hpmg_vcycle(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, int nrhs, hipStream_t stream) {
   try {
     require(h && u && b, "NULL argument");
-    require(nrhs == 1, "vcycle supports nrhs == 1");
+    require(nrhs >= 1 && nrhs <= h->opt.max_rhs, "nrhs out of range");
     require(dtype >= HPMG_F64 && dtype <= HPMG_BF16, "bad dtype");
     h->trace_state[dtype] = -1;
     by_dtype(h, dtype, [&](auto tag) {
       using T = std::remove_pointer_t<decltype(tag)>;
-      vcycle_dg<T>(h, 0, (T*)u, (const T*)b, false, stream);
+      vcycle_dg<T>(h, 0, (T*)u, (const T*)b, false, nrhs, stream);
     });
     return HPMG_OK;
   } catch (const HpmgError& e) {

@@ -38,13 +38,27 @@ inline void require(bool c, const std::string& msg) {
   if (!c) throw HpmgError(HPMG_E_INVALID, msg);
 }
 
-// Device allocation owned by the handle.
+// Device allocation owned by the handle: hipMalloc, or the caller's
+// allocator (hpmg_options.alloc / free / alloc_ctx).
 struct DevMem {
   std::vector<void*> ptrs;
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* ctx = nullptr;
   void* alloc(size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 16;
-    HIPCHK(hipMalloc(&p, bytes));
+    bytes = (bytes + 255) / 256 * 256;
+    if (alloc_fn) {
+      p = alloc_fn(bytes, ctx);
+      if (!p) throw HpmgError(HPMG_E_NOMEM, "the caller's allocator returned NULL");
+      if ((reinterpret_cast<size_t>(p) & 255) != 0) {
+        free_fn(p, ctx);
+        throw HpmgError(HPMG_E_INVALID, "the caller's allocator returned memory not aligned to 256 bytes");
+      }
+    } else {
+      HIPCHK(hipMalloc(&p, bytes));
+    }
     ptrs.push_back(p);
     return p;
   }
@@ -55,7 +69,12 @@ struct DevMem {
     return p;
   }
   ~DevMem() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) {
+      if (free_fn)
+        free_fn(p, ctx);
+      else
+        (void)hipFree(p);
+    }
   }
 };
 
@@ -86,6 +105,7 @@ struct DGData {
 struct DGLevel {
   int p = 0, N = 0, NC = 0;  // NC: nodes per direction of the next coarser level (2: Q1)
   bool next_cg = false;
+  bool dyn_nc = false;       // next DG level not the halved degree: run-time NC transfer kernels
   double sigma_hat = 0.0;
   size_t ndof = 0, trsize = 0;  // per right-hand side
   DGData<double> d;
@@ -207,6 +227,7 @@ inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
   a.sigma_hat = (C)L.sigma_hat;
   a.omega = (C)h->opt.omega_dg;
   a.gl = h->opt.basis;
+  a.ivar = h->opt.block_variant;
   a.vstride = (long long)L.ndof;
   a.tstride = (long long)L.trsize;
   return a;

@@ -17,7 +17,9 @@ enum DGOp {
   OP_PROJECT = 3,     // traces of u
   OP_PROLONG = 4,     // u += P e, then traces of u
   OP_RESTRICT_Q1 = 5, // OP_RESTRICT to Q1 corner contributions from any degree (one-step p-coarsening)
-  OP_PROLONG_Q1 = 6   // OP_PROLONG from Q1 to any degree
+  OP_PROLONG_Q1 = 6,  // OP_PROLONG from Q1 to any degree
+  OP_RESTRICT_DYN = 7, // OP_RESTRICT to a DG level of a.ncd nodes per direction (explicit p schedules)
+  OP_PROLONG_DYN = 8   // OP_PROLONG from such a level
 };
 
 // Next coarser level of a DG level with N nodes per direction: DG with

@@ -45,11 +45,39 @@ def test_setup_rejects_bad_options():
     for field, val in [("omega_dg", 0.0), ("omega_dg", 1.5), ("omega_cg", -1.0), ("sigma0", 0.0),
                        ("coarsest_n", 1), ("max_rhs", 0), ("precision", 7), ("p_coarsening", 2),
                        ("h_factor", 4), ("h_factor", 1), ("block_recompute", 2),
-                       ("block_recompute", 1)]:  # the last: recompute with constant kappa
+                       ("block_recompute", 1),  # recompute with constant kappa
+                       ("nu_pre_cg", -2), ("nu_post_cg", -5), ("block_variant", 2)]:
         opt = hp.default_options()
         setattr(opt, field, val)
         st, _ = _setup(opt=opt)
         assert st == 1, field
+    # p schedules: not decreasing, below 2, not below p (p = 2 here: any entry)
+    for sched in ([3, 3], [1], [2]):
+        opt = hp.default_options()
+        opt.p_schedule = (ctypes.c_int * 8)(*(sched + [0] * (8 - len(sched))))
+        st, _ = _setup(p=4 if sched != [2] else 2, opt=opt)
+        assert st == 1, sched
+    # interior block with a per-cell kappa, or with no interior cell
+    import numpy as np
+    k = np.ones(64)
+    opt = hp.default_options()
+    opt.block_variant = 1
+    st, _ = _setup(per_cell=1, kappa=k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), opt=opt)
+    assert st == 1
+    st, _ = _setup(n=2, opt=opt)
+    assert st == 1
+    # an allocator without its free function
+    opt = hp.default_options()
+    opt.alloc = hp.ALLOC_FN(lambda n, c: None)
+    st, _ = _setup(opt=opt)
+    assert st == 1
+
+
+def test_default_options_new_fields():
+    o = hp.default_options()
+    assert (o.nu_pre, o.nu_post, o.nu_pre_cg, o.nu_post_cg) == (2, 2, -1, -1)
+    assert o.block_variant == 0 and list(o.p_schedule) == [0] * 8
+    assert not o.alloc and not o.free and not o.alloc_ctx
 
 
 def test_setup_rejects_nonpositive_per_cell_kappa():
@@ -67,6 +95,7 @@ def test_null_handle_rejected():
     assert lib.hpmg_vcycle(None, 0, None, None, 1, None) == 1
     assert lib.hpmg_solve(None, None, None, 1, 1e-10, 10, None, None) == 1
     assert lib.hpmg_mgmult(None, None, None, 1e-7, 10, 0, None, None) == 1
+    assert lib.hpmg_smooth_noalloc(None, 0, None, None, 1, 1, None) == 1
     assert lib.hpmg_ndof(None) == 0
     lib.hpmg_destroy(None)
 

@@ -58,7 +58,7 @@ def test_one_iteration_matches_oracle():
         for r in range(nrhs):
             err = rel_err(got[r * nd:(r + 1) * nd], refs[j][r * nd:(r + 1) * nd])
             log(f"  n={n} p={p} rhs={r}: rel err {err:.3e}")
-            assert err <= 1e-3
+            assert err <= 1e-5  # one FP32 V-cycle (about 10 u32 per traversal)
         assert infos[j].iterations == 1
     assert batch.grid in (256, 512, 1024, 2048, 4096)
 
@@ -173,7 +173,7 @@ def test_batch_smooth_matches_oracle(nsweeps):
                                     for r in range(nrhs)]))
         u0s.append(u0)
         bs.append(b)
-    for dt, tol in ((torch.float64, 1e-11), (torch.float32, 1e-4)):
+    for dt, tol in ((torch.float64, 1e-11), (torch.float32, 1e-5)):
         ud = [to_dev(u, dt) for u in u0s]
         bd = [to_dev(b, dt) for b in bs]
         log(f"batch smooth nsweeps={nsweeps} {dt}")

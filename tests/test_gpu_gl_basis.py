@@ -39,7 +39,7 @@ def test_gl_apply_smooth_vcycle(dim, n, p, kind):
     u0 = synth.random_vector(nd, seed=51)
     b = synth.random_rhs(nd, seed=52)
     g = hp.Solver(dim, n, p, k, basis=1)
-    for dt, ta, ts, tv in ((torch.float64, 1e-12, 1e-11, 1e-10), (torch.float32, 1e-5, 1e-4, 1e-3)):
+    for dt, ta, ts, tv in ((torch.float64, 1e-12, 1e-11, 1e-10), (torch.float32, 1e-5, 1e-5, 1e-5)):
         ud = to_dev(u0, dt)
         yd = torch.empty_like(ud)
         g.apply_A(ud, yd)

@@ -43,7 +43,7 @@ def test_vcycle_paper_options(dim, n, p, kind, pc, hf):
     b = synth.random_rhs(nd, seed=42)
     ref = H.vcycle(0, u0.copy(), b)
     g = hp.Solver(dim, n, p, _kappa(dim, n, kind), p_coarsening=pc, h_factor=hf)
-    for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-3)):
+    for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):  # FP32: about 10 u32 per traversal
         ud, bd = to_dev(u0, dt), to_dev(b, dt)
         g.vcycle(ud, bd)
         err = rel_err(to_host(ud), ref)

@@ -12,6 +12,13 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+# FP32 against the FP64 oracle: inputs rounded to FP32 (u32 = 2^-24) and
+# about 10 u32 of arithmetic error per fine-level traversal (the
+# sum-factorised contractions sum N terms per stage over 2d stages); three
+# sweeps or one V-cycle (about eight fine-level traversals) stay below 1e-5.
+TOL32_SMOOTH = 1e-5
+TOL32_VCYCLE = 1e-5
+
 CASES = [
     # dim, n, p, kappa kind
     (2, 5, 1, "const"),
@@ -75,7 +82,7 @@ def test_smooth_matches_block_jacobi(dim, n, p, kind):
     g.smooth(ud, bd, 3)
     err = rel_err(to_host(ud), ref)
     log(f"  fp32 rel err {err:.3e}")
-    assert err <= 1e-4
+    assert err <= TOL32_SMOOTH
 
 
 @pytest.mark.parametrize("dim,n,p,kind", CASES)
@@ -96,7 +103,7 @@ def test_vcycle_matches_oracle(dim, n, p, kind):
     g.vcycle(ud, bd)
     err = rel_err(to_host(ud), ref)
     log(f"  fp32 rel err {err:.3e}")
-    assert err <= 1e-3
+    assert err <= TOL32_VCYCLE
 
 
 @pytest.mark.parametrize("dim,n,p,kind", [(2, 16, 2, "const"), (3, 4, 3, "var"), (3, 5, 4, "const")])

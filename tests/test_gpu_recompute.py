@@ -48,7 +48,7 @@ def test_recompute_apply_and_sweeps(dim, n, p):
     u = synth.random_vector(nd, seed=2000 + p)
     b = synth.random_rhs(nd, seed=2100 + p)
     gr, gs = _solvers(dim, n, p)
-    for dt, tol_a, tol_s, tol_x in ((torch.float64, 1e-12, 1e-11, 1e-12), (torch.float32, 1e-5, 1e-4, 1e-5)):
+    for dt, tol_a, tol_s, tol_x in ((torch.float64, 1e-12, 1e-11, 1e-12), (torch.float32, 1e-5, 1e-5, 1e-5)):
         ud = to_dev(u, dt)
         yr, ys = torch.empty_like(ud), torch.empty_like(ud)
         gr.apply_A(ud, yr)
@@ -104,4 +104,4 @@ def test_recompute_16bit_storage_sweep():
     gr.smooth(ud, bd, 2)
     err = rel_err(to_host(ud), ref)
     log(f"  fp16 storage, 2 sweeps vs oracle {err:.3e}")
-    assert err <= 1e-2
+    assert err <= 1.5e-3  # about one FP16 rounding (u16 = 2^-11) of u per sweep
