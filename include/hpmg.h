@@ -90,7 +90,7 @@ typedef struct {
                          every cell block at setup and stream it in each traversal; 1 rebuild it in
                          every traversal from kappa (a Jacobi eigensolve per cell and axis inside the
                          kernels), the paper's "recompute the block inverse per cell" variant that
-                         mimics inhomogeneous problems (Section 6 experiments).  Same operator and
+                         mimics inhomogeneous problems (Section 7, single-core measurements).  Same operator and
                          iterates up to rounding; setup skips the per-cell eigendata.  Setting it with
                          constant kappa is HPMG_E_INVALID. */
   int nu_pre_cg;      /* point-Jacobi steps on Q1 levels before their coarse correction (-1, the
@@ -244,7 +244,7 @@ void hpmg_destroy(hpmg_handle h);
  * and large problems share the chip instead of running one after another;
  * one outer iteration of all problems is captured once as a HIP graph and
  * replayed.  This is the GPU counterpart of the task-based execution that
- * the paper uses to absorb uneven subdomain sizes (Section 6, subsections
+ * the paper uses to absorb uneven subdomain sizes (Section 7, subsections
  * on task-based realisation and on imbalanced domain decomposition): here
  * the uneven units are whole problems, merged into shared launches.
  */

@@ -492,7 +492,7 @@ __device__ __forceinline__ int tangential(int k, int pass) {
 // copy) and transforms along t1; pass 1 transforms along t2 (3D).  Work items are
 // ordered (facet, cell, line) so that a wave mostly sees one facet
 // direction and therefore one matrix.
-template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL = false>
+template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL = false, bool IVAR = false>
 __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int c0, int nc, int pass, CT<T>* sNB,
                                            const CT<T>* sE, const CT<T>* sKF) {
   using C = CT<T>;
@@ -513,11 +513,11 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
     const int lo = pass == 0 ? N * li : li;
     C* g = sNB + (cl * Sh::NF + f) * TL + lo;
     const int mask = FROM_GLOBAL ? a.bmask[c] : mask_lds<D, N, VARK>(sKF)[cl];
-    const int smask = a.ivar ? 0 : mask;  // boundary classes of the block solve
+    const int smask = IVAR ? 0 : mask;  // boundary classes of the block solve
     C x1[N], x2[N], o1[N], o2[N];
     if (pass == 0) {
       const bool bdy = (mask >> f) & 1;
-      if (bdy && !(FROM_GLOBAL && a.ivar)) {  // boundary facet: no neighbour, zero flux fields
+      if (bdy && !(FROM_GLOBAL && IVAR)) {  // boundary facet: no neighbour, zero flux fields
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           g[j] = C(0);
@@ -529,15 +529,24 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
       if constexpr (FROM_GLOBAL) {
         const int s = f & 1;
         const int stc = ipow<D>(a.n, k);
-        // interior-block smoother: a boundary facet reads the cell's own
-        // traces, negated
-        const T* src = bdy ? tr + ((size_t)f * a.ncell + c) * TL + lo
-                           : tr + ((size_t)(f ^ 1) * a.ncell + (s ? c + stc : c - stc)) * TL + lo;
-        const C sg = bdy ? C(-1) : C(1);
+        if constexpr (IVAR) {
+          // interior-block smoother: a boundary facet reads the cell's own
+          // traces, negated
+          const T* src = bdy ? tr + ((size_t)f * a.ncell + c) * TL + lo
+                             : tr + ((size_t)(f ^ 1) * a.ncell + (s ? c + stc : c - stc)) * TL + lo;
+          const C sg = bdy ? C(-1) : C(1);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-          gv[j] = sg * (C)src[j];
-          qv[j] = sg * (C)src[L + j];
+          for (int j = 0; j < N; ++j) {
+            gv[j] = sg * (C)src[j];
+            qv[j] = sg * (C)src[L + j];
+          }
+        } else {
+          const T* src = tr + ((size_t)(f ^ 1) * a.ncell + (s ? c + stc : c - stc)) * TL + lo;
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            gv[j] = src[j];
+            qv[j] = src[L + j];
+          }
         }
       } else {
 #pragma unroll
@@ -706,13 +715,13 @@ __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const 
 
 // All facet flux fields of the block in sNB, the eigendata in sE and the
 // boundary masks of the block's cells in LDS; ends with a barrier.
-template <typename T, int D, int N, bool VARK, bool AT_ONCE = true>
+template <typename T, int D, int N, bool VARK, bool AT_ONCE = true, bool IVAR = false>
 __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB, CT<T>* sE, CT<T>* sKF) {
   int* sMask = mask_lds<D, N, VARK>(sKF);
   const int tid = work_tid<D, N>();
   if constexpr (!VARK && AT_ONCE) {
-    if (a.ivar) {  // interior-block smoother: item after item (boundary facets read own traces)
-      facet_pass<T, D, N, false, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
+    if constexpr (IVAR) {  // interior-block smoother: item after item (boundary facets read own traces)
+      facet_pass<T, D, N, false, true, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
       load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
       if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
     } else {
@@ -720,7 +729,7 @@ __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int
     }
     __syncthreads();
   } else if constexpr (!VARK) {
-    facet_pass<T, D, N, false, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
+    facet_pass<T, D, N, false, true, IVAR>(a, tr, c0, nc, 0, sNB, sE, sKF);
     load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
     if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
     __syncthreads();
@@ -739,7 +748,7 @@ __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int
     __syncthreads();
   }
   if constexpr (D == 3) {
-    facet_pass<T, D, N, VARK>(a, tr, c0, nc, 1, sNB, sE, sKF);
+    facet_pass<T, D, N, VARK, false, IVAR>(a, tr, c0, nc, 1, sNB, sE, sKF);
     __syncthreads();
   }
 }
@@ -772,7 +781,7 @@ __device__ __forceinline__ void add_lifts(const DGArgs<T>& a, int cl, int k, int
 
 // Traces (value, outward normal derivative) of a line along axis k, stored
 // straight to the trace buffer for the facets that are not on the boundary.
-template <typename T, int D, int N>
+template <typename T, int D, int N, bool IVAR = false>
 __device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, int c, int mask, int k, int ln,
                                                   const CT<T> (&u)[N]) {
   using C = CT<T>;
@@ -798,12 +807,12 @@ __device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, 
       g1 += ev1[j] * u[j];
     }
   }
-  if (a.ivar || !((mask >> (2 * k)) & 1)) {
+  if (IVAR || !((mask >> (2 * k)) & 1)) {
     T* t0 = trout + ((size_t)(2 * k) * a.ncell + c) * TL;
     t0[ln] = g0;
     t0[L + ln] = d0;
   }
-  if (a.ivar || !((mask >> (2 * k + 1)) & 1)) {
+  if (IVAR || !((mask >> (2 * k + 1)) & 1)) {
     T* t1 = trout + ((size_t)(2 * k + 1) * a.ncell + c) * TL;
     t1[ln] = g1;
     t1[L + ln] = d1;
@@ -811,7 +820,7 @@ __device__ __forceinline__ void store_line_traces(const DGArgs<T>& a, T* trout, 
 }
 
 // Traces of the y (and z) lines of the cell vector staged in sU.
-template <typename T, int D, int N>
+template <typename T, int D, int N, bool IVAR = false>
 __device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, const CT<T>* sU, int cl, int c, int mask,
                                                 int ln) {
   using C = CT<T>;
@@ -822,7 +831,7 @@ __device__ __forceinline__ void store_yz_traces(const DGArgs<T>& a, T* trout, co
     C u[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) u[j] = sU[base + j * line_stride<N>(k)];
-    store_line_traces<T, D, N>(a, trout, c, mask, k, ln, u);
+    store_line_traces<T, D, N, IVAR>(a, trout, c, mask, k, ln, u);
   }
 }
 
@@ -864,7 +873,7 @@ constexpr int cell_lds_bytes() {
          (int)sizeof(int) * Sh::CPB;
 }
 
-template <typename T, int D, int N, bool UZERO, bool VARK>
+template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR = false>
 __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
@@ -884,7 +893,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
   const int mask = a.bmask[c];
-  const int smask = a.ivar ? 0 : mask;  // boundary classes of the block solve
+  const int smask = IVAR ? 0 : mask;  // boundary classes of the block solve
 
   C ul[N], bl[N];
   if (act) {
@@ -898,7 +907,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
     }
   }
   if (!UZERO) {
-    flux_fields<T, D, N, VARK, batched_trace_loads<T, N>()>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+    flux_fields<T, D, N, VARK, batched_trace_loads<T, N>(), IVAR>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   } else {
     load_eig<T, D, N, VARK>(a, c0, nc, sE, sKF);
     __syncthreads();
@@ -971,7 +980,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
           sW[base + j] = t[j];
           uo[j] = t[j];
         }
-        store_line_traces<T, D, N>(a, trout, c, mask, 0, ln, t);
+        store_line_traces<T, D, N, IVAR>(a, trout, c, mask, 0, ln, t);
       } else {
 #pragma unroll
         for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = t[j];
@@ -979,7 +988,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
     }
     __syncthreads();
   }
-  if (act) store_yz_traces<T, D, N>(a, trout, sW, cl, c, mask, ln);
+  if (act) store_yz_traces<T, D, N, IVAR>(a, trout, sW, cl, c, mask, ln);
 }
 
 // At least two waves per SIMD for the 3D FP64 degree 7 and 8 sweeps: left to
@@ -987,13 +996,15 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
 // registers) in vector registers and reaches 256 VGPRs (one wave per SIMD).
 template <typename T, int D, int N>
 constexpr int sweep_waves_per_eu() {
-  return (D == 3 && sizeof(CT<T>) == 8 && N >= 8) ? 2 : 1;
+  // the FP64 degree-4 sweep fits 128 VGPRs (four waves per SIMD) without
+  // spills, which the compiler does not choose by itself
+  return (D == 3 && sizeof(CT<T>) == 8 && N >= 8) ? 2 : ((D == 3 && sizeof(CT<T>) == 8 && N == 5) ? 4 : 1);
 }
-template <typename T, int D, int N, bool UZERO, bool VARK>
+template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR>
 __global__ __launch_bounds__((DGShape<D, N>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, D, N>()))) void k_sweep(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
-  sweep_body<T, D, N, UZERO, VARK>(a, blockIdx.x, blockIdx.y, lds);
+  sweep_body<T, D, N, UZERO, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1002,7 +1013,7 @@ __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, D, N>()))) void k_sweep
 // from the coarse nodes (DG_q: a coarse cell vector; Q1: the 2^d corner
 // contributions of each cell, summed over cells by the gather kernel).
 // Needs the traces of u in tr_in.
-template <typename T, int D, int N, int NC, bool RESID, bool VARK>
+template <typename T, int D, int N, int NC, bool RESID, bool VARK, bool IVAR = false>
 __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
@@ -1022,7 +1033,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
   const int mask = a.bmask[c];
-  const int smask = a.ivar ? 0 : mask;  // boundary classes of the block solve
+  const int smask = IVAR ? 0 : mask;  // boundary classes of the block solve
 
   C ul[N], bl[N];
   if (act) {
@@ -1035,7 +1046,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       for (int j = 0; j < N; ++j) bl[j] = bs[j];
     }
   }
-  flux_fields<T, D, N, VARK>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+  flux_fields<T, D, N, VARK, true, IVAR>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   double pdot = 0.0;  // share of p.(A p) (kdot)
 
   // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
@@ -1205,11 +1216,11 @@ template <typename T, int N>
 constexpr int apply_waves_per_eu() {
   return (sizeof(T) == 8 && N <= 5) ? 4 : 1;
 }
-template <typename T, int D, int N, int NC, bool RESID, bool VARK>
+template <typename T, int D, int N, int NC, bool RESID, bool VARK, bool IVAR>
 __global__ __launch_bounds__((DGShape<D, N>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(apply_waves_per_eu<T, N>()))) void k_apply(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
-  apply_body<T, D, N, NC, RESID, VARK>(a, blockIdx.x, blockIdx.y, lds);
+  apply_body<T, D, N, NC, RESID, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1224,7 +1235,7 @@ constexpr int prolong_lds_bytes() {
   return (int)sizeof(C) * (Sh::CPB * Sh::NV + (NC != 0 ? Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L : 0));
 }
 
-template <typename T, int D, int N, int NC>
+template <typename T, int D, int N, int NC, bool IVAR = false>
 __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
@@ -1375,16 +1386,16 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) sU[base + j] = u[j];
-    store_line_traces<T, D, N>(a, trout, c, mask, 0, ln, u);
+    store_line_traces<T, D, N, IVAR>(a, trout, c, mask, 0, ln, u);
   }
   __syncthreads();
-  if (act) store_yz_traces<T, D, N>(a, trout, sU, cl, c, mask, ln);
+  if (act) store_yz_traces<T, D, N, IVAR>(a, trout, sU, cl, c, mask, ln);
 }
 
-template <typename T, int D, int N, int NC>
+template <typename T, int D, int N, int NC, bool IVAR>
 __global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_prolong(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[prolong_lds_bytes<T, D, N, NC>()];
-  prolong_body<T, D, N, NC>(a, blockIdx.x, blockIdx.y, lds);
+  prolong_body<T, D, N, NC, IVAR>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 }  // namespace dgk
@@ -1395,14 +1406,19 @@ void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s) {
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
   if (a.vark) {
     if (uzero)
-      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, true>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, true, false>), grid, dim3(Sh::NT), 0, s, a);
     else
-      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, true>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, true, false>), grid, dim3(Sh::NT), 0, s, a);
+  } else if (a.ivar) {
+    if (uzero)
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, false, true>), grid, dim3(Sh::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, false, true>), grid, dim3(Sh::NT), 0, s, a);
   } else {
     if (uzero)
-      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, false>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, false, false>), grid, dim3(Sh::NT), 0, s, a);
     else
-      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, false>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, false, false>), grid, dim3(Sh::NT), 0, s, a);
   }
 }
 
@@ -1412,14 +1428,19 @@ void launch_apply(const DGArgs<T>& a, int nrhs, bool resid, hipStream_t s) {
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
   if (a.vark) {
     if (resid)
-      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, true>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, true, false>), grid, dim3(Sh::NT), 0, s, a);
     else
-      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, true>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, true, false>), grid, dim3(Sh::NT), 0, s, a);
+  } else if (a.ivar) {
+    if (resid)
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, false, true>), grid, dim3(Sh::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, false, true>), grid, dim3(Sh::NT), 0, s, a);
   } else {
     if (resid)
-      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, false>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, false, false>), grid, dim3(Sh::NT), 0, s, a);
     else
-      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, false>), grid, dim3(Sh::NT), 0, s, a);
+      hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, false, false>), grid, dim3(Sh::NT), 0, s, a);
   }
 }
 
@@ -1427,7 +1448,10 @@ template <typename T, int D, int N, int NC>
 void launch_prolong(const DGArgs<T>& a, int nrhs, hipStream_t s) {
   using Sh = DGShape<D, N>;
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
-  hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC>), grid, dim3(Sh::NT), 0, s, a);
+  if (a.ivar)
+    hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC, true>), grid, dim3(Sh::NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC, false>), grid, dim3(Sh::NT), 0, s, a);
 }
 
 }  // namespace hpmg
