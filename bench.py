@@ -500,8 +500,12 @@ def run_single(args):
         sweep_in[name] = (torch.zeros(nd, dtype=dt, device=dev), bb,
                           [torch.cuda.Event(enable_timing=True) for _ in range(2)])
     u = torch.zeros(nd, dtype=torch.float64, device=dev)
-    solves = ("fp64", "mixed_f32", "mixed_f16", "mixed_bf16")
-    solver_of = {"fp64": g64, "mixed_f32": gmx, "mixed_f16": g16, "mixed_bf16": gb16}
+    # 16-bit storage sweeps with the volume contractions on the matrix cores
+    gmf = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F16, mfma=1)
+    mf_in = {name: (torch.zeros(nd, dtype=sweep_in[name][1].dtype, device=dev), sweep_in[name][1],
+                    [torch.cuda.Event(enable_timing=True) for _ in range(2)]) for name in ("f16", "bf16")}
+    solves = ("fp64", "mixed_f32", "mixed_f16", "mixed_bf16", "mixed_f16_mfma")
+    solver_of = {"fp64": g64, "mixed_f32": gmx, "mixed_f16": g16, "mixed_bf16": gb16, "mixed_f16_mfma": gmf}
     rc_in = {}
     t_setup_rc = None
     if vark:
@@ -521,9 +525,9 @@ def run_single(args):
         batch1 = hp.Batch([gmx])
     S = args.sweeps
 
-    def sweeps_timed(which=("sw_", "swrc_")):
+    def sweeps_timed(which=("sw_", "swmf_", "swrc_")):
         out = {}
-        for gs, ins, pre in ((g64, sweep_in, "sw_"),) + (((grc, rc_in, "swrc_"),) if vark else ()):
+        for gs, ins, pre in ((g64, sweep_in, "sw_"), (gmf, mf_in, "swmf_")) + (((grc, rc_in, "swrc_"),) if vark else ()):
             if pre not in which:
                 continue
             for uu, bb, evs in ins.values():
@@ -532,7 +536,7 @@ def run_single(args):
                 gs.sweep(uu, bb, S)
                 evs[1].record(stream)
         torch.cuda.synchronize()
-        for pre, ins in (("sw_", sweep_in), ("swrc_", rc_in)):
+        for pre, ins in (("sw_", sweep_in), ("swmf_", mf_in), ("swrc_", rc_in)):
             if pre not in which:
                 continue
             for name, (_, _, evs) in ins.items():
@@ -540,7 +544,7 @@ def run_single(args):
         return out
 
     if args.profile_sweeps:
-        t = sweeps_timed(("swrc_",) if (vark and args.block_recompute) else ("sw_",))
+        t = sweeps_timed(("swrc_",) if (vark and args.block_recompute) else ("sw_", "swmf_"))
         if args.copy_calibration:
             copy_calibration(torch, dev)
         print(json.dumps({"profile_sweeps": S, "mean_sweep_s": t}), flush=True)
@@ -584,7 +588,7 @@ def run_single(args):
     # "not converged" with the residual it reached) gets its time to that
     # residual reported separately
     floor = {k: {"seconds": tmed[k], "rel_residual": final_rel[k]} for k in solves if not conv[k]}
-    cyc = {"fp64": 8, "mixed_f32": 4, "mixed_f16": 2, "mixed_bf16": 2, "mixed_f32_graph": 4}
+    cyc = {"fp64": 8, "mixed_f32": 4, "mixed_f16": 2, "mixed_bf16": 2, "mixed_f32_graph": 4, "mixed_f16_mfma": 2}
     tts = {}
     for k, isz_c in cyc.items():
         if k in solves and tt.get(k):
@@ -626,6 +630,10 @@ def run_single(args):
                                   "mean_launch_s": tsw[name],
                                   "traffic": counter_traffic(tsum, srcs, f"traffic_bytes_per_launch_{name}")}
                            for name in sweep_in},
+        "sweep_matrix_cores_16bit": {
+            name: {"dofs_per_s": nd / tmf, "frac": bysw[name] / tmf / 1e9 / HBM_PEAK_GBS, "mean_launch_s": tmf,
+                   "traffic": counter_traffic(tsum, srcs, f"traffic_bytes_per_launch_{name}_mfma")}
+            for name, tmf in ((nm, _median([r["swmf_" + nm] for r in res])) for nm in mf_in)},
         "time_to_1e-10_s": tt,
         "time_to_attained_residual_s": floor or None,
         "time_to_solution_roofline": tts,

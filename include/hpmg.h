@@ -108,6 +108,11 @@ typedef struct {
                          current device aligned to 256 bytes, or NULL on failure (HPMG_E_NOMEM). */
   void (*free)(void* ptr, void* ctx);      /* releases what alloc returned (hpmg_destroy, batch destroy) */
   void* alloc_ctx;    /* passed to alloc and free */
+  int mfma;           /* 16-bit storage (F16 / BF16) sweeps in 3D: 0 (default) run the contractions of
+                         the block solve on the vector units in FP32; 1 run its six volume contractions
+                         on the matrix cores (v_mfma_f32_16x16x16 with FP16 or BF16 operands, FP32
+                         accumulation; the operands of every contraction are rounded to the storage
+                         format).  Facet transforms, lifts and updates stay in FP32.  1 needs dim 3. */
 } hpmg_options;
 
 /* Fill *opt with the defaults listed above. */

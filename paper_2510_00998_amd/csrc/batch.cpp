@@ -715,7 +715,7 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
       require(h->p + 1 >= hpmg::BATCH_NMIN && h->p + 1 <= hpmg::BATCH_NMAX, "batched solver supports 1 <= p <= 5");
       require(h->opt.nu_pre >= 1, "batched solver needs nu_pre >= 1");
       require(h->opt.p_coarsening == 0 && h->opt.p_schedule[0] == 0 && h->opt.h_factor == 2 &&
-                  h->opt.basis == 0 && h->opt.block_variant == 0,
+                  h->opt.basis == 0 && h->opt.block_variant == 0 && h->opt.mfma == 0,
               "batched solver supports the default p- and h-coarsening, basis and block");
       require(h->opt.nu_pre == hs[0]->opt.nu_pre && h->opt.nu_post == hs[0]->opt.nu_post &&
                   h->opt.nu_pre_cg == hs[0]->opt.nu_pre_cg && h->opt.nu_post_cg == hs[0]->opt.nu_post_cg,

@@ -130,6 +130,10 @@ struct DGArgs {
   // stored on boundary facets too.
   int ivar = 0;
   int ncd = 0;         // nodes per direction of the coarse DG level (transfers with a run-time degree)
+  // 16-bit storage sweeps (3D): 1 runs the six volume contractions of the
+  // block solve on the matrix cores (16-bit operands, FP32 accumulation);
+  // 0 keeps them on the vector units in FP32
+  int mfma = 0;
   const void* zlow = nullptr;
   const double* kscal = nullptr;
   double kmul = 1.0;

@@ -991,6 +991,227 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   if (act) store_yz_traces<T, D, N, IVAR>(a, trout, sW, cl, c, mask, ln);
 }
 
+// ---------------------------------------------------------------------------
+// Volume contractions of the 16-bit storage sweep on the matrix cores.
+//
+// One contraction stage replaces every line along axis k of the block's
+// cells (FP32, in sW) by G_cell x line, with G = S^T (TR) or S of the cell's
+// axis-k record.  A 16x16x16 product D = A B holds NB = 16/N cells on the
+// block diagonal of A = diag(G_c0, .., G_c(NB-1)) (zero padded) and 16 lines
+// of each of those cells as the columns of B (row N kb + j of B: node j of
+// the line in cell kb), so that D row N rb + i, column c is node i of line c
+// of cell rb.  The operands are rounded to the storage format (FP16 or BF16)
+// and the products accumulate in FP32.  Operand lane layout (16x16x16):
+// lane l holds A[l%16][4(l/16)+j], B[4(l/16)+j][l%16] and D[4(l/16)+j][l%16],
+// j = 0..3.  SCALE multiplies the result by 1 / (lambda sum) of the node
+// (the diagonal of the fast-diagonalised block inverse, applied after S^T
+// along the last axis).  Called by every thread of the block (whole waves);
+// the products of a wave cover disjoint lines.
+typedef _Float16 mf_half4 __attribute__((ext_vector_type(4)));
+typedef short mf_short4 __attribute__((ext_vector_type(4)));
+typedef float mf_float4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<_Float16> {
+  static __device__ __forceinline__ mf_float4 mul(const float (&a)[4], const float (&b)[4]) {
+    mf_half4 x, y;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x[j] = (_Float16)a[j];
+      y[j] = (_Float16)b[j];
+    }
+    const mf_float4 z = {0.f, 0.f, 0.f, 0.f};
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(x, y, z, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16<__bf16> {
+  static __device__ __forceinline__ mf_float4 mul(const float (&a)[4], const float (&b)[4]) {
+    mf_short4 x, y;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x[j] = __builtin_bit_cast(short, (__bf16)a[j]);
+      y[j] = __builtin_bit_cast(short, (__bf16)b[j]);
+    }
+    const mf_float4 z = {0.f, 0.f, 0.f, 0.f};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, z, 0, 0, 0);
+  }
+};
+
+template <typename T, int D, int N, bool VARK, bool IVAR, bool TR, bool SCALE>
+__device__ __forceinline__ void mfma_stage(float* sW, const float* sE, const int* sMask, int nc, int k) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  constexpr int L = Sh::L;
+  constexpr int NB = 16 / N;               // cells per product
+  constexpr int CH = (L + 15) / 16;        // 16-line chunks per cell
+  constexpr int TASKS = (Sh::CPB + NB - 1) / NB * CH;
+  constexpr int NW = Sh::BLOCK / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, kq = lane >> 4;
+  const int stride = line_stride<N>(k);
+  // cell record of block-diagonal block b (clamped to a staged cell)
+  auto rec = [&](int cl) -> const float* {
+    if constexpr (VARK)
+      return sE + (cl * D + k) * Sh::EGS;
+    else
+      return sE + (IVAR ? 0 : axis_class(sMask[cl], k)) * Sh::EGS;
+  };
+  for (int t = wave; t < TASKS; t += NW) {  // uniform over the wave
+    const int g = t / CH, q = t % CH;
+    const int line = 16 * q + c;
+    const int lc = min(line, L - 1);
+    const int lb = line_base<D, N>(k, lc);
+    float av[4], bv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = 4 * kq + j;
+      const int kb = kk / N, jj = kk % N;
+      const int cl = g * NB + kb;
+      const bool okb = kb < NB && cl < nc && line < L;
+      const int clc = min(cl, nc - 1);
+      const float x = sW[clc * Sh::NV + lb + (jj < N ? jj : 0) * stride];
+      bv[j] = okb ? x : 0.f;
+      const int rb = c / N, ii = c % N;
+      const int cla = g * NB + rb;
+      const bool oka = rb == kb && rb < NB && cla < nc;
+      const float* G = rec(min(cla, nc - 1));
+      const float gv = TR ? G[jj * N + ii] : G[ii * N + jj];
+      av[j] = oka ? gv : 0.f;
+    }
+    const mf_float4 d = Mfma16<T>::mul(av, bv);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * kq + j;
+      const int rb = i / N, ii = i % N;
+      const int cl = g * NB + rb;
+      if (rb < NB && cl < nc && line < L) {
+        float v = d[j];
+        if constexpr (SCALE) {
+          // lambda sum of node (line, ii) along the last axis k = D - 1
+          const int clc = cl;
+          float ls;
+          if constexpr (D == 2) {
+            const float* E0 = VARK ? sE + (clc * D + 0) * Sh::EGS : sE + (IVAR ? 0 : axis_class(sMask[clc], 0)) * Sh::EGS;
+            const float* E1 = VARK ? sE + (clc * D + 1) * Sh::EGS : sE + (IVAR ? 0 : axis_class(sMask[clc], 1)) * Sh::EGS;
+            ls = E0[2 * NN + line] + E1[2 * NN + ii];
+          } else {
+            const float* E0 = VARK ? sE + (clc * D + 0) * Sh::EGS : sE + (IVAR ? 0 : axis_class(sMask[clc], 0)) * Sh::EGS;
+            const float* E1 = VARK ? sE + (clc * D + 1) * Sh::EGS : sE + (IVAR ? 0 : axis_class(sMask[clc], 1)) * Sh::EGS;
+            const float* E2 = VARK ? sE + (clc * D + 2) * Sh::EGS : sE + (IVAR ? 0 : axis_class(sMask[clc], 2)) * Sh::EGS;
+            ls = E0[2 * NN + line % N] + E1[2 * NN + line / N] + E2[2 * NN + ii];
+          }
+          v *= recip(ls);
+        }
+        sW[cl * Sh::NV + lb + ii * stride] = v;
+      }
+    }
+  }
+}
+
+// Fused sweep of a 16-bit storage type with the volume contractions on the
+// matrix cores (mfma_stage); facet flux fields, lifts, update and traces as
+// in sweep_body.  Launched with whole waves (DGShape::BLOCK threads).
+template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR>
+__device__ __forceinline__ void sweep_body_mfma(const DGArgs<T>& a, int bx, int by, char* lds) {
+  using C = CT<T>;
+  static_assert(sizeof(C) == 4, "matrix-core sweep: 16-bit storage, FP32 compute");
+  using Sh = DGShape<D, N>;
+  constexpr int L = Sh::L;
+  C* sW = (C*)lds;
+  C* sNB = sW + Sh::CPB * Sh::NV;
+  C* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
+  C* sKF = sE + EigLDS<D, N, VARK>::SIZE;
+  int* sMask = mask_lds<D, N, VARK>(sKF);
+
+  const int c0 = bx * Sh::CPB;
+  const int nc = min(Sh::CPB, a.ncell - c0);
+  const size_t rv = (size_t)by * a.vstride, rt = (size_t)by * a.tstride;
+  const int tid = work_tid<D, N>();
+  const int cl = tid / L, ln = tid % L;
+  const bool act = tid < Sh::NT && cl < nc;
+  const int c = c0 + (act ? cl : 0);
+  const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
+  const int mask = a.bmask[c];
+
+  C ul[N], bl[N];
+  if (act) {
+    const T* bs = a.b + rv + (size_t)c0 * Sh::NV + base0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) bl[j] = bs[j];
+    if (!UZERO) {
+      const T* us = a.u_in + rv + (size_t)c0 * Sh::NV + base0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) ul[j] = us[j];
+    }
+  }
+  if (!UZERO) {
+    flux_fields<T, D, N, VARK, batched_trace_loads<T, N>(), IVAR>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+  } else {
+    load_eig<T, D, N, VARK>(a, c0, nc, sE, sKF);
+    if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
+    __syncthreads();
+    if constexpr (VARK) {
+      if (a.rk) {
+        recompute_eig<T, D, N>(a, nc, sE, sKF);
+        __syncthreads();
+      }
+      make_si<T, D, N>(a, nc, sE);
+      __syncthreads();
+    }
+  }
+  // forward: right-hand side minus the facet lifts along each axis (vector
+  // units, one thread per line), then S^T along that axis on the matrix
+  // cores; the last forward stage applies the diagonal scaling
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (act && (k == 0 || !UZERO)) {
+      const int base = cl * Sh::NV + line_base<D, N>(k, ln);
+      C r[N];
+      if (k == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[j] = a.h_fwd * bl[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
+      }
+      if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
+#pragma unroll
+      for (int j = 0; j < N; ++j) sW[base + j * line_stride<N>(k)] = r[j];
+    }
+    __syncthreads();
+    if (k == D - 1)
+      mfma_stage<T, D, N, VARK, IVAR, true, true>(sW, sE, sMask, nc, k);
+    else
+      mfma_stage<T, D, N, VARK, IVAR, true, false>(sW, sE, sMask, nc, k);
+    __syncthreads();
+  }
+  // inverse: S along every axis, last axis first
+#pragma unroll
+  for (int k = D - 1; k >= 0; --k) {
+    mfma_stage<T, D, N, VARK, IVAR, false, false>(sW, sE, sMask, nc, k);
+    __syncthreads();
+  }
+  // update, store of u and of the traces
+  T* trout = a.tr_out + rt;
+  if (act) {
+    T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
+    C t[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const C uo0 = UZERO ? C(0) : ul[j];
+      t[j] = (C(1) - a.omega) * uo0 + a.omega * sW[base0 + j];
+      sW[base0 + j] = t[j];
+      uo[j] = t[j];
+    }
+    store_line_traces<T, D, N, IVAR>(a, trout, c, mask, 0, ln, t);
+  }
+  __syncthreads();
+  if (act) store_yz_traces<T, D, N, IVAR>(a, trout, sW, cl, c, mask, ln);
+}
+
 // At least two waves per SIMD for the 3D FP64 degree 7 and 8 sweeps: left to
 // itself the compiler keeps a whole 1D matrix (too large for scalar
 // registers) in vector registers and reaches 256 VGPRs (one wave per SIMD).
@@ -1000,11 +1221,14 @@ constexpr int sweep_waves_per_eu() {
   // spills, which the compiler does not choose by itself
   return (D == 3 && sizeof(CT<T>) == 8 && N >= 8) ? 2 : ((D == 3 && sizeof(CT<T>) == 8 && N == 5) ? 4 : 1);
 }
-template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR>
+template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR, bool MF = false>
 __global__ __launch_bounds__((DGShape<D, N>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, D, N>()))) void k_sweep(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
-  sweep_body<T, D, N, UZERO, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
+  if constexpr (MF)
+    sweep_body_mfma<T, D, N, UZERO, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
+  else
+    sweep_body<T, D, N, UZERO, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1400,10 +1624,39 @@ __global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_prolong(DGArgs<T> a)
 
 }  // namespace dgk
 
+// Matrix-core sweep (16-bit storage, 3D): whole waves per block.
+template <typename T, int D, int N>
+bool launch_sweep_mfma(const DGArgs<T>& a, dim3 grid, bool uzero, hipStream_t s) {
+  if constexpr (sizeof(T) == 2 && D == 3) {
+    using Sh = DGShape<D, N>;
+    const dim3 blk(Sh::BLOCK);
+    if (a.vark) {
+      if (uzero)
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, true, false, true>), grid, blk, 0, s, a);
+      else
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, true, false, true>), grid, blk, 0, s, a);
+    } else if (a.ivar) {
+      if (uzero)
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, false, true, true>), grid, blk, 0, s, a);
+      else
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, false, true, true>), grid, blk, 0, s, a);
+    } else {
+      if (uzero)
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, false, false, true>), grid, blk, 0, s, a);
+      else
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, false, false, true>), grid, blk, 0, s, a);
+    }
+    return true;
+  } else {
+    return false;
+  }
+}
+
 template <typename T, int D, int N>
 void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s) {
   using Sh = DGShape<D, N>;
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
+  if (a.mfma && launch_sweep_mfma<T, D, N>(a, grid, uzero, s)) return;
   if (a.vark) {
     if (uzero)
       hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, true, false>), grid, dim3(Sh::NT), 0, s, a);

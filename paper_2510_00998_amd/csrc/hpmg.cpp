@@ -886,6 +886,7 @@ void hpmg_default_options(hpmg_options* o) {
   o->alloc = nullptr;
   o->free = nullptr;
   o->alloc_ctx = nullptr;
+  o->mfma = 0;
 }
 
 const char* hpmg_status_string(hpmg_status s) {
@@ -935,6 +936,7 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     require(h->opt.basis == 0 || h->opt.basis == 1, "basis must be 0 (Gauss-Lobatto) or 1 (Gauss-Legendre)");
     require(h->opt.nu_pre_cg >= -1 && h->opt.nu_post_cg >= -1, "nu_pre_cg / nu_post_cg must be >= -1");
     require(h->opt.block_variant == 0 || h->opt.block_variant == 1, "block_variant must be 0 or 1");
+    require(h->opt.mfma == 0 || (h->opt.mfma == 1 && mesh->dim == 3), "mfma must be 0, or 1 with dim 3");
     require((h->opt.alloc == nullptr) == (h->opt.free == nullptr), "alloc and free must be given together");
     h->mem.alloc_fn = h->opt.alloc;
     h->mem.free_fn = h->opt.free;

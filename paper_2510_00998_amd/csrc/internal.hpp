@@ -228,6 +228,7 @@ inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
   a.omega = (C)h->opt.omega_dg;
   a.gl = h->opt.basis;
   a.ivar = h->opt.block_variant;
+  a.mfma = h->opt.mfma;
   a.vstride = (long long)L.ndof;
   a.tstride = (long long)L.trsize;
   return a;

@@ -46,7 +46,7 @@ def test_setup_rejects_bad_options():
                        ("coarsest_n", 1), ("max_rhs", 0), ("precision", 7), ("p_coarsening", 2),
                        ("h_factor", 4), ("h_factor", 1), ("block_recompute", 2),
                        ("block_recompute", 1),  # recompute with constant kappa
-                       ("nu_pre_cg", -2), ("nu_post_cg", -5), ("block_variant", 2)]:
+                       ("nu_pre_cg", -2), ("nu_post_cg", -5), ("block_variant", 2), ("mfma", 2)]:
         opt = hp.default_options()
         setattr(opt, field, val)
         st, _ = _setup(opt=opt)
@@ -65,6 +65,11 @@ def test_setup_rejects_bad_options():
     st, _ = _setup(per_cell=1, kappa=k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), opt=opt)
     assert st == 1
     st, _ = _setup(n=2, opt=opt)
+    assert st == 1
+    # matrix-core sweeps need dim 3
+    opt = hp.default_options()
+    opt.mfma = 1
+    st, _ = _setup(dim=2, opt=opt)
     assert st == 1
     # an allocator without its free function
     opt = hp.default_options()
