@@ -501,11 +501,13 @@ def run_single(args):
                           [torch.cuda.Event(enable_timing=True) for _ in range(2)])
     u = torch.zeros(nd, dtype=torch.float64, device=dev)
     # 16-bit storage sweeps with the volume contractions on the matrix cores
-    gmf = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F16, mfma=1)
+    # (the solve uses BF16 operands: FP16 operands of the contractions can
+    # overflow under strong coefficient contrast)
+    gmf = hp.Solver(dim, n, p, kappa, precision=hp.PREC_BF16, mfma=1)
     mf_in = {name: (torch.zeros(nd, dtype=sweep_in[name][1].dtype, device=dev), sweep_in[name][1],
                     [torch.cuda.Event(enable_timing=True) for _ in range(2)]) for name in ("f16", "bf16")}
-    solves = ("fp64", "mixed_f32", "mixed_f16", "mixed_bf16", "mixed_f16_mfma")
-    solver_of = {"fp64": g64, "mixed_f32": gmx, "mixed_f16": g16, "mixed_bf16": gb16, "mixed_f16_mfma": gmf}
+    solves = ("fp64", "mixed_f32", "mixed_f16", "mixed_bf16", "mixed_bf16_mfma")
+    solver_of = {"fp64": g64, "mixed_f32": gmx, "mixed_f16": g16, "mixed_bf16": gb16, "mixed_bf16_mfma": gmf}
     rc_in = {}
     t_setup_rc = None
     if vark:
@@ -520,14 +522,21 @@ def run_single(args):
                  for name, dt in (("f64", torch.float64), ("f32", torch.float32))}
         solves += ("mixed_f32_block_recompute",)
         solver_of["mixed_f32_block_recompute"] = grc
+        # split and postpone: stored records, next traversal's rebuilt on a
+        # second stream during each sweep
+        gsp = hp.Solver(dim, n, p, kappa, block_recompute=2)
+        sp_in = {name: (torch.zeros(nd, dtype=dt, device=dev), b64.to(dt),
+                        [torch.cuda.Event(enable_timing=True) for _ in range(2)])
+                 for name, dt in (("f64", torch.float64), ("f32", torch.float32))}
     else:
         solves += ("mixed_f32_graph",)
         batch1 = hp.Batch([gmx])
     S = args.sweeps
 
-    def sweeps_timed(which=("sw_", "swmf_", "swrc_")):
+    def sweeps_timed(which=("sw_", "swmf_", "swrc_", "swsp_")):
         out = {}
-        for gs, ins, pre in ((g64, sweep_in, "sw_"), (gmf, mf_in, "swmf_")) + (((grc, rc_in, "swrc_"),) if vark else ()):
+        for gs, ins, pre in ((g64, sweep_in, "sw_"), (gmf, mf_in, "swmf_")) + (
+                ((grc, rc_in, "swrc_"), (gsp, sp_in, "swsp_")) if vark else ()):
             if pre not in which:
                 continue
             for uu, bb, evs in ins.values():
@@ -536,7 +545,7 @@ def run_single(args):
                 gs.sweep(uu, bb, S)
                 evs[1].record(stream)
         torch.cuda.synchronize()
-        for pre, ins in (("sw_", sweep_in), ("swmf_", mf_in), ("swrc_", rc_in)):
+        for pre, ins in (("sw_", sweep_in), ("swmf_", mf_in), ("swrc_", rc_in)) + ((("swsp_", sp_in),) if vark else ()):
             if pre not in which:
                 continue
             for name, (_, _, evs) in ins.items():
@@ -544,7 +553,7 @@ def run_single(args):
         return out
 
     if args.profile_sweeps:
-        t = sweeps_timed(("swrc_",) if (vark and args.block_recompute) else ("sw_", "swmf_"))
+        t = sweeps_timed(("swrc_", "swsp_") if (vark and args.block_recompute) else ("sw_", "swmf_"))
         if args.copy_calibration:
             copy_calibration(torch, dev)
         print(json.dumps({"profile_sweeps": S, "mean_sweep_s": t}), flush=True)
@@ -588,7 +597,7 @@ def run_single(args):
     # "not converged" with the residual it reached) gets its time to that
     # residual reported separately
     floor = {k: {"seconds": tmed[k], "rel_residual": final_rel[k]} for k in solves if not conv[k]}
-    cyc = {"fp64": 8, "mixed_f32": 4, "mixed_f16": 2, "mixed_bf16": 2, "mixed_f32_graph": 4, "mixed_f16_mfma": 2}
+    cyc = {"fp64": 8, "mixed_f32": 4, "mixed_f16": 2, "mixed_bf16": 2, "mixed_f32_graph": 4, "mixed_bf16_mfma": 2}
     tts = {}
     for k, isz_c in cyc.items():
         if k in solves and tt.get(k):
@@ -652,6 +661,12 @@ def run_single(args):
             "sweep_mean_launch_s": trc,
             "sweep_roofline_frac": {name: byrc[name] / trc[name] / 1e9 / HBM_PEAK_GBS for name in rc_in},
             "algorithmic_bytes_per_launch": byrc}
+        tsp = {name: _median([r["swsp_" + name] for r in res]) for name in sp_in}
+        line["split_and_postpone"] = {
+            "sweep_dofs_per_s": {name: nd / t for name, t in tsp.items()},
+            "sweep_mean_s": tsp,
+            "sweep_roofline_frac_stored_bytes": {name: bysw[name] / tsp[name] / 1e9 / HBM_PEAK_GBS for name in sp_in},
+            "note": "mean time per sweep while the next traversal's records are rebuilt on a second stream"}
     print(json.dumps(line), flush=True)
 
 

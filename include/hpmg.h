@@ -86,13 +86,18 @@ typedef struct {
   int h_factor;       /* Q1 h-coarsening factor, 2 (default) or 3 (the paper's 3^k meshes) */
   int basis;          /* DG nodes: 0 Gauss-Lobatto (default), 1 Gauss-Legendre (diagonal mass, dense
                          facet value functionals; Section 4.1 remark on the two bases) */
-  int block_recompute; /* variable kappa only: 0 (default) precompute the fast-diagonalisation data of
-                         every cell block at setup and stream it in each traversal; 1 rebuild it in
-                         every traversal from kappa (a Jacobi eigensolve per cell and axis inside the
-                         kernels), the paper's "recompute the block inverse per cell" variant that
-                         mimics inhomogeneous problems (Section 7, single-core measurements).  Same operator and
-                         iterates up to rounding; setup skips the per-cell eigendata.  Setting it with
-                         constant kappa is HPMG_E_INVALID. */
+  int block_recompute; /* variable kappa only.  0 (default): the fast-diagonalisation data of every cell
+                         block is built once at setup (on the device, by a Jacobi eigensolve per cell and
+                         axis) and streamed in each traversal.  1: rebuilt inside every traversal from
+                         kappa (the same eigensolve in the sweep/apply kernels), the paper's "recompute
+                         the block inverse per cell" variant that mimics inhomogeneous problems (Section
+                         7, single-core measurements); setup stores no per-cell data.  2: split and
+                         postpone (Section 4.3): every finest-level sweep of hpmg_smooth / hpmg_sweep
+                         reads stored records while the records of the next traversal are rebuilt from
+                         kappa on a second stream of the handle into a second buffer (overlapping the
+                         compute-bound rebuild with the memory-bound sweep); other calls read the
+                         current records.  Same operator and iterates up to rounding in all three.  1 or
+                         2 with constant kappa is HPMG_E_INVALID. */
   int nu_pre_cg;      /* point-Jacobi steps on Q1 levels before their coarse correction (-1, the
                          default: nu_pre); the h-multigrid of Section 5.2 pre- and post-smooths */
   int nu_post_cg;     /* point-Jacobi steps on Q1 levels after it (-1, the default: nu_post) */

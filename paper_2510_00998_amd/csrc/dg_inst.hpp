@@ -24,6 +24,9 @@ void run(int op, const DGArgs<T>& a, int nrhs, int flag, hipStream_t s) {
     case OP_PROLONG_DYN:
       if constexpr (N >= 4) launch_prolong<T, D, N, -1>(a, nrhs, s);
       break;
+    case OP_BUILD_EIG:
+      if constexpr (std::is_same<T, double>::value || std::is_same<T, float>::value) launch_build_eig<T, D, N>(a, s);
+      break;
     default: break;
   }
 }

@@ -134,6 +134,7 @@ struct DGArgs {
   // block solve on the matrix cores (16-bit operands, FP32 accumulation);
   // 0 keeps them on the vector units in FP32
   int mfma = 0;
+  int* flag = nullptr;  // eigendata build: set to 1 if a block eigenvalue is not positive and finite
   const void* zlow = nullptr;
   const double* kscal = nullptr;
   double kmul = 1.0;
@@ -141,6 +142,7 @@ struct DGArgs {
 };
 
 template <typename T, int D, int N> void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s);
+template <typename C, int D, int N> void launch_build_eig(const DGArgs<C>& a, hipStream_t s);
 template <typename T, int D, int N, int NC> void launch_apply(const DGArgs<T>& a, int nrhs, bool resid, hipStream_t s);
 template <typename T, int D, int N, int NC> void launch_prolong(const DGArgs<T>& a, int nrhs, hipStream_t s);
 

@@ -992,6 +992,44 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
 }
 
 // ---------------------------------------------------------------------------
+// Per-cell fast-diagonalisation data of a variable-coefficient level, built
+// on the device at setup with the eigensolve of recompute_eig (FP64): for
+// every cell and axis the record S (N^2) | lambda (N) of L_k S = Mhat S
+// diag(lambda), S^T Mhat S = I, in the layout the stored-eigendata kernels
+// read ([cell][axis][S | lambda]).  a.rk holds [Khat | C^-1], a.kappa the
+// per-cell kappa; a.out receives the records, a.flag is set to 1 if an
+// eigenvalue is not positive and finite (the cell block is not positive
+// definite).
+template <typename C, int D, int N>
+constexpr int build_eig_lds_bytes() {
+  return (int)sizeof(C) * (EigLDS<D, N, true>::SIZE + kappa_lds_entries<D, N, true>()) +
+         (int)sizeof(int) * DGShape<D, N>::CPB;
+}
+template <typename C, int D, int N>
+__global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_build_eig(DGArgs<C> a) {
+  using Sh = DGShape<D, N>;
+  constexpr int NN = N * N;
+  __shared__ __attribute__((aligned(16))) char lds[build_eig_lds_bytes<C, D, N>()];
+  C* sE = (C*)lds;
+  C* sKF = sE + EigLDS<D, N, true>::SIZE;
+  const int c0 = blockIdx.x * Sh::CPB;
+  const int nc = min(Sh::CPB, a.ncell - c0);
+  load_eig<C, D, N, true>(a, c0, nc, sE, sKF);
+  __syncthreads();
+  recompute_eig<C, D, N>(a, nc, sE, sKF);
+  __syncthreads();
+  C* out = a.out + (size_t)c0 * D * (NN + N);
+  bool bad = false;
+  for (int i = work_tid<D, N>(); i < nc * D * (NN + N); i += Sh::NT) {
+    const int ck = i / (NN + N), e = i % (NN + N);
+    const C v = sE[ck * Sh::EGS + (e < NN ? e : NN + e)];
+    out[i] = v;
+    if (e >= NN && !(v > C(0) && v < C(1e30))) bad = true;
+  }
+  if (bad && a.flag) atomicOr(a.flag, 1);
+}
+
+// ---------------------------------------------------------------------------
 // Volume contractions of the 16-bit storage sweep on the matrix cores.
 //
 // One contraction stage replaces every line along axis k of the block's
@@ -1623,6 +1661,12 @@ __global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_prolong(DGArgs<T> a)
 }
 
 }  // namespace dgk
+
+template <typename C, int D, int N>
+void launch_build_eig(const DGArgs<C>& a, hipStream_t s) {
+  using Sh = DGShape<D, N>;
+  hipLaunchKernelGGL((dgk::k_build_eig<C, D, N>), dim3((a.ncell + Sh::CPB - 1) / Sh::CPB), dim3(Sh::NT), 0, s, a);
+}
 
 // Matrix-core sweep (16-bit storage, 3D): whole waves per block.
 template <typename T, int D, int N>

@@ -121,6 +121,35 @@ void eig_even_odd(const hpmg::Basis1D& B, const std::vector<double>& L, double* 
       throw HpmgError(HPMG_E_INVALID, "cell block is not positive definite (penalty too small?)");
 }
 
+// [Khat | W] with W = C^-1 and Mhat = C C^T (Cholesky in long double).
+std::vector<double> khat_and_inverse_cholesky(const hpmg::Basis1D& B) {
+  const int N = B.N, NN = N * N;
+  std::vector<double> tab((size_t)2 * NN, 0.0);
+  std::copy(B.K.begin(), B.K.end(), tab.begin());
+  std::vector<long double> Cm((size_t)NN, 0.0L), Wm((size_t)NN, 0.0L);
+  for (int j = 0; j < N; ++j) {
+    long double sd = B.M[(size_t)j * N + j];
+    for (int k = 0; k < j; ++k) sd -= Cm[(size_t)j * N + k] * Cm[(size_t)j * N + k];
+    if (!(sd > 0.0L)) throw HpmgError(HPMG_E_DEVICE, "mass matrix not positive definite");
+    Cm[(size_t)j * N + j] = std::sqrt(sd);
+    for (int i = j + 1; i < N; ++i) {
+      long double t = B.M[(size_t)i * N + j];
+      for (int k = 0; k < j; ++k) t -= Cm[(size_t)i * N + k] * Cm[(size_t)j * N + k];
+      Cm[(size_t)i * N + j] = t / Cm[(size_t)j * N + j];
+    }
+  }
+  for (int j = 0; j < N; ++j) {
+    Wm[(size_t)j * N + j] = 1.0L / Cm[(size_t)j * N + j];
+    for (int i = j + 1; i < N; ++i) {
+      long double t = 0.0L;
+      for (int k = j; k < i; ++k) t += Cm[(size_t)i * N + k] * Wm[(size_t)k * N + j];
+      Wm[(size_t)i * N + j] = -t / Cm[(size_t)i * N + i];
+    }
+  }
+  for (int i = 0; i < NN; ++i) tab[(size_t)NN + i] = (double)Wm[i];
+  return tab;
+}
+
 void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg::Basis1D* Bnext,
                     hipStream_t s) {
   const int N = B.N, NN = N * N, D = h->dim;
@@ -181,74 +210,48 @@ void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg:
     }
     L.d.eig = h->mem.upload(tab, s);
     L.f.eig = h->mem.upload(cast_vec<float>(tab), s);
-  } else if (h->opt.block_recompute) {
-    // the kernels rebuild S, lambda per cell and axis from kappa: they need
-    // Khat and W = C^-1 with Mhat = C C^T (then W L W^T is symmetric and its
-    // eigenvectors V give S = W^T V)
-    std::vector<double> tab((size_t)2 * NN, 0.0);
-    std::copy(B.K.begin(), B.K.end(), tab.begin());
-    std::vector<long double> Cm((size_t)NN, 0.0L), Wm((size_t)NN, 0.0L);
-    for (int j = 0; j < N; ++j) {
-      long double sd = B.M[(size_t)j * N + j];
-      for (int k = 0; k < j; ++k) sd -= Cm[(size_t)j * N + k] * Cm[(size_t)j * N + k];
-      if (!(sd > 0.0L)) throw HpmgError(HPMG_E_DEVICE, "mass matrix not positive definite");
-      Cm[(size_t)j * N + j] = std::sqrt(sd);
-      for (int i = j + 1; i < N; ++i) {
-        long double t = B.M[(size_t)i * N + j];
-        for (int k = 0; k < j; ++k) t -= Cm[(size_t)i * N + k] * Cm[(size_t)j * N + k];
-        Cm[(size_t)i * N + j] = t / Cm[(size_t)j * N + j];
-      }
-    }
-    for (int j = 0; j < N; ++j) {
-      Wm[(size_t)j * N + j] = 1.0L / Cm[(size_t)j * N + j];
-      for (int i = j + 1; i < N; ++i) {
-        long double t = 0.0L;
-        for (int k = j; k < i; ++k) t += Cm[(size_t)i * N + k] * Wm[(size_t)k * N + j];
-        Wm[(size_t)i * N + j] = -t / Cm[(size_t)i * N + i];
-      }
-    }
-    for (int i = 0; i < NN; ++i) tab[(size_t)NN + i] = (double)Wm[i];
-    L.d.rk = h->mem.upload(tab, s);
-    L.f.rk = h->mem.upload(cast_vec<float>(tab), s);
-    L.d.kappa = h->mem.upload(h->kappa, s);
-    L.f.kappa = h->mem.upload(cast_vec<float>(h->kappa), s);
   } else {
-    const int W = NN + N;
-    std::vector<double> tab((size_t)h->ncell * D * W);
-    const int n = h->n;
-    const double* kap = h->kappa.data();
-    const double sh = L.sigma_hat;
-    const unsigned nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> th;
-    std::vector<std::string> err(nth);
-    for (unsigned t = 0; t < nth; ++t)
-      th.emplace_back([&, t]() {
-        try {
-          std::vector<double> Lloc;
-          for (int c = (int)t; c < h->ncell; c += (int)nth) {
-            for (int k = 0; k < D; ++k) {
-              const int st = ipow(n, k);
-              const int x = (c / st) % n;
-              const bool b0 = x == 0, b1 = x == n - 1;
-              const double kK = kap[c];
-              const double k0 = b0 ? 0.0 : 2.0 * kK * kap[c - st] / (kK + kap[c - st]);
-              const double k1 = b1 ? 0.0 : 2.0 * kK * kap[c + st] / (kK + kap[c + st]);
-              axis_operator(B, kK, k0, b0, k1, b1, sh, Lloc);
-              double* S = &tab[((size_t)c * D + k) * W];
-              eig_of(B, Lloc, S, S + NN);
-            }
-          }
-        } catch (const std::exception& e) {
-          err[t] = e.what();
-        }
-      });
-    for (auto& x : th) x.join();
-    for (auto& e : err)
-      if (!e.empty()) throw HpmgError(HPMG_E_INVALID, e);
-    L.d.eig = h->mem.upload(tab, s);
-    L.f.eig = h->mem.upload(cast_vec<float>(tab), s);
+    // the kernels rebuild S, lambda per cell and axis from kappa
+    // (block_recompute) or read them from per-cell records built here on the
+    // device by the same eigensolve: both need Khat and W = C^-1 with
+    // Mhat = C C^T (then W L W^T is symmetric and its eigenvectors V give
+    // S = W^T V)
+    const std::vector<double> tab = khat_and_inverse_cholesky(B);
+    const double* rk = h->mem.upload(tab, s);
     L.d.kappa = h->mem.upload(h->kappa, s);
     L.f.kappa = h->mem.upload(cast_vec<float>(h->kappa), s);
+    if (h->opt.block_recompute == 1) {
+      L.d.rk = const_cast<double*>(rk);
+      L.f.rk = h->mem.upload(cast_vec<float>(tab), s);
+    } else {
+      const size_t ne = (size_t)h->ncell * D * (NN + N);
+      L.d.eig = (double*)h->mem.alloc(ne * sizeof(double));
+      L.f.eig = (float*)h->mem.alloc(ne * sizeof(float));
+      int* flag = (int*)h->mem.alloc(sizeof(int));
+      HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
+      hpmg::DGArgs<double> a = dg_args<double>(h, L);
+      a.rk = rk;
+      a.out = L.d.eig;
+      a.flag = flag;
+      dg_run(h, hpmg::OP_BUILD_EIG, a, N, 1, 0, s);
+      hpmg::cast_down<float>(ne, L.d.eig, L.f.eig, nullptr, 1.0, s);
+      int hflag = 0;
+      HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (hflag) throw HpmgError(HPMG_E_INVALID, "cell block is not positive definite (penalty too small?)");
+      if (h->opt.block_recompute == 2) {
+        // second record buffer of each precision (a copy: both valid), and
+        // the rebuild tables
+        L.d.ebuf[0] = L.d.eig;
+        L.f.ebuf[0] = L.f.eig;
+        L.d.ebuf[1] = (double*)h->mem.alloc(ne * sizeof(double));
+        L.f.ebuf[1] = (float*)h->mem.alloc(ne * sizeof(float));
+        HIPCHK(hipMemcpyAsync(L.d.ebuf[1], L.d.eig, ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(L.f.ebuf[1], L.f.eig, ne * sizeof(float), hipMemcpyDeviceToDevice, s));
+        L.d.rkb = const_cast<double*>(rk);
+        L.f.rkb = h->mem.upload(cast_vec<float>(tab), s);
+      }
+    }
   }
   const size_t R = (size_t)h->opt.max_rhs;
   for (int b = 0; b < 2; ++b) {
@@ -684,6 +687,41 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, int nrhs, hipSt
   }
 }
 
+// One finest-level sweep with block_recompute = 2 (split and postpone,
+// Section 4.3): the sweep reads the current per-cell records while the
+// records of the next traversal are rebuilt from kappa (the eigensolve of
+// the recompute variant) on the handle's second stream into the other
+// buffer; the next sweep waits for that rebuild, a rebuild waits for the
+// last sweep that read its buffer.
+template <typename T>
+void sweep_split(hpmg_ctx* h, T* u, const T* b, const T* trin, T* trout, int nrhs, hipStream_t s) {
+  using C = hpmg::CT<T>;
+  DGLevel& L = h->dg[0];
+  DGData<C>& dc = data<C>(L);
+  const int pi = std::is_same<C, double>::value ? 0 : 1;
+  const int cur = dc.ecur, nxt = cur ^ 1;
+  HIPCHK(hipStreamWaitEvent(s, h->ev_built[pi][cur], 0));
+  sweep<T>(h, 0, u, b, trin, trout, false, nrhs, s);
+  HIPCHK(hipEventRecord(h->ev_used[pi][cur], s));
+  HIPCHK(hipStreamWaitEvent(h->bs, h->ev_used[pi][nxt], 0));
+  hpmg::DGArgs<C> a = dg_args<C>(h, L);
+  a.rk = dc.rkb;
+  a.out = dc.ebuf[nxt];
+  a.flag = nullptr;
+  dg_run(h, hpmg::OP_BUILD_EIG, a, L.N, 1, 0, h->bs);
+  HIPCHK(hipEventRecord(h->ev_built[pi][nxt], h->bs));
+  dc.ecur = nxt;
+  dc.eig = dc.ebuf[nxt];
+}
+
+// After split sweeps: work queued next on s sees the current records.
+template <typename T>
+void split_join(hpmg_ctx* h, hipStream_t s) {
+  using C = hpmg::CT<T>;
+  const int pi = std::is_same<C, double>::value ? 0 : 1;
+  HIPCHK(hipStreamWaitEvent(s, h->ev_built[pi][data<C>(h->dg[0]).ecur], 0));
+}
+
 // Finest-level traces of a 16-bit storage type, allocated on first use.
 template <typename T>
 void ensure_traces(hpmg_ctx* h) {
@@ -954,8 +992,8 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
       require(coeff->kappa_const > 0.0 && std::isfinite(coeff->kappa_const), "kappa_const must be positive");
       h->kappa_const = coeff->kappa_const;
     }
-    require(h->opt.block_recompute == 0 || (h->opt.block_recompute == 1 && h->vark),
-            "block_recompute must be 0, or 1 with a per-cell kappa");
+    require(h->opt.block_recompute == 0 || ((h->opt.block_recompute == 1 || h->opt.block_recompute == 2) && h->vark),
+            "block_recompute must be 0, or 1 or 2 with a per-cell kappa");
     require(h->opt.block_variant == 0 || (!h->vark && h->n >= 3),
             "block_variant 1 (interior block) needs constant kappa and n >= 3");
     for (int i = 0, prev = p; i < 8 && h->opt.p_schedule[i] != 0; prev = h->opt.p_schedule[i], ++i)
@@ -1022,6 +1060,14 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
       }
     }
     h->ndof = h->dg[0].ndof;
+    if (h->opt.block_recompute == 2) {
+      HIPCHK(hipStreamCreateWithFlags(&h->bs, hipStreamNonBlocking));
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          HIPCHK(hipEventCreateWithFlags(&h->ev_built[i][j], hipEventDisableTiming));
+          HIPCHK(hipEventCreateWithFlags(&h->ev_used[i][j], hipEventDisableTiming));
+        }
+    }
     build_cg_levels(h.get(), stream);
     // outer solver workspace
     const size_t nd = h->ndof;
@@ -1171,8 +1217,13 @@ hpmg_status hpmg_smooth(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b,
       using T = std::remove_pointer_t<decltype(tag)>;
       DGData<T>& d = data<T>(h->dg[0]);
       project<T>(h, 0, (const T*)u, d.tr[0], nrhs, stream);
-      for (int k = 0; k < nsweeps; ++k)
-        sweep<T>(h, 0, (T*)u, (const T*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
+      for (int k = 0; k < nsweeps; ++k) {
+        if (h->opt.block_recompute == 2)
+          sweep_split<T>(h, (T*)u, (const T*)b, d.tr[k & 1], d.tr[(k + 1) & 1], nrhs, stream);
+        else
+          sweep<T>(h, 0, (T*)u, (const T*)b, d.tr[k & 1], d.tr[(k + 1) & 1], false, nrhs, stream);
+      }
+      if (h->opt.block_recompute == 2) split_join<T>(h, stream);
     });
     h->trace_state[dtype] = nsweeps & 1;
     h->trace_rhs[dtype] = nrhs;
@@ -1213,9 +1264,13 @@ hpmg_status hpmg_sweep(hpmg_handle h, hpmg_dtype dtype, void* u, const void* b, 
       using T = std::remove_pointer_t<decltype(tag)>;
       DGData<T>& d = data<T>(h->dg[0]);
       for (int k = 0; k < nsweeps; ++k) {
-        sweep<T>(h, 0, (T*)u, (const T*)b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, stream);
+        if (h->opt.block_recompute == 2)
+          sweep_split<T>(h, (T*)u, (const T*)b, d.tr[cur], d.tr[cur ^ 1], nrhs, stream);
+        else
+          sweep<T>(h, 0, (T*)u, (const T*)b, d.tr[cur], d.tr[cur ^ 1], false, nrhs, stream);
         cur ^= 1;
       }
+      if (h->opt.block_recompute == 2) split_join<T>(h, stream);
     });
     h->trace_state[dtype] = cur;
     return HPMG_OK;

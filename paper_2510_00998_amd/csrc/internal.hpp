@@ -95,6 +95,11 @@ struct DGData {
   T* ref = nullptr;
   T* eig = nullptr;
   T* rk = nullptr;       // block_recompute: [Khat | C^-1], Mhat = C C^T
+  // block_recompute = 2: the two record buffers (eig is ebuf[ecur]) and the
+  // [Khat | C^-1] table of the rebuild kernel
+  T* ebuf[2] = {nullptr, nullptr};
+  int ecur = 0;
+  T* rkb = nullptr;
   T* kappa = nullptr;
   T* u = nullptr;        // coarse levels only
   T* b = nullptr;        // coarse levels only
@@ -175,7 +180,18 @@ struct hpmg_ctx {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int graph_prec = -1;
+  // block_recompute = 2: rebuild stream and, per precision (FP64, FP32) and
+  // record buffer, the events "rebuild done" and "last sweep reading it done"
+  hipStream_t bs = nullptr;
+  hipEvent_t ev_built[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipEvent_t ev_used[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   ~hpmg_ctx() {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        if (ev_built[i][j]) (void)hipEventDestroy(ev_built[i][j]);
+        if (ev_used[i][j]) (void)hipEventDestroy(ev_used[i][j]);
+      }
+    if (bs) (void)hipStreamDestroy(bs);
     for (int i = 0; i < 2; ++i) {
       if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
       if (graph[i]) (void)hipGraphDestroy(graph[i]);

@@ -19,7 +19,8 @@ enum DGOp {
   OP_RESTRICT_Q1 = 5, // OP_RESTRICT to Q1 corner contributions from any degree (one-step p-coarsening)
   OP_PROLONG_Q1 = 6,  // OP_PROLONG from Q1 to any degree
   OP_RESTRICT_DYN = 7, // OP_RESTRICT to a DG level of a.ncd nodes per direction (explicit p schedules)
-  OP_PROLONG_DYN = 8   // OP_PROLONG from such a level
+  OP_PROLONG_DYN = 8,  // OP_PROLONG from such a level
+  OP_BUILD_EIG = 9     // per-cell fast-diagonalisation data of every cell (variable kappa) into a.out
 };
 
 // Next coarser level of a DG level with N nodes per direction: DG with

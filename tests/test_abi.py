@@ -45,7 +45,8 @@ def test_setup_rejects_bad_options():
     for field, val in [("omega_dg", 0.0), ("omega_dg", 1.5), ("omega_cg", -1.0), ("sigma0", 0.0),
                        ("coarsest_n", 1), ("max_rhs", 0), ("precision", 7), ("p_coarsening", 2),
                        ("h_factor", 4), ("h_factor", 1), ("block_recompute", 2),
-                       ("block_recompute", 1),  # recompute with constant kappa
+                       ("block_recompute", 1), ("block_recompute", 2),  # recompute with constant kappa
+                       ("block_recompute", 3),
                        ("nu_pre_cg", -2), ("nu_post_cg", -5), ("block_variant", 2), ("mfma", 2)]:
         opt = hp.default_options()
         setattr(opt, field, val)

@@ -22,10 +22,13 @@ torch = pytest.importorskip("torch")
 U = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 K_SMOOTH, K_VCYCLE = 40, 60
 
-# (degree 8 with the log-uniform coefficient overflows FP16 on these unscaled
-# inputs in either sweep; degree 8 runs with constant kappa)
 CASES = [(3, 4, 1, "const"), (3, 5, 2, "var"), (3, 4, 3, "const"), (3, 4, 4, "var"), (3, 3, 4, "const"),
-         (3, 3, 5, "var"), (3, 2, 6, "const"), (3, 2, 7, "var"), (3, 2, 8, "const")]
+         (3, 3, 5, "var"), (3, 2, 6, "const"), (3, 2, 7, "var"), (3, 2, 8, "var")]
+
+# FP16 inputs are scaled by 2^-6 (exactly): with kappa up to 100 and degree 7
+# or 8 the facet fluxes of O(1) data exceed the FP16 range (65504) in either
+# sweep; the solver's 16-bit cycles scale their residual for the same reason.
+SCALE = {"f16": 2.0 ** -6, "bf16": 1.0}
 
 
 def _kappa(dim, n, kind, seed=700):
@@ -37,7 +40,7 @@ def _dt(name):
 
 
 def _rounded(x, name):
-    return torch.tensor(x, dtype=torch.float64).to(_dt(name)).double().numpy()
+    return torch.tensor(x * SCALE[name], dtype=torch.float64).to(_dt(name)).double().numpy()
 
 
 @pytest.mark.parametrize("name", ["f16", "bf16"])
