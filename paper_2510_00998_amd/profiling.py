@@ -9,6 +9,7 @@ autotuner (same kernels, other grids) are excluded:
 
   python -m paper_2510_00998_amd.profiling times  <kernel_trace.csv> <S> <regex>
   python -m paper_2510_00998_amd.profiling counter <counter_collection.csv> <S> <regex>
+  python -m paper_2510_00998_amd.profiling summary <trace> <fetch> <write> <S> <keys json> <sources> <title> <command>
 
 `times` prints the mean duration per dispatch; `counter` the mean counter
 value per dispatch (KiB for FETCH_SIZE / WRITE_SIZE) and the copy kernel's
@@ -80,7 +81,61 @@ def dispatch_counter(path, last, pattern, counter):
     return out
 
 
+def summary(trace, fetch, write, last, keys, sources, title, command):
+    """Markdown summary of one --profile-sweeps workload: per matching kernel
+    the mean duration and copy-calibrated HBM bytes of its last `last`
+    dispatches, and per key (a regex over kernel names) the sums over the
+    matching kernels; the copy calibration divides the known 256 MiB of the
+    last three copy dispatches by their counter readings."""
+    import hashlib
+    import json
+    import os
+    keys = json.loads(keys)
+    pat = "|".join(f"(?:{r})" for r in keys.values())
+    t = dispatch_times(trace, last, pat)
+    f = dispatch_counter(fetch, last, pat, "FETCH_SIZE")
+    w = dispatch_counter(write, last, pat, "WRITE_SIZE")
+    cf = dispatch_counter(fetch, 3, r"copyBuffer", "FETCH_SIZE")
+    cw = dispatch_counter(write, 3, r"copyBuffer", "WRITE_SIZE")
+    kf = 262144.0 / list(cf.values())[0][1]
+    kw = 262144.0 / list(cw.values())[0][1]
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for src in sources.split(","):
+        h.update(open(os.path.join(csrc, src), "rb").read())
+    out = [f"# {title}", "", "Commands (from /tmp with TMPDIR=/tmp, repository at $R; each counter in a run of its own):",
+           ""] + ["    " + c for c in command.split(" ;; ")] + [
+        "", f"Only the last {last} dispatches of each kernel are kept (the timed sweeps; autotuner launches of the same "
+            "kernels come earlier).  Copy calibration: a 256 MiB device copy reads FETCH_SIZE = "
+            f"{list(cf.values())[0][1]:.1f} KiB and WRITE_SIZE = {list(cw.values())[0][1]:.1f} KiB per dispatch, so "
+            f"FETCH_SIZE is scaled by {kf:.4f} and WRITE_SIZE by {kw:.4f} to give bytes.", "",
+        "| kernel | dispatches | mean duration [us] | read [MB] | write [MB] | total [MB] |", "|---|---|---|---|---|---|"]
+    tot = {}
+    for k in sorted(t):
+        rd = f[k][1] * 1024 * kf if k in f else float("nan")
+        wr = w[k][1] * 1024 * kw if k in w else float("nan")
+        out.append(f"| `{k[:100]}` | {t[k][0]} | {t[k][1]:.2f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | {(rd + wr) / 1e6:.2f} |")
+        for key, rx in keys.items():
+            if re.search(rx, k):
+                a = tot.setdefault(key, [0.0, 0.0])
+                a[0] += t[k][1]
+                a[1] += rd + wr
+    out += ["", "| key | summed mean duration [us] | summed bytes per launch |", "|---|---|---|"]
+    for key, (dur, by) in tot.items():
+        out.append(f"| {key} | {dur:.2f} | {by:.0f} |")
+    out += ["", "Machine-readable (bench.py reads these while the kernel sources hash to the value below):", "",
+            f"    source_sha256: {h.hexdigest()}"]
+    for key, (dur, by) in tot.items():
+        out.append(f"    traffic_bytes_{key}: {by:.0f}")
+        out.append(f"    mean_duration_us_{key}: {dur:.3f}")
+    print("\n".join(out))
+
+
 def main(argv):
+    if argv[0] == "summary":
+        # summary <trace.csv> <fetch.csv> <write.csv> <last> <keys json> <sources> <title> <command>
+        summary(argv[1], argv[2], argv[3], int(argv[4]), argv[5], argv[6], argv[7], argv[8])
+        return
     mode, path, last, pattern = argv[0], argv[1], int(argv[2]), argv[3]
     if mode == "times":
         res = dispatch_times(path, last, pattern)
