@@ -123,3 +123,89 @@ def test_fullsize_batched_workload():
                  np.linalg.norm(b[r * nd:(r + 1) * nd]) for r in range(R))
         log(f"  problem {j} (n={n}, p={p}): oracle residual {rr:.2e}")
         assert rr <= 2e-10
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_fullsize_variant_sweeps_sampled(name):
+    # one sweep with 16-bit storage of u and traces (FP32 arithmetic) on all
+    # three workloads, and, for the variable-coefficient ones, one sweep with
+    # the block data rebuilt in the traversal (block_recompute = 1) and with
+    # split-and-postpone rebuilds (block_recompute = 2), against the oracle's
+    # block-Jacobi step on sampled cells
+    import paper_2510_00998_amd as hp
+    dim, n, p, kf = WORKLOADS[name]
+    kappa = kf()
+    vark = not isinstance(kappa, float)
+    log(f"full-size variants {name}: dim={dim} n={n} p={p}")
+    s = SIPG(dim, n, p, kappa)
+    cells = _sample_cells(n, dim, 64, seed=9)
+    u0 = synth.random_vector(s.ndof, seed=21)
+    b = synth.random_rhs(s.ndof, seed=22)
+    blocks = s._diag_blocks_for(cells)
+
+    def step_ref(uu, bb):
+        r = bb.reshape(s.ncell, s.nd)[cells] - s.apply_rows(cells, uu)
+        return uu.reshape(s.ncell, s.nd)[cells] + 0.7 * np.linalg.solve(blocks, r[..., None])[..., 0]
+
+    g = hp.Solver(dim, n, p, kappa)
+    # 16-bit storage: inputs rounded to the format; one sweep stores u and
+    # the traces once (about 2 unit roundoffs of the format, bound 4)
+    for dt, u in ((torch.float16, 2.0 ** -11), (torch.bfloat16, 2.0 ** -8)):
+        ud = torch.tensor(u0, dtype=torch.float64, device="cuda").to(dt)
+        bd = torch.tensor(b, dtype=torch.float64, device="cuda").to(dt)
+        ur, br = to_host(ud), to_host(bd)
+        ref = step_ref(ur, br)
+        g.smooth(ud, bd, 1)
+        got = to_host(ud).reshape(s.ncell, s.nd)[cells]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        log(f"  {dt}: sweep rel err {err:.2e} on {len(cells)} cells")
+        assert err <= 4 * u
+        del ud, bd
+    g.close()
+    if vark:
+        ref = step_ref(u0, b)
+        for mode in (1, 2):
+            gr = hp.Solver(dim, n, p, kappa, block_recompute=mode)
+            for dt, tol in ((torch.float64, 1e-11), (torch.float32, 1e-5)):
+                ud = torch.tensor(u0, dtype=dt, device="cuda")
+                bd = torch.tensor(b, dtype=dt, device="cuda")
+                gr.smooth(ud, bd, 1)
+                got = to_host(ud).reshape(s.ncell, s.nd)[cells]
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                log(f"  block_recompute={mode} {dt}: sweep rel err {err:.2e}")
+                assert err <= tol
+                del ud, bd
+            gr.close()
+
+
+def test_q4_manufactured_solution_rate():
+    # the Q4 workload's path (FP32 cycle inside FP64 FCG to 1e-10) on 8^3,
+    # 16^3, 32^3: the L2 error of u = prod sin(pi x_i) decreases at the rate
+    # p + 1 = 5, and at 32^3 it equals the error of a far tighter FP64-cycle
+    # solve within 1% (the solve error is below the discretisation error)
+    import paper_2510_00998_amd as hp
+    from oracle import manufactured as mf
+    uex, _ = mf.sin_product(3, 1)
+    errs = {}
+    for n in (8, 16, 32):
+        s = SIPG(3, n, 4)
+        g = hp.Solver(3, n, 4, 1.0)
+        bd = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+        g.load_vector(1, 1.0, bd)
+        x = torch.zeros_like(bd)
+        info, st = g.solve(x, bd, rtol=1e-10, maxit=100)
+        assert st == 0
+        errs[n] = s.l2_error(to_host(x), uex)
+        log(f"Q4 n={n}: L2 error {errs[n]:.4e} ({info.iterations} its)")
+        if n == 32:
+            g64 = hp.Solver(3, n, 4, 1.0, precision=hp.PREC_F64)
+            x2 = torch.zeros_like(bd)
+            g64.solve(x2, bd, rtol=1e-13, maxit=200, check=False)
+            e_tight = s.l2_error(to_host(x2), uex)
+            log(f"  32^3 tight FP64 solve: L2 error {e_tight:.4e}")
+            assert abs(errs[n] - e_tight) <= 0.01 * e_tight
+        g.close()
+    for a, b_ in ((8, 16), (16, 32)):
+        rate = np.log2(errs[a] / errs[b_])
+        log(f"  rate {a}->{b_}: {rate:.3f}")
+        assert abs(rate - 5.0) <= 0.25
