@@ -239,6 +239,28 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
   }
 }
 
+// Round-robin slot moves of the parallel Jacobi sweep: the slots 0 .. M - 2
+// form a circle (position c sits in slot M - 2 for c = 0, in slot 2 (c - 1)
+// for 1 <= c < M / 2, in slot 2 (M - 2 - c) + 1 otherwise), paired so that
+// circle positions c and M - 1 - c share a slot pair and position 0 pairs
+// with the fixed slot M - 1; one step moves position c to c + 1.
+template <int M>
+__host__ __device__ constexpr int jac_circle_slot(int c) {
+  return c == 0 ? M - 2 : (c < M / 2 ? 2 * (c - 1) : 2 * (M - 2 - c) + 1);
+}
+template <int M>
+__host__ __device__ constexpr int jac_slot_circle(int s) {
+  return s == M - 2 ? 0 : ((s & 1) == 0 ? s / 2 + 1 : M - 2 - (s - 1) / 2);
+}
+template <int M>
+__host__ __device__ constexpr int jac_next(int s) {
+  return s == M - 1 ? s : jac_circle_slot<M>((jac_slot_circle<M>(s) + 1) % (M - 1));
+}
+template <int M>
+__host__ __device__ constexpr int jac_prev(int s) {
+  return s == M - 1 ? s : jac_circle_slot<M>((jac_slot_circle<M>(s) + M - 2) % (M - 1));
+}
+
 // Fast-diagonalisation data of every staged (cell, axis), rebuilt from kappa
 // (block_recompute; the paper's variant that forms the block inverse anew in
 // each cell and traversal), in the cell's own S | Si | lambda record in LDS:
@@ -246,14 +268,14 @@ __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<
 //         (c1, c2) = (-kappa_F/2, sigma_hat kappa_F) interior, (-kappa_K,
 //         2 sigma_hat kappa_K) on the boundary (a boundary facet has kappa_F 0)
 //   A   = W L W^T with W = C^-1, Mhat = C C^T (symmetric), in the Si slot
-//   cyclic Jacobi rotations A <- J^T A J, V <- V J (V in the S slot) until A
+//   parallel Jacobi rotations A <- J^T A J, V <- V J (V in the S slot) until A
 //   is diagonal to working precision (at most 8 sweeps in FP64, 6 in FP32)
 //   lambda = diag(A), S = W^T V, so that L S = Mhat S diag(lambda), S^T Mhat S = I.
 // N lanes of one wave share a (cell, axis): lane r owns row r of every
-// product and entry r of the two columns and rows each rotation changes;
-// the rotation angle is formed redundantly by the N lanes.  The lanes of a
-// problem are in one wave, whose LDS accesses complete in program order, so
-// a wavefront-scope fence between the phases orders them.
+// product; the products that form A and S go through the cell's LDS record,
+// and the rotations run in registers with cross-lane shuffles.  The lanes of
+// a problem are in one wave, whose LDS accesses complete in program order,
+// so a wavefront-scope fence between the phases orders them.
 template <typename T, int D, int N>
 __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>* sE, const CT<T>* sKF) {
   using C = CT<T>;
@@ -341,62 +363,116 @@ __device__ __forceinline__ void recompute_eig(const DGArgs<T>& a, int nc, CT<T>*
       for (int j = 0; j < N; ++j) A[r * N + j] = row[j];
     }
     wave_sync();
-    bool done = false;
+    // Parallel Jacobi rotations in registers (round-robin ordering): the
+    // rows and columns of A sit in M = N + (N & 1) slots; every round
+    // rotates the disjoint slot pairs (2k, 2k+1) (for odd N slot N is an
+    // empty placeholder, so slot N - 1 waits), then moves the indices one
+    // step along a circle of the slots 0 .. M - 2 (slot M - 1 stays), so
+    // that in M - 1 rounds every index pair meets once.  Lane r holds the
+    // row of slot r of A and of V (V's rows stay in the original order, its
+    // columns move with A's).  The order of the eigenpairs that results is
+    // immaterial: lambda and the columns of S move together.
+    constexpr int M = N + (N & 1);
+    C arow[N], vrow[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      arow[j] = A[r * N + j];
+      vrow[j] = j == r ? C(1) : C(0);
+    }
+    const int base = lane - r;  // lane of slot 0 of this problem
+    const int pr = r ^ 1;       // partner slot
+    const bool paired = pr < N;
+    const bool lower = (r & 1) == 0;
+    const int src_pair = base + (paired ? pr : r);
+    const int src_move = base + jac_prev<M>(r);  // slot whose row moves into slot r
+    bool done = !act;
 #pragma unroll 1
     for (int sw = 0; sw < SWEEPS; ++sw) {
       // stop once the off-diagonal part is below working precision (every
       // lane of a problem forms the same sums)
+      C offr = 0, dgr = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if (j == r)
+          dgr = arow[j] * arow[j];
+        else
+          offr += arow[j] * arow[j];
+      }
       C off = 0, dg = 0;
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        dg += A[i * N + i] * A[i * N + i];
-#pragma unroll
-        for (int j = i + 1; j < N; ++j) off += A[i * N + j] * A[i * N + j];
+      for (int m = 0; m < N; ++m) {
+        off += __shfl(offr, base + m, 64);
+        dg += __shfl(dgr, base + m, 64);
       }
-      done = done || off <= (sizeof(C) == 8 ? C(1e-30) : C(1e-14)) * dg;
+      done = done || C(0.5) * off <= (sizeof(C) == 8 ? C(1e-30) : C(1e-14)) * dg;
       if (__all(done)) break;  // every problem of the wave has converged
 #pragma unroll 1
-      for (int p = 0; p < N - 1; ++p) {
-#pragma unroll 1
-        for (int q = p + 1; q < N; ++q) {
-          const C apq = A[p * N + q];
-          const bool rot = !done && apq != C(0);
-          C cs = C(1), sn = C(0);
-          if (rot) {
-            const C tau = (A[q * N + q] - A[p * N + p]) / (C(2) * apq);
-            const C at = tau < C(0) ? -tau : tau;
-            // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), without overflow
-            const C root =
-                at > C(1) ? at * __builtin_sqrt(C(1) + (C(1) / at) * (C(1) / at)) : __builtin_sqrt(C(1) + at * at);
-            const C tn = (tau < C(0) ? C(-1) : C(1)) / (at + root);
-            cs = C(1) / __builtin_sqrt(C(1) + tn * tn);
-            sn = tn * cs;
-          }
-          wave_sync();
-          // columns p, q: entry r
-          const C x = A[r * N + p], y = A[r * N + q];
-          wave_sync();
-          if (act && rot) {
-            A[r * N + p] = cs * x - sn * y;
-            A[r * N + q] = sn * x + cs * y;
-          }
-          wave_sync();
-          // rows p, q: entry r
-          const C xr = A[p * N + r], yr = A[q * N + r];
-          const C vx = V[r * N + p], vy = V[r * N + q];
-          wave_sync();
-          if (act && rot) {
-            A[p * N + r] = cs * xr - sn * yr;
-            A[q * N + r] = sn * xr + cs * yr;
-            V[r * N + p] = cs * vx - sn * vy;
-            V[r * N + q] = sn * vx + cs * vy;
-          }
-          wave_sync();
-          if (act && rot && r == 0) A[p * N + q] = A[q * N + p] = C(0);
-          wave_sync();
+      for (int t = 0; t < M - 1; ++t) {
+        C mydiag = 0, myoff = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          if (j == r) mydiag = arow[j];
+          if (j == pr) myoff = arow[j];
+        }
+        const C pdiag = __shfl(mydiag, src_pair, 64);
+        const C poff = __shfl(myoff, src_pair, 64);
+        // both lanes of a pair form the angle from the lower slot's entry
+        const C app = lower ? mydiag : pdiag, aqq = lower ? pdiag : mydiag, apq = lower ? myoff : poff;
+        // an unpaired, converged or already zero pair rotates by the identity
+        const bool rot = paired && !done && apq != C(0);
+        const C tau = (aqq - app) / (C(2) * (rot ? apq : C(1)));
+        const C at = __builtin_fabs(tau);
+        // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), without overflow
+        const C ia = C(1) / (at > C(1) ? at : C(1));
+        const C root = at > C(1) ? at * __builtin_sqrt(C(1) + ia * ia) : __builtin_sqrt(C(1) + at * at);
+        const C tn = __builtin_copysign(C(1), tau) / (at + root);
+        const C cs = rot ? C(1) / __builtin_sqrt(C(1) + tn * tn) : C(1);
+        const C sn = rot ? tn * cs : C(0);
+        // columns 2k, 2k+1 of the rows of A and V (the pair's angle is held
+        // by the lane of slot 2k)
+#pragma unroll
+        for (int k = 0; 2 * k + 1 < N; ++k) {
+          const C cj = __shfl(cs, base + 2 * k, 64), sj = __shfl(sn, base + 2 * k, 64);
+          const C x = arow[2 * k], y = arow[2 * k + 1];
+          arow[2 * k] = cj * x - sj * y;
+          arow[2 * k + 1] = sj * x + cj * y;
+          const C vx = vrow[2 * k], vy = vrow[2 * k + 1];
+          vrow[2 * k] = cj * vx - sj * vy;
+          vrow[2 * k + 1] = sj * vx + cj * vy;
+        }
+        // rows: p' = cs p - sn q, q' = sn p + cs q; the pair's entry is zero
+        // afterwards
+        const C so = lower ? -sn : sn;  // coefficient of the partner's row
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const C pj = __shfl(arow[j], src_pair, 64);
+          const C nv = cs * arow[j] + so * pj;
+          arow[j] = (rot && j == pr) ? C(0) : nv;
+        }
+        // move every index one step along the circle: row of slot prev(r)
+        // into slot r, column j into column next(j)
+        C na[N], nvr[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          na[jac_next<M>(j)] = __shfl(arow[j], src_move, 64);
+          nvr[jac_next<M>(j)] = vrow[j];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          arow[j] = na[j];
+          vrow[j] = nvr[j];
         }
       }
     }
+    wave_sync();
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        A[r * N + j] = arow[j];
+        V[r * N + j] = vrow[j];
+      }
+    }
+    wave_sync();
     // lambda = diag(A); S = W^T V, row r: S[r][c] = sum_{m >= r} W[m][r] V[m][c]
     const C lr = A[r * N + r];
 #pragma unroll
