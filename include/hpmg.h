@@ -288,7 +288,10 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
  * caller's `stream` is synchronised; the call returns when done.
  * HPMG_E_NOT_CONVERGED after maxit iterations or when a segment's true
  * residual stays above rtol after 3 restarts (as in hpmg_solve),
- * HPMG_E_BREAKDOWN if a segment met a non-finite value. */
+ * HPMG_E_BREAKDOWN if a segment met a non-finite value.  A batch of one
+ * problem solved for one right-hand side whose handle has precision
+ * HPMG_F32 runs hpmg_solve on it (the same iteration without work lists;
+ * infos[0] then carries its residual history). */
 hpmg_status hpmg_batch_solve(hpmg_batch b, double* const* u, const double* const* rhs, int nrhs, double rtol,
                              int maxit, hpmg_solve_info* infos, hipStream_t stream);
 
@@ -308,9 +311,21 @@ hpmg_status hpmg_batch_smooth(hpmg_batch b, hpmg_dtype dtype, void* const* u, co
  * of right-hand sides: out[0] persistent grid (blocks) of the V-cycle
  * launches, out[1] 1 if they run one launch per polynomial degree (else
  * one launch over all degrees), out[2..3] the same for FP32
- * hpmg_batch_smooth, out[4..5] for FP64 (0 where not tuned yet).  out: host
- * array of 6 ints. */
+ * hpmg_batch_smooth, out[4..5] for FP64, out[6..8] the tile masks of the
+ * V-cycle, FP32 and FP64 smoothing launches: bit N (N = p + 1) set if the
+ * degree-p launches use half the cells per workgroup (about 128 instead of
+ * 256 threads).  0 where not tuned yet.  out: host array of 9 ints. */
 hpmg_status hpmg_batch_tuning(hpmg_batch b, int* out);
+
+/* Replace the launch configuration of the batch's current plan (the one
+ * built by the last hpmg_batch_solve or hpmg_batch_smooth call): cfg (host,
+ * 9 ints) as returned by hpmg_batch_tuning; a part whose grid entry
+ * (cfg[0], cfg[2], cfg[4]) is 0 is left unchanged.  A tile mask may only
+ * name degrees 1 <= p <= 5 and needs split 1.  For callers that reuse a
+ * configuration tuned earlier, or compare configurations; all do the same
+ * arithmetic per cell and agree to rounding.  HPMG_E_INVALID without a
+ * plan or with an entry out of range. */
+hpmg_status hpmg_batch_set_tuning(hpmg_batch b, const int* cfg);
 
 /* Release the batch (not its handles; NULL is ignored). */
 void hpmg_batch_destroy(hpmg_batch b);

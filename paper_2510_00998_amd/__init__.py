@@ -108,6 +108,8 @@ _lib.hpmg_batch_smooth.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctype
 _lib.hpmg_batch_smooth.restype = ctypes.c_int
 _lib.hpmg_batch_tuning.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
 _lib.hpmg_batch_tuning.restype = ctypes.c_int
+_lib.hpmg_batch_set_tuning.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
+_lib.hpmg_batch_set_tuning.restype = ctypes.c_int
 _lib.hpmg_batch_destroy.argtypes = [_vp]
 _lib.hpmg_batch_destroy.restype = None
 _lib.hpmg_status_string.argtypes = [ctypes.c_int]
@@ -318,11 +320,29 @@ class Batch:
     @property
     def tuning(self) -> dict:
         """Autotuned launch configuration (hpmg_batch_tuning)."""
-        out = (ctypes.c_int * 6)()
+        out = (ctypes.c_int * 9)()
         _check(_lib.hpmg_batch_tuning(self._b, out), "hpmg_batch_tuning")
+
+        def half_tiles(mask):  # degrees p whose launches use half the cells per workgroup
+            return [n - 1 for n in range(2, 31) if (mask >> n) & 1]
         return {"vcycle_grid": out[0], "vcycle_split_by_degree": bool(out[1]),
                 "smooth_f32_grid": out[2], "smooth_f32_split_by_degree": bool(out[3]),
-                "smooth_f64_grid": out[4], "smooth_f64_split_by_degree": bool(out[5])}
+                "smooth_f64_grid": out[4], "smooth_f64_split_by_degree": bool(out[5]),
+                "vcycle_half_tile_degrees": half_tiles(out[6]),
+                "smooth_f32_half_tile_degrees": half_tiles(out[7]),
+                "smooth_f64_half_tile_degrees": half_tiles(out[8])}
+
+    def set_tuning(self, cfg):
+        """Replace the launch configuration (hpmg_batch_set_tuning): cfg is the
+        9-int list of hpmg_batch_tuning (see tuning_raw)."""
+        arr = (ctypes.c_int * 9)(*cfg)
+        _check(_lib.hpmg_batch_set_tuning(self._b, arr), "hpmg_batch_set_tuning")
+
+    @property
+    def tuning_raw(self) -> list:
+        out = (ctypes.c_int * 9)()
+        _check(_lib.hpmg_batch_tuning(self._b, out), "hpmg_batch_tuning")
+        return list(out)
 
     @property
     def grid(self) -> int:

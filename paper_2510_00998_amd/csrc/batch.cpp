@@ -3,8 +3,9 @@
 // V-cycle runs as one persistent launch over a work list that covers every
 // problem and right-hand side at that level; one iteration of the FP64
 // flexible CG (FP32 V-cycle inside) is captured once as a HIP graph and
-// replayed.  The persistent grid size is chosen by timing the V-cycle
-// (autotuning) at the first solve.
+// replayed.  The persistent grid size, one launch per degree or one for all,
+// and the cells per block of each degree (tile variant) are chosen by timing
+// the V-cycle (autotuning) at the first solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,27 +27,40 @@ struct Launch {
   int kind = 0;  // 0: DG float, 1: DG double, 2: Q1 float
   int op = 0;
   const void* args = nullptr;
-  const hpmg::WorkItem* items = nullptr;  // DG: sorted by degree
+  const hpmg::WorkItem* items = nullptr;  // DG: sorted by degree; cell blocks of tile variant 0
   int nitems = 0;
   // DG: runs of equal degree in `items` (degree, first item, count)
   std::vector<int3> runs;
+  // DG: the same work in the cell blocks of tile variant 1 (half the cells
+  // per block), for the one-launch-per-degree kernels
+  const hpmg::WorkItem* items1 = nullptr;
+  std::vector<int3> runs1;
 };
 
-// DG launch over `items` (sorted here by degree, stable), uploaded to mem.
-Launch dg_launch(DevMem& mem, int kind, int op, const void* args, std::vector<hpmg::WorkItem> items, hipStream_t s) {
+// Items sorted by degree (stable), uploaded to mem, and their degree runs.
+const hpmg::WorkItem* sorted_runs(DevMem& mem, std::vector<hpmg::WorkItem> items, std::vector<int3>& runs,
+                                  hipStream_t s) {
   std::stable_sort(items.begin(), items.end(),
                    [](const hpmg::WorkItem& a, const hpmg::WorkItem& b) { return a.w < b.w; });
+  for (int i = 0; i < (int)items.size(); ++i) {
+    if (runs.empty() || runs.back().x != items[i].w) runs.push_back(int3{items[i].w, i, 0});
+    ++runs.back().z;
+  }
+  return mem.upload(items, s);
+}
+
+// DG launch over `items` (tile variant 0) and `items1` (the same work in
+// tile variant 1).
+Launch dg_launch(DevMem& mem, int kind, int op, const void* args, std::vector<hpmg::WorkItem> items,
+                 std::vector<hpmg::WorkItem> items1, hipStream_t s) {
   Launch L;
   L.kind = kind;
   L.op = op;
   L.args = args;
   L.nitems = (int)items.size();
   if (items.empty()) return L;
-  L.items = mem.upload(items, s);
-  for (int i = 0; i < L.nitems; ++i) {
-    if (L.runs.empty() || L.runs.back().x != items[i].w) L.runs.push_back(int3{items[i].w, i, 0});
-    ++L.runs.back().z;
-  }
+  L.items = sorted_runs(mem, std::move(items), L.runs, s);
+  L.items1 = sorted_runs(mem, std::move(items1), L.runs1, s);
   return L;
 }
 
@@ -57,6 +71,7 @@ Launch dg_launch(DevMem& mem, int kind, int op, const void* args, std::vector<hp
 struct BatchPlan {
   int nrhs = 0;
   bool split = true;         // one launch per degree (tuned with the grid)
+  int tile = 0;              // bit N: degree-N launches use tile variant 1 (tuned after the grid)
   std::vector<size_t> off0;  // offset of each problem in the workspace vectors
   size_t total = 0;          // their length
   int grid = 0;  // persistent grid (blocks) of the batched launches, 0: not tuned
@@ -84,6 +99,7 @@ struct BatchPlan {
     Launch proj, even, odd;
     int grid = 0;
     bool split = true;
+    int tile = 0;
     hipEvent_t copied = nullptr;  // the last staging copy has completed
   } sm[2];
   ~BatchPlan() {
@@ -113,18 +129,11 @@ namespace {
 template <typename T>
 struct Table {
   std::vector<T> args;
-  std::vector<hpmg::WorkItem> items;
+  std::vector<hpmg::WorkItem> items;   // cell blocks of tile variant 0
+  std::vector<hpmg::WorkItem> items1;  // of tile variant 1 (DG only)
 };
 
-int cpb_of(int N) {
-  switch (N) {
-    case 2: return hpmg::DGShape<3, 2>::CPB;
-    case 3: return hpmg::DGShape<3, 3>::CPB;
-    case 4: return hpmg::DGShape<3, 4>::CPB;
-    case 5: return hpmg::DGShape<3, 5>::CPB;
-    default: return hpmg::DGShape<3, 6>::CPB;
-  }
-}
+int cpb_of(int N, int V) { return hpmg::cells_per_block_v(3, N, V); }
 
 // Launch builder: collects per-problem arguments and work items, uploads.
 struct Builder {
@@ -133,7 +142,7 @@ struct Builder {
   template <typename T>
   Launch dg(int op, Table<hpmg::DGArgs<T>>& t) {
     if (t.items.empty()) return Launch{};
-    return dg_launch(b->mem, sizeof(T) == 4 ? 0 : 1, op, b->mem.upload(t.args, s), t.items, s);
+    return dg_launch(b->mem, sizeof(T) == 4 ? 0 : 1, op, b->mem.upload(t.args, s), t.items, t.items1, s);
   }
   Launch cg(Table<hpmg::CGArgs<float>>& t) {
     Launch L;
@@ -150,9 +159,11 @@ template <typename T>
 void add_dg_items(Table<hpmg::DGArgs<T>>& t, const hpmg::DGArgs<T>& a, int N, int nrhs) {
   const int idx = (int)t.args.size();
   t.args.push_back(a);
-  const int nb = (a.ncell + cpb_of(N) - 1) / cpb_of(N);
-  for (int r = 0; r < nrhs; ++r)
-    for (int blk = 0; blk < nb; ++blk) t.items.push_back(hpmg::WorkItem{idx, blk, r, N});
+  for (int V = 0; V < hpmg::kTileVariants; ++V) {
+    const int nb = (a.ncell + cpb_of(N, V) - 1) / cpb_of(N, V);
+    for (int r = 0; r < nrhs; ++r)
+      for (int blk = 0; blk < nb; ++blk) (V == 0 ? t.items : t.items1).push_back(hpmg::WorkItem{idx, blk, r, N});
+  }
 }
 
 void add_cg_items(Table<hpmg::CGArgs<float>>& t, const hpmg::CGArgs<float>& a, int count, int nrhs) {
@@ -413,20 +424,31 @@ void build_vcycle(BatchPlan* B, const std::vector<hpmg_handle>& hs, const std::v
   rec(0);
 }
 
-// split: one launch per degree run (each with its own kernel), else one
-// launch over all degrees
-void run_grid(const std::vector<Launch>& v, int grid, bool split, hipStream_t s) {
+// One-degree launch of a degree run in tile variant V.
+template <typename T>
+void dg_run(int V, int op, const int3& r, const void* args, const hpmg::WorkItem* items, int grid, hipStream_t s) {
+  if (V == 0)
+    hpmg::batch_dg_n_t0<T>(op, r.x, (const hpmg::DGArgs<T>*)args, items + r.y, r.z, grid, s);
+  else
+    hpmg::batch_dg_n_t1<T>(op, r.x, (const hpmg::DGArgs<T>*)args, items + r.y, r.z, grid, s);
+}
+
+// split: one launch per degree run (each with its own kernel; degree N in
+// tile variant (tile >> N) & 1), else one launch over all degrees
+void run_grid(const std::vector<Launch>& v, int grid, bool split, int tile, hipStream_t s) {
   for (const Launch& L : v) {
     if (L.nitems == 0) continue;
     if (L.kind == 2) {
       hpmg::batch_cg<float>((const hpmg::CGArgs<float>*)L.args, L.items, L.nitems, grid, s);
     } else if (split) {
-      for (const int3& r : L.runs) {
-        if (L.kind == 0)
-          hpmg::batch_dg_n<float>(L.op, r.x, (const hpmg::DGArgs<float>*)L.args, L.items + r.y, r.z, grid, s);
-        else
-          hpmg::batch_dg_n<double>(L.op, r.x, (const hpmg::DGArgs<double>*)L.args, L.items + r.y, r.z, grid, s);
-      }
+      for (int V = 0; V < hpmg::kTileVariants; ++V)
+        for (const int3& r : V == 0 ? L.runs : L.runs1) {
+          if (((tile >> r.x) & 1) != V) continue;
+          if (L.kind == 0)
+            dg_run<float>(V, L.op, r, L.args, V == 0 ? L.items : L.items1, grid, s);
+          else
+            dg_run<double>(V, L.op, r, L.args, V == 0 ? L.items : L.items1, grid, s);
+        }
     } else if (L.kind == 0) {
       hpmg::batch_dg<float>(L.op, (const hpmg::DGArgs<float>*)L.args, L.items, L.nitems, grid, s);
     } else {
@@ -437,7 +459,7 @@ void run_grid(const std::vector<Launch>& v, int grid, bool split, hipStream_t s)
 }
 
 void run(BatchPlan* B, const std::vector<Launch>& v, hipStream_t s) {
-  run_grid(v, B->grid > 0 ? B->grid : 1024, B->split, s);  // before tuning: a default
+  run_grid(v, B->grid > 0 ? B->grid : 1024, B->split, B->tile, s);  // before tuning: a default
 }
 
 // One iteration of the flexible CG for every segment; r32 holds r cast to
@@ -554,57 +576,88 @@ std::unique_ptr<BatchPlan> make_plan(const std::vector<hpmg_handle>& hs, int nrh
     }
   B->resid_args = (hpmg::DGArgs<double>*)M.alloc(all.size() * sizeof(hpmg::DGArgs<double>));
   B->resid_args_h = all;
-  auto shifted = [&](int by) {
-    std::vector<hpmg::WorkItem> v = tr.items;
+  auto shifted = [&](const std::vector<hpmg::WorkItem>& items, int by) {
+    std::vector<hpmg::WorkItem> v = items;
     for (auto& w : v) w.x += by;
     return v;
   };
-  B->proj_u = dg_launch(M, 1, hpmg::BOP_PROJECT, B->resid_args, tpu.items, s);
-  B->resid_r = dg_launch(M, 1, hpmg::BOP_RESID, B->resid_args, shifted(np), s);
-  B->resid_z = dg_launch(M, 1, hpmg::BOP_RESID, B->resid_args, shifted(2 * np), s);
+  B->proj_u = dg_launch(M, 1, hpmg::BOP_PROJECT, B->resid_args, tpu.items, tpu.items1, s);
+  B->resid_r = dg_launch(M, 1, hpmg::BOP_RESID, B->resid_args, shifted(tr.items, np), shifted(tr.items1, np), s);
+  B->resid_z =
+      dg_launch(M, 1, hpmg::BOP_RESID, B->resid_args, shifted(tr.items, 2 * np), shifted(tr.items1, 2 * np), s);
   HIPCHK(hipStreamSynchronize(s));
   return B;
 }
 
-// Autotuner: the fastest (grid, split) among the candidates, timed with
-// events on s; work(grid, split, reps) enqueues the timed work.
+// Autotuner over the launch configuration (grid, split, tile): first the
+// fastest (grid, split) among the candidates with tile variant 0, then,
+// degree by degree, tile variant 1 for that degree's one-degree launches
+// where it is faster.  Timed with events on s; work(grid, split, tile,
+// reps) enqueues the timed work; `degrees` are the degrees N present.
 template <class F>
-void tune(const std::vector<int>& grids, F work, hipStream_t s, int& grid, bool& split) {
+void tune(const std::vector<int>& grids, const std::vector<int>& degrees, F work, hipStream_t s, int& grid,
+          bool& split, int& tile) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  auto timed = [&](int g, bool sp, int tl) {
+    work(g, sp, tl, 1);  // warm-up
+    HIPCHK(hipEventRecord(e0, s));
+    work(g, sp, tl, 2);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms;
+  };
   double tbest = 1e30;
+  tile = 0;
   for (bool sp : {true, false})
     for (int g : grids) {
-      work(g, sp, 1);  // warm-up
-      HIPCHK(hipEventRecord(e0, s));
-      work(g, sp, 2);
-      HIPCHK(hipEventRecord(e1, s));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      const double ms = timed(g, sp, 0);
       if (ms < tbest) {
         tbest = ms;
         grid = g;
         split = sp;
       }
     }
+  for (int N : degrees) {
+    const int t1 = tile | (1 << N);
+    const double ms = timed(grid, true, t1);
+    if (ms < tbest) {
+      tbest = ms;
+      tile = t1;
+      split = true;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
 
-// Persistent grid size and degree split of the V-cycle launches, tuned on
-// the V-cycle of the batch (run on the current r32).
+// Degrees N of the DG launches in v.
+std::vector<int> degrees_of(const std::vector<Launch>& v) {
+  int mask = 0;
+  for (const Launch& L : v)
+    for (const int3& r : L.runs) mask |= 1 << r.x;
+  std::vector<int> out;
+  for (int N = 0; N < 31; ++N)
+    if ((mask >> N) & 1) out.push_back(N);
+  return out;
+}
+
+// Persistent grid size, degree split and tile variants of the V-cycle
+// launches, tuned on the V-cycle of the batch (run on the current r32).
 void autotune_vcycle(BatchPlan* B, hipStream_t s) {
-  int grid = 1024;
+  int grid = 1024, tile = 0;
   bool split = true;
-  tune({256, 512, 1024, 2048, 4096},
-       [&](int g, bool sp, int reps) {
-         for (int i = 0; i < reps; ++i) run_grid(B->vcycle, g, sp, s);
+  tune({256, 512, 1024, 2048, 4096}, degrees_of(B->vcycle),
+       [&](int g, bool sp, int tl, int reps) {
+         for (int i = 0; i < reps; ++i) run_grid(B->vcycle, g, sp, tl, s);
        },
-       s, grid, split);
+       s, grid, split, tile);
   B->grid = grid;
   B->split = split;
+  B->tile = tile;
 }
 
 template <typename T>
@@ -636,10 +689,10 @@ void stage_smooth(BatchPlan* B, BatchPlan::Smooth& S, int np, T* const* u, const
 }
 
 template <typename T>
-void smooth_launches(BatchPlan::Smooth& S, int nsweeps, int grid, bool split, hipStream_t s) {
+void smooth_launches(BatchPlan::Smooth& S, int nsweeps, int grid, bool split, int tile, hipStream_t s) {
   std::vector<Launch> v = {S.proj};
   for (int i = 0; i < nsweeps; ++i) v.push_back((i & 1) ? S.odd : S.even);
-  run_grid(v, grid, split, s);
+  run_grid(v, grid, split, tile, s);
 }
 
 // Tables of hpmg_batch_smooth for dtype T; the persistent grid is tuned on
@@ -672,16 +725,16 @@ void prepare_smooth(BatchPlan* B, const std::vector<hpmg_handle>& hs, hipStream_
   std::memcpy(S.host, all.data(), S.bytes);
   HIPCHK(hipEventCreateWithFlags(&S.copied, hipEventDisableTiming));
   HIPCHK(hipEventRecord(S.copied, s));
-  auto shifted = [&](int by) {
-    std::vector<hpmg::WorkItem> v = t.items;
+  auto shifted = [&](const std::vector<hpmg::WorkItem>& items, int by) {
+    std::vector<hpmg::WorkItem> v = items;
     for (auto& w : v) w.x += by;
     return v;
   };
   const int ni = (int)t.items.size();
   const int kind = sizeof(T) == 8 ? 1 : 0;
-  S.proj = dg_launch(B->mem, kind, hpmg::BOP_PROJECT, S.args, shifted(0), s);
-  S.even = dg_launch(B->mem, kind, hpmg::BOP_SWEEP, S.args, shifted(np), s);
-  S.odd = dg_launch(B->mem, kind, hpmg::BOP_SWEEP, S.args, shifted(2 * np), s);
+  S.proj = dg_launch(B->mem, kind, hpmg::BOP_PROJECT, S.args, shifted(t.items, 0), shifted(t.items1, 0), s);
+  S.even = dg_launch(B->mem, kind, hpmg::BOP_SWEEP, S.args, shifted(t.items, np), shifted(t.items1, np), s);
+  S.odd = dg_launch(B->mem, kind, hpmg::BOP_SWEEP, S.args, shifted(t.items, 2 * np), shifted(t.items1, 2 * np), s);
   // grid: persistent candidates and one block per item
   std::vector<T*> su(np);
   std::vector<const T*> sb(np);
@@ -692,8 +745,9 @@ void prepare_smooth(BatchPlan* B, const std::vector<hpmg_handle>& hs, hipStream_
   hpmg::fill<T>(ws_u<T>(B), B->total, T(0), s);
   hpmg::fill<T>(ws_b<T>(B), B->total, T(0), s);
   stage_smooth<T>(B, S, np, su.data(), sb.data(), s);
-  tune({1024, 2048, 4096, 8192, ni},
-       [&](int g, bool sp, int reps) { smooth_launches<T>(S, 2 * reps, g, sp, s); }, s, S.grid, S.split);
+  tune({1024, 2048, 4096, 8192, ni}, degrees_of({S.even}),
+       [&](int g, bool sp, int tl, int reps) { smooth_launches<T>(S, 2 * reps, g, sp, tl, s); }, s, S.grid, S.split,
+       S.tile);
 }
 
 }  // namespace
@@ -749,7 +803,44 @@ hpmg_status hpmg_batch_tuning(hpmg_batch b, int* out) {
     out[2 + 2 * k] = P ? P->sm[k].grid : 0;
     out[3 + 2 * k] = P ? (int)P->sm[k].split : 0;
   }
+  out[6] = P ? P->tile : 0;
+  out[7] = P ? P->sm[0].tile : 0;
+  out[8] = P ? P->sm[1].tile : 0;
   return HPMG_OK;
+}
+
+hpmg_status hpmg_batch_set_tuning(hpmg_batch b, const int* cfg) {
+  try {
+    require(b && cfg, "NULL argument");
+    BatchPlan* P = b->plan.get();
+    require(P != nullptr, "no launch plan yet: solve or smooth once first");
+    const int tmask = ((1 << (hpmg::BATCH_NMAX + 1)) - 1) & ~((1 << hpmg::BATCH_NMIN) - 1);
+    for (int k = 0; k < 3; ++k) {
+      require(cfg[2 * k] >= 0 && (cfg[2 * k + 1] == 0 || cfg[2 * k + 1] == 1), "bad grid or split");
+      require((cfg[6 + k] & ~tmask) == 0, "tile mask names a degree outside the batched range");
+      require(cfg[6 + k] == 0 || cfg[2 * k + 1] == 1, "half tiles need one launch per degree");
+    }
+    if (cfg[0] > 0) {
+      P->grid = cfg[0];
+      P->split = cfg[1] != 0;
+      P->tile = cfg[6];
+      // the captured iteration holds the old launch configuration
+      if (P->exec) (void)hipGraphExecDestroy(P->exec);
+      if (P->graph) (void)hipGraphDestroy(P->graph);
+      P->exec = nullptr;
+      P->graph = nullptr;
+    }
+    for (int k = 0; k < 2; ++k)
+      if (cfg[2 + 2 * k] > 0) {
+        P->sm[k].grid = cfg[2 + 2 * k];
+        P->sm[k].split = cfg[3 + 2 * k] != 0;
+        P->sm[k].tile = cfg[7 + k];
+      }
+    return HPMG_OK;
+  } catch (const HpmgError& e) {
+    set_last_error(e.what());
+    return e.st;
+  }
 }
 
 hpmg_status hpmg_batch_smooth(hpmg_batch bt, hpmg_dtype dtype, void* const* u, const void* const* b, int nsweeps,
@@ -775,12 +866,12 @@ hpmg_status hpmg_batch_smooth(hpmg_batch bt, hpmg_dtype dtype, void* const* u, c
       prepare_smooth<double>(B, hs, stream);
       BatchPlan::Smooth& S = B->sm[1];
       stage_smooth<double>(B, S, np, (double* const*)u, (const double* const*)b, stream);
-      smooth_launches<double>(S, nsweeps, S.grid, S.split, stream);
+      smooth_launches<double>(S, nsweeps, S.grid, S.split, S.tile, stream);
     } else {
       prepare_smooth<float>(B, hs, stream);
       BatchPlan::Smooth& S = B->sm[0];
       stage_smooth<float>(B, S, np, (float* const*)u, (const float* const*)b, stream);
-      smooth_launches<float>(S, nsweeps, S.grid, S.split, stream);
+      smooth_launches<float>(S, nsweeps, S.grid, S.split, S.tile, stream);
     }
     return HPMG_OK;
   } catch (const HpmgError& e) {
@@ -806,6 +897,12 @@ hpmg_status hpmg_batch_solve(hpmg_batch bt, double* const* u, const double* cons
       require(hs[j]->opt.max_rhs >= nrhs, "nrhs exceeds a handle's max_rhs");
       hs[j]->trace_state[0] = hs[j]->trace_state[1] = -1;
     }
+    // A single segment (one problem, one right-hand side) with the FP32
+    // cycle: every phase is that one problem's work, which the
+    // single-problem captured iteration (the problem's own kernels, no work
+    // lists or segment tables) does with less overhead.
+    if (np == 1 && R == 1 && hs[0]->opt.precision == HPMG_F32)
+      return hpmg_solve(hs[0], u[0], b[0], 1, rtol, maxit, infos, stream);
     hipStream_t s = bt->st;
     // work queued on the caller's stream (e.g. writes of u, b) completes first
     HIPCHK(hipStreamSynchronize(stream));

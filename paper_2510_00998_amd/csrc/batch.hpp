@@ -67,9 +67,13 @@ constexpr double BATCH_MAX_RESTARTS = 3;  // restarts from the true residual per
 
 template <typename T>
 void batch_dg(int op, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
-// The same with one kernel per degree N: items must all have w = N.
+// The same with one kernel per degree N (items must all have w = N) and the
+// cells per block of tile variant 0 or 1 (DGShapeV; the items' cell blocks
+// must be those of that variant).
 template <typename T>
-void batch_dg_n(int op, int N, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
+void batch_dg_n_t0(int op, int N, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
+template <typename T>
+void batch_dg_n_t1(int op, int N, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
 template <typename T>
 void batch_cg(const CGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s);
 

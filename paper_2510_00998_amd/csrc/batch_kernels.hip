@@ -1,41 +1,10 @@
 // Persistent batched kernels: every launch walks a work list covering all
 // problems of a batch, so one launch serves one multigrid phase of every
 // problem regardless of its mesh size and polynomial degree.
-#include "batch.hpp"
-#include "dg_kernels_impl.hpp"
-#include "kernels.hpp"
+#include "batch_dg_body.hpp"
 
 namespace hpmg {
 namespace {
-
-template <typename T, int N, int OP>
-__device__ __forceinline__ void dg_item(const DGArgs<T>& a, int bx, int by, char* lds) {
-  constexpr int NC = nc_next(N);
-  if constexpr (OP == BOP_SWEEP)
-    dgk::sweep_body<T, 3, N, false, false>(a, bx, by, lds);
-  else if constexpr (OP == BOP_SWEEP0)
-    dgk::sweep_body<T, 3, N, true, false>(a, bx, by, lds);
-  else if constexpr (OP == BOP_RESTRICT)
-    dgk::apply_body<T, 3, N, NC, true, false>(a, bx, by, lds);
-  else if constexpr (OP == BOP_PROLONG)
-    dgk::prolong_body<T, 3, N, NC>(a, bx, by, lds);
-  else if constexpr (OP == BOP_PROJECT)
-    dgk::prolong_body<T, 3, N, 0>(a, bx, by, lds);
-  else if constexpr (OP == BOP_RESID)
-    dgk::apply_body<T, 3, N, 0, true, false>(a, bx, by, lds);
-  else
-    dgk::apply_body<T, 3, N, 0, false, false>(a, bx, by, lds);
-}
-
-template <typename T, int N, int OP>
-constexpr int item_lds() {
-  if constexpr (OP == BOP_PROLONG)
-    return dgk::prolong_lds_bytes<T, 3, N, nc_next(N)>();
-  else if constexpr (OP == BOP_PROJECT)
-    return dgk::prolong_lds_bytes<T, 3, N, 0>();
-  else
-    return dgk::cell_lds_bytes<T, 3, N, false>();
-}
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -60,20 +29,6 @@ __global__ __launch_bounds__(256) void k_dg_batch(const DGArgs<T>* __restrict__ 
       case 6: dg_item<T, 6, OP>(a, w.y, w.z, lds); break;
       default: break;
     }
-    __syncthreads();  // the next item reuses the LDS
-  }
-}
-
-// One degree per launch: the kernel takes only that degree's registers and
-// LDS (items of other degrees are not expected in its list).
-template <typename T, int OP, int N>
-__global__ __launch_bounds__(256) void k_dg_batch_n(const DGArgs<T>* __restrict__ args,
-                                                    const WorkItem* __restrict__ items, int nitems) {
-  __shared__ __attribute__((aligned(16))) char lds[item_lds<T, N, OP>()];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const WorkItem w = items[it];
-    const DGArgs<T> a = args[w.x];
-    dg_item<T, N, OP>(a, w.y, w.z, lds);
     __syncthreads();  // the next item reuses the LDS
   }
 }
@@ -204,6 +159,11 @@ __global__ __launch_bounds__(256) void k_cg_batch(const CGArgs<T>* __restrict__ 
 }
 
 // ----------------------------------------------------- segmented vectors
+// One block of BV threads per 16,384-element chunk: 16 elements per thread,
+// unrolled by 4, so that a single problem of a few million unknowns (a few
+// hundred chunks) still keeps enough loads in flight to stream HBM.
+constexpr int BV = 1024;
+
 __device__ __forceinline__ double bsum(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -217,14 +177,15 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
 }
 
 // partial[2*chunk + {0,1}] = x.y, x.z over the chunk (z may be NULL)
-__global__ __launch_bounds__(256) void k_bdot(SegTable t, const double* __restrict__ x, const double* __restrict__ y,
+__global__ __launch_bounds__(BV) void k_bdot(SegTable t, const double* __restrict__ x, const double* __restrict__ y,
                                               const double* __restrict__ z, double* __restrict__ partial) {
-  __shared__ double sh[4];
+  __shared__ double sh[BV / 64];
   for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
     const int2 ch = t.chunks[ci];
     const long long o = t.off[ch.x] + ch.y;
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
     double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < len; i += blockDim.x) {
       const double xi = x[o + i];
       s0 += xi * y[o + i];
@@ -242,16 +203,17 @@ __global__ __launch_bounds__(256) void k_bdot(SegTable t, const double* __restri
 // Preconditioned residual straight from the FP32 cycle: z = z32 / s[14]
 // (s[14]: scale the cycle's right-hand side was cast with).
 // partial[2*chunk + {0,1}] = z.r, z.q over the chunk.
-__global__ __launch_bounds__(256) void k_bdot_z(SegTable t, const float* __restrict__ z32,
+__global__ __launch_bounds__(BV) void k_bdot_z(SegTable t, const float* __restrict__ z32,
                                                 const double* __restrict__ r, const double* __restrict__ q,
                                                 const double* __restrict__ scal, double* __restrict__ partial) {
-  __shared__ double sh[4];
+  __shared__ double sh[BV / 64];
   for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
     const int2 ch = t.chunks[ci];
     const long long o = t.off[ch.x] + ch.y;
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
     const double sc = 1.0 / scal[(size_t)ch.x * BATCH_SCAL + 14];
     double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < len; i += blockDim.x) {
       const double zi = (double)z32[o + i] * sc;
       s0 += zi * r[o + i];
@@ -345,7 +307,7 @@ __global__ __launch_bounds__(64) void k_bfinal(SegTable t, int op, const double*
 }
 
 // p = z + beta p with z = z32 / s[14]
-__global__ __launch_bounds__(256) void k_bupdate_p(SegTable t, const float* __restrict__ z32, double* __restrict__ p,
+__global__ __launch_bounds__(BV) void k_bupdate_p(SegTable t, const float* __restrict__ z32, double* __restrict__ p,
                                                    const double* __restrict__ scal) {
   for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
     const int2 ch = t.chunks[ci];
@@ -353,6 +315,7 @@ __global__ __launch_bounds__(256) void k_bupdate_p(SegTable t, const float* __re
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
     const double* sg = scal + (size_t)ch.x * BATCH_SCAL;
     const double beta = sg[3], sc = 1.0 / sg[14];
+#pragma unroll 4
     for (int i = threadIdx.x; i < len; i += blockDim.x) {
       const double zi = (double)z32[o + i] * sc;
       p[o + i] = beta == 0.0 ? zi : zi + beta * p[o + i];
@@ -362,10 +325,10 @@ __global__ __launch_bounds__(256) void k_bupdate_p(SegTable t, const float* __re
 
 // u += alpha p, r -= alpha q, r32 = r s[7] (the next cycle's right-hand
 // side), partial[2*chunk] = r.r
-__global__ __launch_bounds__(256) void k_bupdate_ur(SegTable t, double* __restrict__ r, float* __restrict__ r32,
+__global__ __launch_bounds__(BV) void k_bupdate_ur(SegTable t, double* __restrict__ r, float* __restrict__ r32,
                                                     const double* __restrict__ p, const double* __restrict__ q,
                                                     const double* __restrict__ scal, double* __restrict__ partial) {
-  __shared__ double sh[4];
+  __shared__ double sh[BV / 64];
   for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
     const int2 ch = t.chunks[ci];
     const long long o = t.off[ch.x] + ch.y;
@@ -374,6 +337,7 @@ __global__ __launch_bounds__(256) void k_bupdate_ur(SegTable t, double* __restri
     const double alpha = sg[5], sc = sg[7];
     double* u = t.u[ch.x] + ch.y;
     double acc = 0.0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < len; i += blockDim.x) {
       double rn = r[o + i];
       if (alpha != 0.0) {
@@ -393,7 +357,7 @@ __global__ __launch_bounds__(256) void k_bupdate_ur(SegTable t, double* __restri
 }
 
 // Segments whose true residual missed the tolerance restart from it.
-__global__ __launch_bounds__(256) void k_bselect(SegTable t, const double* __restrict__ q, double* __restrict__ r,
+__global__ __launch_bounds__(BV) void k_bselect(SegTable t, const double* __restrict__ q, double* __restrict__ r,
                                                  const double* __restrict__ scal) {
   for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
     const int2 ch = t.chunks[ci];
@@ -401,17 +365,19 @@ __global__ __launch_bounds__(256) void k_bselect(SegTable t, const double* __res
     if (!(s[10] == 0.0 && s[11] == 1.0)) continue;
     const long long o = t.off[ch.x] + ch.y;
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
+#pragma unroll 4
     for (int i = threadIdx.x; i < len; i += blockDim.x) r[o + i] = q[o + i];
   }
 }
 
-__global__ __launch_bounds__(256) void k_bcast_down(SegTable t, const double* __restrict__ x, float* __restrict__ y,
+__global__ __launch_bounds__(BV) void k_bcast_down(SegTable t, const double* __restrict__ x, float* __restrict__ y,
                                                     const double* __restrict__ scal) {
   for (int ci = blockIdx.x; ci < t.nchunks; ci += gridDim.x) {
     const int2 ch = t.chunks[ci];
     const long long o = t.off[ch.x] + ch.y;
     const int len = min(BATCH_CHUNK, t.len[ch.x] - ch.y);
     const double sc = scal[(size_t)ch.x * BATCH_SCAL + 7];
+#pragma unroll 4
     for (int i = threadIdx.x; i < len; i += blockDim.x) y[o + i] = (float)(x[o + i] * sc);
   }
 }
@@ -457,33 +423,6 @@ void batch_dg(int op, const DGArgs<T>* args, const WorkItem* items, int nitems, 
   }
 }
 
-template <typename T, int OP>
-void launch_n(int N, const DGArgs<T>* args, const WorkItem* items, int nitems, dim3 g, hipStream_t s) {
-  switch (N) {
-    case 2: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 2>), g, dim3(256), 0, s, args, items, nitems); break;
-    case 3: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 3>), g, dim3(256), 0, s, args, items, nitems); break;
-    case 4: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 4>), g, dim3(256), 0, s, args, items, nitems); break;
-    case 5: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 5>), g, dim3(256), 0, s, args, items, nitems); break;
-    default: hipLaunchKernelGGL((k_dg_batch_n<T, OP, 6>), g, dim3(256), 0, s, args, items, nitems); break;
-  }
-}
-
-template <typename T>
-void batch_dg_n(int op, int N, const DGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s) {
-  const dim3 g(grid_for(nitems, grid));
-  switch (op) {
-    case BOP_SWEEP: launch_n<T, BOP_SWEEP>(N, args, items, nitems, g, s); break;
-    case BOP_SWEEP0: launch_n<T, BOP_SWEEP0>(N, args, items, nitems, g, s); break;
-    case BOP_RESTRICT: launch_n<T, BOP_RESTRICT>(N, args, items, nitems, g, s); break;
-    case BOP_PROLONG: launch_n<T, BOP_PROLONG>(N, args, items, nitems, g, s); break;
-    case BOP_PROJECT: launch_n<T, BOP_PROJECT>(N, args, items, nitems, g, s); break;
-    case BOP_RESID: launch_n<T, BOP_RESID>(N, args, items, nitems, g, s); break;
-    default: launch_n<T, BOP_APPLY>(N, args, items, nitems, g, s); break;
-  }
-}
-template void batch_dg_n<float>(int, int, const DGArgs<float>*, const WorkItem*, int, int, hipStream_t);
-template void batch_dg_n<double>(int, int, const DGArgs<double>*, const WorkItem*, int, int, hipStream_t);
-
 template <typename T>
 void batch_cg(const CGArgs<T>* args, const WorkItem* items, int nitems, int grid, hipStream_t s) {
   hipLaunchKernelGGL((k_cg_batch<T>), dim3(grid_for(nitems, grid)), dim3(256), 0, s, args, items, nitems);
@@ -495,30 +434,30 @@ template void batch_cg<float>(const CGArgs<float>*, const WorkItem*, int, int, h
 template void batch_cg<double>(const CGArgs<double>*, const WorkItem*, int, int, hipStream_t);
 
 void bk_dot(const SegTable& t, const double* x, const double* y, const double* z, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_bdot, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, x, y, z, partial);
+  hipLaunchKernelGGL(k_bdot, dim3(grid_for(t.nchunks, 2048)), dim3(BV), 0, s, t, x, y, z, partial);
 }
 void bk_dot_z(const SegTable& t, const float* z32, const double* r, const double* q, const double* scal,
               double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_bdot_z, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, z32, r, q, scal, partial);
+  hipLaunchKernelGGL(k_bdot_z, dim3(grid_for(t.nchunks, 2048)), dim3(BV), 0, s, t, z32, r, q, scal, partial);
 }
 void bk_finalize(const SegTable& t, int op, const double* partial, double* scal, double rtol2, hipStream_t s) {
   hipLaunchKernelGGL(k_bfinal, dim3(t.nseg), dim3(64), 0, s, t, op, partial, scal, rtol2);
 }
 void bk_update_p(const SegTable& t, const float* z32, double* p, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_bupdate_p, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, z32, p, scal);
+  hipLaunchKernelGGL(k_bupdate_p, dim3(grid_for(t.nchunks, 2048)), dim3(BV), 0, s, t, z32, p, scal);
 }
 void bk_update_ur(const SegTable& t, double* r, float* r32, const double* p, const double* q, const double* scal,
                   double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_bupdate_ur, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, r, r32, p, q, scal, partial);
+  hipLaunchKernelGGL(k_bupdate_ur, dim3(grid_for(t.nchunks, 2048)), dim3(BV), 0, s, t, r, r32, p, q, scal, partial);
 }
 void bk_cast_down(const SegTable& t, const double* x, float* y, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcast_down, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, x, y, scal);
+  hipLaunchKernelGGL(k_bcast_down, dim3(grid_for(t.nchunks, 2048)), dim3(BV), 0, s, t, x, y, scal);
 }
 void bk_count(const SegTable& t, const double* scal, int* count, hipStream_t s) {
   hipLaunchKernelGGL(k_bcount, dim3(1), dim3(256), 0, s, t, scal, count);
 }
 void bk_select(const SegTable& t, const double* q, double* r, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_bselect, dim3(grid_for(t.nchunks, 4096)), dim3(256), 0, s, t, q, r, scal);
+  hipLaunchKernelGGL(k_bselect, dim3(grid_for(t.nchunks, 2048)), dim3(BV), 0, s, t, q, r, scal);
 }
 
 }  // namespace hpmg

@@ -23,6 +23,7 @@ SOURCES = [
     "hpmg.cpp",
     "cg_kernels.hip",
     "batch_kernels.hip",
+    "batch_tile1.hip",
     "batch.cpp",
     "noalloc.hip",
     "dg_inst_2d_float.hip",

@@ -41,16 +41,25 @@ __host__ __device__ constexpr int cells_per_block(int D, int N) {
   return (D == 3 && N == HPMG_CPB3D_N) ? HPMG_CPB3D
                                        : ((256 / (D == 2 ? N : N * N)) > 0 ? (256 / (D == 2 ? N : N * N)) : 1);
 }
-template <int D, int N>
-struct DGShape {
+// Tile variants of a cell-block kernel (picked by the batched driver's
+// autotuner): V = 0 the cells of about 256 threads, V = 1 half as many
+// cells (about 128 threads, at least one cell).
+constexpr int kTileVariants = 2;
+__host__ __device__ constexpr int cells_per_block_v(int D, int N, int V) {
+  return V == 0 ? cells_per_block(D, N) : (cells_per_block(D, N) / 2 > 0 ? cells_per_block(D, N) / 2 : 1);
+}
+template <int D, int N, int V>
+struct DGShapeV {
   static constexpr int L = (D == 2) ? N : N * N;  // lines per cell = nodes per facet
   static constexpr int NV = L * N;                // nodes per cell
   static constexpr int NF = 2 * D;                // facets per cell
-  static constexpr int CPB = cells_per_block(D, N);
+  static constexpr int CPB = cells_per_block_v(D, N, V);
   static constexpr int NT = CPB * L;
   static constexpr int BLOCK = (NT + 63) / 64 * 64;  // launch bound: whole waves
   static constexpr int EGS = 2 * N * N + N;       // S, Si, lambda of one direction
 };
+template <int D, int N>
+using DGShape = DGShapeV<D, N, 0>;
 
 // Per-level reference data (type T), in global memory:
 //   [0, N^2)            Mhat (1D mass on [0,1], symmetric)

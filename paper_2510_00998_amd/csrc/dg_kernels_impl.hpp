@@ -17,8 +17,25 @@
 
 #include "dg_kernels.hpp"
 
+// A translation unit may compile the cell kernels for another tile variant
+// (cells per block, see DGShapeV) by defining HPMG_TILE first: they then
+// live in namespace dgk_t<HPMG_TILE>, the host launchers below are left
+// out, and unqualified DGShape<D, N> names the variant's shape.
+#ifndef HPMG_TILE
+#define HPMG_TILE 0
+#endif
+#if HPMG_TILE == 0
+#define HPMG_DGK dgk
+#else
+#define HPMG_DGK_CAT2(a, b) a##b
+#define HPMG_DGK_CAT(a, b) HPMG_DGK_CAT2(a, b)
+#define HPMG_DGK HPMG_DGK_CAT(dgk_t, HPMG_TILE)
+#endif
+
 namespace hpmg {
-namespace dgk {
+namespace HPMG_DGK {
+template <int D, int N>
+using DGShape = ::hpmg::DGShapeV<D, N, HPMG_TILE>;
 
 // Offset of the first node of the line of thread `ln` along axis k, and the
 // node stride along that axis (x fastest).  The facet node index of the line
@@ -1736,7 +1753,9 @@ __global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_prolong(DGArgs<T> a)
   prolong_body<T, D, N, NC, IVAR>(a, blockIdx.x, blockIdx.y, lds);
 }
 
-}  // namespace dgk
+}  // namespace HPMG_DGK
+
+#if HPMG_TILE == 0
 
 template <typename C, int D, int N>
 void launch_build_eig(const DGArgs<C>& a, hipStream_t s) {
@@ -1827,4 +1846,5 @@ void launch_prolong(const DGArgs<T>& a, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC, false>), grid, dim3(Sh::NT), 0, s, a);
 }
 
+#endif  // HPMG_TILE == 0
 }  // namespace hpmg

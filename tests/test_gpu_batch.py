@@ -213,3 +213,93 @@ def test_batch_reuse_with_a_different_tolerance():
             assert rr <= 2 * rtol
             if rtol == 1e-6:
                 assert rr > 1e-9  # stopped at the loose tolerance, not at the previous call's
+
+
+def test_one_problem_batch():
+    """One problem, one right-hand side: the batch runs the single-problem
+    iteration (same iterates as hpmg_solve); with two right-hand sides it
+    runs the batched iteration, which agrees with it to 1e-8."""
+    import paper_2510_00998_amd as hp
+    n, p = 6, 4
+    s = hp.Solver(3, n, p, KAPPA, max_rhs=2, precision=hp.PREC_F32)
+    batch = hp.Batch([s])
+    nd = s.ndof
+    A = SIPG(3, n, p, KAPPA).A
+    for nrhs in (1, 2):
+        b = _rhs(0, nd, nrhs, base=SEED + 11)
+        bd = to_dev(b, torch.float64)
+        ub = torch.zeros(nrhs * nd, dtype=torch.float64, device="cuda")
+        us = torch.zeros_like(ub)
+        infos, st = batch.solve([ub], [bd], rtol=1e-10, maxit=200, nrhs=nrhs)
+        info1, st1 = s.solve(us, bd, rtol=1e-10, maxit=200, nrhs=nrhs)
+        assert st == 0 and st1 == 0
+        u = to_host(ub)
+        worst = max(np.linalg.norm(b[r * nd:(r + 1) * nd] - A @ u[r * nd:(r + 1) * nd]) /
+                    np.linalg.norm(b[r * nd:(r + 1) * nd]) for r in range(nrhs))
+        log(f"one-problem batch nrhs={nrhs}: its {infos[0].iterations} (single {info1.iterations}), "
+            f"oracle residual {worst:.3e}")
+        assert worst <= 2e-10
+        if nrhs == 1:
+            assert np.array_equal(u, to_host(us)) and infos[0].iterations == info1.iterations
+        else:
+            assert rel_err(u, to_host(us)) <= 1e-8 and abs(infos[0].iterations - info1.iterations) <= 2
+
+
+def test_launch_configurations_agree():
+    """Every launch configuration the autotuner may pick (grid, one launch per
+    degree or one for all, half-size cell tiles per degree) does the same
+    per-cell arithmetic up to the compiler's rounding order in each kernel:
+    smoothing agrees to rounding, solves to 1e-8 with the same iteration
+    counts (+-2), and every solve meets the oracle residual."""
+    import paper_2510_00998_amd as hp
+    nrhs = 2
+    solvers, batch = _batch(PROBLEMS)
+    bh = [_rhs(j, s.ndof, nrhs, base=SEED + 13) for j, s in enumerate(solvers)]
+    bs = [to_dev(b, torch.float64) for b in bh]
+    all_tiles = sum(1 << (p + 1) for p in range(1, 6))
+    configs = [[512, 1, 512, 1, 512, 1, 0, 0, 0],       # one launch per degree, full tiles (reference)
+               [700, 1, 700, 1, 700, 1, all_tiles, all_tiles, all_tiles],  # half tiles everywhere
+               [300, 0, 300, 0, 300, 0, 0, 0, 0],       # one launch for all degrees
+               None]                                    # the autotuner's choice
+    sols, smooths, its = [], [], []
+    for k, cfg in enumerate(configs):
+        us = [torch.zeros(nrhs * s.ndof, dtype=torch.float64, device="cuda") for s in solvers]
+        if k == 0:  # a plan exists only after the first call
+            batch.solve(us, bs, rtol=1e-10, maxit=200, nrhs=nrhs)
+            auto = batch.tuning_raw
+            us = [torch.zeros_like(u) for u in us]
+        if cfg is None:
+            cfg = auto
+        batch.set_tuning(cfg)
+        got = batch.tuning_raw
+        assert all(got[i] == cfg[i] for i in range(9) if cfg[2 * (i % 3 if i >= 6 else i // 2)] > 0)
+        infos, st = batch.solve(us, bs, rtol=1e-10, maxit=200, nrhs=nrhs)
+        assert st == 0
+        sols.append([to_host(u) for u in us])
+        its.append([i.iterations for i in infos])
+        sm = []
+        for dt in (torch.float64, torch.float32):
+            uu = [torch.zeros(nrhs * s.ndof, dtype=dt, device="cuda") for s in solvers]
+            batch.smooth(uu, [b.to(dt) for b in bs], 3, nrhs=nrhs)
+            torch.cuda.synchronize()
+            sm.append([to_host(u) for u in uu])
+        smooths.append(sm)
+        log(f"config {list(cfg)}: iterations {its[-1]}")
+    for k in range(1, len(configs)):
+        for j in range(len(solvers)):
+            e64 = rel_err(smooths[k][0][j], smooths[0][0][j])
+            e32 = rel_err(smooths[k][1][j], smooths[0][1][j])
+            es = rel_err(sols[k][j], sols[0][j])
+            if j == 0:
+                log(f"  config {k} vs 0, problem 0: smoothing FP64 {e64:.1e} FP32 {e32:.1e}, solution {es:.1e}")
+            assert e64 <= 1e-13 and e32 <= 1e-5
+            assert es <= 1e-8 and abs(its[k][j] - its[0][j]) <= 2
+    for k in range(len(configs)):
+        for j, ((n, p), s) in enumerate(zip(PROBLEMS, solvers)):
+            A = SIPG(3, n, p, KAPPA).A
+            nd = s.ndof
+            for r in range(nrhs):
+                br = bh[j][r * nd:(r + 1) * nd]
+                assert np.linalg.norm(br - A @ sols[k][j][r * nd:(r + 1) * nd]) / np.linalg.norm(br) <= 2e-10
+    with pytest.raises(hp.HpmgError):  # half tiles without one launch per degree
+        batch.set_tuning([512, 0, 0, 0, 0, 0, all_tiles, 0, 0])
