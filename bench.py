@@ -50,10 +50,11 @@ def _sha(files):
     return h.hexdigest()
 
 
-def counter_traffic(summary, sources, key):
+def counter_traffic(summary, sources, key, require=None):
     """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (copy-calibrated), or None if the kernel sources have
-    changed since the counters were taken."""
+    changed since the counters were taken, or if a `require` entry (launch
+    configuration) differs from the one recorded with the counters."""
     try:
         txt = open(os.path.join(ROOT, "profiles", summary)).read()
         sha = _sha(sources)
@@ -62,11 +63,15 @@ def counter_traffic(summary, sources, key):
     vals = {}
     for line in txt.splitlines():
         line = line.strip()
-        if ":" in line and (line.startswith("source_sha256") or line.startswith("traffic_bytes")):
+        if ":" in line and (line.startswith("source_sha256") or line.startswith("traffic_bytes")
+                            or line.startswith("launch_")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != sha or key not in vals:
         return None
+    for k, v in (require or {}).items():
+        if vals.get(k) != v:
+            return None
     return float(vals[key])
 
 
@@ -125,6 +130,9 @@ def parse():
                          "in every traversal instead of the stored-eigendata sweeps (same kernel names, so each "
                          "variant is profiled in its own process)")
     ap.add_argument("--seq-reps", type=int, default=3, help="repetitions of the problem-after-problem solves")
+    ap.add_argument("--smooth-tuning", default=None,
+                    help="batched workload: 9 comma-separated ints for hpmg_batch_set_tuning after the first calls "
+                         "(a launch configuration recorded with a profile)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain device copies of known size (for counter calibration)")
     return ap.parse_args()
@@ -227,7 +235,14 @@ def run_batched(args):
     batch.smooth(us, bs, 0, nrhs=R)
     batch.smooth(us32, bs32, 0, nrhs=R)
     torch.cuda.synchronize()
+    if args.smooth_tuning:
+        batch.set_tuning([int(x) for x in args.smooth_tuning.split(",")])
     tuning = batch.tuning
+    raw = batch.tuning_raw
+    # smoothing launch configuration as recorded with the counter profile:
+    # one launch per degree or one for all, and the half-tile degree mask
+    launch_cfg = {"launch_smooth_f64": f"split={raw[5]} tile={raw[8]}",
+                  "launch_smooth_f32": f"split={raw[3]} tile={raw[7]}"}
 
     def smooth_timed():
         out = {}
@@ -252,7 +267,7 @@ def run_batched(args):
         if args.copy_calibration:
             copy_calibration(torch, dev)
         print(json.dumps({"profile_sweeps": S, "mean_sweep_s": t, "algorithmic_bytes": {"f64": by64, "f32": by32},
-                          "autotuned_launch": tuning}), flush=True)
+                          "autotuned_launch": tuning, "tuning_raw": raw, "launch_config": launch_cfg}), flush=True)
         return
 
     def step():
@@ -331,9 +346,12 @@ def run_batched(args):
     copy_gbs = measured_copy_bandwidth(torch, dev, stream)
     ach = by64 / t64 / 1e9
     split = tuning["smooth_f64_split_by_degree"]
-    kern64 = ("k_dg_batch_n<double,0,N> for N = " + ",".join(str(p + 1) for p in degs) +
-              " (one launch per degree per sweep)") if split else "k_dg_batch<double,0> (one launch per sweep)"
-    srcs = ["dg_kernels_impl.hpp", "batch_kernels.hip"]
+    half = set(tuning["smooth_f64_half_tile_degrees"])
+    kern64 = ("k_dg_batch_n<double,0,N,V> for (N,V) = " +
+              ",".join(f"({p + 1},{int(p in half)})" for p in degs) +
+              " (one launch per degree per sweep; V = 1: half the cells per workgroup)") if split \
+        else "k_dg_batch<double,0> (one launch per sweep)"
+    srcs = ["dg_kernels_impl.hpp", "batch_dg_body.hpp", "batch_kernels.hip"]
     # time-to-solution roofline: bytes of one FCG iteration of every segment
     # (the captured graph iterates all segments until the last converges)
     iter_bytes = R * sum(traffic.fcg_iteration_bytes(3, n, p, 4) for n, p in probs)
@@ -361,7 +379,8 @@ def run_batched(args):
                    "problems": len(probs), "rhs": R, "total_dofs": total, "sweeps_per_step": S},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS,
-                     "traffic": counter_traffic("batched_64x4_hbm_traffic.md", srcs, "traffic_bytes_per_sweep_f64"),
+                     "traffic": counter_traffic("batched_64x4_hbm_traffic.md", srcs, "traffic_bytes_per_sweep_f64",
+                                                {"launch_smooth_f64": launch_cfg["launch_smooth_f64"]}),
                      "kernel": kern64 + " (batched fused sweep of all problems and RHS, FP64)",
                      "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64,
                      "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": ach / copy_gbs},
@@ -369,7 +388,8 @@ def run_batched(args):
         "sweep_roofline_f32": {"achieved": by32 / t32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": by32 / t32 / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by32,
                                "traffic": counter_traffic("batched_64x4_hbm_traffic.md", srcs,
-                                                          "traffic_bytes_per_sweep_f32"),
+                                                          "traffic_bytes_per_sweep_f32",
+                                                          {"launch_smooth_f32": launch_cfg["launch_smooth_f32"]}),
                                "mean_launch_s": t32},
         "time_to_1e-10_s": {"batched_mixed": t_batch, "sequential_mixed": _median(seq_mx) if ok_mx else None,
                             "sequential_fp64": seq_64 if ok_64 else None},

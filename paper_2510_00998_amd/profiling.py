@@ -9,7 +9,8 @@ autotuner (same kernels, other grids) are excluded:
 
   python -m paper_2510_00998_amd.profiling times  <kernel_trace.csv> <S> <regex>
   python -m paper_2510_00998_amd.profiling counter <counter_collection.csv> <S> <regex>
-  python -m paper_2510_00998_amd.profiling summary <trace> <fetch> <write> <S> <keys json> <sources> <title> <command>
+  python -m paper_2510_00998_amd.profiling summary <trace> <fetch> <write> <S> <keys json> <sources> <title> <command> [<extra json>]
+  python -m paper_2510_00998_amd.profiling sq <counter_collection.csv> <S> <keys json> <title> <command>
 
 `times` prints the mean duration per dispatch; `counter` the mean counter
 value per dispatch (KiB for FETCH_SIZE / WRITE_SIZE) and the copy kernel's
@@ -81,7 +82,7 @@ def dispatch_counter(path, last, pattern, counter):
     return out
 
 
-def summary(trace, fetch, write, last, keys, sources, title, command):
+def summary(trace, fetch, write, last, keys, sources, title, command, extra=None):
     """Markdown summary of one --profile-sweeps workload: per matching kernel
     the mean duration and copy-calibrated HBM bytes of its last `last`
     dispatches, and per key (a regex over kernel names) the sums over the
@@ -128,13 +129,57 @@ def summary(trace, fetch, write, last, keys, sources, title, command):
     for key, (dur, by) in tot.items():
         out.append(f"    traffic_bytes_{key}: {by:.0f}")
         out.append(f"    mean_duration_us_{key}: {dur:.3f}")
+    for k, v in json.loads(extra or "{}").items():  # launch configuration the counters belong to
+        out.append(f"    {k}: {v}")
+    print("\n".join(out))
+
+
+# SQ counters of one pass (at most 8) and the derived activity of a kernel:
+# busy = SQ_BUSY_CYCLES / 32 shader engines (cycles the kernel kept the
+# sequencers busy); VALU and LDS busy = 4 x SQ_ACTIVE_INST_* (quad-cycles)
+# / (1024 SIMDs x busy); MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x
+# busy).
+SQ_COUNTERS = ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_INSTS_VALU",
+               "SQ_INSTS_MFMA", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_LDS"]
+
+
+def sq(path, last, keys, title, command):
+    """Markdown table of the SQ_COUNTERS pass: per key (label -> regex that
+    matches one kernel name) the mean of its last `last` dispatches."""
+    import json
+    keys = json.loads(keys)
+    out = [f"# {title}", "", "Command (from /tmp with TMPDIR=/tmp, repository at $R):", ""] + \
+        ["    " + c for c in command.split(" ;; ")] + [
+        "", f"Mean over the last {last} dispatches of each kernel.  busy = SQ_BUSY_CYCLES / 32 shader engines; "
+            "VALU (LDS) busy = 4 x SQ_ACTIVE_INST_VALU (_LDS) / (1024 SIMDs x busy); MFMA busy = "
+            "SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x busy).", "",
+        "| kernel | " + " | ".join(c[3:] for c in SQ_COUNTERS) + " | busy [cycles] | VALU busy | LDS busy | MFMA busy |",
+        "|---" * (len(SQ_COUNTERS) + 5) + "|"]
+    for label, rx in keys.items():
+        vals = {}
+        for c in SQ_COUNTERS:
+            r = dispatch_counter(path, last, rx, c)
+            if len(r) != 1:
+                raise SystemExit(f"{label}: regex {rx} matches {len(r)} kernels for {c}")
+            vals[c] = list(r.values())[0][1]
+        busy = vals["SQ_BUSY_CYCLES"] / 32
+        v = 4 * vals["SQ_ACTIVE_INST_VALU"] / (1024 * busy)
+        lds = 4 * vals["SQ_ACTIVE_INST_LDS"] / (1024 * busy)
+        mf = vals["SQ_VALU_MFMA_BUSY_CYCLES"] / (1024 * busy)
+        out.append(f"| {label} | " + " | ".join(f"{vals[c]:.0f}" for c in SQ_COUNTERS) +
+                   f" | {busy:.0f} | {100 * v:.0f}% | {100 * lds:.0f}% | {100 * mf:.0f}% |")
     print("\n".join(out))
 
 
 def main(argv):
+    if argv[0] == "sq":
+        # sq <counter_collection.csv> <last> <keys json> <title> <command>
+        sq(argv[1], int(argv[2]), argv[3], argv[4], argv[5])
+        return
     if argv[0] == "summary":
-        # summary <trace.csv> <fetch.csv> <write.csv> <last> <keys json> <sources> <title> <command>
-        summary(argv[1], argv[2], argv[3], int(argv[4]), argv[5], argv[6], argv[7], argv[8])
+        # summary <trace.csv> <fetch.csv> <write.csv> <last> <keys json> <sources> <title> <command> [<extra json>]
+        summary(argv[1], argv[2], argv[3], int(argv[4]), argv[5], argv[6], argv[7], argv[8],
+                argv[9] if len(argv) > 9 else None)
         return
     mode, path, last, pattern = argv[0], argv[1], int(argv[2]), argv[3]
     if mode == "times":
