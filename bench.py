@@ -75,6 +75,25 @@ def counter_traffic(summary, sources, key, require=None):
     return float(vals[key])
 
 
+def recorded_launch(summary, sources):
+    """The batched launch configuration (hpmg_batch_tuning's 9 ints) recorded
+    with a committed counter profile, or None if the kernel sources have
+    changed since (then the autotuner's own choice is timed)."""
+    try:
+        txt = open(os.path.join(ROOT, "profiles", summary)).read()
+        sha = _sha(sources)
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if ":" in line:
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != sha or "launch_tuning_raw" not in vals:
+        return None
+    return [int(x) for x in vals["launch_tuning_raw"].split(",")]
+
+
 def measured_copy_bandwidth(torch, dev, stream, mib=1024, reps=10):
     """Read + write bytes per second of a plain device-to-device copy of
     `mib` MiB (the achievable streaming rate, beside the datasheet peak)."""
@@ -235,8 +254,18 @@ def run_batched(args):
     batch.smooth(us, bs, 0, nrhs=R)
     batch.smooth(us32, bs32, 0, nrhs=R)
     torch.cuda.synchronize()
-    if args.smooth_tuning:
-        batch.set_tuning([int(x) for x in args.smooth_tuning.split(",")])
+    autotuned = batch.tuning
+    # the timed smoothing runs the launch configuration recorded with the
+    # committed counter profile (so that roofline.traffic describes exactly
+    # the timed kernels; the autotuner's choice among near-equal
+    # configurations varies from run to run), else the autotuned one
+    srcs = ["dg_kernels_impl.hpp", "batch_dg_body.hpp", "batch_kernels.hip"]
+    forced = [int(x) for x in args.smooth_tuning.split(",")] if args.smooth_tuning else None
+    if forced is None and not args.profile_sweeps:
+        forced = recorded_launch("batched_64x4_hbm_traffic.md", srcs)
+    if forced is not None:
+        # smoothing parts only; the V-cycle tunes at its first solve
+        batch.set_tuning([0, 0] + forced[2:6] + [0] + forced[7:9])
     tuning = batch.tuning
     raw = batch.tuning_raw
     # smoothing launch configuration as recorded with the counter profile:
@@ -267,7 +296,10 @@ def run_batched(args):
         if args.copy_calibration:
             copy_calibration(torch, dev)
         print(json.dumps({"profile_sweeps": S, "mean_sweep_s": t, "algorithmic_bytes": {"f64": by64, "f32": by32},
-                          "autotuned_launch": tuning, "tuning_raw": raw, "launch_config": launch_cfg}), flush=True)
+                          "autotuned_launch": autotuned,
+        "timed_launch": tuning,
+        "timed_launch_source": ("--smooth-tuning" if args.smooth_tuning else
+                                "recorded with profiles/batched_64x4_hbm_traffic.md" if forced else "autotuned"), "tuning_raw": raw, "launch_config": launch_cfg}), flush=True)
         return
 
     def step():
@@ -351,7 +383,6 @@ def run_batched(args):
               ",".join(f"({p + 1},{int(p in half)})" for p in degs) +
               " (one launch per degree per sweep; V = 1: half the cells per workgroup)") if split \
         else "k_dg_batch<double,0> (one launch per sweep)"
-    srcs = ["dg_kernels_impl.hpp", "batch_dg_body.hpp", "batch_kernels.hip"]
     # time-to-solution roofline: bytes of one FCG iteration of every segment
     # (the captured graph iterates all segments until the last converges)
     iter_bytes = R * sum(traffic.fcg_iteration_bytes(3, n, p, 4) for n, p in probs)
@@ -398,7 +429,10 @@ def run_batched(args):
                               "sequential_fp64": its_seq_64},
         "solves_converged": {"batched_mixed": ok_batch, "sequential_mixed": ok_mx, "sequential_fp64": ok_64},
         "batched_worst_true_rel_residual": worst,
-        "autotuned_launch": tuning,
+        "autotuned_launch": autotuned,
+        "timed_launch": tuning,
+        "timed_launch_source": ("--smooth-tuning" if args.smooth_tuning else
+                                "recorded with profiles/batched_64x4_hbm_traffic.md" if forced else "autotuned"),
         "setup_s": t_setup,
     }
     if base is not None:
@@ -682,6 +716,8 @@ def run_single(args):
     }
     if vark:
         trc = {name: _median([r["swrc_" + name] for r in res]) for name in rc_in}
+        rsum = {3: "variable_kappa_q3_64cube_recompute_hbm_traffic.md", 5: "sweep_q5_96cube_recompute_hbm_traffic.md"}[
+            args.config]
         byrc = {name: traffic.sweep_bytes(dim, n, p, isz[name], per_cell_kappa=True, block_recompute=True)
                 for name in rc_in}
         line["block_recompute"] = {
@@ -689,12 +725,16 @@ def run_single(args):
             "sweep_dofs_per_s": {name: nd / t for name, t in trc.items()},
             "sweep_mean_launch_s": trc,
             "sweep_roofline_frac": {name: byrc[name] / trc[name] / 1e9 / HBM_PEAK_GBS for name in rc_in},
-            "algorithmic_bytes_per_launch": byrc}
+            "algorithmic_bytes_per_launch": byrc,
+            "traffic": {name: counter_traffic(rsum, srcs, f"traffic_bytes_per_launch_{name}_recompute")
+                        for name in rc_in}}
         tsp = {name: _median([r["swsp_" + name] for r in res]) for name in sp_in}
         line["split_and_postpone"] = {
             "sweep_dofs_per_s": {name: nd / t for name, t in tsp.items()},
             "sweep_mean_s": tsp,
             "sweep_roofline_frac_stored_bytes": {name: bysw[name] / tsp[name] / 1e9 / HBM_PEAK_GBS for name in sp_in},
+            "traffic_sweep_and_rebuild": {name: counter_traffic(rsum, srcs, f"traffic_bytes_per_launch_{name}_split")
+                                          for name in sp_in},
             "note": "mean time per sweep while the next traversal's records are rebuilt on a second stream"}
     print(json.dumps(line), flush=True)
 

@@ -40,9 +40,10 @@ def _rows(path):
         return header, list(r)
 
 
-def dispatch_times(path, last, pattern):
+def dispatch_times(path, last, pattern, skip=0):
     """{kernel name: (dispatches kept, mean duration in us)} over the last
-    `last` dispatches of every kernel whose name matches `pattern`."""
+    `last` dispatches (before the final `skip` ones) of every kernel whose
+    name matches `pattern`."""
     header, rows = _rows(path)
     kn = _col(header, "Kernel_Name")
     t0 = _col(header, "Start_Timestamp")
@@ -56,14 +57,16 @@ def dispatch_times(path, last, pattern):
     out = {}
     for k, v in per.items():
         v.sort()
-        kept = [d for _, d in v[-last:]]
-        out[k] = (len(kept), statistics.fmean(kept))
+        kept = [d for _, d in v[len(v) - last - skip:len(v) - skip]]
+        if kept:
+            out[k] = (len(kept), statistics.fmean(kept))
     return out
 
 
-def dispatch_counter(path, last, pattern, counter):
+def dispatch_counter(path, last, pattern, counter, skip=0):
     """{kernel name: (dispatches kept, mean value)} of `counter` over the last
-    `last` dispatches of every matching kernel."""
+    `last` dispatches (before the final `skip` ones) of every matching
+    kernel."""
     header, rows = _rows(path)
     kn = _col(header, "Kernel_Name")
     di = _col(header, "Dispatch_Id", "Correlation_Id")
@@ -77,25 +80,25 @@ def dispatch_counter(path, last, pattern, counter):
             per[row[kn]][d] = per[row[kn]].get(d, 0.0) + float(row[cv])  # summed over dimensions
     out = {}
     for k, v in per.items():
-        kept = [v[d] for d in sorted(v)[-last:]]
-        out[k] = (len(kept), statistics.fmean(kept))
+        ids = sorted(v)
+        kept = [v[d] for d in ids[len(ids) - last - skip:len(ids) - skip]]
+        if kept:
+            out[k] = (len(kept), statistics.fmean(kept))
     return out
 
 
 def summary(trace, fetch, write, last, keys, sources, title, command, extra=None):
-    """Markdown summary of one --profile-sweeps workload: per matching kernel
-    the mean duration and copy-calibrated HBM bytes of its last `last`
-    dispatches, and per key (a regex over kernel names) the sums over the
-    matching kernels; the copy calibration divides the known 256 MiB of the
-    last three copy dispatches by their counter readings."""
+    """Markdown summary of one --profile-sweeps workload: per key (a regex
+    over kernel names, or [regex, skip] to leave out the final `skip`
+    dispatches of the matching kernels, e.g. a second timed series of the
+    same kernel) the mean duration and copy-calibrated HBM bytes of the last
+    `last` dispatches of every matching kernel, and their sums; the copy
+    calibration divides the known 256 MiB of the last three copy dispatches
+    by their counter readings."""
     import hashlib
     import json
     import os
     keys = json.loads(keys)
-    pat = "|".join(f"(?:{r})" for r in keys.values())
-    t = dispatch_times(trace, last, pat)
-    f = dispatch_counter(fetch, last, pat, "FETCH_SIZE")
-    w = dispatch_counter(write, last, pat, "WRITE_SIZE")
     cf = dispatch_counter(fetch, 3, r"copyBuffer", "FETCH_SIZE")
     cw = dispatch_counter(write, 3, r"copyBuffer", "WRITE_SIZE")
     kf = 262144.0 / list(cf.values())[0][1]
@@ -106,21 +109,27 @@ def summary(trace, fetch, write, last, keys, sources, title, command, extra=None
         h.update(open(os.path.join(csrc, src), "rb").read())
     out = [f"# {title}", "", "Commands (from /tmp with TMPDIR=/tmp, repository at $R; each counter in a run of its own):",
            ""] + ["    " + c for c in command.split(" ;; ")] + [
-        "", f"Only the last {last} dispatches of each kernel are kept (the timed sweeps; autotuner launches of the same "
-            "kernels come earlier).  Copy calibration: a 256 MiB device copy reads FETCH_SIZE = "
+        "", f"Per key, the last {last} dispatches of each matching kernel are kept (the timed sweeps; autotuner and "
+            "setup launches of the same kernels come earlier; where a key skips dispatches, a later timed series of "
+            "the same kernel is left out).  Copy calibration: a 256 MiB device copy reads FETCH_SIZE = "
             f"{list(cf.values())[0][1]:.1f} KiB and WRITE_SIZE = {list(cw.values())[0][1]:.1f} KiB per dispatch, so "
             f"FETCH_SIZE is scaled by {kf:.4f} and WRITE_SIZE by {kw:.4f} to give bytes.", "",
-        "| kernel | dispatches | mean duration [us] | read [MB] | write [MB] | total [MB] |", "|---|---|---|---|---|---|"]
+        "| key | kernel | dispatches | mean duration [us] | read [MB] | write [MB] | total [MB] |",
+        "|---|---|---|---|---|---|---|"]
     tot = {}
-    for k in sorted(t):
-        rd = f[k][1] * 1024 * kf if k in f else float("nan")
-        wr = w[k][1] * 1024 * kw if k in w else float("nan")
-        out.append(f"| `{k[:100]}` | {t[k][0]} | {t[k][1]:.2f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | {(rd + wr) / 1e6:.2f} |")
-        for key, rx in keys.items():
-            if re.search(rx, k):
-                a = tot.setdefault(key, [0.0, 0.0])
-                a[0] += t[k][1]
-                a[1] += rd + wr
+    for key, spec in keys.items():
+        rx, skip = (spec, 0) if isinstance(spec, str) else (spec[0], int(spec[1]))
+        t = dispatch_times(trace, last, rx, skip)
+        f = dispatch_counter(fetch, last, rx, "FETCH_SIZE", skip)
+        w = dispatch_counter(write, last, rx, "WRITE_SIZE", skip)
+        a = tot.setdefault(key, [0.0, 0.0])
+        for k in sorted(t):
+            rd = f[k][1] * 1024 * kf if k in f else float("nan")
+            wr = w[k][1] * 1024 * kw if k in w else float("nan")
+            out.append(f"| {key} | `{k[:90]}` | {t[k][0]} | {t[k][1]:.2f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | "
+                       f"{(rd + wr) / 1e6:.2f} |")
+            a[0] += t[k][1]
+            a[1] += rd + wr
     out += ["", "| key | summed mean duration [us] | summed bytes per launch |", "|---|---|---|"]
     for key, (dur, by) in tot.items():
         out.append(f"| {key} | {dur:.2f} | {by:.0f} |")
