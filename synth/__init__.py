@@ -114,3 +114,116 @@ def batched_problem_list(count: int = 64, seed: int = 1004, nmin: int = 8, nmax:
 def batched_rhs_seed(base: int, problem: int, rhs: int) -> int:
     """Stream id of right-hand side `rhs` of problem `problem`."""
     return base * (1 << 32) + 4 * problem + rhs
+
+
+# ---------------------------------------------------------------- spacetrees
+# Leaf lists of hierarchical Cartesian meshes: n^dim base cells (level 0),
+# a cell at level l split into r^dim children of width 1/(n r^(l+1)).  A
+# leaf is (level, x_0, .., x_{dim-1}) with integer coordinates at its level.
+# Mesh generation only: which cells are refined, then the facet balance
+# (facet neighbours at most one level apart), then the depth-first order
+# (base cells x fastest, children x fastest within their parent).
+
+def _children(node, dim, r):
+    lvl, x = node
+    out = []
+    for m in range(r ** dim):
+        off = [(m // r ** k) % r for k in range(dim)]
+        out.append((lvl + 1, tuple(r * x[k] + off[k] for k in range(dim))))
+    return out
+
+
+def _leaves_of(dim, n, r, refined):
+    """Depth-first leaf list of the tree whose refined nodes are `refined`."""
+    leaves = []
+
+    def visit(node):
+        if node in refined:
+            for ch in _children(node, dim, r):
+                visit(ch)
+        else:
+            leaves.append((node[0],) + node[1])
+
+    for b in range(n ** dim):
+        visit((0, tuple((b // n ** k) % n for k in range(dim))))
+    return np.array(leaves, dtype=np.int64).reshape(-1, 1 + dim)
+
+
+def _balance(dim, n, r, refined):
+    """Refine leaves until every facet neighbour of a leaf at level l is a
+    leaf at level l-1, l or l+1."""
+    refined = set(refined)
+    while True:
+        leaves = _leaves_of(dim, n, r, refined)
+        add = []
+        for row in leaves:
+            lvl, x = int(row[0]), tuple(int(v) for v in row[1:])
+            ext = n * r ** lvl
+            for k in range(dim):
+                for s in (-1, 1):
+                    y = list(x)
+                    y[k] += s
+                    if not 0 <= y[k] < ext:
+                        continue
+                    nb = (lvl, tuple(y))
+                    if nb not in refined:
+                        continue
+                    # children of the neighbour that touch the shared facet
+                    for ch in _children(nb, dim, r):
+                        if ch[1][k] == (r * y[k] + (0 if s > 0 else r - 1)) and ch in refined:
+                            add.append((lvl, x))
+                            break
+        add = set(add) - refined
+        if not add:
+            return leaves
+        refined |= add
+
+
+def spacetree_leaves(dim: int, n: int, r: int, refine, max_level: int) -> np.ndarray:
+    """Leaves of the balanced spacetree in which a node (level l, coordinates
+    x) with l < max_level is refined when refine(l, lower corner, width) is
+    true; shape (nleaf, 1 + dim), rows (level, x_0, ..)."""
+    refined = set()
+    frontier = [(0, tuple((b // n ** k) % n for k in range(dim))) for b in range(n ** dim)]
+    while frontier:
+        nxt = []
+        for node in frontier:
+            lvl, x = node
+            h = 1.0 / (n * r ** lvl)
+            if lvl < max_level and refine(lvl, np.array(x, dtype=np.float64) * h, h):
+                refined.add(node)
+                nxt.extend(_children(node, dim, r))
+        frontier = nxt
+    return _balance(dim, n, r, refined)
+
+
+def ball_refinement(centres, radii):
+    """Refinement test: refine the cells that meet one of the balls."""
+    centres = [np.asarray(c, dtype=np.float64) for c in centres]
+
+    def refine(lvl, lo, h):
+        for c, rad in zip(centres, radii):
+            nearest = np.clip(c[: len(lo)], lo, lo + h)
+            if np.sum((nearest - c[: len(lo)]) ** 2) <= rad * rad:
+                return True
+        return False
+
+    return refine
+
+
+def random_refinement(seed: int, frac: float):
+    """Refinement test: refine a cell with probability frac (one uniform per
+    cell, drawn from stream seed at an index hashed from level and corner)."""
+    def refine(lvl, lo, h):
+        key = int(lvl) * 1000003 + int(round(lo[0] / h)) * 7919 + int(round(lo[1] / h)) * 104729
+        if len(lo) > 2:
+            key += int(round(lo[2] / h)) * 1299709
+        return float(uniform(seed * (1 << 20) + key, 1)[0]) < frac
+
+    return refine
+
+
+def leaf_centres(dim: int, n: int, r: int, leaves: np.ndarray) -> np.ndarray:
+    """Centres of the leaves (nleaf, dim)."""
+    h = 1.0 / (n * np.power(float(r), leaves[:, 0]))
+    return (leaves[:, 1:1 + dim] + 0.5) * h[:, None]
