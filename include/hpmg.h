@@ -132,7 +132,47 @@ void hpmg_default_options(hpmg_options* opt);
 hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff,
                        const hpmg_options* opt, hipStream_t stream, hpmg_handle* out);
 
-/* Number of DG degrees of freedom n^dim (p+1)^dim of one right-hand side. */
+/* Adaptive mesh: the leaves of a spacetree over the unit box (Section 2.1,
+ * hierarchical Cartesian meshes).  The n^dim base cells (width 1/n) form
+ * level 0; a refined cell of level l splits every axis into `refine` parts
+ * (2, or 3 as the paper's spacetree), giving r^dim cells of level l + 1 and
+ * width 1/(n r^(l+1)).  leaves: HOST array of nleaf rows (level, x_0, ..,
+ * x_{dim-1}), integer coordinates at the leaf's level (0 <= x_k < n r^l),
+ * copied during setup; the row order is the cell order of every vector.
+ * The leaves must cover the box without overlap, and leaves that share a
+ * facet must be at most one level apart (facet balance), so that a facet
+ * is conforming or the coarse facet of a "hanging" facet covered by
+ * r^(dim-1) finer leaves.  level <= 12, n r^level <= 2^20. */
+typedef struct {
+  int dim;
+  int n;              /* base cells per axis, >= 2 */
+  int refine;         /* subdivision factor r: 2 or 3 */
+  int nleaf;
+  const int* leaves;  /* [nleaf][1 + dim] */
+} hpmg_adaptive_mesh;
+
+/* hpmg_setup on an adaptive mesh: the SIPG operator of eq. weak_form_IP on
+ * the leaves, with the penalty of a piece of the skeleton taken from the
+ * finer of its two cells (sigma0 (p+1)^2 / min(h-, h+); 2 sigma0 (p+1)^2 /
+ * h_K on the boundary).  The cell kernels read the neighbour-side traces of
+ * each facet through a slot table; after every traversal that writes
+ * traces, a remap kernel turns the traces at hanging facets into each
+ * side's view (the coarse facet polynomial restricted to each fine facet;
+ * the L2 projection of the fine traces onto the coarse facet), so that the
+ * fused sweep stays one traversal per step.  Multigrid: the DG levels of
+ * lower degree on the same leaves, then continuous Q1 on the base mesh
+ * (the coarsest spacetree level; transfer by evaluating its trilinear
+ * functions at the leaves' nodes), then the h-levels of the base mesh.
+ * Constant kappa only (coeff->per_cell = 0), Gauss-Lobatto or Gauss-Legendre
+ * nodes, exact blocks (block_variant 0, block_recompute 0, mfma 0), FP64
+ * or FP32 vectors and cycles (F16 / BF16: HPMG_E_UNSUPPORTED); every other
+ * entry point works on the handle (not hpmg_batch_create).  HPMG_E_INVALID
+ * for a mesh that breaks the rules above. */
+hpmg_status hpmg_setup_adaptive(const hpmg_adaptive_mesh* mesh, int p, const hpmg_coeff* coeff,
+                                const hpmg_options* opt, hipStream_t stream, hpmg_handle* out);
+
+/* Number of DG degrees of freedom n^dim (p+1)^dim (adaptive meshes: nleaf
+ * (p+1)^dim) of one right-hand side. */
 size_t hpmg_ndof(hpmg_handle h);
 
 /* Load vector b_i = int f phi_i ((p+3)-point Gauss per direction) for a

@@ -307,12 +307,12 @@ class AdaptiveHierarchy(Hierarchy):
     """hp-multigrid DG_p -> DG_{p/2} -> ... (on the leaves) -> Q1 (base mesh)
     -> Q1 (base mesh / 2) ...; V-cycle, smoothers and solvers of Hierarchy."""
 
-    def __init__(self, dim, n, r, leaves, p, opts: HierarchyOptions | None = None):
+    def __init__(self, dim, n, r, leaves, p, opts: HierarchyOptions | None = None, kappa=None):
         self.opts = opts or HierarchyOptions()
         if self.opts.block != "exact":
             raise ValueError("adaptive meshes take the exact cell block")
         self.dim = dim
-        fine = AdaptiveSIPG(dim, n, r, leaves, p, sigma0=self.opts.sigma0, basis=self.opts.basis)
+        fine = AdaptiveSIPG(dim, n, r, leaves, p, kappa, sigma0=self.opts.sigma0, basis=self.opts.basis)
         self.fine = fine
         self.levels, self.P = [], []
         A = fine.A.tocsr()
@@ -322,7 +322,7 @@ class AdaptiveHierarchy(Hierarchy):
             self.levels.append(Level("dg", A, n, q, extract_diagonal_blocks(A, (q + 1) ** dim)))
             if li + 1 < len(degs):
                 P = cur.dg_prolongation(degs[li + 1])
-                cur = AdaptiveSIPG(dim, n, r, leaves, degs[li + 1], p_penalty=p, sigma0=self.opts.sigma0,
+                cur = AdaptiveSIPG(dim, n, r, leaves, degs[li + 1], kappa, p_penalty=p, sigma0=self.opts.sigma0,
                                    basis=self.opts.basis)
             else:
                 P = cur.base_q1_prolongation()

@@ -43,6 +43,11 @@ class Mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3)]
 
 
+class AdaptiveMesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("refine", ctypes.c_int), ("nleaf", ctypes.c_int),
+                ("leaves", ctypes.POINTER(ctypes.c_int))]
+
+
 class Coeff(ctypes.Structure):
     _fields_ = [("per_cell", ctypes.c_int), ("kappa_const", ctypes.c_double),
                 ("kappa", ctypes.POINTER(ctypes.c_double))]
@@ -74,6 +79,9 @@ _lib.hpmg_default_options.restype = None
 _lib.hpmg_setup.argtypes = [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.POINTER(Coeff), ctypes.POINTER(Options),
                             _vp, ctypes.POINTER(_vp)]
 _lib.hpmg_setup.restype = ctypes.c_int
+_lib.hpmg_setup_adaptive.argtypes = [ctypes.POINTER(AdaptiveMesh), ctypes.c_int, ctypes.POINTER(Coeff),
+                                     ctypes.POINTER(Options), _vp, ctypes.POINTER(_vp)]
+_lib.hpmg_setup_adaptive.restype = ctypes.c_int
 _lib.hpmg_ndof.argtypes = [_vp]
 _lib.hpmg_ndof.restype = ctypes.c_size_t
 _lib.hpmg_load_vector.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _vp]
@@ -176,13 +184,17 @@ def _code(t):
 
 
 class Solver:
-    """One SIPG problem -div(kappa grad u) = f on [0,1]^dim (hpmg_setup)."""
+    """One SIPG problem -div(kappa grad u) = f on [0,1]^dim (hpmg_setup, or
+    hpmg_setup_adaptive when `leaves` is given)."""
 
-    def __init__(self, dim: int, n: int, p: int, kappa=1.0, stream=None, allocator=None, **options):
+    def __init__(self, dim: int, n: int, p: int, kappa=1.0, stream=None, allocator=None, leaves=None,
+                 refine: int = 2, **options):
         """options: fields of hpmg_options (p_schedule as a sequence of degrees);
         allocator: optional (alloc(nbytes) -> device pointer int, free(pointer))
         pair through which the library obtains every device buffer of the
-        handle (e.g. torch's caching allocator); kept alive with the solver."""
+        handle (e.g. torch's caching allocator); kept alive with the solver;
+        leaves: (nleaf, 1 + dim) integer rows (level, coordinates) of an
+        adaptive mesh over n^dim base cells with subdivision factor refine."""
         opt = default_options()
         for k, v in options.items():
             if not hasattr(opt, k) or k in ("alloc", "free", "alloc_ctx"):
@@ -220,8 +232,18 @@ class Solver:
             self._kappa_buf = arr
             coeff = Coeff(1, 0.0, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         h = ctypes.c_void_p()
-        _check(_lib.hpmg_setup(ctypes.byref(mesh), p, ctypes.byref(coeff), ctypes.byref(opt), _stream(stream),
-                               ctypes.byref(h)), "hpmg_setup")
+        self.leaves = None
+        if leaves is not None:
+            lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32))
+            if lv.ndim != 2 or lv.shape[1] != 1 + dim:
+                raise ValueError("leaves must have shape (nleaf, 1 + dim)")
+            self.leaves = lv
+            am = AdaptiveMesh(dim, n, refine, lv.shape[0], lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+            _check(_lib.hpmg_setup_adaptive(ctypes.byref(am), p, ctypes.byref(coeff), ctypes.byref(opt),
+                                            _stream(stream), ctypes.byref(h)), "hpmg_setup_adaptive")
+        else:
+            _check(_lib.hpmg_setup(ctypes.byref(mesh), p, ctypes.byref(coeff), ctypes.byref(opt), _stream(stream),
+                                   ctypes.byref(h)), "hpmg_setup")
         self._h = h
         self.dim, self.n, self.p, self.options = dim, n, p, opt
         self.ndof = int(_lib.hpmg_ndof(h))

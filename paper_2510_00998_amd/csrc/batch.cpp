@@ -766,6 +766,7 @@ hpmg_status hpmg_batch_create(const hpmg_handle* hs, int count, hpmg_batch* out)
       for (int k = 0; k < j; ++k) require(hs[k] != h, "a handle appears twice in the batch");
       require(h->dim == 3, "batched solver supports dim = 3");
       require(!h->vark, "batched solver supports constant kappa");
+      require(!h->adapt, "batched solver supports uniform meshes");
       require(h->p + 1 >= hpmg::BATCH_NMIN && h->p + 1 <= hpmg::BATCH_NMAX, "batched solver supports 1 <= p <= 5");
       require(h->opt.nu_pre >= 1, "batched solver needs nu_pre >= 1");
       require(h->opt.p_coarsening == 0 && h->opt.p_schedule[0] == 0 && h->opt.h_factor == 2 &&

@@ -26,6 +26,7 @@ SOURCES = [
     "batch_tile1.hip",
     "batch.cpp",
     "noalloc.hip",
+    "adapt_kernels.hip",
     "dg_inst_2d_float.hip",
     "dg_inst_2d_double.hip",
     "dg_inst_2d_f16.hip",

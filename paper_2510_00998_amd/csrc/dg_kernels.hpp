@@ -113,11 +113,11 @@ struct DGArgs {
   const T* u_in;       // cell vector
   T* u_out;            // cell vector (may alias u_in)
   const T* b;          // cell vector
-  const T* tr_in;      // traces [2D][ncell][2][L]
+  const T* tr_in;      // traces [2D][ncell][2][L] (adaptive meshes: then the hanging-facet slots)
   T* tr_out;
   C* out;              // apply: y; resid: r (NC=0) or coarse right-hand side (next level, compute type)
   const C* coarse;     // prolong: coarse cell vector (DG) or Q1 interior vertex vector (CG)
-  int coarse_cg;       // prolong/restrict partner is Q1 (vertex gather) rather than DG
+  int coarse_cg;       // prolong partner: 0 DG, 1 Q1 (vertex gather), 2 Q1 corner values per cell [c][2^d]
   long long vstride;   // per right-hand side stride of cell vectors
   long long tstride;   // per right-hand side stride of trace buffers
   long long cstride;   // per right-hand side stride of coarse vectors
@@ -143,6 +143,22 @@ struct DGArgs {
   // block solve on the matrix cores (16-bit operands, FP32 accumulation);
   // 0 keeps them on the vector units in FP32
   int mfma = 0;
+  // Adaptive (spacetree) meshes with constant kappa (Section 2.1; the
+  // kernels' AD instances): amask[c] holds bit f if facet f of cell c lies
+  // on the boundary and bit 8 + f if facet f is the coarse side of a
+  // hanging facet (r^(d-1) finer neighbours, penalty sig_hang = r
+  // sigma_hat); nbslot[f ncell + c] is the trace slot (unit 2L values)
+  // that holds the neighbour-side traces of facet f in the neighbour's
+  // reference units: the neighbour's own slot (f^1) ncell + c' across a
+  // conforming facet, else a slot filled by the hanging-facet remap;
+  // hscale[c] = (h_base / h_c)^(d-2) (nullptr: 1); mort = the remap
+  // tables of the level (host side only).
+  int adapt = 0;
+  C sig_hang = 0;
+  const unsigned short* amask = nullptr;
+  const int* nbslot = nullptr;
+  const C* hscale = nullptr;
+  const C* mort = nullptr;
   int* flag = nullptr;  // eigendata build: set to 1 if a block eigenvalue is not positive and finite
   const void* zlow = nullptr;
   const double* kscal = nullptr;

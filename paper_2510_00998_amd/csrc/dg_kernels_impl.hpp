@@ -173,11 +173,34 @@ __device__ __forceinline__ int work_tid() {
 // boundary); the class of the cell along axis k is (mask >> 2k) & 3.
 __device__ __forceinline__ int axis_class(int mask, int k) { return (mask >> (2 * k)) & 3; }
 
-// LDS size of the staged eigendata: constant kappa shares the 4 class
-// tables, variable kappa stages one set per cell and axis.
-template <int D, int N, bool VARK>
+// Adaptive meshes (AD): the mask also holds bit 8 + f for a facet f that is
+// the coarse side of a hanging facet (its penalty is r times the conforming
+// one), and the class of axis k adds those two bits: 16 class tables.
+template <bool AD>
+__device__ __forceinline__ int axis_cls(int mask, int k) {
+  if constexpr (AD)
+    return ((mask >> (2 * k)) & 3) | (((mask >> (8 + 2 * k)) & 3) << 2);
+  else
+    return (mask >> (2 * k)) & 3;
+}
+template <bool AD>
+constexpr int n_classes() {
+  return AD ? 16 : 4;
+}
+template <bool AD, typename T>
+__device__ __forceinline__ int cell_mask(const DGArgs<T>& a, int c) {
+  if constexpr (AD)
+    return a.amask[c];
+  else
+    return a.bmask[c];
+}
+
+// LDS size of the staged eigendata: constant kappa shares the 4 (adaptive:
+// 16) class tables, variable kappa stages one set per cell and axis.
+template <int D, int N, bool VARK, bool AD = false>
 struct EigLDS {
-  static constexpr int SIZE = VARK ? DGShape<D, N>::CPB * D * DGShape<D, N>::EGS : 4 * DGShape<D, N>::EGS;
+  static constexpr int SIZE =
+      VARK ? DGShape<D, N>::CPB * D * DGShape<D, N>::EGS : n_classes<AD>() * DGShape<D, N>::EGS;
 };
 
 // LDS after the staged eigendata: kappa_F per (cell, facet) (variable
@@ -199,14 +222,14 @@ __device__ __forceinline__ const int* mask_lds(const C* sKF) {
 
 // Stage the eigendata (and, per cell, kappa_F of every facet; 0 on the
 // boundary) of the block's cells.
-template <typename T, int D, int N, bool VARK>
+template <typename T, int D, int N, bool VARK, bool AD = false>
 __device__ __forceinline__ void load_eig(const DGArgs<T>& a, int c0, int nc, CT<T>* sE, CT<T>* sKF) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int NN = N * N;
   const int tid = work_tid<D, N>();
   if constexpr (!VARK) {
-    for (int i = tid; i < 4 * Sh::EGS; i += Sh::NT) sE[i] = a.eig[i];
+    for (int i = tid; i < n_classes<AD>() * Sh::EGS; i += Sh::NT) sE[i] = a.eig[i];
   } else {
     // every load of the thread is issued before the first LDS store (no
     // load waits on another): eigendata, then kappa of the cell and of its
@@ -532,7 +555,7 @@ __device__ __forceinline__ void make_si(const DGArgs<T>& a, int nc, CT<T>* sE) {
 // lane of the wave needs the same boundary class the record is read from
 // the global class table with scalar loads; otherwise from the LDS copy
 // (LDS = true, after the block staged it) or per lane from global memory.
-template <typename T, int D, int N, bool VARK, bool TR, bool SIM, bool LDS = true>
+template <typename T, int D, int N, bool VARK, bool TR, bool SIM, bool LDS = true, bool AD = false>
 __device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const CT<T>* sE, int cl, int mask, int k,
                                          const CT<T> (&in)[N], CT<T> (&out)[N]) {
   using C = CT<T>;
@@ -543,7 +566,7 @@ __device__ __forceinline__ void stage_mv(const DGArgs<T>& a, const CT<T>* sE, in
   if constexpr (VARK) {
     mv<N, TR>(sE + (cl * D + k) * Sh::EGS + off, in, out);
   } else {
-    const int cls = axis_class(mask, k);
+    const int cls = axis_cls<AD>(mask, k);
     bool uni = false;
     int c0 = cls;
     if constexpr (SCALAR_OK) {
@@ -585,7 +608,7 @@ __device__ __forceinline__ int tangential(int k, int pass) {
 // copy) and transforms along t1; pass 1 transforms along t2 (3D).  Work items are
 // ordered (facet, cell, line) so that a wave mostly sees one facet
 // direction and therefore one matrix.
-template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL = false, bool IVAR = false>
+template <typename T, int D, int N, bool VARK, bool FROM_GLOBAL = false, bool IVAR = false, bool AD = false>
 __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int c0, int nc, int pass, CT<T>* sNB,
                                            const CT<T>* sE, const CT<T>* sKF) {
   using C = CT<T>;
@@ -666,8 +689,8 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
       }
     }
     if (t < k) {
-      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, smask, t, x1, o1);
-      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL>(a, sE, cl, smask, t, x2, o2);
+      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL, AD>(a, sE, cl, smask, t, x1, o1);
+      stage_mv<T, D, N, VARK, false, true, !FROM_GLOBAL, AD>(a, sE, cl, smask, t, x2, o2);
     } else {
       mv<N, false>(Mh, x1, o1);
       mv<N, false>(Mh, x2, o2);
@@ -684,8 +707,11 @@ __device__ __forceinline__ void facet_pass(const DGArgs<T>& a, const T* tr, int 
 // before the first use of any of them: the class tables, the boundary masks
 // of its items' cells and the neighbour traces (neighbour index clamped into
 // the mesh, boundary facets zeroed by a select afterwards), so that the
-// block waits for memory once.  Stages the class tables in sE.
-template <typename T, int D, int N>
+// block waits for memory once.  Stages the class tables in sE.  AD
+// (adaptive meshes): the neighbour-side traces of (cell, facet) come from
+// slot nbslot[f ncell + c], and the coarse side of a hanging facet takes
+// the penalty sig_hang.
+template <typename T, int D, int N, bool AD = false>
 __device__ __forceinline__ void facet_pass0_const(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB,
                                                   CT<T>* sE, int* sMask) {
   using C = CT<T>;
@@ -696,7 +722,7 @@ __device__ __forceinline__ void facet_pass0_const(const DGArgs<T>& a, const T* t
   constexpr int LINES = (D == 2) ? 1 : N;
   constexpr int ITEMS = Sh::CPB * Sh::NF * LINES;
   constexpr int IT = (ITEMS + Sh::NT - 1) / Sh::NT;
-  constexpr int NE = 4 * Sh::EGS;
+  constexpr int NE = n_classes<AD>() * Sh::EGS;
   constexpr int IE = (NE + Sh::NT - 1) / Sh::NT;
   const int tid = work_tid<D, N>();
   const cptr<C> Mh = as_const(a.ref) + RefOff<N>::M;
@@ -717,17 +743,23 @@ __device__ __forceinline__ void facet_pass0_const(const DGArgs<T>& a, const T* t
     const int cl = rem / LINES, li = rem % LINES;
     const bool valid = i < ITEMS && cl < nc;
     const int c = c0 + (valid ? cl : 0);
-    const int stc = ipow<D>(a.n, f >> 1);
-    const int nb = min(max((f & 1) ? c + stc : c - stc, 0), a.ncell - 1);
-    const T* src = valid ? tr + ((size_t)(f ^ 1) * a.ncell + nb) * TL + N * li : tr;
+    size_t slot;
+    if constexpr (AD) {
+      slot = (size_t)a.nbslot[(size_t)f * a.ncell + c];
+    } else {
+      const int stc = ipow<D>(a.n, f >> 1);
+      const int nb = min(max((f & 1) ? c + stc : c - stc, 0), a.ncell - 1);
+      slot = (size_t)(f ^ 1) * a.ncell + nb;
+    }
+    const T* src = valid ? tr + slot * TL + N * li : tr;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       gv[m][j] = src[j];
       qv[m][j] = src[L + j];
     }
-    msk[m] = a.bmask[c];
+    msk[m] = cell_mask<AD>(a, c);
   }
-  const int cmask = a.bmask[c0 + min(tid, nc - 1)];
+  const int cmask = cell_mask<AD>(a, c0 + min(tid, nc - 1));
   // keep every use of the loaded values below this point, so that the
   // compiler does not wait for one item's data before issuing the next loads
   __builtin_amdgcn_sched_barrier(0);
@@ -747,17 +779,19 @@ __device__ __forceinline__ void facet_pass0_const(const DGArgs<T>& a, const T* t
     const int t = tangential<D>(k, 0);
     const bool bdy = (msk[m] >> f) & 1;
     const C kf = a.kappa_const;
+    C sh = a.sigma_hat;
+    if constexpr (AD) sh = ((msk[m] >> (8 + f)) & 1) ? a.sig_hang : a.sigma_hat;
     C x1[N], x2[N], o1[N], o2[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const C g = bdy ? C(0) : gv[m][j];
       const C q = bdy ? C(0) : qv[m][j];
-      x1[j] = kf * (C(0.5) * q - a.sigma_hat * g);
+      x1[j] = kf * (C(0.5) * q - sh * g);
       x2[j] = C(0.5) * kf * g;
     }
     if (t < k) {
-      stage_mv<T, D, N, false, false, true, false>(a, sE, cl, msk[m], t, x1, o1);
-      stage_mv<T, D, N, false, false, true, false>(a, sE, cl, msk[m], t, x2, o2);
+      stage_mv<T, D, N, false, false, true, false, AD>(a, sE, cl, msk[m], t, x1, o1);
+      stage_mv<T, D, N, false, false, true, false, AD>(a, sE, cl, msk[m], t, x2, o2);
     } else {
       mv<N, false>(Mh, x1, o1);
       mv<N, false>(Mh, x2, o2);
@@ -808,8 +842,9 @@ __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const 
 
 // All facet flux fields of the block in sNB, the eigendata in sE and the
 // boundary masks of the block's cells in LDS; ends with a barrier.
-template <typename T, int D, int N, bool VARK, bool AT_ONCE = true, bool IVAR = false>
+template <typename T, int D, int N, bool VARK, bool AT_ONCE = true, bool IVAR = false, bool AD = false>
 __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB, CT<T>* sE, CT<T>* sKF) {
+  static_assert(!AD || (!VARK && AT_ONCE && !IVAR), "adaptive meshes: constant kappa, exact blocks, loads at once");
   int* sMask = mask_lds<D, N, VARK>(sKF);
   const int tid = work_tid<D, N>();
   if constexpr (!VARK && AT_ONCE) {
@@ -818,7 +853,7 @@ __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int
       load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
       if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
     } else {
-      facet_pass0_const<T, D, N>(a, tr, c0, nc, sNB, sE, sMask);
+      facet_pass0_const<T, D, N, AD>(a, tr, c0, nc, sNB, sE, sMask);
     }
     __syncthreads();
   } else if constexpr (!VARK) {
@@ -841,7 +876,7 @@ __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int
     __syncthreads();
   }
   if constexpr (D == 3) {
-    facet_pass<T, D, N, VARK, false, IVAR>(a, tr, c0, nc, 1, sNB, sE, sKF);
+    facet_pass<T, D, N, VARK, false, IVAR, AD>(a, tr, c0, nc, 1, sNB, sE, sKF);
     __syncthreads();
   }
 }
@@ -957,16 +992,18 @@ __device__ __forceinline__ void block_partial(double v, double* sh, double* out)
 // neighbour traces are not read.  The x-line of u and b of each thread
 // stay in registers from the load to the update.
 // LDS bytes of the sweep / apply bodies.
-template <typename T, int D, int N, bool VARK>
+template <typename T, int D, int N, bool VARK, bool AD = false>
 constexpr int cell_lds_bytes() {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
-  return (int)sizeof(C) *
-         (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK>::SIZE + kappa_lds_entries<D, N, VARK>()) +
+  return (int)sizeof(C) * (Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L + EigLDS<D, N, VARK, AD>::SIZE +
+                           kappa_lds_entries<D, N, VARK>()) +
          (int)sizeof(int) * Sh::CPB;
 }
 
-template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR = false>
+// AD: adaptive mesh (neighbour traces by slot table, 16 class tables, per
+// cell h scaling of b in 3D).
+template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR = false, bool AD = false>
 __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
@@ -975,7 +1012,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   C* sW = (C*)lds;
   C* sNB = sW + Sh::CPB * Sh::NV;
   C* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
-  C* sKF = sE + EigLDS<D, N, VARK>::SIZE;
+  C* sKF = sE + EigLDS<D, N, VARK, AD>::SIZE;
 
   const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -985,8 +1022,12 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
   const bool act = tid < Sh::NT && cl < nc;
   const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
-  const int mask = a.bmask[c];
+  const int mask = cell_mask<AD>(a, c);
   const int smask = IVAR ? 0 : mask;  // boundary classes of the block solve
+  C hf = a.h_fwd;
+  if constexpr (AD) {
+    if (a.hscale) hf *= a.hscale[c];
+  }
 
   C ul[N], bl[N];
   if (act) {
@@ -1000,9 +1041,9 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
     }
   }
   if (!UZERO) {
-    flux_fields<T, D, N, VARK, batched_trace_loads<T, N>(), IVAR>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+    flux_fields<T, D, N, VARK, AD || batched_trace_loads<T, N>(), IVAR, AD>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   } else {
-    load_eig<T, D, N, VARK>(a, c0, nc, sE, sKF);
+    load_eig<T, D, N, VARK, AD>(a, c0, nc, sE, sKF);
     __syncthreads();
     if constexpr (VARK) {
       if (a.rk) {
@@ -1023,28 +1064,28 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
       C r[N], t[N];
       if (k == 0) {
 #pragma unroll
-        for (int j = 0; j < N; ++j) r[j] = a.h_fwd * bl[j];
+        for (int j = 0; j < N; ++j) r[j] = hf * bl[j];
       } else {
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
       if (!UZERO) add_lifts<T, D, N, -1>(a, cl, k, ln, sNB, r);
-      stage_mv<T, D, N, VARK, true, false>(a, sE, cl, smask, k, r, t);  // S^T
+      stage_mv<T, D, N, VARK, true, false, true, AD>(a, sE, cl, smask, k, r, t);  // S^T
       if (k == D - 1) {
         // diagonal scaling and the first inverse transform along the last axis
-        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(smask, 0) * Sh::EGS;
-        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(smask, 1) * Sh::EGS;
+        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_cls<AD>(smask, 0) * Sh::EGS;
+        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_cls<AD>(smask, 1) * Sh::EGS;
         if constexpr (D == 2) {
           const C ls = E0[2 * NN + ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= recip(ls + E1[2 * NN + j]);
         } else {
-          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(smask, 2) * Sh::EGS;
+          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_cls<AD>(smask, 2) * Sh::EGS;
           const C ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= recip(ls + E2[2 * NN + j]);
         }
-        stage_mv<T, D, N, VARK, false, false>(a, sE, cl, smask, k, t, r);  // S
+        stage_mv<T, D, N, VARK, false, false, true, AD>(a, sE, cl, smask, k, t, r);  // S
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
       }
@@ -1063,7 +1104,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
       C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, false, false>(a, sE, cl, smask, k, r, t);
+      stage_mv<T, D, N, VARK, false, false, true, AD>(a, sE, cl, smask, k, r, t);
       if (k == 0) {
         T* uo = a.u_out + rv + (size_t)c0 * Sh::NV + base0;
 #pragma unroll
@@ -1352,14 +1393,14 @@ constexpr int sweep_waves_per_eu() {
   // spills, which the compiler does not choose by itself
   return (D == 3 && sizeof(CT<T>) == 8 && N >= 8) ? 2 : ((D == 3 && sizeof(CT<T>) == 8 && N == 5) ? 4 : 1);
 }
-template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR, bool MF = false>
+template <typename T, int D, int N, bool UZERO, bool VARK, bool IVAR, bool MF = false, bool AD = false>
 __global__ __launch_bounds__((DGShape<D, N>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, D, N>()))) void k_sweep(DGArgs<T> a) {
-  __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
+  __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK, AD>()];
   if constexpr (MF)
     sweep_body_mfma<T, D, N, UZERO, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
   else
-    sweep_body<T, D, N, UZERO, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
+    sweep_body<T, D, N, UZERO, VARK, IVAR, AD>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1368,7 +1409,7 @@ __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<T, D, N>()))) void k_sweep
 // from the coarse nodes (DG_q: a coarse cell vector; Q1: the 2^d corner
 // contributions of each cell, summed over cells by the gather kernel).
 // Needs the traces of u in tr_in.
-template <typename T, int D, int N, int NC, bool RESID, bool VARK, bool IVAR = false>
+template <typename T, int D, int N, int NC, bool RESID, bool VARK, bool IVAR = false, bool AD = false>
 __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
@@ -1377,7 +1418,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   C* sW = (C*)lds;
   C* sNB = sW + Sh::CPB * Sh::NV;
   C* sE = sNB + Sh::CPB * Sh::NF * 2 * L;
-  C* sKF = sE + EigLDS<D, N, VARK>::SIZE;
+  C* sKF = sE + EigLDS<D, N, VARK, AD>::SIZE;
 
   const int c0 = bx * Sh::CPB;
   const int nc = min(Sh::CPB, a.ncell - c0);
@@ -1387,8 +1428,12 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
   const bool act = tid < Sh::NT && cl < nc;
   const int c = c0 + (act ? cl : 0);
   const int base0 = cl * Sh::NV + line_base<D, N>(0, ln);
-  const int mask = a.bmask[c];
+  const int mask = cell_mask<AD>(a, c);
   const int smask = IVAR ? 0 : mask;  // boundary classes of the block solve
+  C ha = a.h_apply;
+  if constexpr (AD) {
+    if (a.hscale) ha /= a.hscale[c];
+  }
 
   C ul[N], bl[N];
   if (act) {
@@ -1401,7 +1446,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       for (int j = 0; j < N; ++j) bl[j] = bs[j];
     }
   }
-  flux_fields<T, D, N, VARK, true, IVAR>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+  flux_fields<T, D, N, VARK, true, IVAR, AD>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   double pdot = 0.0;  // share of p.(A p) (kdot)
 
   // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
@@ -1418,21 +1463,21 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
       }
-      stage_mv<T, D, N, VARK, false, true>(a, sE, cl, smask, k, r, t);  // Si
+      stage_mv<T, D, N, VARK, false, true, true, AD>(a, sE, cl, smask, k, r, t);  // Si
       if (k == D - 1) {
-        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_class(smask, 0) * Sh::EGS;
-        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_class(smask, 1) * Sh::EGS;
+        const C* E0 = VARK ? sE + (cl * D + 0) * Sh::EGS : sE + axis_cls<AD>(smask, 0) * Sh::EGS;
+        const C* E1 = VARK ? sE + (cl * D + 1) * Sh::EGS : sE + axis_cls<AD>(smask, 1) * Sh::EGS;
         if constexpr (D == 2) {
           const C ls = E0[2 * NN + ln];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + E1[2 * NN + j]);
         } else {
-          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_class(smask, 2) * Sh::EGS;
+          const C* E2 = VARK ? sE + (cl * D + 2) * Sh::EGS : sE + axis_cls<AD>(smask, 2) * Sh::EGS;
           const C ls = E0[2 * NN + ln % N] + E1[2 * NN + ln / N];
 #pragma unroll
           for (int j = 0; j < N; ++j) t[j] *= (ls + E2[2 * NN + j]);
         }
-        stage_mv<T, D, N, VARK, true, true>(a, sE, cl, smask, k, t, r);  // Si^T
+        stage_mv<T, D, N, VARK, true, true, true, AD>(a, sE, cl, smask, k, t, r);  // Si^T
         add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, r);
 #pragma unroll
         for (int j = 0; j < N; ++j) t[j] = r[j];
@@ -1449,12 +1494,12 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       C r[N], t[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) r[j] = sW[base + j * line_stride<N>(k)];
-      stage_mv<T, D, N, VARK, true, true>(a, sE, cl, smask, k, r, t);
+      stage_mv<T, D, N, VARK, true, true, true, AD>(a, sE, cl, smask, k, r, t);
       add_lifts<T, D, N, +1>(a, cl, k, ln, sNB, t);
       if (k == 0) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          t[j] *= a.h_apply;
+          t[j] *= ha;
           if (RESID) t[j] = bl[j] - t[j];
         }
         if constexpr (NC == 0) {
@@ -1571,11 +1616,11 @@ template <typename T, int N>
 constexpr int apply_waves_per_eu() {
   return (sizeof(T) == 8 && N <= 5) ? 4 : 1;
 }
-template <typename T, int D, int N, int NC, bool RESID, bool VARK, bool IVAR>
+template <typename T, int D, int N, int NC, bool RESID, bool VARK, bool IVAR, bool AD = false>
 __global__ __launch_bounds__((DGShape<D, N>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(apply_waves_per_eu<T, N>()))) void k_apply(DGArgs<T> a) {
-  __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK>()];
-  apply_body<T, D, N, NC, RESID, VARK, IVAR>(a, blockIdx.x, blockIdx.y, lds);
+  __shared__ __attribute__((aligned(16))) char lds[cell_lds_bytes<T, D, N, VARK, AD>()];
+  apply_body<T, D, N, NC, RESID, VARK, IVAR, AD>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1590,7 +1635,7 @@ constexpr int prolong_lds_bytes() {
   return (int)sizeof(C) * (Sh::CPB * Sh::NV + (NC != 0 ? Sh::CPB * Sh::NV + Sh::CPB * Sh::NF * 2 * Sh::L : 0));
 }
 
-template <typename T, int D, int N, int NC, bool IVAR = false>
+template <typename T, int D, int N, int NC, bool IVAR = false, bool AD = false>
 __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by, char* lds) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
@@ -1606,7 +1651,7 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
   const int cl = tid / L, ln = tid % L;
   const bool act = tid < Sh::NT && cl < nc;
   const int c = c0 + (act ? cl : 0);
-  const int mask = a.bmask[c];
+  const int mask = cell_mask<AD>(a, c);
   // NC < 0: coarse node count ncr at run time (a.ncd <= N); loops run to
   // NCB = N with the entries past ncr skipped
   constexpr int NCB = NC > 0 ? NC : (NC < 0 ? N : 1);
@@ -1636,7 +1681,8 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
   }
   if constexpr (NC != 0) {
     const C* cs = a.coarse + (size_t)by * a.cstride;
-    if (!a.coarse_cg) {
+    if (a.coarse_cg != 1) {
+      // a coarse DG cell vector, or the Q1 corner values of every cell
       for (int i = tid; i < nc * NCD; i += Sh::NT) sW[(i / NCD) * Sh::NV + i % NCD] = cs[(size_t)c0 * NCD + i];
     } else {
       // Q1 corner values of each cell from the interior-vertex vector
@@ -1747,10 +1793,10 @@ __device__ __forceinline__ void prolong_body(const DGArgs<T>& a, int bx, int by,
   if (act) store_yz_traces<T, D, N, IVAR>(a, trout, sU, cl, c, mask, ln);
 }
 
-template <typename T, int D, int N, int NC, bool IVAR>
+template <typename T, int D, int N, int NC, bool IVAR, bool AD = false>
 __global__ __launch_bounds__((DGShape<D, N>::BLOCK)) void k_prolong(DGArgs<T> a) {
   __shared__ __attribute__((aligned(16))) char lds[prolong_lds_bytes<T, D, N, NC>()];
-  prolong_body<T, D, N, NC, IVAR>(a, blockIdx.x, blockIdx.y, lds);
+  prolong_body<T, D, N, NC, IVAR, AD>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 }  // namespace HPMG_DGK
@@ -1796,7 +1842,14 @@ void launch_sweep(const DGArgs<T>& a, int nrhs, bool uzero, hipStream_t s) {
   using Sh = DGShape<D, N>;
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
   if (a.mfma && launch_sweep_mfma<T, D, N>(a, grid, uzero, s)) return;
-  if (a.vark) {
+  if (a.adapt) {  // adaptive meshes: FP64 and FP32 storage
+    if constexpr (sizeof(T) >= 4) {
+      if (uzero)
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, false, false, false, true>), grid, dim3(Sh::NT), 0, s, a);
+      else
+        hipLaunchKernelGGL((dgk::k_sweep<T, D, N, false, false, false, false, true>), grid, dim3(Sh::NT), 0, s, a);
+    }
+  } else if (a.vark) {
     if (uzero)
       hipLaunchKernelGGL((dgk::k_sweep<T, D, N, true, true, false>), grid, dim3(Sh::NT), 0, s, a);
     else
@@ -1818,7 +1871,14 @@ template <typename T, int D, int N, int NC>
 void launch_apply(const DGArgs<T>& a, int nrhs, bool resid, hipStream_t s) {
   using Sh = DGShape<D, N>;
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
-  if (a.vark) {
+  if (a.adapt) {
+    if constexpr (sizeof(T) >= 4) {
+      if (resid)
+        hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, false, false, true>), grid, dim3(Sh::NT), 0, s, a);
+      else
+        hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, false, false, false, true>), grid, dim3(Sh::NT), 0, s, a);
+    }
+  } else if (a.vark) {
     if (resid)
       hipLaunchKernelGGL((dgk::k_apply<T, D, N, NC, true, true, false>), grid, dim3(Sh::NT), 0, s, a);
     else
@@ -1840,7 +1900,9 @@ template <typename T, int D, int N, int NC>
 void launch_prolong(const DGArgs<T>& a, int nrhs, hipStream_t s) {
   using Sh = DGShape<D, N>;
   dim3 grid((a.ncell + Sh::CPB - 1) / Sh::CPB, nrhs);
-  if (a.ivar)
+  if (a.adapt) {
+    if constexpr (sizeof(T) >= 4) hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC, false, true>), grid, dim3(Sh::NT), 0, s, a);
+  } else if (a.ivar)
     hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC, true>), grid, dim3(Sh::NT), 0, s, a);
   else
     hipLaunchKernelGGL((dgk::k_prolong<T, D, N, NC, false>), grid, dim3(Sh::NT), 0, s, a);

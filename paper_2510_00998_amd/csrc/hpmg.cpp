@@ -14,6 +14,7 @@
 #include <string>
 #include <thread>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "basis.hpp"
@@ -42,8 +43,11 @@ namespace {
 // factor L_k of A_{K<-K}): kappa_K Khat plus, for each of the two facets,
 // c1 (e ep^T + ep e^T) + c2 e e^T with (c1, c2) = (-kF/2, sigma_hat kF) on
 // interior facets and (-kappa_K, 2 sigma_hat kappa_K) on boundary facets.
+// pen0 / pen1 multiply the penalty of an interior facet (adaptive meshes:
+// r on the coarse side of a hanging facet, whose penalty is that of the
+// finer cells).
 void axis_operator(const hpmg::Basis1D& B, double kK, double kF0, bool bdy0, double kF1, bool bdy1,
-                   double sigma_hat, std::vector<double>& L) {
+                   double sigma_hat, std::vector<double>& L, double pen0 = 1.0, double pen1 = 1.0) {
   const int N = B.N;
   L.assign((size_t)N * N, 0.0);
   for (int i = 0; i < N * N; ++i) L[i] = kK * B.K[i];
@@ -51,7 +55,7 @@ void axis_operator(const hpmg::Basis1D& B, double kK, double kF0, bool bdy0, dou
     const bool bdy = s ? bdy1 : bdy0;
     const double kF = s ? kF1 : kF0;
     const double c1 = bdy ? -kK : -0.5 * kF;
-    const double c2 = bdy ? 2.0 * sigma_hat * kK : sigma_hat * kF;
+    const double c2 = bdy ? 2.0 * sigma_hat * kK : sigma_hat * kF * (s ? pen1 : pen0);
     const std::vector<double>& e = s ? B.e1 : B.e0;
     const std::vector<double>& ep = s ? B.ep1 : B.ep0;
     for (int i = 0; i < N; ++i)
@@ -150,11 +154,64 @@ std::vector<double> khat_and_inverse_cholesky(const hpmg::Basis1D& B) {
   return tab;
 }
 
+// Solve Mhat X = Y for the N x N matrices of the hanging-facet projection
+// (Gaussian elimination with partial pivoting in long double).
+std::vector<double> mass_solve(const hpmg::Basis1D& B, const std::vector<double>& Y) {
+  const int N = B.N;
+  std::vector<long double> A(B.M.begin(), B.M.end()), X(Y.begin(), Y.end());
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (std::fabs((double)A[(size_t)r * N + c]) > std::fabs((double)A[(size_t)piv * N + c])) piv = r;
+    for (int j = 0; j < N; ++j) {
+      std::swap(A[(size_t)c * N + j], A[(size_t)piv * N + j]);
+      std::swap(X[(size_t)c * N + j], X[(size_t)piv * N + j]);
+    }
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      const long double f = A[(size_t)r * N + c] / A[(size_t)c * N + c];
+      for (int j = 0; j < N; ++j) {
+        A[(size_t)r * N + j] -= f * A[(size_t)c * N + j];
+        X[(size_t)r * N + j] -= f * X[(size_t)c * N + j];
+      }
+    }
+  }
+  std::vector<double> out((size_t)N * N);
+  for (int r = 0; r < N; ++r)
+    for (int j = 0; j < N; ++j) out[(size_t)r * N + j] = (double)(X[(size_t)r * N + j] / A[(size_t)r * N + r]);
+  return out;
+}
+
+// Hanging-facet remap tables of a level (adaptive meshes): I_j[a][b] =
+// l_b((xi_a + j) / r) (the coarse facet polynomial at the nodes of the j-th
+// fine facet along one axis) for j < r, then P_j = (1/r) Mhat^-1 I_j^T Mhat
+// (L2 projection of a polynomial on the j-th part onto the coarse facet).
+std::vector<double> remap_tables(const hpmg::Basis1D& B, int r) {
+  const int N = B.N, NN = N * N;
+  std::vector<double> out((size_t)2 * r * NN);
+  for (int j = 0; j < r; ++j) {
+    std::vector<double> pts(N);
+    for (int a = 0; a < N; ++a) pts[a] = (B.xi[a] + j) / r;
+    const std::vector<double> I = hpmg::interp_matrix(pts, B.xi);
+    std::copy(I.begin(), I.end(), out.begin() + (size_t)j * NN);
+    std::vector<double> Y((size_t)NN, 0.0);  // (1/r) I^T Mhat
+    for (int a = 0; a < N; ++a)
+      for (int c = 0; c < N; ++c) {
+        long double acc = 0.0L;
+        for (int m = 0; m < N; ++m) acc += (long double)I[(size_t)m * N + a] * B.M[(size_t)m * N + c];
+        Y[(size_t)a * N + c] = (double)(acc / r);
+      }
+    const std::vector<double> P = mass_solve(B, Y);
+    std::copy(P.begin(), P.end(), out.begin() + (size_t)(r + j) * NN);
+  }
+  return out;
+}
+
 void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg::Basis1D* Bnext,
                     hipStream_t s) {
   const int N = B.N, NN = N * N, D = h->dim;
   L.ndof = (size_t)h->ncell * ipow(N, D);
-  L.trsize = (size_t)2 * D * h->ncell * 2 * ipow(N, D - 1);
+  L.trsize = ((size_t)2 * D * h->ncell + (size_t)h->nif * (h->mif + 1)) * 2 * ipow(N, D - 1);
   // reference data
   std::vector<double> ref;
   ref.insert(ref.end(), B.M.begin(), B.M.end());
@@ -177,14 +234,20 @@ void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg:
   const int EGS = 2 * NN + N;
   std::vector<double> Lm;
   if (!h->vark) {
-    std::vector<double> tab((size_t)4 * EGS, 0.0);
+    // classes: bit 0 / 1 lower / upper facet on the boundary; adaptive
+    // meshes add bit 2 / 3 for a lower / upper hanging facet (coarse side)
+    const int ncls = h->adapt ? 16 : 4;
+    std::vector<double> tab((size_t)ncls * EGS, 0.0);
     const double k = h->kappa_const;
-    for (int cls = 0; cls < 4; ++cls) {
-      if (cls == 3 && h->n > 1) {  // both facets on the boundary only when n == 1
-        std::copy(tab.begin(), tab.begin() + EGS, tab.begin() + 3 * EGS);
+    for (int cls = 0; cls < ncls; ++cls) {
+      const bool b0 = cls & 1, b1 = (cls >> 1) & 1, g0 = (cls >> 2) & 1, g1 = (cls >> 3) & 1;
+      if ((b0 && b1 && h->n > 1) || (b0 && g0) || (b1 && g1)) {
+        // no cell has this class (both facets on the boundary only when
+        // n == 1; a boundary facet does not hang)
+        std::copy(tab.begin(), tab.begin() + EGS, tab.begin() + (size_t)cls * EGS);
         continue;
       }
-      axis_operator(B, k, k, cls & 1, k, (cls >> 1) & 1, L.sigma_hat, Lm);
+      axis_operator(B, k, k, b0, k, b1, L.sigma_hat, Lm, g0 ? h->rfac : 1.0, g1 ? h->rfac : 1.0);
       double* S = &tab[(size_t)cls * EGS];
       double* Si = S + NN;
       double* lam = S + 2 * NN;
@@ -210,6 +273,11 @@ void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg:
     }
     L.d.eig = h->mem.upload(tab, s);
     L.f.eig = h->mem.upload(cast_vec<float>(tab), s);
+    if (h->adapt) {
+      const std::vector<double> mt = remap_tables(B, h->rfac);
+      L.d.mort = h->mem.upload(mt, s);
+      L.f.mort = h->mem.upload(cast_vec<float>(mt), s);
+    }
   } else {
     // the kernels rebuild S, lambda per cell and axis from kappa
     // (block_recompute) or read them from per-cell records built here on the
@@ -397,7 +465,7 @@ std::vector<double> rap(int D, int n, const std::vector<double>& st, int nc, int
 
 void build_cg_levels(hpmg_ctx* h, hipStream_t s) {
   const int D = h->dim;
-  std::vector<double> kap = h->vark ? h->kappa : std::vector<double>(h->ncell, h->kappa_const);
+  std::vector<double> kap = h->vark ? h->kappa : std::vector<double>((size_t)ipow(h->n, D), h->kappa_const);
   std::vector<double> st = q1_stencil(D, h->n, kap);
   int m = h->n;
   while (true) {
@@ -510,6 +578,225 @@ void build_cg_levels(hpmg_ctx* h, hipStream_t s) {
   }
 }
 
+// ------------------------------------------------------- adaptive meshes
+// Leaves of a spacetree over the unit box (Section 2.1): n^dim base cells,
+// a refined cell split into r^dim children.  Validated here: coordinates in
+// range, no duplicate leaf, no leaf inside another, the leaves cover the
+// box, facet neighbours at most one level apart.  Built: per cell the mask
+// (boundary bits f, hanging-coarse-side bits 8 + f), the neighbour-side
+// trace slot of every facet, the hanging interfaces, (h_base / h_c)^(d-2),
+// the leaf geometry, and the Q1 transfers between the base mesh's interior
+// vertices and the leaves' corners.
+uint64_t leaf_key(int lvl, const int* x, int D) {
+  uint64_t k = (uint64_t)lvl;
+  for (int i = 0; i < D; ++i) k |= (uint64_t)x[i] << (4 + 20 * i);
+  return k;
+}
+
+void build_adaptive(hpmg_ctx* h, const hpmg_adaptive_mesh* am, hipStream_t s) {
+  const int D = h->dim, n = h->n, r = h->rfac, nl = h->ncell;
+  const int m = ipow(r, D - 1);
+  h->mif = m;
+  std::vector<int> lev(nl), X((size_t)nl * 3, 0);
+  int lmax = 0;
+  for (int c = 0; c < nl; ++c) {
+    const int* row = am->leaves + (size_t)c * (1 + D);
+    lev[c] = row[0];
+    require(row[0] >= 0 && row[0] <= 12, "leaf level must be in [0, 12]");
+    lmax = std::max(lmax, row[0]);
+  }
+  long long ext_max = n;
+  for (int l = 0; l < lmax; ++l) ext_max *= r;
+  require(ext_max <= (1 << 20), "leaves too fine: n r^level must not exceed 2^20");
+  std::unordered_map<uint64_t, int> idx;
+  idx.reserve((size_t)nl * 2);
+  unsigned long long vol = 0, full = 1;
+  for (int k = 0; k < D; ++k) full *= (unsigned long long)ext_max;
+  for (int c = 0; c < nl; ++c) {
+    const int* row = am->leaves + (size_t)c * (1 + D);
+    const long long ext = n * (long long)std::pow((double)r, lev[c]) + 0.5;
+    for (int k = 0; k < D; ++k) {
+      require(row[1 + k] >= 0 && row[1 + k] < ext, "leaf coordinate out of range for its level");
+      X[(size_t)c * 3 + k] = row[1 + k];
+    }
+    require(idx.emplace(leaf_key(lev[c], &X[(size_t)c * 3], D), c).second, "duplicate leaf");
+    unsigned long long v = 1;
+    for (int l = lev[c]; l < lmax; ++l) v *= (unsigned long long)ipow(r, D);
+    vol += v;
+  }
+  for (int c = 0; c < nl; ++c) {  // no leaf lies inside another leaf
+    int y[3] = {X[(size_t)c * 3], X[(size_t)c * 3 + 1], X[(size_t)c * 3 + 2]};
+    for (int l = lev[c] - 1; l >= 0; --l) {
+      for (int k = 0; k < D; ++k) y[k] /= r;
+      require(idx.find(leaf_key(l, y, D)) == idx.end(), "a leaf lies inside another leaf");
+    }
+  }
+  require(vol == full, "the leaves do not cover the unit box");
+  auto find = [&](int l, const int* y) -> int {
+    auto it = idx.find(leaf_key(l, y, D));
+    return it == idx.end() ? -1 : it->second;
+  };
+  std::vector<unsigned short> amask(nl, 0);
+  std::vector<int> nbslot((size_t)2 * D * nl, 0);
+  std::vector<int> itab;  // [nif][2 + m]
+  std::unordered_map<long long, int> iface;  // (coarse cell, facet) -> interface
+  auto get_iface = [&](int B, int fB) -> int {
+    const long long key = (long long)B * 8 + fB;
+    auto it = iface.find(key);
+    if (it != iface.end()) return it->second;
+    const int i = (int)iface.size();
+    iface.emplace(key, i);
+    itab.resize((size_t)(i + 1) * (2 + m), -1);
+    itab[(size_t)i * (2 + m)] = B;
+    itab[(size_t)i * (2 + m) + 1] = fB;
+    return i;
+  };
+  std::vector<std::pair<int, int>> slot_fix;  // (index into nbslot, interface slot offset)
+  std::vector<int> slot_if;
+  for (int c = 0; c < nl; ++c) {
+    const int l = lev[c];
+    const int* x = &X[(size_t)c * 3];
+    const long long ext = n * (long long)std::pow((double)r, l) + 0.5;
+    for (int f = 0; f < 2 * D; ++f) {
+      const int k = f >> 1, sd = f & 1;
+      const size_t ns = (size_t)f * nl + c;
+      int y[3] = {x[0], x[1], x[2]};
+      y[k] += sd ? 1 : -1;
+      if (y[k] < 0 || y[k] >= ext) {
+        amask[c] |= (unsigned short)(1u << f);
+        nbslot[ns] = (int)ns;  // read, then zeroed: any valid slot
+        continue;
+      }
+      const int nb = find(l, y);
+      if (nb >= 0) {
+        nbslot[ns] = (int)((size_t)(f ^ 1) * nl + nb);
+        continue;
+      }
+      int yc[3] = {y[0] / r, y[1] / r, y[2] / r};
+      const int big = l > 0 ? find(l - 1, yc) : -1;
+      if (big >= 0) {
+        // c is a fine cell of the hanging facet (big, f ^ 1); its position
+        // along the tangential axes, lower axis first
+        const int i = get_iface(big, f ^ 1);
+        int pos = 0, mul = 1;
+        for (int t = 0; t < D; ++t) {
+          if (t == k) continue;
+          pos += (x[t] - r * yc[t]) * mul;
+          mul *= r;
+        }
+        require(itab[(size_t)i * (2 + m) + 2 + pos] == -1, "two leaves on one part of a hanging facet");
+        itab[(size_t)i * (2 + m) + 2 + pos] = c;
+        slot_fix.push_back({(int)ns, pos});
+        slot_if.push_back(i);
+        continue;
+      }
+      // the neighbour region is refined: its r^(d-1) children on the facet
+      // must be leaves
+      const int i = get_iface(c, f);
+      for (int q = 0; q < m; ++q) {
+        int z[3] = {r * y[0], r * y[1], r * y[2]};
+        z[k] = r * y[k] + (sd ? 0 : r - 1);
+        int qq = q;
+        for (int t = 0; t < D; ++t) {
+          if (t == k) continue;
+          z[t] += qq % r;
+          qq /= r;
+        }
+        require(find(l + 1, z) >= 0, "facet neighbours more than one level apart (the mesh is not balanced)");
+      }
+      amask[c] |= (unsigned short)(1u << (8 + f));
+      slot_fix.push_back({(int)ns, m});
+      slot_if.push_back(i);
+    }
+  }
+  h->nif = (int)iface.size();
+  for (int i = 0; i < h->nif; ++i)
+    for (int q = 0; q < m; ++q)
+      require(itab[(size_t)i * (2 + m) + 2 + q] >= 0, "a hanging facet is not covered by finer leaves");
+  const size_t base0 = (size_t)2 * D * nl;
+  for (size_t j = 0; j < slot_fix.size(); ++j)
+    nbslot[slot_fix[j].first] = (int)(base0 + (size_t)slot_if[j] * (m + 1) + slot_fix[j].second);
+  require(base0 + (size_t)h->nif * (m + 1) < (size_t)1 << 31, "mesh too large");
+  h->amask = h->mem.upload(amask, s);
+  h->nbslot = h->mem.upload(nbslot, s);
+  if (h->nif > 0) h->itab = h->mem.upload(itab, s);
+  std::vector<unsigned char> bm(nl);
+  for (int c = 0; c < nl; ++c) bm[c] = (unsigned char)(amask[c] & 0xff);
+  h->bmask = h->mem.upload(bm, s);
+  // geometry and h scaling
+  h->leaf_h.resize(nl);
+  h->leaf_org.resize((size_t)nl * D);
+  std::vector<double> hs(nl, 1.0);
+  for (int c = 0; c < nl; ++c) {
+    const double rl = std::pow((double)r, lev[c]);
+    h->leaf_h[c] = 1.0 / (n * rl);
+    for (int k = 0; k < D; ++k) h->leaf_org[(size_t)c * D + k] = X[(size_t)c * 3 + k] * h->leaf_h[c];
+    hs[c] = std::pow(rl, D - 2);
+  }
+  if (D == 3) {
+    h->hs_d = h->mem.upload(hs, s);
+    h->hs_f = h->mem.upload(cast_vec<float>(hs), s);
+  }
+  // Q1 transfers: corner j of leaf c lies at t = (x - B r^l + bit(j)) / r^l
+  // inside its base cell B; the base vertex B + w (w in {0,1}^d) has the
+  // weight prod_k (w_k ? t_k : 1 - t_k) there (zero boundary vertices left out)
+  const int nv = n - 1, nc = 1 << D;
+  std::vector<std::vector<std::pair<int, double>>> prow((size_t)nl * nc);
+  std::vector<std::vector<std::pair<int, double>>> rrow((size_t)ipow(nv, D));
+  for (int c = 0; c < nl; ++c) {
+    const long long rl = (long long)(std::pow((double)r, lev[c]) + 0.5);
+    for (int j = 0; j < nc; ++j) {
+      double t[3];
+      int Bc[3];
+      for (int k = 0; k < D; ++k) {
+        const long long xk = X[(size_t)c * 3 + k];
+        Bc[k] = (int)(xk / rl);
+        t[k] = (double)(xk - Bc[k] * rl + ((j >> k) & 1)) / (double)rl;
+      }
+      for (int w = 0; w < nc; ++w) {
+        double wt = 1.0;
+        int vid = 0, mul = 1;
+        bool inside = true;
+        for (int k = 0; k < D; ++k) {
+          const int bit = (w >> k) & 1;
+          wt *= bit ? t[k] : 1.0 - t[k];
+          const int v = Bc[k] + bit;
+          inside = inside && v > 0 && v < n;
+          vid += (v - 1) * mul;
+          mul *= nv;
+        }
+        if (!inside || wt == 0.0) continue;
+        prow[(size_t)c * nc + j].push_back({vid, wt});
+        rrow[vid].push_back({c * nc + j, wt});
+      }
+    }
+  }
+  auto upload_csr = [&](const std::vector<std::vector<std::pair<int, double>>>& rows, int** ptr, int** col,
+                        double** wd, float** wf) {
+    std::vector<int> pv(rows.size() + 1, 0), cv;
+    std::vector<double> wv;
+    for (size_t i = 0; i < rows.size(); ++i) {
+      for (auto& e : rows[i]) {
+        cv.push_back(e.first);
+        wv.push_back(e.second);
+      }
+      pv[i + 1] = (int)cv.size();
+    }
+    if (cv.empty()) {
+      cv.push_back(0);
+      wv.push_back(0.0);
+    }
+    *ptr = h->mem.upload(pv, s);
+    *col = h->mem.upload(cv, s);
+    *wd = h->mem.upload(wv, s);
+    *wf = h->mem.upload(cast_vec<float>(wv), s);
+  };
+  h->q1p_rows = (int)prow.size();
+  h->q1r_rows = (int)rrow.size();
+  upload_csr(prow, &h->q1p_ptr, &h->q1p_col, &h->q1p_wd, &h->q1p_wf);
+  upload_csr(rrow, &h->q1r_ptr, &h->q1r_col, &h->q1r_wd, &h->q1r_wf);
+}
+
 // --------------------------------------------------------------- execution
 template <typename T>
 void project(hpmg_ctx* h, int l, const T* u, T* tr, int nrhs, hipStream_t s) {
@@ -615,6 +902,16 @@ void vcycle_cg(hpmg_ctx* h, int m, bool uzero, int col, hipStream_t s) {
   HIPCHK(hipGetLastError());
 }
 
+// Weights of the Q1 transfers of an adaptive mesh in the compute type
+// (restriction: rows = base vertices; else prolongation: rows = corners).
+template <typename C>
+const C* q1_weights(const hpmg_ctx* h, bool restr) {
+  if constexpr (std::is_same<C, double>::value)
+    return restr ? h->q1r_wd : h->q1p_wd;
+  else
+    return restr ? h->q1r_wf : h->q1p_wf;
+}
+
 // One V-cycle on DG level l for nrhs stacked right-hand sides; u, b are the
 // level's vectors (for l = 0 the caller's).  Traversals on the level:
 // [projection], nu_pre sweeps, residual + restriction, prolongation +
@@ -665,20 +962,37 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, int nrhs, hipSt
     CGLevel& Cg = h->cg[0];
     CGData<C>& dc = data<C>(Cg);
     const size_t nct = (size_t)h->ncell << h->dim;
-    a.out = data<C>(L).contrib;
+    C* contrib = data<C>(L).contrib;
+    a.out = contrib;
     a.cstride = (long long)nct;
     dg_run(h, hpmg::OP_RESTRICT_Q1, a, L.N, nrhs, 1, s);
     for (int c = 0; c < nrhs; ++c) {
-      hpmg::gather_corners<C>(h->dim, h->n, data<C>(L).contrib + c * nct, dc.b + c * Cg.size, s);
+      if (h->adapt)  // base vertices <- corners of the leaves inside their cells
+        hpmg::csr_apply<C>(h->q1r_rows, h->q1r_ptr, h->q1r_col, q1_weights<C>(h, true), contrib + c * nct,
+                           dc.b + c * Cg.size, s);
+      else
+        hpmg::gather_corners<C>(h->dim, h->n, contrib + c * nct, dc.b + c * Cg.size, s);
       vcycle_cg<C>(h, 0, true, c, s);
     }
     hpmg::DGArgs<T> pa = dg_args<T>(h, L);
     pa.u_in = u;
     pa.u_out = u;
     pa.tr_out = d.tr[cur];
-    pa.coarse = dc.u[Cg.cur];
-    pa.coarse_cg = 1;
-    pa.cstride = (long long)Cg.size;
+    if (h->adapt) {
+      // corner values of every leaf from the base vertices (the Q1
+      // function evaluated at the leaf's corners), then the per-cell
+      // trilinear interpolation of the prolongation kernel
+      for (int c = 0; c < nrhs; ++c)
+        hpmg::csr_apply<C>(h->q1p_rows, h->q1p_ptr, h->q1p_col, q1_weights<C>(h, false),
+                           dc.u[Cg.cur] + c * Cg.size, contrib + c * nct, s);
+      pa.coarse = contrib;
+      pa.coarse_cg = 2;
+      pa.cstride = (long long)nct;
+    } else {
+      pa.coarse = dc.u[Cg.cur];
+      pa.coarse_cg = 1;
+      pa.cstride = (long long)Cg.size;
+    }
     dg_run(h, hpmg::OP_PROLONG_Q1, pa, L.N, nrhs, 0, s);
   }
   for (int i = 0; i < h->opt.nu_post; ++i) {
@@ -740,10 +1054,12 @@ void by_dtype(hpmg_ctx* h, int dtype, F f) {
     case HPMG_F64: f((double*)nullptr); break;
     case HPMG_F32: f((float*)nullptr); break;
     case HPMG_F16:
+      if (h->adapt) throw HpmgError(HPMG_E_UNSUPPORTED, "adaptive meshes take FP64 or FP32 vectors");
       ensure_traces<_Float16>(h);
       f((_Float16*)nullptr);
       break;
     case HPMG_BF16:
+      if (h->adapt) throw HpmgError(HPMG_E_UNSUPPORTED, "adaptive meshes take FP64 or FP32 vectors");
       ensure_traces<__bf16>(h);
       f((__bf16*)nullptr);
       break;
@@ -942,20 +1258,22 @@ const char* hpmg_status_string(hpmg_status s) {
 
 const char* hpmg_last_error(void) { return g_last_error.c_str(); }
 
-hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, const hpmg_options* opt,
-                       hipStream_t stream, hpmg_handle* out) {
+namespace {
+
+// Common setup of hpmg_setup (am = NULL: the uniform n^dim mesh) and
+// hpmg_setup_adaptive (the leaves of am over n^dim base cells).
+hpmg_status setup_impl(int dim, int nbase, const hpmg_adaptive_mesh* am, int p, const hpmg_coeff* coeff,
+                       const hpmg_options* opt, hipStream_t stream, hpmg_handle* out) {
   try {
     require(out != nullptr, "out is NULL");
     *out = nullptr;
-    require(mesh != nullptr && coeff != nullptr, "mesh/coeff is NULL");
-    require(mesh->dim == 2 || mesh->dim == 3, "dim must be 2 or 3");
-    require(mesh->n[0] >= 2, "n must be >= 2");
-    require(mesh->n[1] == mesh->n[0] && (mesh->dim == 2 || mesh->n[2] == mesh->n[0]),
-            "only n x n (x n) meshes are supported");
+    require(coeff != nullptr, "coeff is NULL");
+    require(dim == 2 || dim == 3, "dim must be 2 or 3");
+    require(nbase >= 2, "n must be >= 2");
     require(p >= 1 && p <= 8, "p must be in [1, 8]");
-    const long long ncell_ll = mesh->dim == 2 ? (long long)mesh->n[0] * mesh->n[0]
-                                              : (long long)mesh->n[0] * mesh->n[0] * mesh->n[0];
-    require(ncell_ll < (1LL << 31) / 2, "mesh too large");
+    const long long ncell_ll = am ? (long long)am->nleaf
+                                  : (dim == 2 ? (long long)nbase * nbase : (long long)nbase * nbase * nbase);
+    require(ncell_ll >= 1 && ncell_ll < (1LL << 31) / 2, "mesh too large");
     std::unique_ptr<hpmg_ctx> h(new hpmg_ctx());
     if (opt) {
       h->opt = *opt;
@@ -974,15 +1292,25 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     require(h->opt.basis == 0 || h->opt.basis == 1, "basis must be 0 (Gauss-Lobatto) or 1 (Gauss-Legendre)");
     require(h->opt.nu_pre_cg >= -1 && h->opt.nu_post_cg >= -1, "nu_pre_cg / nu_post_cg must be >= -1");
     require(h->opt.block_variant == 0 || h->opt.block_variant == 1, "block_variant must be 0 or 1");
-    require(h->opt.mfma == 0 || (h->opt.mfma == 1 && mesh->dim == 3), "mfma must be 0, or 1 with dim 3");
+    require(h->opt.mfma == 0 || (h->opt.mfma == 1 && dim == 3), "mfma must be 0, or 1 with dim 3");
     require((h->opt.alloc == nullptr) == (h->opt.free == nullptr), "alloc and free must be given together");
     h->mem.alloc_fn = h->opt.alloc;
     h->mem.free_fn = h->opt.free;
     h->mem.ctx = h->opt.alloc_ctx;
-    h->dim = mesh->dim;
-    h->n = mesh->n[0];
+    h->dim = dim;
+    h->n = nbase;
     h->p = p;
     h->ncell = (int)ncell_ll;
+    if (am) {
+      require(am->refine == 2 || am->refine == 3, "refine must be 2 or 3");
+      require(!coeff->per_cell, "adaptive meshes take a constant kappa");
+      require(h->opt.block_variant == 0 && h->opt.block_recompute == 0 && h->opt.mfma == 0,
+              "adaptive meshes take the exact block, block_recompute 0 and mfma 0");
+      require(h->opt.precision == HPMG_PREC_F64 || h->opt.precision == HPMG_PREC_F32,
+              "adaptive meshes take an FP64 or FP32 cycle");
+      h->adapt = true;
+      h->rfac = am->refine;
+    }
     if (coeff->per_cell) {
       require(coeff->kappa != nullptr, "kappa is NULL");
       h->vark = true;
@@ -1008,7 +1336,9 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
     HIPCHK(hipGetDevice(&dev));
     h->dev = dev;
     init_noalloc_scratch(dev);
-    {
+    if (am) {
+      build_adaptive(h.get(), am, stream);
+    } else {
       std::vector<unsigned char> m(h->ncell);
       const int n = h->n;
       for (int c = 0; c < h->ncell; ++c) {
@@ -1093,6 +1423,32 @@ hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, co
   }
 }
 
+}  // namespace
+
+hpmg_status hpmg_setup(const hpmg_mesh* mesh, int p, const hpmg_coeff* coeff, const hpmg_options* opt,
+                       hipStream_t stream, hpmg_handle* out) {
+  if (out) *out = nullptr;
+  if (mesh == nullptr) {
+    g_last_error = "mesh is NULL";
+    return HPMG_E_INVALID;
+  }
+  if (mesh->n[1] != mesh->n[0] || (mesh->dim == 3 && mesh->n[2] != mesh->n[0])) {
+    g_last_error = "only n x n (x n) meshes are supported";
+    return HPMG_E_INVALID;
+  }
+  return setup_impl(mesh->dim, mesh->n[0], nullptr, p, coeff, opt, stream, out);
+}
+
+hpmg_status hpmg_setup_adaptive(const hpmg_adaptive_mesh* mesh, int p, const hpmg_coeff* coeff,
+                                const hpmg_options* opt, hipStream_t stream, hpmg_handle* out) {
+  if (out) *out = nullptr;
+  if (mesh == nullptr || mesh->leaves == nullptr || mesh->nleaf < 1) {
+    g_last_error = "mesh is NULL or has no leaves";
+    return HPMG_E_INVALID;
+  }
+  return setup_impl(mesh->dim, mesh->n, mesh, p, coeff, opt, stream, out);
+}
+
 size_t hpmg_ndof(hpmg_handle h) { return h ? h->ndof : 0; }
 
 void hpmg_destroy(hpmg_handle h) { delete h; }
@@ -1110,28 +1466,71 @@ hpmg_status hpmg_load_vector(hpmg_handle h, int kind, const double* params, doub
     hpmg::gauss_legendre(h->p + 3, xq, wq);
     std::vector<double> V = hpmg::interp_matrix(xq, B.xi);
     const int nq = (int)xq.size();
-    if (kind == 2) {
-      // f = -Laplace u2, u2 = P G, P = x(1-x)y(1-y), G = 2 e1 - e2,
-      // e = exp(-|x - x0|^2 / (2 s^2)):  Laplace u2 = G Laplace P
-      // + 2 grad P . grad G + P Laplace G, grad e = -(x - x0) e / s^2,
-      // Laplace e = (|x - x0|^2 / s^4 - 2 / s^2) e
-      auto f2 = [](double x, double y) {
-        const double cx[2] = {0.3, 0.8}, cy[2] = {0.4, 0.6}, sg[2] = {0.2, 0.1}, wt[2] = {2.0, -1.0};
-        double G = 0.0, Gx = 0.0, Gy = 0.0, LG = 0.0;
-        for (int i = 0; i < 2; ++i) {
-          const double dx = x - cx[i], dy = y - cy[i], s2 = sg[i] * sg[i];
-          const double r2 = dx * dx + dy * dy;
-          const double e = std::exp(-r2 / (2.0 * s2));
-          G += wt[i] * e;
-          Gx += wt[i] * (-dx / s2) * e;
-          Gy += wt[i] * (-dy / s2) * e;
-          LG += wt[i] * (r2 / (s2 * s2) - 2.0 / s2) * e;
+    // f = -Laplace u2, u2 = P G, P = x(1-x)y(1-y), G = 2 e1 - e2,
+    // e = exp(-|x - x0|^2 / (2 s^2)):  Laplace u2 = G Laplace P
+    // + 2 grad P . grad G + P Laplace G, grad e = -(x - x0) e / s^2,
+    // Laplace e = (|x - x0|^2 / s^4 - 2 / s^2) e
+    auto f2 = [](double x, double y) {
+      const double cx[2] = {0.3, 0.8}, cy[2] = {0.4, 0.6}, sg[2] = {0.2, 0.1}, wt[2] = {2.0, -1.0};
+      double G = 0.0, Gx = 0.0, Gy = 0.0, LG = 0.0;
+      for (int i = 0; i < 2; ++i) {
+        const double dx = x - cx[i], dy = y - cy[i], s2 = sg[i] * sg[i];
+        const double r2 = dx * dx + dy * dy;
+        const double e = std::exp(-r2 / (2.0 * s2));
+        G += wt[i] * e;
+        Gx += wt[i] * (-dx / s2) * e;
+        Gy += wt[i] * (-dy / s2) * e;
+        LG += wt[i] * (r2 / (s2 * s2) - 2.0 / s2) * e;
+      }
+      const double px = x * (1.0 - x), py = y * (1.0 - y);
+      const double P = px * py, Px = (1.0 - 2.0 * x) * py, Py = px * (1.0 - 2.0 * y);
+      const double LP = -2.0 * (py + px);
+      return -(G * LP + 2.0 * (Px * Gx + Py * Gy) + P * LG);
+    };
+    if (h->adapt) {
+      // per leaf: width hK, lower corner o; separable kinds per axis
+      // G_k[a] = hK int g(o_k + hK xi) l_a(xi), the two-peak load by the
+      // tensor rule on the leaf
+      std::vector<double> out(h->ndof);
+      const int nd = ipow(N, D);
+      const double kf = kind == 1 ? params[0] : 0.0;
+      const double coef = kind == 0 ? params[0] : D * kf * kf * M_PI * M_PI;
+      std::vector<double> G((size_t)D * N);
+      for (int c = 0; c < h->ncell; ++c) {
+        const double hK = h->leaf_h[c];
+        const double* o = &h->leaf_org[(size_t)c * D];
+        if (kind == 2) {
+          for (int i = 0; i < nd; ++i) {
+            const int a = i % N, bb = i / N;
+            double v = 0.0;
+            for (int qy = 0; qy < nq; ++qy)
+              for (int qx = 0; qx < nq; ++qx)
+                v += wq[qx] * wq[qy] * f2(o[0] + hK * xq[qx], o[1] + hK * xq[qy]) * V[(size_t)qx * N + a] *
+                     V[(size_t)qy * N + bb];
+            out[(size_t)c * nd + i] = v * hK * hK;
+          }
+          continue;
         }
-        const double px = x * (1.0 - x), py = y * (1.0 - y);
-        const double P = px * py, Px = (1.0 - 2.0 * x) * py, Py = px * (1.0 - 2.0 * y);
-        const double LP = -2.0 * (py + px);
-        return -(G * LP + 2.0 * (Px * Gx + Py * Gy) + P * LG);
-      };
+        for (int k = 0; k < D; ++k)
+          for (int a = 0; a < N; ++a) {
+            double sum = 0.0;
+            for (int q = 0; q < nq; ++q) {
+              const double g = kind == 0 ? 1.0 : std::sin(kf * M_PI * (o[k] + hK * xq[q]));
+              sum += wq[q] * g * V[(size_t)q * N + a];
+            }
+            G[(size_t)k * N + a] = sum * hK;
+          }
+        for (int i = 0; i < nd; ++i) {
+          double v = coef;
+          for (int k = 0, ii = i; k < D; ++k, ii /= N) v *= G[(size_t)k * N + ii % N];
+          out[(size_t)c * nd + i] = v;
+        }
+      }
+      HIPCHK(hipMemcpyAsync(b, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      return HPMG_OK;
+    }
+    if (kind == 2) {
       std::vector<double> out(h->ndof);
       const int nd2 = N * N;
       for (int c = 0; c < h->ncell; ++c) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdexcept>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -105,6 +106,7 @@ struct DGData {
   T* b = nullptr;        // coarse levels only
   T* tr[2] = {nullptr, nullptr};
   T* contrib = nullptr;  // corner contributions (last DG level, restriction to Q1)
+  T* mort = nullptr;     // adaptive meshes: hanging-facet remap tables [I_j | P_j], j < r
 };
 
 struct DGLevel {
@@ -159,6 +161,25 @@ struct hpmg_ctx {
   double* coarse_inv = nullptr;  // dense inverse of the coarsest Q1 operator
   unsigned char* bmask = nullptr;  // per cell boundary-facet mask (all DG levels)
   int coarse_m = 0;
+  // Adaptive (spacetree) mesh, hpmg_setup_adaptive: n is the base mesh,
+  // ncell the number of leaves.  rfac: subdivision factor r; nif hanging
+  // interfaces of mif = r^(d-1) fine cells each (itab rows: coarse cell, its
+  // facet, the fine cells); amask / nbslot as the kernels read them;
+  // hscale (h_base / h_c)^(d-2) per cell (3D); CSR transfers between the Q1
+  // base vertices and the cells' corners (restriction: rows = vertices,
+  // prolongation: rows = cell corners); leaf geometry for load vectors.
+  bool adapt = false;
+  int rfac = 0, nif = 0, mif = 0;
+  unsigned short* amask = nullptr;
+  int* nbslot = nullptr;
+  int* itab = nullptr;
+  double* hs_d = nullptr;
+  float* hs_f = nullptr;
+  int q1r_rows = 0, q1p_rows = 0;
+  int *q1r_ptr = nullptr, *q1r_col = nullptr, *q1p_ptr = nullptr, *q1p_col = nullptr;
+  double *q1r_wd = nullptr, *q1p_wd = nullptr;
+  float *q1r_wf = nullptr, *q1p_wf = nullptr;
+  std::vector<double> leaf_h, leaf_org;  // per leaf: width, lower corner (dim values)
   // outer solver workspace (FP64) and the FP32 cycle vectors
   double *r = nullptr, *rold = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
   float *r32 = nullptr, *z32 = nullptr;
@@ -247,6 +268,17 @@ inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
   a.mfma = h->opt.mfma;
   a.vstride = (long long)L.ndof;
   a.tstride = (long long)L.trsize;
+  if (h->adapt) {
+    a.adapt = 1;
+    a.amask = h->amask;
+    a.nbslot = h->nbslot;
+    if constexpr (std::is_same<C, double>::value)
+      a.hscale = h->hs_d;
+    else
+      a.hscale = h->hs_f;
+    a.sig_hang = (C)(L.sigma_hat * h->rfac);
+    a.mort = d.mort;
+  }
   return a;
 }
 
@@ -255,6 +287,18 @@ inline void dg_run(hpmg_ctx* h, int op, const hpmg::DGArgs<T>& a, int N, int nrh
   if (!hpmg::dg_dispatch(h->dim, N, op, a, nrhs, flag, s))
     throw HpmgError(HPMG_E_UNSUPPORTED, "no kernel for this degree");
   HIPCHK(hipGetLastError());
+  // adaptive meshes: every traversal that writes traces is followed by the
+  // hanging-facet remap of the buffer it wrote
+  if (h->adapt && (op == hpmg::OP_SWEEP || op == hpmg::OP_PROJECT || op == hpmg::OP_PROLONG ||
+                   op == hpmg::OP_PROLONG_Q1 || op == hpmg::OP_PROLONG_DYN)) {
+    if constexpr (sizeof(T) >= 4) {
+      hpmg::remap_hanging<T>(h->dim, N, h->ncell, h->nif, h->mif, h->rfac, h->itab, a.mort, a.tr_out, a.tstride,
+                             nrhs, s);
+      HIPCHK(hipGetLastError());
+    } else {
+      throw HpmgError(HPMG_E_UNSUPPORTED, "adaptive meshes take FP64 or FP32 vectors");
+    }
+  }
 }
 
 

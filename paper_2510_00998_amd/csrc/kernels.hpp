@@ -53,6 +53,16 @@ template <typename T>
 void gather_corners(int D, int n, const T* contrib, T* bcg, hipStream_t s);
 template <typename T>
 void dense_solve(int m, const double* Ainv, const T* b, T* x, hipStream_t s);
+// Adaptive meshes: fill the hanging-facet slots of the trace buffer tr
+// (nrhs columns tstride apart) from the cells' own traces; itab [nif][2 + m]
+// = (coarse cell, its facet, the m = r^(d-1) fine cells), mort = [I_j | P_j]
+// for j < r (N x N each, adapt_kernels.hip).
+template <typename T>
+void remap_hanging(int D, int N, int ncell, int nif, int m, int r, const int* itab, const CT<T>* mort, T* tr,
+                   long long tstride, int nrhs, hipStream_t s);
+// y = W x for a CSR matrix W (the Q1 transfers of adaptive meshes)
+template <typename T>
+void csr_apply(int nrow, const int* ptr, const int* col, const T* w, const T* x, T* y, hipStream_t s);
 template <typename T>
 void fill(T* x, size_t n, T v, hipStream_t s);
 

@@ -1,0 +1,185 @@
+"""GPU parity on adaptive spacetree meshes with hanging facets (paper Section
+2.1; hpmg_setup_adaptive) against the oracle's assembled operator and
+hp-multigrid on the same leaves (oracle/adaptive.py), element by element,
+through the C ABI.  The meshes span several cell blocks with a ragged last
+block; subdivision factors 2 and 3, one and two refinement levels, 2D and
+3D.  Tolerances as for uniform meshes (FP64 summation order; FP32 inputs
+rounded to 2^-24 with about 10 u32 per traversal, the remap adding one
+contraction per hanging facet)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.adaptive import AdaptiveHierarchy, AdaptiveSIPG
+from oracle.mg import HierarchyOptions
+from tests.gpu_common import log, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL32 = 1e-5
+KAPPA = 2.5
+
+CASES = [
+    # dim, n, r, p, refinement, max level
+    (2, 4, 2, 1, "ball", 1),
+    (2, 4, 2, 3, "ball", 2),
+    (2, 3, 3, 2, "random", 1),
+    (2, 3, 2, 8, "random", 1),
+    (3, 3, 2, 2, "ball", 1),
+    (3, 2, 3, 1, "random", 1),
+    (3, 3, 2, 4, "random", 1),
+    (3, 2, 2, 3, "ball", 2),
+    (3, 2, 2, 5, "ball", 1),
+]
+
+
+def _leaves(dim, n, r, kind, lev, seed=3):
+    if kind == "ball":
+        ref = synth.ball_refinement([(0.3, 0.4, 0.45)], [0.2])
+    else:
+        ref = synth.random_refinement(seed, 0.35)
+    return synth.spacetree_leaves(dim, n, r, ref, lev)
+
+
+def _solver(dim, n, r, p, leaves, **opt):
+    import paper_2510_00998_amd as hp
+    return hp.Solver(dim, n, p, KAPPA, leaves=leaves, refine=r, **opt)
+
+
+def _has_hanging(leaves):
+    return len(np.unique(leaves[:, 0])) > 1
+
+
+@pytest.mark.parametrize("dim,n,r,p,kind,lev", CASES)
+def test_adaptive_apply_A(dim, n, r, p, kind, lev):
+    leaves = _leaves(dim, n, r, kind, lev)
+    assert _has_hanging(leaves)
+    log(f"adaptive apply dim={dim} n={n} r={r} p={p} {kind} lev={lev} leaves={len(leaves)}")
+    s = AdaptiveSIPG(dim, n, r, leaves, p, KAPPA)
+    u = synth.random_vector(s.ndof, seed=1000 + p)
+    g = _solver(dim, n, r, p, leaves)
+    assert g.ndof == s.ndof
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, TOL32)):
+        ud = to_dev(u, dt)
+        yd = torch.empty_like(ud)
+        g.apply_A(ud, yd)
+        ref = s.A @ (u if dt == torch.float64 else u.astype(np.float32).astype(np.float64))
+        err = rel_err(to_host(yd), ref)
+        log(f"  {dt}: rel err {err:.3e}")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("dim,n,r,p,kind,lev", CASES)
+def test_adaptive_smooth_and_vcycle(dim, n, r, p, kind, lev):
+    leaves = _leaves(dim, n, r, kind, lev)
+    log(f"adaptive smooth/vcycle dim={dim} n={n} r={r} p={p} {kind} lev={lev}")
+    H = AdaptiveHierarchy(dim, n, r, leaves, p, kappa=KAPPA)
+    nd = H.fine.ndof
+    u0 = synth.random_vector(nd, seed=7)
+    b = synth.random_rhs(nd, seed=8)
+    ref_s = H.smooth(0, u0.copy(), b, 3)
+    ref_v = H.vcycle(0, u0.copy(), b)
+    g = _solver(dim, n, r, p, leaves)
+    for dt, ts, tv in ((torch.float64, 1e-11, 1e-10), (torch.float32, TOL32, TOL32)):
+        ud, bd = to_dev(u0, dt), to_dev(b, dt)
+        g.smooth(ud, bd, 3)
+        es = rel_err(to_host(ud), ref_s)
+        ud = to_dev(u0, dt)
+        g.vcycle(ud, bd)
+        ev = rel_err(to_host(ud), ref_v)
+        log(f"  {dt}: smooth {es:.3e} vcycle {ev:.3e}")
+        assert es <= ts and ev <= tv
+
+
+@pytest.mark.parametrize("dim,n,r,p,kind,lev", [(2, 4, 2, 3, "ball", 2), (3, 3, 2, 4, "random", 1),
+                                                (3, 2, 3, 2, "ball", 1)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_adaptive_solve_reaches_tolerance(dim, n, r, p, kind, lev, prec):
+    leaves = _leaves(dim, n, r, kind, lev)
+    log(f"adaptive solve dim={dim} n={n} r={r} p={p} prec={prec}")
+    s = AdaptiveSIPG(dim, n, r, leaves, p, KAPPA)
+    b = synth.random_rhs(s.ndof, seed=33)
+    g = _solver(dim, n, r, p, leaves, precision=prec)
+    ud, bd = torch.zeros(s.ndof, dtype=torch.float64, device="cuda"), to_dev(b, torch.float64)
+    info, st = g.solve(ud, bd, rtol=1e-10, maxit=300)
+    rr = np.linalg.norm(b - s.A @ to_host(ud)) / np.linalg.norm(b)
+    log(f"  its {info.iterations} oracle residual {rr:.3e}")
+    assert st == 0 and rr <= 2e-10
+
+
+@pytest.mark.parametrize("dim,n,r,p", [(2, 4, 2, 2), (3, 3, 3, 2)])
+def test_adaptive_multiple_rhs_and_options(dim, n, r, p):
+    # two right-hand sides per call, one-step p-coarsening, Q1 V(1,1),
+    # Gauss-Legendre nodes: each against the oracle with the same options
+    leaves = _leaves(dim, n, r, "random", 1)
+    log(f"adaptive nrhs/options dim={dim} n={n} r={r} p={p}")
+    for opts, oopts in (({"p_coarsening": 1, "nu_pre_cg": 1, "nu_post_cg": 1},
+                         HierarchyOptions(p_coarsening="direct", nu_pre_cg=1, nu_post_cg=1)),
+                        ({"basis": 1}, HierarchyOptions(basis="gl"))):
+        H = AdaptiveHierarchy(dim, n, r, leaves, p, oopts, kappa=KAPPA)
+        nd = H.fine.ndof
+        u0 = np.concatenate([synth.random_vector(nd, seed=70), synth.random_vector(nd, seed=71)])
+        b = np.concatenate([synth.random_rhs(nd, seed=80), synth.random_rhs(nd, seed=81)])
+        g = _solver(dim, n, r, p, leaves, max_rhs=2, **opts)
+        ud, bd = to_dev(u0, torch.float64), to_dev(b, torch.float64)
+        g.vcycle(ud, bd, nrhs=2)
+        out = to_host(ud)
+        for c in range(2):
+            ref = H.vcycle(0, u0[c * nd:(c + 1) * nd].copy(), b[c * nd:(c + 1) * nd])
+            err = rel_err(out[c * nd:(c + 1) * nd], ref)
+            log(f"  {opts} column {c}: vcycle rel err {err:.3e}")
+            assert err <= 1e-10
+        ud = to_dev(u0, torch.float64)
+        yd = torch.empty_like(ud)
+        g.apply_A(ud, yd, nrhs=2)
+        y = to_host(yd)
+        for c in range(2):
+            assert rel_err(y[c * nd:(c + 1) * nd], H.levels[0].A @ u0[c * nd:(c + 1) * nd]) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,n,r,p", [(2, 4, 2, 3), (3, 3, 2, 2)])
+def test_adaptive_load_vector(dim, n, r, p):
+    import math
+    leaves = _leaves(dim, n, r, "ball", 1)
+    s = AdaptiveSIPG(dim, n, r, leaves, p)
+    g = _solver(dim, n, r, p, leaves)
+    bd = torch.empty(s.ndof, dtype=torch.float64, device="cuda")
+    g.load_vector(1, 1.0, bd)
+    ref = s.load_vector(lambda X: dim * math.pi ** 2 * np.prod(np.sin(math.pi * X), axis=1))
+    assert rel_err(to_host(bd), ref) <= 1e-13
+    g.load_vector(0, 2.0, bd)
+    assert rel_err(to_host(bd), s.load_vector(lambda X: np.full(len(X), 2.0))) <= 1e-13
+
+
+def test_adaptive_rejects_bad_meshes_and_options():
+    import paper_2510_00998_amd as hp
+    leaves = _leaves(2, 3, 2, "ball", 1)
+    with pytest.raises(hp.HpmgError):  # a leaf twice
+        _solver(2, 3, 2, 2, np.vstack([leaves, leaves[:1]]))
+    with pytest.raises(hp.HpmgError):  # a gap
+        _solver(2, 3, 2, 2, leaves[1:])
+    with pytest.raises(hp.HpmgError):  # a leaf inside another
+        _solver(2, 3, 2, 2, np.vstack([leaves, [[1, 0, 0]]]) if leaves[0, 0] == 0 else
+                np.vstack([leaves, [[2, 0, 0]]]))
+    # two levels across a facet: refine one child of a refined cell twice
+    bad = []
+    for row in synth.spacetree_leaves(2, 2, 2, lambda *a: False, 0):
+        if row[1] == 0 and row[2] == 0:
+            for m in range(4):
+                cx, cy = m % 2, m // 2
+                if m == 3:
+                    bad += [[2, 2 * cx + q % 2, 2 * cy + q // 2] for q in range(4)]
+                else:
+                    bad.append([1, cx, cy])
+        else:
+            bad.append(list(row))
+    with pytest.raises(hp.HpmgError):
+        _solver(2, 2, 2, 1, np.array(bad))
+    with pytest.raises(hp.HpmgError):
+        _solver(2, 3, 2, 2, leaves, precision=2)
+    g = _solver(2, 3, 2, 2, leaves)
+    u = torch.zeros(g.ndof, dtype=torch.float16, device="cuda")
+    with pytest.raises(hp.HpmgError):
+        g.smooth(u, u.clone(), 1)
