@@ -21,8 +21,9 @@ cycle and with the FP64 cycle.
 
 value = FP64 sweep DoF/s over all problems and right-hand sides.
 --config 2|3|5 measures the single-problem workloads (Q4 32^3, Q3 64^3 with
-log-uniform kappa, Q5 96^3 with log-normal kappa); --paper-tables the paper's
-2D cycle-count study.  Prints one JSON line (the library runs on one GPU).
+log-uniform kappa, Q5 96^3 with log-normal kappa); --config 6 the adaptive
+spacetree workload (Q4 on 16^3 base cells refined twice by 2 around two
+balls, 33,734 leaves); --paper-tables the paper's 2D cycle-count study.  Prints one JSON line (the library runs on one GPU).
 """
 from __future__ import annotations
 
@@ -135,9 +136,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=20, help="fused sweeps per precision per step")
-    ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4, 5],
+    ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4, 5, 6],
                     help="4: 64 problems x 4 RHS batched (default, largest workload); 2: Q4 32^3 kappa=1; "
-                         "3: Q3 64^3 log-uniform kappa; 5: Q5 96^3 log-normal kappa")
+                         "3: Q3 64^3 log-uniform kappa; 5: Q5 96^3 log-normal kappa; 6: Q4 adaptive spacetree "
+                         "(16^3 base cells, two levels of refinement by 2 around two balls)")
     ap.add_argument("--paper-tables", action="store_true",
                     help="paper-mode cycle counts: 2D, one-step DG_p -> Q1, factor-3 h-coarsening, MGMult to 1e-7")
     ap.add_argument("--profile-sweeps", action="store_true",
@@ -739,6 +741,155 @@ def run_single(args):
     print(json.dumps(line), flush=True)
 
 
+ADAPTIVE_BALLS = ([(0.3, 0.4, 0.5), (0.75, 0.6, 0.5)], [0.25, 0.15])
+
+
+def adaptive_leaves(n, r=2, max_level=2):
+    """Leaves of the adaptive workload: base n^3, cells meeting two balls
+    refined by r up to max_level, facet-balanced (synth)."""
+    import synth
+    return synth.spacetree_leaves(3, n, r, synth.ball_refinement(*ADAPTIVE_BALLS), max_level)
+
+
+def _adaptive_oracle_baseline(seconds):
+    """The oracle on a bounded sample of the adaptive workload: the same
+    refinement pattern on 3^3 base cells, assembled SIPG block-Jacobi sweeps
+    (dense Cholesky blocks) for about `seconds` on one core, one BLAS thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle.adaptive import AdaptiveHierarchy
+
+    leaves = adaptive_leaves(3)
+    with threadpool_limits(limits=1):
+        H = AdaptiveHierarchy(3, 3, 2, leaves, 4)
+        nd = H.fine.ndof
+        b = synth.random_rhs(nd, seed=6)
+        u = np.zeros_like(b)
+        sweeps, t = 0, 0.0
+        t0 = time.perf_counter()
+        while t < seconds or sweeps < 2:
+            u = H.smooth(0, u, b, 1)
+            sweeps += 1
+            t = time.perf_counter() - t0
+    return {"value": nd * sweeps / t, "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"same refinement on 3^3 base cells ({len(leaves)} leaves, {nd} DoFs), {sweeps} assembled "
+                      f"block-Jacobi sweeps in {t:.1f} s"}
+
+
+def run_adaptive(args):
+    import torch
+
+    import paper_2510_00998_amd as hp
+    from paper_2510_00998_amd import traffic
+
+    n, r, p, dim = 16, 2, 4, 3
+    cpu = None if args.no_cpu_baseline else _adaptive_oracle_baseline(args.cpu_seconds)
+    leaves = adaptive_leaves(n, r)
+    counts = traffic.adaptive_facet_counts(dim, n, r, leaves)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    t_setup = time.perf_counter()
+    g64 = hp.Solver(dim, n, p, 1.0, leaves=leaves, refine=r, precision=hp.PREC_F64)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    gmx = hp.Solver(dim, n, p, 1.0, leaves=leaves, refine=r, precision=hp.PREC_F32)
+    nd = g64.ndof
+    b64 = torch.empty(nd, dtype=torch.float64, device=dev)
+    g64.load_vector(1, 1.0, b64)
+    sweep_in = {name: (torch.zeros(nd, dtype=dt, device=dev), b64.to(dt),
+                       [torch.cuda.Event(enable_timing=True) for _ in range(2)])
+                for name, dt in (("f64", torch.float64), ("f32", torch.float32))}
+    u = torch.zeros(nd, dtype=torch.float64, device=dev)
+    S = args.sweeps
+    solves = {"fp64": g64, "mixed_f32": gmx}
+
+    def sweeps_timed():
+        for uu, bb, evs in sweep_in.values():
+            g64.project(uu)
+            evs[0].record(stream)
+            g64.sweep(uu, bb, S)
+            evs[1].record(stream)
+        torch.cuda.synchronize()
+        return {name: evs[0].elapsed_time(evs[1]) * 1e-3 / S for name, (_, _, evs) in sweep_in.items()}
+
+    if args.profile_sweeps:
+        t = sweeps_timed()
+        if args.copy_calibration:
+            copy_calibration(torch, dev)
+        print(json.dumps({"profile_sweeps": S, "mean_sweep_s": t}), flush=True)
+        return
+
+    def step():
+        out = sweeps_timed()
+        for name, g in solves.items():
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info, st = g.solve(u, b64, rtol=1e-10, maxit=300, check=False)
+            torch.cuda.synchronize()
+            out[name] = (time.perf_counter() - t0, info.iterations, st,
+                         info.final_residual / max(info.initial_residual, 1e-300))
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    T0 = time.perf_counter()
+    res = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    T = time.perf_counter() - T0
+    tsw = {name: _median([rr[name] for rr in res]) for name in sweep_in}
+    isz = {"f64": 8, "f32": 4}
+    bysw = {name: traffic.adaptive_sweep_bytes(dim, n, r, leaves, p, isz[name], counts) for name in sweep_in}
+    conv = {k: all(rr[k][2] == 0 for rr in res) for k in solves}
+    tt = {k: (_median([rr[k][0] for rr in res]) if conv[k] else None) for k in solves}
+    srcs = ["dg_kernels_impl.hpp", "adapt_kernels.hip"]
+    tsum = "adaptive_q4_16cube_hbm_traffic.md"
+    ach = {name: bysw[name] / tsw[name] / 1e9 for name in sweep_in}
+    levels = {int(l): int(c) for l, c in zip(*__import__("numpy").unique(leaves[:, 0], return_counts=True))}
+    line = {
+        "metric": METRIC,
+        "value": nd / tsw["f64"],
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D SIPG Q{p} on an adaptive spacetree: {n}^3 base cells, cells meeting balls "
+                               f"{ADAPTIVE_BALLS[0]} radii {ADAPTIVE_BALLS[1]} refined by {r} up to level 2, "
+                               f"facet-balanced: {len(leaves)} leaves {levels}, {nd} DoFs, "
+                               f"{counts['interfaces']} hanging facets; u=prod sin(pi x_i); fused sweep + "
+                               "hanging-facet remap, hp V(2,2) (p halved, then Q1 on the base mesh), FCG to 1e-10",
+                   "dim": dim, "n_base": n, "refine": r, "p": p, "nleaf": len(leaves), "ndof": nd,
+                   "hanging_facets": counts["interfaces"], "sweeps_per_step": S},
+        "roofline": {"bound": "hbm", "achieved": ach["f64"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach["f64"] / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(tsum, srcs, "traffic_bytes_per_launch_f64"),
+                     "kernel": f"k_sweep<double,3,{p + 1},false,false,false,false,true> + k_remap<double> "
+                               "(fused sweep and hanging-facet remap, FP64)",
+                     "algorithmic_bytes_per_launch": bysw["f64"], "mean_launch_s": tsw["f64"]},
+        "sweep_dofs_per_s": {name: nd / t for name, t in tsw.items()},
+        "sweep_roofline": {name: {"achieved": ach[name], "frac": ach[name] / HBM_PEAK_GBS,
+                                  "algorithmic_bytes_per_launch": bysw[name], "mean_launch_s": tsw[name],
+                                  "traffic": counter_traffic(tsum, srcs, f"traffic_bytes_per_launch_{name}")}
+                           for name in sweep_in},
+        "time_to_1e-10_s": tt,
+        "solver_iterations": {k: res[-1][k][1] for k in solves},
+        "converged_by_solver": conv,
+        "final_rel_residual_by_solver": {k: res[-1][k][3] for k in solves},
+        "setup_s": t_setup,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -749,6 +900,8 @@ def main():
         run_paper_tables(args)
     elif args.config == 4:
         run_batched(args)
+    elif args.config == 6:
+        run_adaptive(args)
     else:
         run_single(args)
 

@@ -168,8 +168,57 @@ class AdaptiveSIPG:
             self._A = self._assemble()
         return self._A
 
+    def _volume_block(self, K):
+        """kappa_K int grad phi_j . grad phi_i over leaf K, Gauss (p+1)^d."""
+        d, N = self.dim, self.N
+        xq, wq = gauss_rule(N)
+        Q = np.stack([xq[(np.arange(N ** d) // N ** k) % N] for k in range(d)], axis=1)
+        Wq = np.ones(N ** d)
+        for k in range(d):
+            Wq *= wq[(np.arange(N ** d) // N ** k) % N]
+        X = self.origin[K][None, :] + Q * self.h[K]
+        _, G = self.eval_basis(K, X)
+        w = Wq * self.h[K] ** d
+        return self.kappa[K] * sum((G[:, :, k] * w[:, None]).T @ G[:, :, k] for k in range(d))
+
+    def _piece_blocks(self, piece):
+        """Blocks of one skeleton piece: [(row cell, column cell, block)]."""
+        d, N = self.dim, self.N
+        Km, Kp, k, side, hF, corner = piece
+        xq1, wq1 = gauss_rule(N)
+        Qf = np.stack([xq1[(np.arange(N ** (d - 1)) // N ** j) % N] for j in range(d - 1)], axis=1)
+        Wf = np.ones(N ** (d - 1))
+        for j in range(d - 1):
+            Wf *= wq1[(np.arange(N ** (d - 1)) // N ** j) % N]
+        pen = self.sigma0 * (self.p_penalty + 1) ** 2
+        tang = [t for t in range(d) if t != k]
+        X = np.repeat(corner[None, :], len(Wf), axis=0)
+        for j, t in enumerate(tang):
+            X[:, t] += Qf[:, j] * hF
+        w = Wf * hF ** (d - 1)
+        Vm, Gm = self.eval_basis(Km, X)
+        if side != 0:
+            # boundary facet: outward normal side * e_k
+            Dn = side * Gm[:, :, k]
+            sig = 2.0 * pen / self.h[Km]
+            WV = Vm * w[:, None]
+            return [(Km, Km, self.kappa[Km] * (-WV.T @ Dn - (Dn * w[:, None]).T @ Vm + sig * WV.T @ Vm))]
+        Vp, Gp = self.eval_basis(Kp, X)
+        Dm, Dp = Gm[:, :, k], Gp[:, :, k]  # derivative along n_F = +e_k
+        kF = 2.0 * self.kappa[Km] * self.kappa[Kp] / (self.kappa[Km] + self.kappa[Kp])
+        sig = pen / min(self.h[Km], self.h[Kp])
+
+        def m(a, b):  # int a_i b_j over the piece
+            return (a * w[:, None]).T @ b
+
+        # a(phi_j, phi_i) with [v] = v- - v+, {dn v} = (dn v- + dn v+)/2
+        return [(Km, Km, kF * (-0.5 * m(Vm, Dm) - 0.5 * m(Dm, Vm) + sig * m(Vm, Vm))),
+                (Km, Kp, kF * (-0.5 * m(Vm, Dp) + 0.5 * m(Dm, Vp) - sig * m(Vm, Vp))),
+                (Kp, Km, kF * (0.5 * m(Vp, Dm) - 0.5 * m(Dp, Vm) - sig * m(Vp, Vm))),
+                (Kp, Kp, kF * (0.5 * m(Vp, Dp) + 0.5 * m(Dp, Vp) + sig * m(Vp, Vp)))]
+
     def _assemble(self):
-        d, nd, N = self.dim, self.nd, self.N
+        nd = self.nd
         rows, cols, vals = [], [], []
 
         def add(I, J, B):
@@ -178,58 +227,29 @@ class AdaptiveSIPG:
             cols.append(jj.ravel())
             vals.append(B.ravel())
 
-        # volume terms: kappa_K int grad phi_j . grad phi_i, Gauss (p+1)^d
-        xq, wq = gauss_rule(N)
-        Q = np.stack([xq[(np.arange(N ** d) // N ** k) % N] for k in range(d)], axis=1)
-        Wq = np.ones(N ** d)
-        for k in range(d):
-            Wq *= wq[(np.arange(N ** d) // N ** k) % N]
         for K in range(self.ncell):
-            X = self.origin[K][None, :] + Q * self.h[K]
-            _, G = self.eval_basis(K, X)
-            w = Wq * self.h[K] ** d
-            B = np.einsum("q,qik,qjk->ij", w, G, G)
-            add(K, K, self.kappa[K] * B)
-        # facet pieces
-        xq1, wq1 = gauss_rule(N)
-        Qf = np.stack([xq1[(np.arange(N ** (d - 1)) // N ** j) % N] for j in range(d - 1)], axis=1)
-        Wf = np.ones(N ** (d - 1))
-        for j in range(d - 1):
-            Wf *= wq1[(np.arange(N ** (d - 1)) // N ** j) % N]
-        pen = self.sigma0 * (self.p_penalty + 1) ** 2
-        for (Km, Kp, k, side, hF, corner) in self.pieces:
-            tang = [t for t in range(d) if t != k]
-            X = np.repeat(corner[None, :], len(Wf), axis=0)
-            for j, t in enumerate(tang):
-                X[:, t] += Qf[:, j] * hF
-            w = Wf * hF ** (d - 1)
-            Vm, Gm = self.eval_basis(Km, X)
-            if side != 0:
-                # boundary facet: outward normal side * e_k
-                Dn = side * Gm[:, :, k]
-                kK = self.kappa[Km]
-                sig = 2.0 * pen / self.h[Km]
-                B = kK * (-np.einsum("q,qi,qj->ij", w, Vm, Dn) - np.einsum("q,qi,qj->ij", w, Dn, Vm)
-                          + sig * np.einsum("q,qi,qj->ij", w, Vm, Vm))
-                add(Km, Km, B)
-                continue
-            Vp, Gp = self.eval_basis(Kp, X)
-            Dm, Dp = Gm[:, :, k], Gp[:, :, k]  # derivative along n_F = +e_k
-            kF = 2.0 * self.kappa[Km] * self.kappa[Kp] / (self.kappa[Km] + self.kappa[Kp])
-            sig = pen / min(self.h[Km], self.h[Kp])
-
-            def m(a, b):
-                return np.einsum("q,qi,qj->ij", w, a, b)
-
-            # a(phi_j, phi_i) with [v] = v- - v+, {dn v} = (dn v- + dn v+)/2
-            add(Km, Km, kF * (-0.5 * m(Vm, Dm) - 0.5 * m(Dm, Vm) + sig * m(Vm, Vm)))
-            add(Km, Kp, kF * (-0.5 * m(Vm, Dp) + 0.5 * m(Dm, Vp) - sig * m(Vm, Vp)))
-            add(Kp, Km, kF * (0.5 * m(Vp, Dm) - 0.5 * m(Dp, Vm) - sig * m(Vp, Vm)))
-            add(Kp, Kp, kF * (0.5 * m(Vp, Dp) + 0.5 * m(Dp, Vp) + sig * m(Vp, Vp)))
+            add(K, K, self._volume_block(K))
+        for piece in self.pieces:
+            for I, J, B in self._piece_blocks(piece):
+                add(I, J, B)
         rows = np.concatenate(rows)
         cols = np.concatenate(cols)
         vals = np.concatenate(vals)
         return sp.csr_matrix((vals, (rows, cols)), shape=(self.ndof, self.ndof))
+
+    def row_blocks(self, cells):
+        """The rows of A belonging to the given leaves, assembled from the
+        same volume and piece blocks without the rest of the matrix: a dict
+        cell -> {column cell: block} (for sampled checks on large meshes)."""
+        want = set(int(c) for c in cells)
+        out = {c: {c: self._volume_block(c)} for c in want}
+        for piece in self.pieces:
+            if piece[0] not in want and piece[1] not in want:
+                continue
+            for I, J, B in self._piece_blocks(piece):
+                if I in want:
+                    out[I][J] = out[I].get(J, 0.0) + B
+        return out
 
     def load_vector(self, f, nq=None):
         """b_i = int f phi_i, (p+3)-point Gauss per direction on every leaf."""

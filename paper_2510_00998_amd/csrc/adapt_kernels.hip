@@ -19,7 +19,9 @@
 // integrates over its own facet, where B's trace is a polynomial of its
 // degree; B integrates over its whole facet against its own test functions
 // (degree p on the facet), for which the projection changes no integral.
-// So the sweep and apply kernels treat every facet as conforming.
+// So the sweep and apply kernels treat every facet as conforming.  The remap
+// moves (m + 1) 2 (p+1)^(d-1) values in and out per interface, a few per cent
+// of a sweep's bytes when hanging facets are a small part of the skeleton.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -27,77 +29,101 @@
 namespace hpmg {
 namespace {
 
-template <typename T>
-__global__ void k_remap(T* tr, long long tstride, const int* itab, int nif, int m, int r, int ncell, int D, int N,
-                        const CT<T>* mort) {
+// One workgroup per interface: the m + 1 source traces (the fine cells' own
+// slots, then the coarse cell's) and the tables are staged in LDS with
+// coalesced loads; the tensor-product maps run as two 1D contractions
+// (3D: along the first tangential axis into LDS, then along the second).
+constexpr int REMAP_THREADS = 256;
+template <int D, int N>
+constexpr int remap_lds_values(int r) {
+  // sources (m+1) 2L, first-stage results (r + m) 2 N^2 (3D), tables 2 r N^2
+  return (D == 2 ? (r + 1) * 2 * N : (r * r + 1) * 2 * N * N + (r + r * r) * 2 * N * N) + 2 * r * N * N;
+}
+template <typename T, int D, int N>
+__global__ __launch_bounds__(REMAP_THREADS) void k_remap(T* tr, long long tstride, const int* itab, int m, int r,
+                                                         int ncell, const CT<T>* mort) {
   using C = CT<T>;
-  const int L = D == 2 ? N : N * N;
-  const int TL = 2 * L;
-  const long long items = (long long)nif * (m + 1) * L;
+  constexpr int L = D == 2 ? N : N * N;
+  constexpr int TL = 2 * L;
+  constexpr int NN = N * N;
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  C* sSrc = (C*)lds_raw;                   // [m + 1][2L]: fine cells 0..m-1, coarse cell m
+  C* sMat = sSrc + (m + 1) * TL;           // [I_0 .. I_{r-1} | P_0 .. P_{r-1}]
+  C* sTmp = sMat + 2 * r * NN;             // 3D: [r + m][2][N][N]
   T* t = tr + (size_t)blockIdx.y * tstride;
-  const size_t base0 = (size_t)2 * D * ncell;
-  const C* Ir = mort;                      // [r][N][N]
-  const C* Pj = mort + (size_t)r * N * N;  // [r][N][N]
+  const int i = blockIdx.x;
+  const int* row = itab + (size_t)i * (2 + m);
+  const int B = row[0], fB = row[1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < (m + 1) * TL; e += REMAP_THREADS) {
+    const int j = e / TL, o = e % TL;
+    const size_t slot = j < m ? (size_t)(fB ^ 1) * ncell + row[2 + j] : (size_t)fB * ncell + B;
+    sSrc[e] = (C)t[slot * TL + o];
+  }
+  for (int e = tid; e < 2 * r * NN; e += REMAP_THREADS) sMat[e] = mort[e];
+  __syncthreads();
+  const C* sI = sMat;
+  const C* sP = sMat + r * NN;
   const C qf = C(1) / C(r);
-  for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (long long)gridDim.x * blockDim.x) {
-    const int l = (int)(it % L);
-    const int j = (int)((it / L) % (m + 1));
-    const long long i = it / ((long long)L * (m + 1));
-    const int* row = itab + (size_t)i * (2 + m);
-    const int B = row[0], fB = row[1];
-    const int a = l % N, b = l / N;  // b = 0 in 2D
-    C g = 0, q = 0;
-    if (j < m) {
-      const int sa = j % r, sb = j / r;
-      const T* src = t + ((size_t)fB * ncell + B) * TL;
-      const C* Ia = Ir + ((size_t)sa * N + a) * N;
-      if (D == 2) {
-        for (int x = 0; x < N; ++x) {
-          g += Ia[x] * (C)src[x];
-          q += Ia[x] * (C)src[L + x];
-        }
+  const size_t base = (size_t)2 * D * ncell + (size_t)i * (m + 1);
+  if constexpr (D == 2) {
+    // fine slot j: I_j g_B; coarse slot: sum_j P_j g_j
+    for (int e = tid; e < (m + 1) * TL; e += REMAP_THREADS) {
+      const int j = e / TL, o = e % TL, f = o / L, a = o % L;
+      C acc = 0;
+      if (j < m) {
+        const C* src = sSrc + m * TL + f * L;
+#pragma unroll
+        for (int x = 0; x < N; ++x) acc += sI[(j * N + a) * N + x] * src[x];
+        if (f) acc *= qf;
       } else {
-        const C* Ib = Ir + ((size_t)sb * N + b) * N;
-        for (int y = 0; y < N; ++y) {
-          C gy = 0, qy = 0;
-          for (int x = 0; x < N; ++x) {
-            gy += Ia[x] * (C)src[x + N * y];
-            qy += Ia[x] * (C)src[L + x + N * y];
-          }
-          g += Ib[y] * gy;
-          q += Ib[y] * qy;
+        for (int s = 0; s < m; ++s) {
+          const C* src = sSrc + s * TL + f * L;
+#pragma unroll
+          for (int x = 0; x < N; ++x) acc += sP[(s * N + a) * N + x] * src[x];
         }
+        if (f) acc *= C(r);
       }
-      q *= qf;
-    } else {
-      for (int s = 0; s < m; ++s) {
-        const int sa = s % r, sb = s / r;
-        const T* src = t + ((size_t)(fB ^ 1) * ncell + row[2 + s]) * TL;
-        const C* Pa = Pj + ((size_t)sa * N + a) * N;
-        if (D == 2) {
-          for (int x = 0; x < N; ++x) {
-            g += Pa[x] * (C)src[x];
-            q += Pa[x] * (C)src[L + x];
-          }
-        } else {
-          const C* Pb = Pj + ((size_t)sb * N + b) * N;
-          for (int y = 0; y < N; ++y) {
-            C gy = 0, qy = 0;
-            for (int x = 0; x < N; ++x) {
-              gy += Pa[x] * (C)src[x + N * y];
-              qy += Pa[x] * (C)src[L + x + N * y];
-            }
-            g += Pb[y] * gy;
-            q += Pb[y] * qy;
-          }
-        }
-      }
-      q *= C(r);
+      t[(base + j) * TL + o] = (T)acc;
     }
-    T* dst = t + (base0 + (size_t)i * (m + 1) + j) * TL;
-    dst[l] = (T)g;
-    dst[L + l] = (T)q;
+  } else {
+    // first tangential axis: tmp[q][f][a][y] = sum_x M[a][x] src[f][x + N y]
+    // with (q < r) M = I_q on the coarse trace, (q = r + s) M = P_{s mod r}
+    // on fine trace s
+    const int nq = r + m;
+    for (int e = tid; e < nq * 2 * NN; e += REMAP_THREADS) {
+      const int q = e / (2 * NN), rem = e % (2 * NN), f = rem / NN, ay = rem % NN, a = ay % N, y = ay / N;
+      const C* M = q < r ? sI + (q * N + a) * N : sP + (((q - r) % r) * N + a) * N;
+      const C* src = sSrc + (q < r ? m : q - r) * TL + f * L + N * y;
+      C acc = 0;
+#pragma unroll
+      for (int x = 0; x < N; ++x) acc += M[x] * src[x];
+      sTmp[e] = acc;
+    }
+    __syncthreads();
+    // second axis: fine slot j = (sa, sb): sum_y I_sb[b][y] tmp[sa][f][a][y];
+    // coarse slot: sum_s sum_y P_{sb(s)}[b][y] tmp[r + s][f][a][y]
+    for (int e = tid; e < (m + 1) * TL; e += REMAP_THREADS) {
+      const int j = e / TL, o = e % TL, f = o / L, l = o % L, a = l % N, b = l / N;
+      C acc = 0;
+      if (j < m) {
+        const int sa = j % r, sb = j / r;
+        const C* M = sI + (sb * N + b) * N;
+        const C* tmp = sTmp + (sa * 2 + f) * NN + a;
+#pragma unroll
+        for (int y = 0; y < N; ++y) acc += M[y] * tmp[N * y];
+        if (f) acc *= qf;
+      } else {
+        for (int s = 0; s < m; ++s) {
+          const C* M = sP + ((s / r) * N + b) * N;
+          const C* tmp = sTmp + ((r + s) * 2 + f) * NN + a;
+#pragma unroll
+          for (int y = 0; y < N; ++y) acc += M[y] * tmp[N * y];
+        }
+        if (f) acc *= C(r);
+      }
+      t[(base + j) * TL + o] = (T)acc;
+    }
   }
 }
 
@@ -113,15 +139,27 @@ __global__ void k_csr(int nrow, const int* ptr, const int* col, const T* w, cons
 
 }  // namespace
 
+template <typename T, int D, int N>
+void remap_launch(int ncell, int nif, int m, int r, const int* itab, const CT<T>* mort, T* tr, long long tstride,
+                  int nrhs, hipStream_t s) {
+  const size_t lds = sizeof(CT<T>) * (size_t)remap_lds_values<D, N>(r);
+  hipLaunchKernelGGL((k_remap<T, D, N>), dim3(nif, nrhs), dim3(REMAP_THREADS), lds, s, tr, tstride, itab, m, r,
+                     ncell, mort);
+}
+
 template <typename T>
 void remap_hanging(int D, int N, int ncell, int nif, int m, int r, const int* itab, const CT<T>* mort, T* tr,
                    long long tstride, int nrhs, hipStream_t s) {
   if (nif == 0) return;
-  const int L = D == 2 ? N : N * N;
-  const long long items = (long long)nif * (m + 1) * L;
-  const int blocks = (int)std::min<long long>((items + 255) / 256, 4096);
-  hipLaunchKernelGGL((k_remap<T>), dim3(blocks, nrhs), dim3(256), 0, s, tr, tstride, itab, nif, m, r, ncell, D,
-                     N, mort);
+  using F = void (*)(int, int, int, int, const int*, const CT<T>*, T*, long long, int, hipStream_t);
+  static const F tab2[10] = {nullptr, nullptr, remap_launch<T, 2, 2>, remap_launch<T, 2, 3>, remap_launch<T, 2, 4>,
+                             remap_launch<T, 2, 5>, remap_launch<T, 2, 6>, remap_launch<T, 2, 7>,
+                             remap_launch<T, 2, 8>, remap_launch<T, 2, 9>};
+  static const F tab3[10] = {nullptr, nullptr, remap_launch<T, 3, 2>, remap_launch<T, 3, 3>, remap_launch<T, 3, 4>,
+                             remap_launch<T, 3, 5>, remap_launch<T, 3, 6>, remap_launch<T, 3, 7>,
+                             remap_launch<T, 3, 8>, remap_launch<T, 3, 9>};
+  if (N < 2 || N > 9) return;
+  (D == 2 ? tab2 : tab3)[N](ncell, nif, m, r, itab, mort, tr, tstride, nrhs, s);
 }
 template void remap_hanging<double>(int, int, int, int, int, int, const int*, const double*, double*, long long, int,
                                     hipStream_t);

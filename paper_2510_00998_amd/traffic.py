@@ -173,3 +173,48 @@ def fcg_iteration_bytes(d: int, n: int, p: int, cycle_itemsize: int, nu_pre: int
     b += (2 * nd + tw) * 8                   # q = A p
     b += nd * 32 + nd * 24 + nd * min(zs, 4)  # update of u, r
     return b
+
+
+def adaptive_facet_counts(d: int, n: int, r: int, leaves) -> dict:
+    """Facet bookkeeping of a spacetree leaf list (rows (level, x_0, ..)):
+    cell-facet sides on the boundary, hanging interfaces (a coarse leaf's
+    facet whose neighbour region is refined) and r^(d-1) cells per
+    interface."""
+    index = {tuple(int(v) for v in row) for row in leaves}
+    bdy = 0
+    nif = 0
+    for row in leaves:
+        lvl, x = int(row[0]), [int(v) for v in row[1:]]
+        ext = n * r ** lvl
+        for k in range(d):
+            for s in (-1, 1):
+                y = list(x)
+                y[k] += s
+                if not 0 <= y[k] < ext:
+                    bdy += 1
+                    continue
+                if (lvl, *y) in index:
+                    continue
+                if lvl > 0 and (lvl - 1, *[v // r for v in y]) in index:
+                    continue
+                nif += 1
+    return {"boundary_sides": bdy, "interfaces": nif, "cells_per_interface": r ** (d - 1)}
+
+
+def adaptive_sweep_bytes(d: int, n: int, r: int, leaves, p: int, itemsize: int, counts: dict | None = None) -> int:
+    """Algorithmic bytes of one fused sweep on an adaptive mesh (the sweep
+    launch and the hanging-facet remap after it): 3 cell vectors; per
+    non-boundary cell-facet side the neighbour-side traces read and the own
+    traces written (2 fields x (p+1)^(d-1) values each); per hanging
+    interface its m + 1 own-trace slots read and its m + 1 remap slots
+    written (m = r^(d-1)); per cell the 2d neighbour-slot indices (4 bytes),
+    the facet mask (2 bytes) and in 3D the h scale (one compute-type value)."""
+    N = p + 1
+    L = N ** (d - 1)
+    c = counts or adaptive_facet_counts(d, n, r, leaves)
+    ncell = len(leaves)
+    sides = 2 * d * ncell - c["boundary_sides"]
+    m = c["cells_per_interface"]
+    words = 3 * ncell * N ** d + sides * 2 * L * 2 + c["interfaces"] * (m + 1) * 2 * L * 2
+    meta = ncell * (4 * 2 * d + 2 + (itemsize if d == 3 else 0))
+    return words * itemsize + meta

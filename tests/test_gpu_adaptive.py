@@ -183,3 +183,78 @@ def test_adaptive_rejects_bad_meshes_and_options():
     u = torch.zeros(g.ndof, dtype=torch.float16, device="cuda")
     with pytest.raises(hp.HpmgError):
         g.smooth(u, u.clone(), 1)
+
+
+def test_adaptive_full_size_sampled_cells():
+    # Q4 on the adaptive benchmark mesh (16^3 base cells, two levels of
+    # refinement by 2 around two balls, 33,734 leaves, 4.2M DoFs) in the
+    # launch configuration the benchmark times: apply and one sweep in FP64
+    # and FP32, checked on sampled cells (hanging facets on either side,
+    # boundary cells, random cells) against rows the oracle assembles one by one
+    n, r, p = 16, 2, 4
+    leaves = synth.spacetree_leaves(3, n, r, synth.ball_refinement([(0.3, 0.4, 0.5), (0.75, 0.6, 0.5)],
+                                                                   [0.25, 0.15]), 2)
+    log(f"adaptive full size: {len(leaves)} leaves")
+    s = AdaptiveSIPG(3, n, r, leaves, p, KAPPA)
+    nd, N3 = s.ndof, s.nd
+    u0 = synth.random_vector(nd, seed=91)
+    b = synth.random_rhs(nd, seed=92)
+    hang = sorted({c for a, bb, _, side, hF, _ in s.pieces if side == 0 and s.h[a] != s.h[bb] for c in (a, bb)})
+    bdy = sorted({a for a, _, _, side, _, _ in s.pieces if side != 0})
+    rng = np.random.default_rng(5)
+    sample = sorted(set(rng.choice(hang, 16, replace=False)) | set(rng.choice(bdy, 8, replace=False))
+                    | set(rng.choice(len(leaves), 16, replace=False)) | {0, len(leaves) - 1})
+    rows = s.row_blocks(sample)
+    g = _solver(3, n, r, p, leaves)
+    omega = g.options.omega_dg
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, TOL32)):
+        uin = u0 if dt == torch.float64 else u0.astype(np.float32).astype(np.float64)
+        bin_ = b if dt == torch.float64 else b.astype(np.float32).astype(np.float64)
+        ud = to_dev(u0, dt)
+        yd = torch.empty_like(ud)
+        g.apply_A(ud, yd)
+        y = to_host(yd)
+        g.smooth(ud, to_dev(b, dt), 1)
+        u1 = to_host(ud)
+        yref = {K: sum(B @ uin[J * N3:(J + 1) * N3] for J, B in rows[K].items()) for K in sample}
+        scale = max(np.abs(v).max() for v in yref.values())
+        ey = max(np.abs(y[K * N3:(K + 1) * N3] - yref[K]).max() for K in sample) / scale
+        u1ref = {K: uin[K * N3:(K + 1) * N3] + omega * np.linalg.solve(rows[K][K], bin_[K * N3:(K + 1) * N3] - yref[K])
+                 for K in sample}
+        su = max(np.abs(v).max() for v in u1ref.values())
+        es = max(np.abs(u1[K * N3:(K + 1) * N3] - u1ref[K]).max() for K in sample) / su
+        log(f"  {dt}: apply {ey:.3e} sweep {es:.3e} on {len(sample)} cells")
+        assert ey <= tol and es <= (1e-11 if dt == torch.float64 else tol)
+
+
+def test_adaptive_solution_has_the_discretisation_error():
+    # u = sin(pi x) sin(pi y) on adaptive meshes (base 8, 16, 32; one level of
+    # refinement by 2 around a ball), Q3: the GPU solution to 1e-10 has the
+    # L2 error of the exact discrete solution (oracle direct solve on the two
+    # smaller meshes) and the rate p + 1
+    import math
+
+    import scipy.sparse.linalg as spla
+
+    import paper_2510_00998_amd as hp
+    p = 3
+    errs = []
+    for n in (8, 16, 32):
+        leaves = synth.spacetree_leaves(2, n, 2, synth.ball_refinement([(0.3, 0.4)], [0.2]), 1)
+        s = AdaptiveSIPG(2, n, 2, leaves, p)
+        g = hp.Solver(2, n, p, 1.0, leaves=leaves, refine=2)
+        bd = torch.empty(s.ndof, dtype=torch.float64, device="cuda")
+        g.load_vector(1, 1.0, bd)
+        ud = torch.zeros_like(bd)
+        info, st = g.solve(ud, bd, rtol=1e-10, maxit=300)
+        assert st == 0
+        uex = lambda X: np.sin(math.pi * X[:, 0]) * np.sin(math.pi * X[:, 1])  # noqa: E731
+        e = s.l2_error(to_host(ud), uex)
+        if n < 32:
+            ed = s.l2_error(spla.spsolve(s.A.tocsc(), to_host(bd)), uex)
+            log(f"  n={n}: GPU L2 error {e:.4e}, direct {ed:.4e}, {info.iterations} its")
+            assert abs(e - ed) <= 1e-3 * ed
+        errs.append(e)
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    log(f"  rates {rates}")
+    assert np.all(np.abs(rates - (p + 1)) < 0.3)

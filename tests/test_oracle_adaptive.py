@@ -184,3 +184,17 @@ def test_rejects_unbalanced_and_overlapping_leaves():
             raw.append(list(row))
     with pytest.raises(ValueError):
         AdaptiveSIPG(2, 2, 2, np.array(raw), 1)
+
+
+def test_row_blocks_equal_the_assembled_rows():
+    leaves = _mesh(3, 2, 2, "random")
+    s = AdaptiveSIPG(3, 2, 2, leaves, 2, kappa=1.7)
+    A = s.A.toarray()
+    cells = [0, 5, len(leaves) - 1]
+    rb = s.row_blocks(cells)
+    nd = s.nd
+    for K in cells:
+        row = np.zeros((nd, s.ndof))
+        for J, B in rb[K].items():
+            row[:, J * nd:(J + 1) * nd] = B
+        assert np.abs(row - A[K * nd:(K + 1) * nd]).max() <= 1e-13 * np.abs(A).max()
