@@ -695,7 +695,7 @@ def run_single(args):
         "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach64 / HBM_PEAK_GBS,
                      "traffic": counter_traffic(tsum, srcs, "traffic_bytes_per_launch_f64"),
-                     "kernel": f"k_sweep<double,3,{p + 1},false,{str(vark).lower()}> (fused sweep, FP64)",
+                     "kernel": f"k_sweep<double,3,{p + 1},false,{str(vark).lower()},false,false,false> (fused sweep, FP64)",
                      "algorithmic_bytes_per_launch": by64, "mean_launch_s": t64,
                      "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": ach64 / copy_gbs},
         "sweep_dofs_per_s": {name: nd / t for name, t in tsw.items()},
