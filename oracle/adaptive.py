@@ -15,11 +15,16 @@ cell, the skeleton is the set of facets between leaves) and Section 2.3
 * the penalty of a piece is sigma = sigma0 (p_pen+1)^2 / min(h-, h+) (the
   finer side's width), 2 sigma0 (p_pen+1)^2 / h_K on boundary facets;
 * coarse spaces for the multigrid: the DG spaces of lower degree on the same
-  leaves (nodal interpolation, Galerkin products), then the continuous Q1
-  space of the base mesh (level 0; vanishing on the boundary), embedded by
+  leaves (nodal interpolation, Galerkin products); then, at the last DG
+  degree, the DG spaces of the coarser spacetree levels (Section 2.1: coarse
+  meshes come from the coarser levels of the spacetree): the leaves of the
+  deepest level merged into their parents, one level at a time, down to the
+  base mesh, each operator rediscretised on its leaves with the fine
+  penalty factor sigma0 (p+1)^2 / h_F and the transfer the nodal
+  interpolation of the parent's polynomial; then the continuous Q1 space of
+  the base mesh (level 0; vanishing on the boundary), embedded by
   evaluating its trilinear functions at the DG nodes of every leaf, then the
-  h-levels of that base mesh as for uniform meshes (Section 5: coarse meshes
-  come from the coarser levels of the spacetree).
+  h-levels of that base mesh as for uniform meshes.
 
 Everything here is the plain definition: every bilinear-form integral is
 evaluated in physical coordinates by Gauss quadrature on the facet pieces
@@ -323,9 +328,45 @@ class AdaptiveSIPG:
                              shape=(self.ndof, nv ** d))
 
 
+def coarser_leaves(leaves, r):
+    """One spacetree level up: every leaf of the deepest level replaced by
+    its parent (each parent listed once, where its first child was); the
+    other leaves unchanged.  Returns (coarse leaves, parent index of every
+    fine leaf)."""
+    leaves = np.asarray(leaves, dtype=np.int64)
+    lmax = int(leaves[:, 0].max())
+    out, where, parent = [], {}, np.empty(len(leaves), dtype=np.int64)
+    for i, row in enumerate(leaves):
+        key = tuple(int(v) for v in row)
+        if key[0] == lmax and lmax > 0:
+            key = (lmax - 1,) + tuple(v // r for v in key[1:])
+        if key not in where:
+            where[key] = len(out)
+            out.append(key)
+        parent[i] = where[key]
+    return np.array(out, dtype=np.int64), parent
+
+
+def spacetree_prolongation(fine: AdaptiveSIPG, coarse: AdaptiveSIPG, parent):
+    """Nodal interpolation from the coarse leaves to the fine ones: the
+    coarse polynomial of the containing leaf evaluated at the fine nodes."""
+    X = fine.dof_coords()
+    rows, cols, vals = [], [], []
+    for K in range(fine.ncell):
+        V, _ = coarse.eval_basis(int(parent[K]), X[K * fine.nd:(K + 1) * fine.nd])
+        ii, jj = np.nonzero(V != 0.0)
+        rows.append(K * fine.nd + ii)
+        cols.append(int(parent[K]) * coarse.nd + jj)
+        vals.append(V[ii, jj])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(fine.ndof, coarse.ndof))
+
+
 class AdaptiveHierarchy(Hierarchy):
-    """hp-multigrid DG_p -> DG_{p/2} -> ... (on the leaves) -> Q1 (base mesh)
-    -> Q1 (base mesh / 2) ...; V-cycle, smoothers and solvers of Hierarchy."""
+    """hp-multigrid DG_p -> DG_{p/2} -> ... (on the leaves) -> the last DG
+    degree on the coarser spacetree levels (opts.spacetree_levels) -> Q1
+    (base mesh) -> Q1 (base mesh / 2) ...; V-cycle, smoothers and solvers of
+    Hierarchy."""
 
     def __init__(self, dim, n, r, leaves, p, opts: HierarchyOptions | None = None, kappa=None):
         self.opts = opts or HierarchyOptions()
@@ -344,10 +385,22 @@ class AdaptiveHierarchy(Hierarchy):
                 P = cur.dg_prolongation(degs[li + 1])
                 cur = AdaptiveSIPG(dim, n, r, leaves, degs[li + 1], kappa, p_penalty=p, sigma0=self.opts.sigma0,
                                    basis=self.opts.basis)
-            else:
-                P = cur.base_q1_prolongation()
-            self.P.append(P)
-            A = (P.T @ A @ P).tocsr()
+                self.P.append(P)
+                A = (P.T @ A @ P).tocsr()
+        lv = np.asarray(leaves, dtype=np.int64)
+        while self.opts.spacetree_levels and lv[:, 0].max() > 0:
+            if kappa is not None and np.ndim(kappa) > 0:
+                raise ValueError("spacetree levels take a constant kappa")
+            lc, parent = coarser_leaves(lv, r)
+            co = AdaptiveSIPG(dim, n, r, lc, cur.p, kappa, p_penalty=p, sigma0=self.opts.sigma0,
+                              basis=self.opts.basis)
+            self.P.append(spacetree_prolongation(cur, co, parent))
+            A = co.A.tocsr()  # rediscretised on the coarser leaves
+            self.levels.append(Level("dg", A, n, cur.p, extract_diagonal_blocks(A, (cur.p + 1) ** dim)))
+            cur, lv = co, lc
+        P = cur.base_q1_prolongation()
+        self.P.append(P)
+        A = (P.T @ A @ P).tocsr()
         m = n
         while True:
             self.levels.append(Level("cg", A, m))

@@ -55,6 +55,9 @@ class HierarchyOptions:
     p_coarsening: str = "halve"  # "halve" (gradual) or "direct" (DG_p -> Q1 in one step, Section 5.2)
     h_factor: int = 2            # Q1 h-coarsening factor (2, or 3 as in the paper's meshes 3^k)
     basis: str = "gll"           # DG nodes: "gll" (Gauss-Lobatto) or "gl" (Gauss-Legendre)
+    spacetree_levels: bool = True  # adaptive meshes: coarsen the last DG level along the spacetree levels
+                                   # (finest leaves merged into their parents, level by level) down to the
+                                   # base mesh before Q1; False: straight to Q1 on the base mesh
     block: str = "exact"         # block-Jacobi block: "exact" A_{K<-K}, or "interior": the block of an
                                  # interior cell for every cell (Section 4, technique approximate
                                  # boundary operators; constant kappa, n >= 3)

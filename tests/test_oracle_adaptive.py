@@ -198,3 +198,39 @@ def test_row_blocks_equal_the_assembled_rows():
         for J, B in rb[K].items():
             row[:, J * nd:(J + 1) * nd] = B
         assert np.abs(row - A[K * nd:(K + 1) * nd]).max() <= 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("dim,n,r,lev", [(2, 4, 2, 2), (2, 3, 3, 1), (3, 2, 2, 2)])
+def test_spacetree_levels_are_balanced_meshes_and_transfers_reproduce_polynomials(dim, n, r, lev):
+    # one level up at a time: every coarser leaf set is a valid balanced
+    # mesh, the last one is the base mesh, and the transfer maps the coarse
+    # interpolant of a global polynomial of the level's degree to the fine one
+    from oracle.adaptive import coarser_leaves, spacetree_prolongation
+    lv = _mesh(dim, n, r, "random", max_level=lev)
+    q = 2
+    coef = np.array([0.7, -1.3, 0.4])[:dim]
+
+    def poly(X):  # in Q_2: degree <= 2 in every coordinate
+        return (X @ coef + 0.5) ** 2 - X[:, 0] * X[:, -1]
+
+    while lv[:, 0].max() > 0:
+        lc, parent = coarser_leaves(lv, r)
+        fine = AdaptiveSIPG(dim, n, r, lv, q)
+        coarse = AdaptiveSIPG(dim, n, r, lc, q)  # validates coverage and balance
+        P = spacetree_prolongation(fine, coarse, parent)
+        assert np.abs(P @ coarse.interpolate(poly) - fine.interpolate(poly)).max() <= 1e-12
+        assert lc[:, 0].max() == lv[:, 0].max() - 1
+        lv = lc
+    assert len(lv) == n ** dim
+
+
+def test_spacetree_levels_cut_the_iteration_count():
+    leaves = synth.spacetree_leaves(2, 8, 2, synth.ball_refinement([(0.3, 0.4)], [0.2]), 2)
+    b = synth.random_rhs(len(leaves) * 25, seed=4)
+    its = {}
+    for st in (True, False):
+        H = AdaptiveHierarchy(2, 8, 2, leaves, 4, HierarchyOptions(spacetree_levels=st))
+        u, hist = H.solve(b, rtol=1e-10, maxit=300)
+        assert hist[-1] <= 1e-10 * hist[0]
+        its[st] = len(hist) - 1
+    assert its[True] <= 30 and its[True] < its[False] / 2, its
