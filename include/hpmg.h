@@ -118,6 +118,12 @@ typedef struct {
                          on the matrix cores (v_mfma_f32_16x16x16 with FP16 or BF16 operands, FP32
                          accumulation; the operands of every contraction are rounded to the storage
                          format).  Facet transforms, lifts and updates stay in FP32.  1 needs dim 3. */
+  int spacetree_levels; /* adaptive meshes (hpmg_setup_adaptive): 1 (default) coarsens the last DG degree of
+                         the p-coarsening along the spacetree (the deepest leaves merged into their parents,
+                         one level at a time, down to the base mesh; each level rediscretised with the fine
+                         penalty factor, transfers by the parents' polynomials) before the Q1 level of the base
+                         mesh; 0 goes from that degree straight to Q1 on the base mesh.  Ignored on uniform
+                         meshes. */
 } hpmg_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -160,9 +166,10 @@ typedef struct {
  * side's view (the coarse facet polynomial restricted to each fine facet;
  * the L2 projection of the fine traces onto the coarse facet), so that the
  * fused sweep stays one traversal per step.  Multigrid: the DG levels of
- * lower degree on the same leaves, then continuous Q1 on the base mesh
- * (the coarsest spacetree level; transfer by evaluating its trilinear
- * functions at the leaves' nodes), then the h-levels of the base mesh.
+ * lower degree on the same leaves, then (options.spacetree_levels) the last
+ * degree on the coarser levels of the spacetree down to the base mesh, then
+ * continuous Q1 on the base mesh (transfer by evaluating its trilinear
+ * functions at the nodes), then the h-levels of the base mesh.
  * Constant kappa only (coeff->per_cell = 0), Gauss-Lobatto or Gauss-Legendre
  * nodes, exact blocks (block_variant 0, block_recompute 0, mfma 0), FP64
  * or FP32 vectors and cycles (F16 / BF16: HPMG_E_UNSUPPORTED); every other

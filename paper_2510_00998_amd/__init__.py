@@ -64,7 +64,7 @@ class Options(ctypes.Structure):
                 ("h_factor", ctypes.c_int), ("basis", ctypes.c_int), ("block_recompute", ctypes.c_int),
                 ("nu_pre_cg", ctypes.c_int), ("nu_post_cg", ctypes.c_int), ("block_variant", ctypes.c_int),
                 ("p_schedule", ctypes.c_int * 8), ("alloc", ALLOC_FN), ("free", FREE_FN),
-                ("alloc_ctx", ctypes.c_void_p), ("mfma", ctypes.c_int)]
+                ("alloc_ctx", ctypes.c_void_p), ("mfma", ctypes.c_int), ("spacetree_levels", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

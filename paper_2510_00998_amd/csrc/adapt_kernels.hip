@@ -127,6 +127,89 @@ __global__ __launch_bounds__(REMAP_THREADS) void k_remap(T* tr, long long tstrid
   }
 }
 
+// Transfers between two spacetree levels of the same degree (the coarser
+// leaf set merges the deepest leaves into their parents).  A fine cell is
+// either a coarse cell itself or the child at position (px, py, pz) of a
+// coarse cell, whose polynomial restricted to the child is the tensor
+// product of I_px, I_py, I_pz (I_j[a][b] = l_b((xi_a + j)/r), the first r
+// tables of the level's remap data).  pmap[fine] = 32 coarse + child
+// position (31: the same cell); rmap[coarse][r^d] = fine cells by child
+// position (the same cell: [fine, -1, ...]).  One workgroup per cell, one
+// thread per node, the 1D contractions through LDS.
+template <typename C, int D, int N>
+__device__ __forceinline__ void tensor_apply(const C* I, int r, int pos, bool transpose, C* s0, C* s1, int tid) {
+  // s0 -> s0 (through s1): along x with I_px, along y with I_py (, z with I_pz),
+  // I or I^T; s0 holds [c][b][a] with a fastest
+  constexpr int NV = D == 2 ? N * N : N * N * N;
+  const int pxyz[3] = {pos % r, (pos / r) % r, pos / (r * r)};
+  C* src = s0;
+  C* dst = s1;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const C* M = I + (size_t)pxyz[k] * N * N;
+    const int st = k == 0 ? 1 : (k == 1 ? N : N * N);
+    if (tid < NV) {
+      const int j = (tid / st) % N, base = tid - j * st;
+      C acc = 0;
+#pragma unroll
+      for (int x = 0; x < N; ++x) acc += (transpose ? M[x * N + j] : M[j * N + x]) * src[base + x * st];
+      dst[tid] = acc;
+    }
+    __syncthreads();
+    C* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != s0) {  // D odd: the result is in s1
+    if (tid < NV) s0[tid] = src[tid];
+    __syncthreads();
+  }
+}
+
+template <typename C, int D, int N>
+__global__ void k_hprolong(C* uf, const C* ec, const int* pmap, int r, const C* I, long long fstride,
+                           long long cstride) {
+  constexpr int NV = D == 2 ? N * N : N * N * N;
+  __shared__ C s0[NV], s1[NV];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  uf += (size_t)blockIdx.y * fstride;
+  ec += (size_t)blockIdx.y * cstride;
+  const int pm = pmap[f], c = pm >> 5, pos = pm & 31;
+  if (pos == 31) {
+    if (tid < NV) uf[(size_t)f * NV + tid] += ec[(size_t)c * NV + tid];
+    return;
+  }
+  if (tid < NV) s0[tid] = ec[(size_t)c * NV + tid];
+  __syncthreads();
+  tensor_apply<C, D, N>(I, r, pos, false, s0, s1, tid);
+  if (tid < NV) uf[(size_t)f * NV + tid] += s0[tid];
+}
+
+template <typename C, int D, int N>
+__global__ void k_hrestrict(const C* rf, C* bc, const int* rmap, int r, const C* I, long long fstride,
+                            long long cstride) {
+  constexpr int NV = D == 2 ? N * N : N * N * N;
+  __shared__ C s0[NV], s1[NV];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  rf += (size_t)blockIdx.y * fstride;
+  bc += (size_t)blockIdx.y * cstride;
+  const int rd = D == 2 ? r * r : r * r * r;
+  const int* row = rmap + (size_t)c * rd;
+  if (row[1] < 0) {
+    if (tid < NV) bc[(size_t)c * NV + tid] = rf[(size_t)row[0] * NV + tid];
+    return;
+  }
+  C acc = 0;
+  for (int q = 0; q < rd; ++q) {
+    if (tid < NV) s0[tid] = rf[(size_t)row[q] * NV + tid];
+    __syncthreads();
+    tensor_apply<C, D, N>(I, r, q, true, s0, s1, tid);
+    if (tid < NV) acc += s0[tid];
+    __syncthreads();
+  }
+  if (tid < NV) bc[(size_t)c * NV + tid] = acc;
+}
+
 // y[i] = sum over e in [ptr[i], ptr[i+1]) of w[e] x[col[e]]
 template <typename T>
 __global__ void k_csr(int nrow, const int* ptr, const int* col, const T* w, const T* x, T* y) {
@@ -174,5 +257,35 @@ void csr_apply(int nrow, const int* ptr, const int* col, const T* w, const T* x,
 }
 template void csr_apply<double>(int, const int*, const int*, const double*, const double*, double*, hipStream_t);
 template void csr_apply<float>(int, const int*, const int*, const float*, const float*, float*, hipStream_t);
+
+template <typename C, int D, int N>
+void htransfer_launch(bool restrict_, int ncells, const int* map, int r, const C* I, const C* src, C* dst,
+                      long long fstride, long long cstride, int nrhs, hipStream_t s) {
+  constexpr int NV = D == 2 ? N * N : N * N * N;
+  const dim3 grid(ncells, nrhs), blk((NV + 63) / 64 * 64);
+  if (restrict_)
+    hipLaunchKernelGGL((k_hrestrict<C, D, N>), grid, blk, 0, s, src, dst, map, r, I, fstride, cstride);
+  else
+    hipLaunchKernelGGL((k_hprolong<C, D, N>), grid, blk, 0, s, dst, src, map, r, I, fstride, cstride);
+}
+
+template <typename C>
+void spacetree_transfer(bool restrict_, int D, int N, int ncells, const int* map, int r, const C* I, const C* src,
+                        C* dst, long long fstride, long long cstride, int nrhs, hipStream_t s) {
+  if (ncells == 0) return;
+  using F = void (*)(bool, int, const int*, int, const C*, const C*, C*, long long, long long, int, hipStream_t);
+  static const F tab2[10] = {nullptr, nullptr, htransfer_launch<C, 2, 2>, htransfer_launch<C, 2, 3>,
+                             htransfer_launch<C, 2, 4>, htransfer_launch<C, 2, 5>, htransfer_launch<C, 2, 6>,
+                             htransfer_launch<C, 2, 7>, htransfer_launch<C, 2, 8>, htransfer_launch<C, 2, 9>};
+  static const F tab3[10] = {nullptr, nullptr, htransfer_launch<C, 3, 2>, htransfer_launch<C, 3, 3>,
+                             htransfer_launch<C, 3, 4>, htransfer_launch<C, 3, 5>, htransfer_launch<C, 3, 6>,
+                             htransfer_launch<C, 3, 7>, htransfer_launch<C, 3, 8>, htransfer_launch<C, 3, 9>};
+  if (N < 2 || N > 9) return;
+  (D == 2 ? tab2 : tab3)[N](restrict_, ncells, map, r, I, src, dst, fstride, cstride, nrhs, s);
+}
+template void spacetree_transfer<double>(bool, int, int, int, const int*, int, const double*, const double*, double*,
+                                         long long, long long, int, hipStream_t);
+template void spacetree_transfer<float>(bool, int, int, int, const int*, int, const float*, const float*, float*,
+                                        long long, long long, int, hipStream_t);
 
 }  // namespace hpmg

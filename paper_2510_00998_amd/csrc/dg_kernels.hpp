@@ -159,6 +159,8 @@ struct DGArgs {
   const int* nbslot = nullptr;
   const C* hscale = nullptr;
   const C* mort = nullptr;
+  const int* itab = nullptr;   // hanging interfaces (host side: the remap launch)
+  int nif = 0, mif = 0, rfac = 0;
   int* flag = nullptr;  // eigendata build: set to 1 if a block eigenvalue is not positive and finite
   const void* zlow = nullptr;
   const double* kscal = nullptr;

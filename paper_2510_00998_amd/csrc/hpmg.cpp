@@ -210,8 +210,10 @@ std::vector<double> remap_tables(const hpmg::Basis1D& B, int r) {
 void build_dg_level(hpmg_ctx* h, DGLevel& L, const hpmg::Basis1D& B, const hpmg::Basis1D* Bnext,
                     hipStream_t s) {
   const int N = B.N, NN = N * N, D = h->dim;
-  L.ndof = (size_t)h->ncell * ipow(N, D);
-  L.trsize = ((size_t)2 * D * h->ncell + (size_t)h->nif * (h->mif + 1)) * 2 * ipow(N, D - 1);
+  const size_t ncell = h->adapt ? (size_t)h->amesh[L.am].ncell : (size_t)h->ncell;
+  const size_t nif = h->adapt ? (size_t)h->amesh[L.am].nif : 0;
+  L.ndof = ncell * ipow(N, D);
+  L.trsize = ((size_t)2 * D * ncell + nif * (h->mif + 1)) * 2 * ipow(N, D - 1);
   // reference data
   std::vector<double> ref;
   ref.insert(ref.end(), B.M.begin(), B.M.end());
@@ -593,45 +595,15 @@ uint64_t leaf_key(int lvl, const int* x, int D) {
   return k;
 }
 
-void build_adaptive(hpmg_ctx* h, const hpmg_adaptive_mesh* am, hipStream_t s) {
-  const int D = h->dim, n = h->n, r = h->rfac, nl = h->ncell;
-  const int m = ipow(r, D - 1);
-  h->mif = m;
-  std::vector<int> lev(nl), X((size_t)nl * 3, 0);
-  int lmax = 0;
-  for (int c = 0; c < nl; ++c) {
-    const int* row = am->leaves + (size_t)c * (1 + D);
-    lev[c] = row[0];
-    require(row[0] >= 0 && row[0] <= 12, "leaf level must be in [0, 12]");
-    lmax = std::max(lmax, row[0]);
-  }
-  long long ext_max = n;
-  for (int l = 0; l < lmax; ++l) ext_max *= r;
-  require(ext_max <= (1 << 20), "leaves too fine: n r^level must not exceed 2^20");
+// Device tables of one leaf set (M.lev, M.X set, validated): per cell the
+// facet mask and the neighbour-trace slot of every facet, the hanging
+// interfaces, (h_base / h_c)^(d-2).  Facet neighbours more than one level
+// apart are rejected.
+void build_mesh_tables(hpmg_ctx* h, AdaptMesh& M, hipStream_t s) {
+  const int D = h->dim, n = h->n, r = h->rfac, nl = M.ncell, m = h->mif;
   std::unordered_map<uint64_t, int> idx;
   idx.reserve((size_t)nl * 2);
-  unsigned long long vol = 0, full = 1;
-  for (int k = 0; k < D; ++k) full *= (unsigned long long)ext_max;
-  for (int c = 0; c < nl; ++c) {
-    const int* row = am->leaves + (size_t)c * (1 + D);
-    const long long ext = n * (long long)std::pow((double)r, lev[c]) + 0.5;
-    for (int k = 0; k < D; ++k) {
-      require(row[1 + k] >= 0 && row[1 + k] < ext, "leaf coordinate out of range for its level");
-      X[(size_t)c * 3 + k] = row[1 + k];
-    }
-    require(idx.emplace(leaf_key(lev[c], &X[(size_t)c * 3], D), c).second, "duplicate leaf");
-    unsigned long long v = 1;
-    for (int l = lev[c]; l < lmax; ++l) v *= (unsigned long long)ipow(r, D);
-    vol += v;
-  }
-  for (int c = 0; c < nl; ++c) {  // no leaf lies inside another leaf
-    int y[3] = {X[(size_t)c * 3], X[(size_t)c * 3 + 1], X[(size_t)c * 3 + 2]};
-    for (int l = lev[c] - 1; l >= 0; --l) {
-      for (int k = 0; k < D; ++k) y[k] /= r;
-      require(idx.find(leaf_key(l, y, D)) == idx.end(), "a leaf lies inside another leaf");
-    }
-  }
-  require(vol == full, "the leaves do not cover the unit box");
+  for (int c = 0; c < nl; ++c) idx.emplace(leaf_key(M.lev[c], &M.X[(size_t)c * 3], D), c);
   auto find = [&](int l, const int* y) -> int {
     auto it = idx.find(leaf_key(l, y, D));
     return it == idx.end() ? -1 : it->second;
@@ -654,8 +626,8 @@ void build_adaptive(hpmg_ctx* h, const hpmg_adaptive_mesh* am, hipStream_t s) {
   std::vector<std::pair<int, int>> slot_fix;  // (index into nbslot, interface slot offset)
   std::vector<int> slot_if;
   for (int c = 0; c < nl; ++c) {
-    const int l = lev[c];
-    const int* x = &X[(size_t)c * 3];
+    const int l = M.lev[c];
+    const int* x = &M.X[(size_t)c * 3];
     const long long ext = n * (long long)std::pow((double)r, l) + 0.5;
     for (int f = 0; f < 2 * D; ++f) {
       const int k = f >> 1, sd = f & 1;
@@ -709,47 +681,148 @@ void build_adaptive(hpmg_ctx* h, const hpmg_adaptive_mesh* am, hipStream_t s) {
       slot_if.push_back(i);
     }
   }
-  h->nif = (int)iface.size();
-  for (int i = 0; i < h->nif; ++i)
+  M.nif = (int)iface.size();
+  for (int i = 0; i < M.nif; ++i)
     for (int q = 0; q < m; ++q)
       require(itab[(size_t)i * (2 + m) + 2 + q] >= 0, "a hanging facet is not covered by finer leaves");
   const size_t base0 = (size_t)2 * D * nl;
   for (size_t j = 0; j < slot_fix.size(); ++j)
     nbslot[slot_fix[j].first] = (int)(base0 + (size_t)slot_if[j] * (m + 1) + slot_fix[j].second);
-  require(base0 + (size_t)h->nif * (m + 1) < (size_t)1 << 31, "mesh too large");
-  h->amask = h->mem.upload(amask, s);
-  h->nbslot = h->mem.upload(nbslot, s);
-  if (h->nif > 0) h->itab = h->mem.upload(itab, s);
+  require(base0 + (size_t)M.nif * (m + 1) < (size_t)1 << 31, "mesh too large");
+  M.amask = h->mem.upload(amask, s);
+  M.nbslot = h->mem.upload(nbslot, s);
+  if (M.nif > 0) M.itab = h->mem.upload(itab, s);
   std::vector<unsigned char> bm(nl);
   for (int c = 0; c < nl; ++c) bm[c] = (unsigned char)(amask[c] & 0xff);
-  h->bmask = h->mem.upload(bm, s);
-  // geometry and h scaling
+  M.bmask = h->mem.upload(bm, s);
+  if (D == 3) {
+    std::vector<double> hs(nl);
+    for (int c = 0; c < nl; ++c) hs[c] = std::pow((double)r, M.lev[c]);
+    M.hs_d = h->mem.upload(hs, s);
+    M.hs_f = h->mem.upload(cast_vec<float>(hs), s);
+  }
+}
+
+// The caller's leaves (validated: coordinates in range, no duplicate, no
+// leaf inside another, the leaves cover the box), then, if the options ask
+// for it, the coarser spacetree levels down to the base mesh with the
+// transfers between consecutive sets, then the Q1 transfers of the last set.
+void build_adaptive(hpmg_ctx* h, const hpmg_adaptive_mesh* am, hipStream_t s) {
+  const int D = h->dim, n = h->n, r = h->rfac, nl = h->ncell;
+  h->mif = ipow(r, D - 1);
+  AdaptMesh M0;
+  M0.ncell = nl;
+  M0.lev.resize(nl);
+  M0.X.assign((size_t)nl * 3, 0);
+  int lmax = 0;
+  for (int c = 0; c < nl; ++c) {
+    const int* row = am->leaves + (size_t)c * (1 + D);
+    M0.lev[c] = row[0];
+    require(row[0] >= 0 && row[0] <= 12, "leaf level must be in [0, 12]");
+    lmax = std::max(lmax, row[0]);
+  }
+  long long ext_max = n;
+  for (int l = 0; l < lmax; ++l) ext_max *= r;
+  require(ext_max <= (1 << 20), "leaves too fine: n r^level must not exceed 2^20");
+  std::unordered_map<uint64_t, int> idx;
+  idx.reserve((size_t)nl * 2);
+  unsigned long long vol = 0, full = 1;
+  for (int k = 0; k < D; ++k) full *= (unsigned long long)ext_max;
+  for (int c = 0; c < nl; ++c) {
+    const int* row = am->leaves + (size_t)c * (1 + D);
+    const long long ext = n * (long long)std::pow((double)r, M0.lev[c]) + 0.5;
+    for (int k = 0; k < D; ++k) {
+      require(row[1 + k] >= 0 && row[1 + k] < ext, "leaf coordinate out of range for its level");
+      M0.X[(size_t)c * 3 + k] = row[1 + k];
+    }
+    require(idx.emplace(leaf_key(M0.lev[c], &M0.X[(size_t)c * 3], D), c).second, "duplicate leaf");
+    unsigned long long v = 1;
+    for (int l = M0.lev[c]; l < lmax; ++l) v *= (unsigned long long)ipow(r, D);
+    vol += v;
+  }
+  for (int c = 0; c < nl; ++c) {  // no leaf lies inside another leaf
+    int y[3] = {M0.X[(size_t)c * 3], M0.X[(size_t)c * 3 + 1], M0.X[(size_t)c * 3 + 2]};
+    for (int l = M0.lev[c] - 1; l >= 0; --l) {
+      for (int k = 0; k < D; ++k) y[k] /= r;
+      require(idx.find(leaf_key(l, y, D)) == idx.end(), "a leaf lies inside another leaf");
+    }
+  }
+  require(vol == full, "the leaves do not cover the unit box");
+  // leaf geometry of the caller's leaves (load vectors)
   h->leaf_h.resize(nl);
   h->leaf_org.resize((size_t)nl * D);
-  std::vector<double> hs(nl, 1.0);
   for (int c = 0; c < nl; ++c) {
-    const double rl = std::pow((double)r, lev[c]);
-    h->leaf_h[c] = 1.0 / (n * rl);
-    for (int k = 0; k < D; ++k) h->leaf_org[(size_t)c * D + k] = X[(size_t)c * 3 + k] * h->leaf_h[c];
-    hs[c] = std::pow(rl, D - 2);
+    h->leaf_h[c] = 1.0 / (n * std::pow((double)r, M0.lev[c]));
+    for (int k = 0; k < D; ++k) h->leaf_org[(size_t)c * D + k] = M0.X[(size_t)c * 3 + k] * h->leaf_h[c];
   }
-  if (D == 3) {
-    h->hs_d = h->mem.upload(hs, s);
-    h->hs_f = h->mem.upload(cast_vec<float>(hs), s);
+  build_mesh_tables(h, M0, s);
+  h->amesh.clear();
+  h->amesh.push_back(std::move(M0));
+  // coarser spacetree levels: the deepest leaves merged into their parents
+  // (each parent placed where its first child was), down to the base mesh
+  const int rd = ipow(r, D);
+  while (h->opt.spacetree_levels) {
+    AdaptMesh& F = h->amesh.back();
+    const int lm = *std::max_element(F.lev.begin(), F.lev.end());
+    if (lm == 0) break;
+    AdaptMesh C;
+    std::unordered_map<uint64_t, int> where;
+    std::vector<int> pmap(F.ncell);
+    std::vector<std::vector<int>> kids;
+    std::vector<char> merged;
+    for (int c = 0; c < F.ncell; ++c) {
+      int l = F.lev[c];
+      int y[3] = {F.X[(size_t)c * 3], F.X[(size_t)c * 3 + 1], F.X[(size_t)c * 3 + 2]};
+      int pos = 31;
+      if (l == lm) {
+        pos = 0;
+        for (int k = D - 1; k >= 0; --k) pos = pos * r + y[k] % r;
+        for (int k = 0; k < D; ++k) y[k] /= r;
+        --l;
+      }
+      const uint64_t key = leaf_key(l, y, D);
+      auto it = where.find(key);
+      int ci;
+      if (it == where.end()) {
+        ci = C.ncell++;
+        where.emplace(key, ci);
+        C.lev.push_back(l);
+        C.X.insert(C.X.end(), y, y + 3);
+        kids.emplace_back(rd, -1);
+        merged.push_back(pos != 31);
+      } else {
+        ci = it->second;
+      }
+      pmap[c] = ci * 32 + pos;
+      kids[ci][pos == 31 ? 0 : pos] = c;
+    }
+    std::vector<int> rmap((size_t)C.ncell * rd);
+    for (int ci = 0; ci < C.ncell; ++ci) {
+      for (int q = 0; q < rd; ++q) {
+        require(!merged[ci] || kids[ci][q] >= 0, "a refined cell without all its children");
+        rmap[(size_t)ci * rd + q] = kids[ci][q];
+      }
+    }
+    F.pmap = h->mem.upload(pmap, s);
+    F.rmap = h->mem.upload(rmap, s);
+    build_mesh_tables(h, C, s);
+    h->amesh.push_back(std::move(C));
   }
-  // Q1 transfers: corner j of leaf c lies at t = (x - B r^l + bit(j)) / r^l
-  // inside its base cell B; the base vertex B + w (w in {0,1}^d) has the
-  // weight prod_k (w_k ? t_k : 1 - t_k) there (zero boundary vertices left out)
+  // Q1 transfers of the last leaf set: corner j of cell c lies at
+  // t = (x - B r^l + bit(j)) / r^l inside its base cell B; the base vertex
+  // B + w (w in {0,1}^d) has the weight prod_k (w_k ? t_k : 1 - t_k) there
+  // (zero boundary vertices left out)
+  const AdaptMesh& L = h->amesh.back();
   const int nv = n - 1, nc = 1 << D;
-  std::vector<std::vector<std::pair<int, double>>> prow((size_t)nl * nc);
+  std::vector<std::vector<std::pair<int, double>>> prow((size_t)L.ncell * nc);
   std::vector<std::vector<std::pair<int, double>>> rrow((size_t)ipow(nv, D));
-  for (int c = 0; c < nl; ++c) {
-    const long long rl = (long long)(std::pow((double)r, lev[c]) + 0.5);
+  for (int c = 0; c < L.ncell; ++c) {
+    const long long rl = (long long)(std::pow((double)r, L.lev[c]) + 0.5);
     for (int j = 0; j < nc; ++j) {
       double t[3];
       int Bc[3];
       for (int k = 0; k < D; ++k) {
-        const long long xk = X[(size_t)c * 3 + k];
+        const long long xk = L.X[(size_t)c * 3 + k];
         Bc[k] = (int)(xk / rl);
         t[k] = (double)(xk - Bc[k] * rl + ((j >> k) & 1)) / (double)rl;
       }
@@ -941,7 +1014,30 @@ void vcycle_dg(hpmg_ctx* h, int l, T* u, const T* b, bool uzero, int nrhs, hipSt
   a.u_in = u;
   a.tr_in = d.tr[cur];
   a.b = b;
-  if (!L.next_cg) {
+  if (L.next_h) {
+    // the same degree on the next coarser spacetree level: r = b - A u,
+    // restricted child by child; the correction prolongated by the parents'
+    // polynomials, then the traces of the corrected u
+    DGLevel& Cl = h->dg[l + 1];
+    DGData<C>& dc = data<C>(Cl);
+    DGData<C>& dl = data<C>(L);
+    const AdaptMesh& Mf = h->amesh[L.am];
+    const AdaptMesh& Mc = h->amesh[Cl.am];
+    a.out = dl.rtmp;
+    dg_run(h, hpmg::OP_APPLY, a, L.N, nrhs, 1, s);
+    hpmg::spacetree_transfer<C>(true, h->dim, L.N, Mc.ncell, Mf.rmap, h->rfac, dl.mort, dl.rtmp, dc.b,
+                                (long long)L.ndof, (long long)Cl.ndof, nrhs, s);
+    HIPCHK(hipGetLastError());
+    vcycle_dg<C>(h, l + 1, dc.u, dc.b, true, nrhs, s);
+    if constexpr (std::is_same<T, C>::value) {
+      hpmg::spacetree_transfer<C>(false, h->dim, L.N, Mf.ncell, Mf.pmap, h->rfac, dl.mort, dc.u, u,
+                                  (long long)L.ndof, (long long)Cl.ndof, nrhs, s);
+      HIPCHK(hipGetLastError());
+    } else {
+      throw HpmgError(HPMG_E_UNSUPPORTED, "adaptive meshes take FP64 or FP32 vectors");
+    }
+    project<T>(h, l, u, d.tr[cur], nrhs, s);
+  } else if (!L.next_cg) {
     DGLevel& Cl = h->dg[l + 1];
     DGData<C>& dc = data<C>(Cl);
     a.out = dc.b;
@@ -1241,6 +1337,7 @@ void hpmg_default_options(hpmg_options* o) {
   o->free = nullptr;
   o->alloc_ctx = nullptr;
   o->mfma = 0;
+  o->spacetree_levels = 1;
 }
 
 const char* hpmg_status_string(hpmg_status s) {
@@ -1293,6 +1390,7 @@ hpmg_status setup_impl(int dim, int nbase, const hpmg_adaptive_mesh* am, int p, 
     require(h->opt.nu_pre_cg >= -1 && h->opt.nu_post_cg >= -1, "nu_pre_cg / nu_post_cg must be >= -1");
     require(h->opt.block_variant == 0 || h->opt.block_variant == 1, "block_variant must be 0 or 1");
     require(h->opt.mfma == 0 || (h->opt.mfma == 1 && dim == 3), "mfma must be 0, or 1 with dim 3");
+    require(h->opt.spacetree_levels == 0 || h->opt.spacetree_levels == 1, "spacetree_levels must be 0 or 1");
     require((h->opt.alloc == nullptr) == (h->opt.free == nullptr), "alloc and free must be given together");
     h->mem.alloc_fn = h->opt.alloc;
     h->mem.free_fn = h->opt.free;
@@ -1362,6 +1460,11 @@ hpmg_status setup_impl(int dim, int nbase, const hpmg_adaptive_mesh* am, int p, 
       for (int q = p / 2; q >= 2; q /= 2) degs.push_back(q);
     }
     const double sigma_hat = h->opt.sigma0 * (p + 1.0) * (p + 1.0);
+    // adaptive meshes: after the p-levels (on the caller's leaves) the last
+    // degree on every coarser spacetree level
+    const int np = (int)degs.size();
+    const int nh = h->adapt ? (int)h->amesh.size() - 1 : 0;
+    for (int k = 0; k < nh; ++k) degs.push_back(degs[np - 1]);
     std::vector<hpmg::Basis1D> bases;
     for (int q : degs) bases.push_back(hpmg::make_basis(q, h->opt.basis == 1));
     h->dg.resize(degs.size());
@@ -1369,13 +1472,15 @@ hpmg_status setup_impl(int dim, int nbase, const hpmg_adaptive_mesh* am, int p, 
       DGLevel& L = h->dg[l];
       L.p = degs[l];
       L.N = degs[l] + 1;
+      L.am = (int)l < np ? 0 : (int)l - np + 1;
       L.next_cg = (l + 1 == degs.size());
+      L.next_h = !L.next_cg && (int)l + 1 >= np;
       L.NC = L.next_cg ? 2 : degs[l + 1] + 1;
       // transfers to a DG level other than the halved degree take the
       // kernels with a run-time coarse degree
-      L.dyn_nc = !L.next_cg && L.NC != hpmg::nc_next(L.N);
+      L.dyn_nc = !L.next_cg && !L.next_h && L.NC != hpmg::nc_next(L.N);
       L.sigma_hat = sigma_hat;
-      build_dg_level(h.get(), L, bases[l], L.next_cg ? nullptr : &bases[l + 1], stream);
+      build_dg_level(h.get(), L, bases[l], (L.next_cg || L.next_h) ? nullptr : &bases[l + 1], stream);
       const size_t R = h->opt.max_rhs;
       if (l > 0) {
         L.d.u = (double*)h->mem.alloc(L.ndof * R * sizeof(double));
@@ -1383,8 +1488,13 @@ hpmg_status setup_impl(int dim, int nbase, const hpmg_adaptive_mesh* am, int p, 
         L.f.u = (float*)h->mem.alloc(L.ndof * R * sizeof(float));
         L.f.b = (float*)h->mem.alloc(L.ndof * R * sizeof(float));
       }
+      if (L.next_h) {
+        L.d.rtmp = (double*)h->mem.alloc(L.ndof * R * sizeof(double));
+        L.f.rtmp = (float*)h->mem.alloc(L.ndof * R * sizeof(float));
+      }
       if (L.next_cg) {
-        const size_t nct = (size_t)h->ncell << h->dim;
+        const size_t ncl = h->adapt ? (size_t)h->amesh[L.am].ncell : (size_t)h->ncell;
+        const size_t nct = ncl << h->dim;
         L.d.contrib = (double*)h->mem.alloc(nct * R * sizeof(double));
         L.f.contrib = (float*)h->mem.alloc(nct * R * sizeof(float));
       }

@@ -107,11 +107,33 @@ struct DGData {
   T* tr[2] = {nullptr, nullptr};
   T* contrib = nullptr;  // corner contributions (last DG level, restriction to Q1)
   T* mort = nullptr;     // adaptive meshes: hanging-facet remap tables [I_j | P_j], j < r
+  T* rtmp = nullptr;     // adaptive meshes: residual of a level followed by a coarser spacetree level
+};
+
+// One leaf set of an adaptive mesh: the caller's leaves, or a coarser
+// spacetree level (the deepest leaves of the previous set merged into
+// their parents).  amask / nbslot / itab / hscale as the kernels read them;
+// pmap / rmap: the transfer to the next coarser leaf set (pmap[cell] =
+// 32 coarse cell + child position, 31 for the same cell; rmap[coarse cell]
+// [r^d] = its cells in this set by child position, or [cell, -1, ...]).
+struct AdaptMesh {
+  int ncell = 0, nif = 0;
+  std::vector<int> lev, X;  // host: level and 3 coordinates per cell
+  unsigned short* amask = nullptr;
+  unsigned char* bmask = nullptr;
+  int* nbslot = nullptr;
+  int* itab = nullptr;
+  double* hs_d = nullptr;
+  float* hs_f = nullptr;
+  int* pmap = nullptr;
+  int* rmap = nullptr;
 };
 
 struct DGLevel {
   int p = 0, N = 0, NC = 0;  // NC: nodes per direction of the next coarser level (2: Q1)
   bool next_cg = false;
+  int am = 0;                // adaptive meshes: the leaf set of this level (index into hpmg_ctx::amesh)
+  bool next_h = false;       // adaptive meshes: the next level has the same degree on the next coarser leaf set
   bool dyn_nc = false;       // next DG level not the halved degree: run-time NC transfer kernels
   double sigma_hat = 0.0;
   size_t ndof = 0, trsize = 0;  // per right-hand side
@@ -162,19 +184,15 @@ struct hpmg_ctx {
   unsigned char* bmask = nullptr;  // per cell boundary-facet mask (all DG levels)
   int coarse_m = 0;
   // Adaptive (spacetree) mesh, hpmg_setup_adaptive: n is the base mesh,
-  // ncell the number of leaves.  rfac: subdivision factor r; nif hanging
-  // interfaces of mif = r^(d-1) fine cells each (itab rows: coarse cell, its
-  // facet, the fine cells); amask / nbslot as the kernels read them;
-  // hscale (h_base / h_c)^(d-2) per cell (3D); CSR transfers between the Q1
-  // base vertices and the cells' corners (restriction: rows = vertices,
-  // prolongation: rows = cell corners); leaf geometry for load vectors.
+  // ncell the number of leaves.  rfac: subdivision factor r; mif = r^(d-1)
+  // fine cells per hanging interface; amesh: the caller's leaf set, then the
+  // coarser spacetree levels (options.spacetree_levels); CSR transfers
+  // between the Q1 base vertices and the corners of the last leaf set's
+  // cells (restriction: rows = vertices, prolongation: rows = cell
+  // corners); leaf geometry of the caller's leaves for load vectors.
   bool adapt = false;
-  int rfac = 0, nif = 0, mif = 0;
-  unsigned short* amask = nullptr;
-  int* nbslot = nullptr;
-  int* itab = nullptr;
-  double* hs_d = nullptr;
-  float* hs_f = nullptr;
+  int rfac = 0, mif = 0;
+  std::vector<hpmg::detail::AdaptMesh> amesh;
   int q1r_rows = 0, q1p_rows = 0;
   int *q1r_ptr = nullptr, *q1r_col = nullptr, *q1p_ptr = nullptr, *q1p_col = nullptr;
   double *q1r_wd = nullptr, *q1p_wd = nullptr;
@@ -269,15 +287,22 @@ inline hpmg::DGArgs<T> dg_args(hpmg_ctx* h, DGLevel& L) {
   a.vstride = (long long)L.ndof;
   a.tstride = (long long)L.trsize;
   if (h->adapt) {
+    const AdaptMesh& M = h->amesh[L.am];
+    a.ncell = M.ncell;
     a.adapt = 1;
-    a.amask = h->amask;
-    a.nbslot = h->nbslot;
+    a.amask = M.amask;
+    a.bmask = M.bmask;
+    a.nbslot = M.nbslot;
     if constexpr (std::is_same<C, double>::value)
-      a.hscale = h->hs_d;
+      a.hscale = M.hs_d;
     else
-      a.hscale = h->hs_f;
+      a.hscale = M.hs_f;
     a.sig_hang = (C)(L.sigma_hat * h->rfac);
     a.mort = d.mort;
+    a.itab = M.itab;
+    a.nif = M.nif;
+    a.mif = h->mif;
+    a.rfac = h->rfac;
   }
   return a;
 }
@@ -292,8 +317,8 @@ inline void dg_run(hpmg_ctx* h, int op, const hpmg::DGArgs<T>& a, int N, int nrh
   if (h->adapt && (op == hpmg::OP_SWEEP || op == hpmg::OP_PROJECT || op == hpmg::OP_PROLONG ||
                    op == hpmg::OP_PROLONG_Q1 || op == hpmg::OP_PROLONG_DYN)) {
     if constexpr (sizeof(T) >= 4) {
-      hpmg::remap_hanging<T>(h->dim, N, h->ncell, h->nif, h->mif, h->rfac, h->itab, a.mort, a.tr_out, a.tstride,
-                             nrhs, s);
+      hpmg::remap_hanging<T>(h->dim, N, a.ncell, a.nif, a.mif, a.rfac, a.itab, a.mort, a.tr_out, a.tstride, nrhs,
+                             s);
       HIPCHK(hipGetLastError());
     } else {
       throw HpmgError(HPMG_E_UNSUPPORTED, "adaptive meshes take FP64 or FP32 vectors");

@@ -60,6 +60,14 @@ void dense_solve(int m, const double* Ainv, const T* b, T* x, hipStream_t s);
 template <typename T>
 void remap_hanging(int D, int N, int ncell, int nif, int m, int r, const int* itab, const CT<T>* mort, T* tr,
                    long long tstride, int nrhs, hipStream_t s);
+// Transfers between two spacetree levels of one degree (adaptive meshes):
+// restrict_ = true: dst (coarse, ncells cells) = P^T src (fine) with map =
+// rmap [coarse][r^d]; false: dst (fine, ncells cells) += P src (coarse) with
+// map = pmap [fine]; I = the level's interpolation tables I_j (j < r).
+// fstride / cstride: per right-hand side strides of the fine / coarse vectors.
+template <typename C>
+void spacetree_transfer(bool restrict_, int D, int N, int ncells, const int* map, int r, const C* I, const C* src,
+                        C* dst, long long fstride, long long cstride, int nrhs, hipStream_t s);
 // y = W x for a CSR matrix W (the Q1 transfers of adaptive meshes)
 template <typename T>
 void csr_apply(int nrow, const int* ptr, const int* col, const T* w, const T* x, T* y, hipStream_t s);

@@ -112,12 +112,14 @@ def test_adaptive_solve_reaches_tolerance(dim, n, r, p, kind, lev, prec):
 @pytest.mark.parametrize("dim,n,r,p", [(2, 4, 2, 2), (3, 3, 3, 2)])
 def test_adaptive_multiple_rhs_and_options(dim, n, r, p):
     # two right-hand sides per call, one-step p-coarsening, Q1 V(1,1),
-    # Gauss-Legendre nodes: each against the oracle with the same options
+    # Gauss-Legendre nodes, no spacetree levels (straight to Q1 on the base
+    # mesh): each against the oracle with the same options
     leaves = _leaves(dim, n, r, "random", 1)
     log(f"adaptive nrhs/options dim={dim} n={n} r={r} p={p}")
     for opts, oopts in (({"p_coarsening": 1, "nu_pre_cg": 1, "nu_post_cg": 1},
                          HierarchyOptions(p_coarsening="direct", nu_pre_cg=1, nu_post_cg=1)),
-                        ({"basis": 1}, HierarchyOptions(basis="gl"))):
+                        ({"basis": 1}, HierarchyOptions(basis="gl")),
+                        ({"spacetree_levels": 0}, HierarchyOptions(spacetree_levels=False))):
         H = AdaptiveHierarchy(dim, n, r, leaves, p, oopts, kappa=KAPPA)
         nd = H.fine.ndof
         u0 = np.concatenate([synth.random_vector(nd, seed=70), synth.random_vector(nd, seed=71)])
