@@ -260,3 +260,19 @@ def test_adaptive_solution_has_the_discretisation_error():
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     log(f"  rates {rates}")
     assert np.all(np.abs(rates - (p + 1)) < 0.3)
+
+
+def test_adaptive_smooth_noalloc_equals_smooth():
+    # the allocation-free smoothing keeps its traces (own slots and the
+    # hanging-facet slots) in the static scratch array: same result as
+    # hpmg_smooth bit for bit, on two calls in a row
+    leaves = _leaves(3, 3, 2, "ball", 2)
+    g = _solver(3, 3, 2, 3, leaves)
+    for dt in (torch.float64, torch.float32):
+        for seed in (11, 12):
+            u0 = synth.random_vector(g.ndof, seed=seed)
+            b = synth.random_rhs(g.ndof, seed=seed + 50)
+            ua, ub, bd = to_dev(u0, dt), to_dev(u0, dt), to_dev(b, dt)
+            g.smooth(ua, bd, 3)
+            g.smooth_noalloc(ub, bd, 3)
+            assert torch.equal(ua, ub)
