@@ -145,7 +145,7 @@ def parse():
     ap.add_argument("--profile-sweeps", action="store_true",
                     help="only setup, autotuning and S timed sweeps per precision (for rocprofv3 runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="oracle sweep time per worker")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="oracle sweep time (batched: per two sample problems)")
     ap.add_argument("--block-recompute", action="store_true",
                     help="with --profile-sweeps and variable kappa: time the sweeps that rebuild the block inverse "
                          "in every traversal instead of the stored-eigendata sweeps (same kernel names, so each "
@@ -160,52 +160,45 @@ def parse():
 
 
 # ----------------------------------------------------------------- CPU side
-def _oracle_worker(job):
-    """Oracle (assembled CSR, FP64) on one problem: block-Jacobi sweeps for
-    `seconds`, then one MG-preconditioned CG solve to 1e-10; one BLAS thread."""
-    n, p, seconds, seed, kappa = job
+def cpu_baseline_cpp(problems, seconds, label):
+    """The C++ oracle (oracle/coracle.py: assembled CSR SIPG, block-Jacobi with
+    dense Cholesky blocks, Galerkin V-cycle, FCG; OpenMP over all host cores
+    given to it, at most 16, the GPU machine's share) on each sample problem in
+    turn: block-Jacobi sweeps for about `seconds`, then one MG-PCG solve to
+    1e-10.  value = DoF sweeps per second over the sample."""
+    os.environ.setdefault("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1)))
+    from oracle.coracle import CHierarchy, threads
+
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
     import synth
-    from oracle import Hierarchy
 
-    with threadpool_limits(limits=1):
-        H = Hierarchy(3, n, p, kappa)
-        nd = H.fine.ndof
-        b = synth.random_rhs(nd, seed=seed)
+    runs = []
+    for n, p, seed in problems:
+        t0 = time.perf_counter()
+        H = CHierarchy(3, n, p, 1.0)
+        t_setup = time.perf_counter() - t0
+        b = synth.random_rhs(H.ndof, seed=seed)
         u = np.zeros_like(b)
         sweeps, t = 0, 0.0
         t0 = time.perf_counter()
         while t < seconds or sweeps < 2:
-            u = H.smooth(0, u, b, 1)
+            u = H.smooth(u, b, 1)
             sweeps += 1
             t = time.perf_counter() - t0
         t0 = time.perf_counter()
         _, hist = H.solve(b, rtol=1e-10, maxit=300)
         ts = time.perf_counter() - t0
-    return {"n": n, "p": p, "ndof": nd, "sweeps": sweeps, "sweep_s": t, "solve_s": ts, "its": len(hist) - 1}
-
-
-def cpu_baseline_pool(jobs, label):
-    """Run the oracle jobs on a process pool, one worker per host core (at
-    most 16, the GPU machine's share); value = DoF sweeps per second summed over
-    the workers, which run concurrently."""
-    import multiprocessing as mp
-    workers = min(16, os.cpu_count() or 1, len(jobs))
-    ctx = mp.get_context("fork")  # called before anything initialises the GPU
-    t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
-        res = pool.map(_oracle_worker, jobs)
-    wall = time.perf_counter() - t0
-    rate = sum(r["ndof"] * r["sweeps"] / r["sweep_s"] for r in res)
+        runs.append({"n": n, "p": p, "ndof": H.ndof, "setup_s": t_setup, "sweeps": sweeps, "sweep_s": t,
+                     "solve_s": ts, "its": len(hist) - 1})
+    rate = sum(r["ndof"] * r["sweeps"] for r in runs) / sum(r["sweep_s"] for r in runs)
     return {
-        "value": rate, "unit": "DoF/s", "cores": workers, "kind": "oracle",
-        "sample": (f"{label}: {len(res)} oracle runs on {workers} processes (one BLAS thread each), each "
-                   f"block-Jacobi sweeps (assembled CSR matvec + dense Cholesky blocks) for about "
-                   f"{jobs[0][2]:.0f} s then one MG-PCG solve to 1e-10; wall {wall:.1f} s"),
-        "runs": res,
-        "time_to_1e-10_s_sample": {f"n{r['n']}_p{r['p']}": r["solve_s"] for r in res},
+        "value": rate, "unit": "DoF/s", "cores": threads(), "kind": "oracle",
+        "sample": (f"{label}: the C++ oracle with {threads()} OpenMP threads, per problem block-Jacobi sweeps "
+                   f"(assembled CSR matvec + dense Cholesky blocks) for about {seconds:.0f} s, then one MG-PCG "
+                   "solve to 1e-10"),
+        "runs": runs,
+        "time_to_1e-10_s_sample": {f"n{r['n']}_p{r['p']}": r["solve_s"] for r in runs},
     }
 
 
@@ -219,15 +212,13 @@ def run_batched(args):
     R = 4
     base = None
     if not args.no_cpu_baseline and not args.profile_sweeps:
-        # the oracle on the six smallest problems of the batch, before the GPU
-        # is initialised (the pool forks)
+        # the oracle on the six smallest problems of the batch
         order = sorted(range(len(probs)), key=lambda j: probs[j][0] ** 3 * (probs[j][1] + 1) ** 3)[:6]
-        workers = min(16, os.cpu_count() or 1)
-        jobs = [(probs[order[i % 6]][0], probs[order[i % 6]][1], args.cpu_seconds,
-                 synth.batched_rhs_seed(1004, order[i % 6], 0), 1.0) for i in range(max(6, workers))]
-        _progress(f"oracle baseline on {len(jobs)} runs of the six smallest problems")
-        base = cpu_baseline_pool(jobs, "the six smallest problems of the batch "
-                                       + ", ".join(f"Q{probs[j][1]} {probs[j][0]}^3" for j in order))
+        _progress("oracle baseline on the six smallest problems")
+        base = cpu_baseline_cpp([(probs[j][0], probs[j][1], synth.batched_rhs_seed(1004, j, 0)) for j in order],
+                                args.cpu_seconds / 2,
+                                "the six smallest problems of the batch "
+                                + ", ".join(f"Q{probs[j][1]} {probs[j][0]}^3" for j in order))
 
     import torch
 

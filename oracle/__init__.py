@@ -7,9 +7,11 @@ textbook operation on that matrix (block-Jacobi, Section 2.3.2 eq.
 block-Jacobi-IP; coarse-grid correction and multiplicative multigrid,
 Section 5, Algorithms CoarseGridCorrection / MGMult).
 
-Only `tests/`, `__graft_entry__.smoke()` and the CPU-baseline leg of
-`bench.py` may import this package.  The HIP library never calls it, and it
-shares no code with the HIP library.
+The same definitions on uniform meshes also exist as plain C++ with OpenMP
+(`c/sipg_oracle.cpp`, loaded by `coracle.py`), pinned against this one and
+timed as the CPU baseline.  Only `tests/`, `__graft_entry__.smoke()` and the
+CPU-baseline leg of `bench.py` may import this package.  The HIP library
+never calls it, and it shares no code with the HIP library.
 
 Parity status of each function is stated in its docstring; functions pinned
 by the CPU test-suite are listed in tests/test_oracle_*.py.
