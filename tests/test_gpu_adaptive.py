@@ -32,6 +32,8 @@ CASES = [
     (3, 3, 2, 4, "random", 1),
     (3, 2, 2, 3, "ball", 2),
     (3, 2, 2, 5, "ball", 1),
+    (3, 2, 3, 3, "ball", 1),
+    (3, 2, 2, 6, "ball", 1),
 ]
 
 
