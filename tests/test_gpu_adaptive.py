@@ -278,3 +278,29 @@ def test_adaptive_smooth_noalloc_equals_smooth():
             g.smooth(ua, bd, 3)
             g.smooth_noalloc(ub, bd, 3)
             assert torch.equal(ua, ub)
+
+
+def test_adaptive_p_schedule_and_mgmult():
+    # an explicit p schedule (5 -> 3 -> 2, transfers with a run-time coarse
+    # degree) and Algorithm MGMult (nu pre- and no post-smoothing on the DG
+    # levels) on an adaptive mesh: V-cycle against the oracle, MGMult cycle
+    # count equal to the oracle's
+    leaves = _leaves(3, 2, 2, "random", 1)
+    H = AdaptiveHierarchy(3, 2, 2, leaves, 5, HierarchyOptions(p_schedule=[3, 2]), kappa=KAPPA)
+    nd = H.fine.ndof
+    u0 = synth.random_vector(nd, seed=41)
+    b = synth.random_rhs(nd, seed=42)
+    g = _solver(3, 2, 2, 5, leaves, p_schedule=[3, 2])
+    ud, bd = to_dev(u0, torch.float64), to_dev(b, torch.float64)
+    g.vcycle(ud, bd)
+    err = rel_err(to_host(ud), H.vcycle(0, u0.copy(), b))
+    log(f"  p schedule 5-3-2 vcycle rel err {err:.3e}")
+    assert err <= 1e-10
+    Hm = AdaptiveHierarchy(3, 2, 2, leaves, 3, HierarchyOptions(nu_pre=2, nu_post=0), kappa=KAPPA)
+    gm = _solver(3, 2, 2, 3, leaves, nu_pre=2, nu_post=0, precision=0)
+    bm = synth.random_rhs(Hm.fine.ndof, seed=43)
+    _, hist, _ = Hm.mgmult(bm, rtol=1e-8, maxit=300)
+    ud = torch.zeros(Hm.fine.ndof, dtype=torch.float64, device="cuda")
+    info, st = gm.mgmult(ud, to_dev(bm, torch.float64), rtol=1e-8, maxit=300)
+    log(f"  MGMult cycles GPU {info.iterations} oracle {len(hist) - 1}")
+    assert st == 0 and info.iterations == len(hist) - 1
