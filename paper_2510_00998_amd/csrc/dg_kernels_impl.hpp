@@ -806,37 +806,55 @@ __device__ __forceinline__ void facet_pass0_const(const DGArgs<T>& a, const T* t
 }
 
 // Plain copy of the neighbour traces into sNB (variable kappa path, whose
-// facet transform needs the staged per-cell eigendata).  Element i of the
-// block is (facet f, cell cl, entry e), i = (f CPB + cl) 2L + e; all loads of
-// a thread are issued before its LDS stores, from neighbour indices clamped
+// facet transform needs the staged per-cell eigendata).  The 2L trace
+// entries of a (facet, cell) record are contiguous in the trace buffer and
+// in sNB, so the copy moves whole vectors of VB bytes (16 where the record
+// size allows; trace buffers are 256-byte aligned and each right-hand side
+// column starts at a multiple of the record size).  Item i of the block is
+// (facet f, cell cl, vector v), i = (f CPB + cl) NVEC + v; all loads of a
+// thread are issued before its LDS stores, from neighbour indices clamped
 // into the mesh (boundary facets take zeros).
 template <typename T, int D, int N>
 __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB) {
   using C = CT<T>;
   using Sh = DGShape<D, N>;
   constexpr int TL = 2 * Sh::L;
-  constexpr int NE = Sh::NF * Sh::CPB * TL;
+  constexpr int RB = TL * (int)sizeof(T);
+  constexpr int VB = RB % 16 == 0 ? 16 : (RB % 8 == 0 ? 8 : (RB % 4 == 0 ? 4 : (int)sizeof(T)));
+  constexpr int VE = VB / (int)sizeof(T);
+  constexpr int NVEC = TL / VE;
+  constexpr int NE = Sh::NF * Sh::CPB * NVEC;
   constexpr int IT = (NE + Sh::NT - 1) / Sh::NT;
+  struct alignas(VB) Vec {
+    T e[VE];
+  };
   const int tid = work_tid<D, N>();
-  C v[IT];
+  Vec v[IT];
 #pragma unroll
   for (int m = 0; m < IT; ++m) {
-    const int i = tid + m * Sh::NT;
-    const int f = min(i / (Sh::CPB * TL), Sh::NF - 1), rem = i % (Sh::CPB * TL);
-    const int cl = min(rem / TL, nc - 1), e = rem % TL;
+    const int i = min(tid + m * Sh::NT, NE - 1);
+    const int r = i / NVEC, e = (i % NVEC) * VE;
+    const int f = r / Sh::CPB, cl = min(r % Sh::CPB, nc - 1);
     const int c = c0 + cl;
     const int st = ipow<D>(a.n, f >> 1);
     const int nb = min(max((f & 1) ? c + st : c - st, 0), a.ncell - 1);
     const bool bdy = (a.bmask[c] >> f) & 1;
-    const C x = tr[((size_t)(f ^ 1) * a.ncell + nb) * TL + e];
-    v[m] = bdy ? C(0) : x;
+    v[m] = *reinterpret_cast<const Vec*>(tr + ((size_t)(f ^ 1) * a.ncell + nb) * TL + e);
+    if (bdy) {
+#pragma unroll
+      for (int j = 0; j < VE; ++j) v[m].e[j] = T(0);
+    }
   }
 #pragma unroll
   for (int m = 0; m < IT; ++m) {
     const int i = tid + m * Sh::NT;
-    const int f = i / (Sh::CPB * TL), rem = i % (Sh::CPB * TL);
-    const int cl = rem / TL, e = rem % TL;
-    if (i < NE && cl < nc) sNB[(cl * Sh::NF + f) * TL + e] = v[m];
+    const int r = i / NVEC, e = (i % NVEC) * VE;
+    const int f = r / Sh::CPB, cl = r % Sh::CPB;
+    if (i < NE && cl < nc) {
+      C* dst = sNB + (cl * Sh::NF + f) * TL + e;
+#pragma unroll
+      for (int j = 0; j < VE; ++j) dst[j] = (C)v[m].e[j];
+    }
   }
 }
 
