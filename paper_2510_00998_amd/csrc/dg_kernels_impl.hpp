@@ -152,13 +152,14 @@ __device__ __forceinline__ float recip(float d) {
   return __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
 }
 
-// Load scheme of the neighbour traces in the constant-kappa sweep: issued
-// all at once (facet_pass0_const) except for the FP64 degree-4 sweep, which
-// measured faster with the traces read item after item (the apply kernels
-// always issue them at once).
-template <typename T, int N>
-constexpr bool batched_trace_loads() {
-  return !(sizeof(T) == 8 && N == 5);
+// Load scheme of the neighbour traces in the constant-kappa sweep: every
+// load of a thread issued at once with the first tangential transform fused
+// (facet_pass0_const), except for the 3D FP64 degree-1 and degree-4 sweeps,
+// which measured faster with each (facet, cell) record first copied into LDS
+// as whole 16-byte vectors (the apply kernels always use the fused loads).
+template <typename T, int D, int N>
+constexpr bool sweep_copies_traces() {
+  return D == 3 && sizeof(T) == 8 && (N == 2 || N == 5);
 }
 
 // Thread index within the block's NT working threads; threads beyond NT
@@ -860,24 +861,25 @@ __device__ __forceinline__ void copy_neighbour_traces(const DGArgs<T>& a, const 
 
 // All facet flux fields of the block in sNB, the eigendata in sE and the
 // boundary masks of the block's cells in LDS; ends with a barrier.
-template <typename T, int D, int N, bool VARK, bool AT_ONCE = true, bool IVAR = false, bool AD = false>
+template <typename T, int D, int N, bool VARK, bool COPY_FIRST = false, bool IVAR = false, bool AD = false>
 __device__ __forceinline__ void flux_fields(const DGArgs<T>& a, const T* tr, int c0, int nc, CT<T>* sNB, CT<T>* sE, CT<T>* sKF) {
-  static_assert(!AD || (!VARK && AT_ONCE && !IVAR), "adaptive meshes: constant kappa, exact blocks, loads at once");
+  static_assert(!AD || (!VARK && !COPY_FIRST && !IVAR), "adaptive meshes: constant kappa, exact blocks, fused loads");
   int* sMask = mask_lds<D, N, VARK>(sKF);
   const int tid = work_tid<D, N>();
-  if constexpr (!VARK && AT_ONCE) {
+  if constexpr (!VARK) {
     if constexpr (IVAR) {  // interior-block smoother: item after item (boundary facets read own traces)
       facet_pass<T, D, N, false, true, true>(a, tr, c0, nc, 0, sNB, sE, sKF);
       load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
       if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
+    } else if constexpr (COPY_FIRST) {  // records copied, then the first transform from LDS
+      copy_neighbour_traces<T, D, N>(a, tr, c0, nc, sNB);
+      load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
+      if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
+      __syncthreads();
+      facet_pass<T, D, N, false>(a, tr, c0, nc, 0, sNB, sE, sKF);
     } else {
       facet_pass0_const<T, D, N, AD>(a, tr, c0, nc, sNB, sE, sMask);
     }
-    __syncthreads();
-  } else if constexpr (!VARK) {
-    facet_pass<T, D, N, false, true, IVAR>(a, tr, c0, nc, 0, sNB, sE, sKF);
-    load_eig<T, D, N, false>(a, c0, nc, sE, sKF);
-    if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
     __syncthreads();
   } else {
     copy_neighbour_traces<T, D, N>(a, tr, c0, nc, sNB);
@@ -1059,7 +1061,7 @@ __device__ __forceinline__ void sweep_body(const DGArgs<T>& a, int bx, int by, c
     }
   }
   if (!UZERO) {
-    flux_fields<T, D, N, VARK, AD || batched_trace_loads<T, N>(), IVAR, AD>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+    flux_fields<T, D, N, VARK, !AD && sweep_copies_traces<T, D, N>(), IVAR, AD>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   } else {
     load_eig<T, D, N, VARK, AD>(a, c0, nc, sE, sKF);
     __syncthreads();
@@ -1338,7 +1340,7 @@ __device__ __forceinline__ void sweep_body_mfma(const DGArgs<T>& a, int bx, int 
     }
   }
   if (!UZERO) {
-    flux_fields<T, D, N, VARK, batched_trace_loads<T, N>(), IVAR>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+    flux_fields<T, D, N, VARK, sweep_copies_traces<T, D, N>(), IVAR>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   } else {
     load_eig<T, D, N, VARK>(a, c0, nc, sE, sKF);
     if (tid < nc) sMask[tid] = a.bmask[c0 + tid];
@@ -1464,7 +1466,7 @@ __device__ __forceinline__ void apply_body(const DGArgs<T>& a, int bx, int by, c
       for (int j = 0; j < N; ++j) bl[j] = bs[j];
     }
   }
-  flux_fields<T, D, N, VARK, true, IVAR, AD>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
+  flux_fields<T, D, N, VARK, false, IVAR, AD>(a, a.tr_in + rt, c0, nc, sNB, sE, sKF);
   double pdot = 0.0;  // share of p.(A p) (kdot)
 
   // Si along every axis, diagonal scaling, then Si^T (= M S) back with the
