@@ -26,6 +26,7 @@ CASES = [
     (2, 7, 3, "var"),
     (2, 3, 8, "var"),
     (3, 3, 1, "var"),
+    (3, 6, 1, "const"),
     (3, 5, 2, "const"),
     (3, 4, 3, "var"),
     (3, 4, 4, "const"),
