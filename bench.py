@@ -144,6 +144,8 @@ def parse():
                     help="paper-mode cycle counts: 2D, one-step DG_p -> Q1, factor-3 h-coarsening, MGMult to 1e-7")
     ap.add_argument("--profile-sweeps", action="store_true",
                     help="only setup, autotuning and S timed sweeps per precision (for rocprofv3 runs)")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="single-problem configs: setup, then three solves with the FP32 cycle only (for rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="oracle sweep time (batched: per two sample problems)")
     ap.add_argument("--block-recompute", action="store_true",
@@ -538,6 +540,20 @@ def run_single(args):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     gmx = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F32)
+    if args.profile_solve:
+        bp = torch.empty(g64.ndof, dtype=torch.float64, device=dev)
+        g64.load_vector(fkind, 1.0, bp)
+        up = torch.zeros_like(bp)
+        out = []
+        for _ in range(3):
+            up.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info, st = gmx.solve(up, bp, rtol=1e-10, maxit=200, check=False)
+            torch.cuda.synchronize()
+            out.append({"seconds": time.perf_counter() - t0, "iterations": info.iterations, "status": st})
+        print(json.dumps({"profile_solve": out}), flush=True)
+        return
     g16 = hp.Solver(dim, n, p, kappa, precision=hp.PREC_F16)
     gb16 = hp.Solver(dim, n, p, kappa, precision=hp.PREC_BF16)
     nd = g64.ndof

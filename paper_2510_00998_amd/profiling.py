@@ -11,10 +11,12 @@ autotuner (same kernels, other grids) are excluded:
   python -m paper_2510_00998_amd.profiling counter <counter_collection.csv> <S> <regex>
   python -m paper_2510_00998_amd.profiling summary <trace> <fetch> <write> <S> <keys json> <sources> <title> <command> [<extra json>]
   python -m paper_2510_00998_amd.profiling sq <counter_collection.csv> <S> <keys json> <title> <command>
+  python -m paper_2510_00998_amd.profiling timeline <kernel_trace.csv> <marker regex> <title> <command>
 
 `times` prints the mean duration per dispatch; `counter` the mean counter
 value per dispatch (KiB for FETCH_SIZE / WRITE_SIZE) and the copy kernel's
-value for calibration.
+value for calibration; `timeline` the kernels of one solver iteration of a
+`bench.py --profile-solve` trace, with the idle gaps between them.
 """
 from __future__ import annotations
 
@@ -180,7 +182,73 @@ def sq(path, last, keys, title, command):
     print("\n".join(out))
 
 
+def _short(name):
+    """Kernel name without its parameter list and anonymous namespaces."""
+    depth = 0
+    if name.endswith(")"):
+        for j in range(len(name) - 1, -1, -1):
+            if name[j] == ")":
+                depth += 1
+            elif name[j] == "(":
+                depth -= 1
+                if depth == 0:
+                    name = name[:j]
+                    break
+    return name.replace("(anonymous namespace)::", "").replace("void ", "")
+
+
+def timeline(path, marker, title, command):
+    """One iteration of a solve from a kernel trace: the dispatches after the
+    second-to-last dispatch of the kernel matching `marker` up to and
+    including the last one (the last complete iteration of the last solve),
+    in start order, with their durations and the idle gaps between them."""
+    header, rows = _rows(path)
+    kn = _col(header, "Kernel_Name")
+    t0 = _col(header, "Start_Timestamp")
+    t1 = _col(header, "End_Timestamp")
+    ev = sorted((int(r[t0]), int(r[t1]), r[kn]) for r in rows)
+    rx = re.compile(marker)
+    marks = [i for i, e in enumerate(ev) if rx.search(e[2])]
+    if len(marks) < 2:
+        raise SystemExit(f"fewer than two dispatches match {marker!r}")
+    a, b = marks[-2], marks[-1]
+    it = ev[a + 1:b + 1]
+    start = ev[a][1]
+    print(f"# {title}\n")
+    print("Command (from /tmp with TMPDIR=/tmp, repository at $R):\n")
+    for c in command.split(" && "):
+        print(f"    {c}")
+    print()
+    print(f"One iteration: the {len(it)} dispatches after the second-to-last `{marker}` dispatch of the trace up to "
+          "and including the last one, in start order; gap = idle time since the previous dispatch ended.\n")
+    print("| # | kernel | start [us] | duration [us] | gap before [us] |")
+    print("|---|---|---|---|---|")
+    prev = start
+    busy = gaps = 0.0
+    per = defaultdict(lambda: [0, 0.0])
+    for i, (s0, s1, k) in enumerate(it):
+        d = (s1 - s0) * 1e-3
+        g = max(0.0, (s0 - prev) * 1e-3)
+        busy += d
+        gaps += g
+        nm = _short(k)
+        per[nm][0] += 1
+        per[nm][1] += d
+        print(f"| {i} | `{nm[:100]}` | {(s0 - start) * 1e-3:.1f} | {d:.1f} | {g:.1f} |")
+        prev = max(prev, s1)
+    span = (it[-1][1] - start) * 1e-3
+    print(f"\nIteration span {span:.1f} us: kernels {busy:.1f} us, idle gaps {gaps:.1f} us.\n")
+    print("| kernel | dispatches | total [us] |")
+    print("|---|---|---|")
+    for nm, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        print(f"| `{nm[:100]}` | {c} | {t:.1f} |")
+
+
 def main(argv):
+    if argv[0] == "timeline":
+        # timeline <kernel_trace.csv> <marker regex> <title> <command>
+        timeline(argv[1], argv[2], argv[3], argv[4])
+        return
     if argv[0] == "sq":
         # sq <counter_collection.csv> <last> <keys json> <title> <command>
         sq(argv[1], int(argv[2]), argv[3], argv[4], argv[5])

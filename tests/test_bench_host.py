@@ -66,3 +66,24 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "exactly one GPU" in res.stdout
+
+
+def test_profiling_timeline_picks_the_last_iteration(tmp_path, capsys):
+    """The timeline summary keeps the dispatches after the second-to-last
+    marker up to the last one, with the idle gaps between them."""
+    from paper_2510_00998_amd import profiling
+    hdr = "Kind,Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp\n"
+    ev = [("k_update_ur(double*)", 0, 1000),            # an earlier iteration's marker
+          ("void hpmg::k_a<float>(int)", 1000, 3000),
+          ("k_update_ur(double*)", 3000, 4000),         # second-to-last marker: iteration starts at 4000
+          ("void hpmg::(anonymous namespace)::k_a<float>(int)", 6000, 8000),   # gap 2 us
+          ("void hpmg::k_b(int)", 8000, 9000),
+          ("k_update_ur(double*)", 9500, 10500)]        # last marker, gap 0.5 us
+    path = tmp_path / "trace.csv"
+    path.write_text(hdr + "".join(f"KERNEL_DISPATCH,{i},\"{k}\",{a},{b}\n" for i, (k, a, b) in enumerate(ev)))
+    profiling.timeline(str(path), "k_update_ur", "t", "cmd")
+    out = capsys.readouterr().out
+    assert "the 3 dispatches after" in out
+    assert "| 0 | `hpmg::k_a<float>` | 2.0 | 2.0 | 2.0 |" in out
+    assert "| 2 | `k_update_ur` | 5.5 | 1.0 | 0.5 |" in out
+    assert "Iteration span 6.5 us: kernels 4.0 us, idle gaps 2.5 us." in out
