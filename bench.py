@@ -374,9 +374,11 @@ def run_batched(args):
     ach = by64 / t64 / 1e9
     split = tuning["smooth_f64_split_by_degree"]
     half = set(tuning["smooth_f64_half_tile_degrees"])
-    kern64 = ("k_dg_batch_n<double,0,N,V> for (N,V) = " +
+    one = "true" if tuning["smooth_f64_grid"] > 8192 else "false"  # the grid covers the item list
+    kern64 = (f"k_dg_batch_n<double,0,N,V,{one}> for (N,V) = " +
               ",".join(f"({p + 1},{int(p in half)})" for p in degs) +
-              " (one launch per degree per sweep; V = 1: half the cells per workgroup)") if split \
+              " (one launch per degree per sweep; V = 1: half the cells per workgroup; true: one workgroup per"
+              " work item)") if split \
         else "k_dg_batch<double,0> (one launch per sweep)"
     # time-to-solution roofline: bytes of one FCG iteration of every segment
     # (the captured graph iterates all segments until the last converges)

@@ -600,15 +600,22 @@ void tune(const std::vector<int>& grids, const std::vector<int>& degrees, F work
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  // best of three timings of two repetitions after a warm-up: one timing
+  // alone varies by a few per cent from run to run, as much as the
+  // differences between the configurations
   auto timed = [&](int g, bool sp, int tl) {
     work(g, sp, tl, 1);  // warm-up
-    HIPCHK(hipEventRecord(e0, s));
-    work(g, sp, tl, 2);
-    HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    return (double)ms;
+    double best = 1e30;
+    for (int k = 0; k < 3; ++k) {
+      HIPCHK(hipEventRecord(e0, s));
+      work(g, sp, tl, 2);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      best = std::min(best, (double)ms);
+    }
+    return best;
   };
   double tbest = 1e30;
   tile = 0;
