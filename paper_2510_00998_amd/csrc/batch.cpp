@@ -652,12 +652,16 @@ std::vector<int> degrees_of(const std::vector<Launch>& v) {
   return out;
 }
 
-// Persistent grid size, degree split and tile variants of the V-cycle
+// Grid cap above every work list: one workgroup per item (the one-degree
+// launches then take their loop-free kernels).
+constexpr int kOnePerItem = 1 << 30;
+
+// Persistent grid size (or one workgroup per item), degree split and tile variants of the V-cycle
 // launches, tuned on the V-cycle of the batch (run on the current r32).
 void autotune_vcycle(BatchPlan* B, hipStream_t s) {
   int grid = 1024, tile = 0;
   bool split = true;
-  tune({256, 512, 1024, 2048, 4096}, degrees_of(B->vcycle),
+  tune({256, 512, 1024, 2048, 4096, kOnePerItem}, degrees_of(B->vcycle),
        [&](int g, bool sp, int tl, int reps) {
          for (int i = 0; i < reps; ++i) run_grid(B->vcycle, g, sp, tl, s);
        },
