@@ -349,14 +349,17 @@ hpmg_status hpmg_batch_solve(hpmg_batch b, double* const* u, const double* const
  * of count DEVICE pointers to nrhs stacked vectors of problem j in dtype
  * (u updated in place).  Enqueued on `stream`; successive calls on one
  * batch must use one stream (they share an argument table).  The first
- * call for a dtype and nrhs tunes the persistent grid on internal vectors.
+ * call for a dtype and nrhs tunes the launch grid on internal vectors.
  * Invalidates the handles' trace state. */
 hpmg_status hpmg_batch_smooth(hpmg_batch b, hpmg_dtype dtype, void* const* u, const void* const* rhs,
                               int nsweeps, int nrhs, hipStream_t stream);
 
 /* Launch configuration the autotuner chose for the batch's current number
- * of right-hand sides: out[0] persistent grid (blocks) of the V-cycle
- * launches, out[1] 1 if they run one launch per polynomial degree (else
+ * of right-hand sides: out[0] grid cap (workgroups) of the V-cycle
+ * launches: a persistent grid, or a cap at least the number of work items
+ * of every launch (1 << 30 from the V-cycle tuner, the total item count
+ * from the smoothing tuner): one workgroup per item, which runs loop-free
+ * one-degree kernels; out[1] 1 if they run one launch per polynomial degree (else
  * one launch over all degrees), out[2..3] the same for FP32
  * hpmg_batch_smooth, out[4..5] for FP64, out[6..8] the tile masks of the
  * V-cycle, FP32 and FP64 smoothing launches: bit N (N = p + 1) set if the
